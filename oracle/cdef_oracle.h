@@ -1,0 +1,99 @@
+/*
+ * cdef_oracle.h -- plain, slow, single-threaded CPU CDEF.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the oracle that the GPU library is
+ * checked against.  Only the tests, the smoke check and the benchmark's CPU
+ * baseline may load it; the product path never does.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * Everything follows "The AV1 Constrained Directional Enhancement Filter
+ * (CDEF)" (Midtskogen and Valin):
+ *   Section 2, Eq. (1)-(5) and Algorithm 1 ... direction search
+ *   Section 3, Eq. (6)-(12) ................... constrained directional filter
+ *   Section 3.2, Eq. (13) ..................... strength ranges, bit depth,
+ *                                               chroma damping, adjustment
+ *   Section 4 ................................. 64x64 filter blocks, skip
+ *   Section 5 ................................. per-filter-block SSE D_{b,p}
+ *
+ * Readings of points where the paper is silent or garbled are listed in the
+ * source file next to the code that takes them.
+ *
+ * All sample buffers are host memory, uint16, row-major with a stride in
+ * samples.  Integer arithmetic only; every result is exact.
+ */
+#ifndef CDEF_ORACLE_H
+#define CDEF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One frame.  nplanes = 1 (luma only) or 3 (4:2:0: chroma planes are
+ * ceil(width/2) x ceil(height/2)).  bitdepth 8..12. */
+typedef struct {
+  const uint16_t *plane[3];
+  int64_t stride[3];
+  int32_t width, height; /* luma size */
+  int32_t bitdepth;
+  int32_t nplanes;
+} cdef_oracle_frame;
+
+/* Line number k of pixel (i, j) (row i, column j, 0..7) of an 8x8 block for
+ * direction d (0..7): the lost Fig. 1, read as described in the source. */
+int cdef_oracle_line_number(int d, int i, int j);
+
+/* Algorithm 1's s[d] (Eq. 5 times 840) for the bw x bh in-frame top-left
+ * part of one 8x8 block (1 <= bw, bh <= 8). */
+void cdef_oracle_direction_costs(const uint16_t *px, int64_t stride, int bw, int bh,
+                                 int bitdepth, int64_t cost[8]);
+
+/* Algorithm 1 on every 8x8 luma block: dir and var are [ceil(h/8)][ceil(w/8)]. */
+void cdef_oracle_find_dir(const uint16_t *luma, int64_t stride, int width, int height,
+                          int bitdepth, uint8_t *dir, int32_t *var);
+
+/* Eq. (7): the constraint function f(d, S, D). */
+int cdef_oracle_constrain(int diff, int strength, int damping);
+
+/* Eq. (13): the luma primary strength after adjustment by the block's
+ * directional contrast v. */
+int cdef_oracle_adjust_strength(int strength, int32_t var);
+
+/* Section 3.2: chroma damping for luma damping D and chroma primary S. */
+int cdef_oracle_chroma_damping(int damping, int pri_strength);
+
+/* Eq. (8)-(12) for one pixel of one plane.  pri/sec strengths and damping are
+ * the values actually used by f (already scaled to the bit depth); w1, w2 are
+ * the primary weights of the inner and outer tap (in 1/16). */
+int cdef_oracle_filter_pixel(const uint16_t *p, int64_t stride, int pw, int ph, int i, int j,
+                             int dir, int pri_strength, int pri_damping, int w1, int w2,
+                             int sec_strength, int sec_damping);
+
+/* Filter a whole frame (Sections 3-4).  dir/var from cdef_oracle_find_dir,
+ * skip [ceil(h/8)][ceil(w/8)] (NULL = no skipped blocks), strengths
+ * [ceil(h/64)][ceil(w/64)][4] = (pri_y, sec_y, pri_uv, sec_uv) in the 8-bit
+ * domain, damping = luma D (3..6). */
+void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3],
+                              const int64_t out_stride[3], const uint8_t *dir,
+                              const int32_t *var, const uint8_t *skip, int damping,
+                              const uint8_t *strengths);
+
+/* Section 5: SSE of one 64x64 filter block (fby, fbx) for every plane and
+ * every (S^(p) = 0..15, S^(s) in {0,1,2,4}) pair, filtering the block in full
+ * for each pair.  sse is [nplanes][16][4]. */
+void cdef_oracle_search_fb(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+                           const uint8_t *dir, const int32_t *var, const uint8_t *skip,
+                           int damping, int fby, int fbx, uint64_t *sse);
+
+/* The whole-frame search: find_dir, then every filter block.
+ * sse is [nplanes][ceil(h/64)][ceil(w/64)][16][4]; dir/var as find_dir. */
+void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+                        const uint8_t *skip, int damping, uint64_t *sse,
+                        uint8_t *dir, int32_t *var);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif
