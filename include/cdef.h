@@ -1,0 +1,139 @@
+/*
+ * cdef.h -- C ABI of the MI355X (gfx950) CDEF library, libcdef_hip.so.
+ *
+ * CDEF is the constrained directional enhancement filter of Midtskogen and
+ * Valin, "The AV1 Constrained Directional Enhancement Filter (CDEF)".  The
+ * library runs the data-parallel part of it on the GPU:
+ *   - the per-8x8 direction search (Section 2, Eq. 1-5, Algorithm 1),
+ *   - the constrained primary/secondary directional filter (Section 3,
+ *     Eq. 6-13) over 64x64 filter blocks (Section 4),
+ *   - the encoder's strength search: every 64x64 filter block filtered under
+ *     every (primary, secondary) strength pair and scored by SSE against the
+ *     source (Section 5, the distortion D_{b,p} with D = ||s - d||^2).
+ *
+ * Conventions shared by every entry point
+ *   - Every buffer pointer is a DEVICE pointer (hipMalloc, or the data of a
+ *     GPU tensor).  The caller owns and allocates all of them; none may
+ *     alias an output of the same call.  The library keeps no per-call state.
+ *   - Samples are uint16, row-major, `stride` counted in samples
+ *     (stride >= plane width).  Values must be < 2^bitdepth: larger values
+ *     are a contract violation (memory-safe, result unspecified).
+ *   - Luma is plane 0.  With CDEF_LAYOUT_420 the chroma planes 1 and 2 are
+ *     ceil(width/2) x ceil(height/2); with CDEF_LAYOUT_400 they are unused.
+ *   - Per-8x8 maps (dir, var, skip) are [ceil(h/8)][ceil(w/8)] row-major
+ *     over the luma plane; per-filter-block maps are [ceil(h/64)][ceil(w/64)].
+ *     At 4:2:0 a 4x4 chroma block uses the direction and skip flag of its
+ *     co-located 8x8 luma block, and a chroma filter block is 32x32.
+ *   - Strengths are given in the 8-bit domain (Section 3.2): primary 0..15,
+ *     secondary one of {0, 1, 2, 4}; luma damping D is 3..6.  For 10-bit
+ *     content the library shifts strengths left by 2 and raises D by 2.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL is the null stream).  They return after enqueueing; outputs are
+ *     valid once the stream has reached that point.
+ *   - Errors: every argument that lives on the host is checked before
+ *     anything is enqueued.  A failed check returns CDEF_E_INVAL or
+ *     CDEF_E_UNSUPPORTED and writes nothing.  A failed launch returns
+ *     CDEF_E_HIP.  Kernels have no data-dependent failure.
+ *   - Every entry point is thread-safe.
+ */
+#ifndef CDEF_H
+#define CDEF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CDEF_OK = 0,
+  CDEF_E_INVAL = -1,       /* bad argument (null pointer, size, range, aliasing) */
+  CDEF_E_UNSUPPORTED = -2, /* valid CDEF input that this library does not handle */
+  CDEF_E_HIP = -3,         /* the HIP runtime reported an error */
+  CDEF_E_NOMEM = -4        /* a caller-provided workspace is too small */
+} cdef_status;
+
+enum { CDEF_LAYOUT_400 = 0, CDEF_LAYOUT_420 = 1 };
+
+/* One frame.  plane[1..2] may be NULL for CDEF_LAYOUT_400.  bitdepth is 8 or
+ * 10 (12-bit content is valid CDEF but returns CDEF_E_UNSUPPORTED). */
+typedef struct {
+  const uint16_t *plane[3];
+  int64_t stride[3];
+  int32_t width, height; /* luma size, >= 1 each */
+  int32_t bitdepth;
+  int32_t layout;
+} cdef_frame;
+
+/* Writable planes of a filtered frame; geometry is that of the input. */
+typedef struct {
+  uint16_t *plane[3];
+  int64_t stride[3];
+} cdef_frame_out;
+
+/* Strengths of one 64x64 filter block, 8-bit domain.  Section 3.2 gives the
+ * ranges: pri 0..15, sec in {0, 1, 2, 4}.  They are read on the device; a
+ * value out of range is a contract violation (the kernel masks pri to 4
+ * bits and treats sec > 4 as 4, and stays memory-safe). */
+typedef struct {
+  uint8_t pri_y, sec_y, pri_uv, sec_uv;
+} cdef_strength;
+
+/* Direction search, Section 2 and Algorithm 1, on the luma plane of `f`.
+ *   dir[b]: the direction 0..7 that minimizes E_d^2 of Eq. (2) (ties go to
+ *           the lowest d).  Direction 0 is the 45-degree line rising to the
+ *           right; each step turns 22.5 degrees clockwise (2 = horizontal,
+ *           6 = vertical).
+ *   var[b]: the directional contrast of Algorithm 1, s_best - s_orthogonal,
+ *           with s_d of Eq. (5) scaled by 840; 0 <= var <= 880,803,840.
+ *   Pixels above 8 bits are reduced to 8 bits (low bits dropped) first.
+ *   Blocks cut by the frame edge use their in-frame pixels only.
+ * Errors: CDEF_E_INVAL for a null frame/plane/output, size < 1, stride <
+ * width, unknown layout; CDEF_E_UNSUPPORTED for bit depth other than 8/10. */
+cdef_status cdef_find_dir(const cdef_frame *f, uint8_t *dir, int32_t *var, void *stream);
+
+/* Filter a frame, Sections 3 and 4: Eq. (7)-(12) with the luma primary
+ * strength adjusted per 8x8 block by Eq. (13) from `var`.
+ *   in, out:  same geometry; out must not overlap in.
+ *   dir, var: from cdef_find_dir on `in`.
+ *   skip8x8:  1 = block has no coded residual and is copied (its co-located
+ *             chroma too); NULL means no block is skipped.
+ *   damping:  luma D, 3..6; chroma uses max(D - 1, floor(log2 pri_uv)).
+ *   fb:       per-filter-block strengths [ceil(h/64)][ceil(w/64)].
+ * Out-of-frame taps are ignored (Section 3.2); every output pixel is computed
+ * from unfiltered input.
+ * Errors: as cdef_find_dir, plus CDEF_E_INVAL for damping outside 3..6, a null
+ * dir/var/fb/out plane, or out overlapping in. */
+cdef_status cdef_filter_frame(const cdef_frame *in, const cdef_frame_out *out,
+                              const uint8_t *dir, const int32_t *var,
+                              const uint8_t *skip8x8, int32_t damping,
+                              const cdef_strength *fb, void *stream);
+
+/* Encoder strength search, Section 5: for every 64x64 filter block b, every
+ * plane and every pair (S^(p) = 0..15, S^(s) in {0,1,2,4}) the SSE between
+ * the source and the reconstruction filtered with that pair (skip-condition
+ * bit off: skipped 8x8 blocks stay unfiltered).  Direction search, filter
+ * and SSE run fused; filtered pixels never reach memory.
+ *   recon, src: same geometry; src is the uncoded frame.
+ *   sse:        uint64 [nplanes][ceil(h/64)][ceil(w/64)][16][4]; the last
+ *               index is S^(s) in the order 0, 1, 2, 4.  In-frame pixels only.
+ *   dir, var:   optional outputs of the direction search (NULL to skip).
+ * Errors: as cdef_filter_frame (damping, geometry), CDEF_E_INVAL for a null
+ * sse or geometry mismatch between recon and src. */
+cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src,
+                                  const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
+                                  uint8_t *dir, int32_t *var, void *stream);
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char *cdef_status_str(cdef_status s);
+
+/* ABI revision of this header; bumped on any incompatible change. */
+#define CDEF_ABI_VERSION 1
+int32_t cdef_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,203 @@
+"""Python binding of the gfx950 CDEF library (libcdef_hip.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/cdef.h.  PyTorch provides the
+device memory and the stream.  There is no CPU fallback: when the library is
+missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdef_hip.so")
+
+CDEF_OK = 0
+CDEF_E_INVAL = -1
+CDEF_E_UNSUPPORTED = -2
+CDEF_E_HIP = -3
+CDEF_E_NOMEM = -4
+LAYOUT_400 = 0
+LAYOUT_420 = 1
+
+# Exported symbols of include/cdef.h (the tests check that each one exists).
+EXPORTS = (
+    "cdef_find_dir",
+    "cdef_filter_frame",
+    "cdef_search_strengths",
+    "cdef_status_str",
+    "cdef_abi_version",
+)
+
+
+class CdefFrame(C.Structure):
+    _fields_ = [
+        ("plane", C.c_void_p * 3),
+        ("stride", C.c_int64 * 3),
+        ("width", C.c_int32),
+        ("height", C.c_int32),
+        ("bitdepth", C.c_int32),
+        ("layout", C.c_int32),
+    ]
+
+
+class CdefFrameOut(C.Structure):
+    _fields_ = [("plane", C.c_void_p * 3), ("stride", C.c_int64 * 3)]
+
+
+class CdefError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcdef_hip.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.cdef_find_dir.argtypes = [C.POINTER(CdefFrame), P, P, P]
+    L.cdef_find_dir.restype = C.c_int
+    L.cdef_filter_frame.argtypes = [C.POINTER(CdefFrame), C.POINTER(CdefFrameOut), P, P, P,
+                                    C.c_int32, P, P]
+    L.cdef_filter_frame.restype = C.c_int
+    L.cdef_search_strengths.argtypes = [C.POINTER(CdefFrame), C.POINTER(CdefFrame), P,
+                                        C.c_int32, P, P, P, P]
+    L.cdef_search_strengths.restype = C.c_int
+    L.cdef_status_str.argtypes = [C.c_int]
+    L.cdef_status_str.restype = C.c_char_p
+    L.cdef_abi_version.argtypes = []
+    L.cdef_abi_version.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    return load().cdef_status_str(status).decode()
+
+
+def _check(status: int, where: str):
+    if status != CDEF_OK:
+        raise CdefError(status, where)
+
+
+@dataclasses.dataclass
+class Frame:
+    """Device-resident frame: 2-D uint16 (or int16) planes, row-major."""
+
+    planes: List  # torch tensors
+    width: int
+    height: int
+    bitdepth: int
+    layout: int
+
+    @property
+    def nplanes(self) -> int:
+        return 3 if self.layout == LAYOUT_420 else 1
+
+    @property
+    def block_shape(self):
+        return ((self.height + 7) // 8, (self.width + 7) // 8)
+
+    @property
+    def fb_shape(self):
+        return ((self.height + 63) // 64, (self.width + 63) // 64)
+
+    def c_struct(self) -> CdefFrame:
+        f = CdefFrame()
+        for p, t in enumerate(self.planes[:3]):
+            if t is None:
+                continue
+            assert t.dim() == 2 and t.stride(1) == 1 and t.element_size() == 2
+            f.plane[p] = t.data_ptr()
+            f.stride[p] = t.stride(0)
+        f.width, f.height, f.bitdepth, f.layout = self.width, self.height, self.bitdepth, self.layout
+        return f
+
+    @staticmethod
+    def from_numpy(planes: Sequence, width: int, height: int, bitdepth: int, layout: int,
+                   device="cuda") -> "Frame":
+        import torch
+        ts = [torch.from_numpy(p.view("int16") if p.dtype.name == "uint16" else p).to(device)
+              for p in planes]
+        return Frame(ts, width, height, bitdepth, layout)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ---- the C ABI, one function per entry point --------------------------------
+
+def cdef_find_dir(frame: Frame, dir, var, stream=None) -> None:
+    st = load().cdef_find_dir(C.byref(frame.c_struct()), _ptr(dir), _ptr(var),
+                              _stream_handle(stream))
+    _check(st, "cdef_find_dir")
+
+
+def cdef_filter_frame(frame: Frame, out_planes: Sequence, dir, var, skip, damping: int, fb,
+                      stream=None) -> None:
+    o = CdefFrameOut()
+    for p, t in enumerate(out_planes[:3]):
+        if t is not None:
+            o.plane[p] = t.data_ptr()
+            o.stride[p] = t.stride(0)
+    st = load().cdef_filter_frame(C.byref(frame.c_struct()), C.byref(o), _ptr(dir), _ptr(var),
+                                  _ptr(skip), damping, _ptr(fb), _stream_handle(stream))
+    _check(st, "cdef_filter_frame")
+
+
+def cdef_search_strengths(recon: Frame, src: Frame, skip, damping: int, sse, dir=None, var=None,
+                          stream=None) -> None:
+    st = load().cdef_search_strengths(C.byref(recon.c_struct()), C.byref(src.c_struct()),
+                                      _ptr(skip), damping, _ptr(sse), _ptr(dir), _ptr(var),
+                                      _stream_handle(stream))
+    _check(st, "cdef_search_strengths")
+
+
+# ---- allocating conveniences -------------------------------------------------
+
+def find_dir(frame: Frame, stream=None):
+    import torch
+    dev = frame.planes[0].device
+    d = torch.empty(frame.block_shape, dtype=torch.uint8, device=dev)
+    v = torch.empty(frame.block_shape, dtype=torch.int32, device=dev)
+    cdef_find_dir(frame, d, v, stream)
+    return d, v
+
+
+def filter_frame(frame: Frame, dir, var, skip, damping: int, fb, stream=None):
+    import torch
+    outs = [torch.empty_like(p) for p in frame.planes[:frame.nplanes]]
+    cdef_filter_frame(frame, outs, dir, var, skip, damping, fb, stream)
+    return outs
+
+
+def search_strengths(recon: Frame, src: Frame, skip, damping: int, want_dir=False, stream=None):
+    import torch
+    dev = recon.planes[0].device
+    fbr, fbc = recon.fb_shape
+    sse = torch.empty((recon.nplanes, fbr, fbc, 16, 4), dtype=torch.int64, device=dev)
+    d = v = None
+    if want_dir:
+        d = torch.empty(recon.block_shape, dtype=torch.uint8, device=dev)
+        v = torch.empty(recon.block_shape, dtype=torch.int32, device=dev)
+    cdef_search_strengths(recon, src, skip, damping, sse, d, v, stream)
+    return (sse, d, v) if want_dir else sse

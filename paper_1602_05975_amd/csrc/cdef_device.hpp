@@ -1,0 +1,230 @@
+// Device-side building blocks of the gfx950 CDEF kernels.
+//
+// Paper: Midtskogen and Valin, "The AV1 Constrained Directional Enhancement
+// Filter (CDEF)".  Section 2 (direction search, Eq. 1-5, Algorithm 1),
+// Section 3 (constraint Eq. 7, 2-D filter Eq. 8-12, strengths and damping,
+// adjustment Eq. 13), Section 4 (64x64 filter blocks, skip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdef {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Value stored in LDS for a position outside the visible frame.  As a signed
+// 16-bit number it is the most negative value (never a signed maximum), as
+// an unsigned one it is 32768 (never an unsigned minimum of valid samples),
+// and its distance to any 10-bit sample is >= 31745, which no strength
+// below 2^9 can pass through the constraint function.
+constexpr uint16_t kOutside = 0x8000;
+
+// ---- Direction geometry (the lost Fig. 1, 4, 5 read as documented) --------
+// Direction 0 is the 45-degree line rising to the right; each step turns the
+// line 22.5 degrees clockwise on screen (row index grows downward).
+
+// Line number of pixel (i, j) of an 8x8 block for direction d.
+__host__ __device__ constexpr int line_key(int d, int i, int j) {
+  return d == 0 ? i + j
+       : d == 1 ? i + (j >> 1)
+       : d == 2 ? i
+       : d == 3 ? i - (j >> 1) + 3
+       : d == 4 ? i - j + 7
+       : d == 5 ? j - (i >> 1) + 3
+       : d == 6 ? j
+                : j + (i >> 1);
+}
+
+// Number of pixels on line k of direction d in a full 8x8 block.
+__host__ __device__ constexpr int line_count(int d, int k) {
+  int n = 0;
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) n += line_key(d, i, j) == k ? 1 : 0;
+  return n;
+}
+
+// Row/column offset of the inner (t = 0) and outer (t = 1) tap along d.
+__host__ __device__ constexpr int tap_dr(int d, int t) {
+  return t == 0 ? (d == 0 ? -1 : d <= 3 ? 0 : 1)
+                : (d == 0 ? -2 : d == 1 ? -1 : d == 2 ? 0 : d == 3 ? 1 : 2);
+}
+__host__ __device__ constexpr int tap_dc(int d, int t) {
+  return t == 0 ? (d <= 4 ? 1 : 0)
+                : (d <= 4 ? 2 : d == 5 ? 1 : d == 6 ? 0 : -1);
+}
+
+__device__ __forceinline__ int floor_log2(int v) { return 31 - __clz(v); }  // v >= 1
+
+// 840 / n for n = 1..8 (840 is the least common multiple of 1..8).
+__device__ __forceinline__ int inv840(int n) {
+  return n == 1 ? 840 : n == 2 ? 420 : n == 3 ? 280 : n == 4 ? 210
+       : n == 5 ? 168 : n == 6 ? 140 : n == 7 ? 120 : 105;
+}
+
+// Algorithm 1 on a full 8x8 block of centred 8-bit values: the 840-scaled
+// s_d of Eq. (5) for all eight directions.  All loops unroll; line sums and
+// counts are compile-time positions.
+__device__ __forceinline__ void dir_costs_full(const int (&x)[64], int (&cost)[8]) {
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    int part[15];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) part[k] = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) part[line_key(d, i, j)] += x[i * 8 + j];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+      const int n = line_count(d, k);
+      if (n > 0) c += __mul24(__mul24(part[k], part[k]), 840 / (n > 0 ? n : 1));
+    }
+    cost[d] = c;
+  }
+}
+
+// The same for a block cut by the frame edge: only the top-left bw x bh
+// pixels exist, and line lengths are counted.
+__device__ __forceinline__ void dir_costs_partial(const int (&x)[64], int bw, int bh, int (&cost)[8]) {
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    int part[15], cnt[15];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) part[k] = cnt[k] = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bool in = i < bh && j < bw;
+        part[line_key(d, i, j)] += in ? x[i * 8 + j] : 0;
+        cnt[line_key(d, i, j)] += in ? 1 : 0;
+      }
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 15; ++k)
+      if (cnt[k] > 0) c += __mul24(__mul24(part[k], part[k]), inv840(cnt[k]));
+    cost[d] = c;
+  }
+}
+
+// Argmax with a strict '>' from d = 0, and the directional contrast
+// v = s_best - s_(best+4 mod 8).
+__device__ __forceinline__ void pick_direction(const int (&cost)[8], int &dir, int &var) {
+  int best = 0, bc = cost[0];
+#pragma unroll
+  for (int d = 1; d < 8; ++d)
+    if (cost[d] > bc) {
+      bc = cost[d];
+      best = d;
+    }
+  int orth = cost[0];
+#pragma unroll
+  for (int d = 1; d < 8; ++d)
+    if (((best + 4) & 7) == d) orth = cost[d];
+  dir = best;
+  var = bc - orth;
+}
+
+// Eq. (13): the luma primary strength adjusted by the contrast v, for all
+// 16 signaled strengths, packed 4 bits each.
+__device__ __forceinline__ uint64_t adjusted_strengths(int var) {
+  if (var < 1024) return 0;
+  const int q = var >> 16;
+  const int i = q == 0 ? 0 : min(floor_log2(q), 12);
+  uint64_t t = 0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) t |= (uint64_t)((s * (4 + i) + 8) >> 4) << (4 * s);
+  return t;
+}
+
+// ---- Tile staging ---------------------------------------------------------
+// Copies rows y0-2 .. y0+TH+1 and columns x0-2 .. x0+TW+1 of a plane into an
+// LDS tile whose column COL0 holds frame column x0.  Positions outside the
+// plane get kOutside.  Threads walk consecutive columns, so global reads
+// coalesce.
+template <int TH, int TW, int STRIDE, int COL0, int NT>
+__device__ __forceinline__ void stage_recon(uint16_t *lds, const uint16_t *plane, int64_t stride,
+                                            int pw, int ph, int y0, int x0, int tid) {
+  constexpr int W = TW + 4, N = (TH + 4) * W;
+  for (int e = tid; e < N; e += NT) {
+    const int r = e / W, c = e - r * W;
+    const int y = y0 - 2 + r, x = x0 - 2 + c;
+    uint16_t v = kOutside;
+    if (y >= 0 && y < ph && x >= 0 && x < pw) v = plane[(int64_t)y * stride + x];
+    lds[r * STRIDE + COL0 - 2 + c] = v;
+  }
+}
+
+// Copies the TH x TW interior (no halo) of a plane; outside positions get 0.
+template <int TH, int TW, int NT>
+__device__ __forceinline__ void stage_interior(uint16_t *lds, const uint16_t *plane,
+                                               int64_t stride, int pw, int ph, int y0, int x0,
+                                               int tid) {
+  for (int e = tid; e < TH * TW; e += NT) {
+    const int r = e / TW, c = e - r * TW;
+    const int y = y0 + r, x = x0 + c;
+    lds[e] = (y < ph && x < pw) ? plane[(int64_t)y * stride + x] : (uint16_t)0;
+  }
+}
+
+// ---- One pixel of the filter, 32-bit lanes (plain path) -------------------
+// Eq. (7): f(diff, S, D) with k = D - floor(log2 S) given as `shift`; the
+// function is anti-symmetric, and S = 0 passes nothing.
+__device__ __forceinline__ int constrain(int diff, int s, int shift) {
+  const int a = abs(diff);
+  const int m = min(a, max(0, s - (a >> shift)));
+  return diff < 0 ? -m : m;
+}
+
+// Eq. (8)-(12) for the pixel at LDS index `base` of a tile with row stride
+// `ts`.  Strengths are scaled to the bit depth; shifts are D - floor(log2 S)
+// (ignored when the strength is 0).  Out-of-frame taps (kOutside) are
+// ignored and excluded from the clamp range.
+__device__ __forceinline__ int filter_pixel(const uint16_t *t, int base, int ts, int d, int ps,
+                                            int pshift, int w1, int w2, int ss, int sshift) {
+  const int x = t[base];
+  int sum = 0, lo = x, hi = x;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int w = k == 0 ? w1 : w2;
+    const int o = tap_dr(d, k) * ts + tap_dc(d, k);
+    const int v0 = t[base + o], v1 = t[base - o];
+    if (v0 != kOutside) {
+      sum += w * constrain(v0 - x, ps, pshift);
+      lo = min(lo, v0);
+      hi = max(hi, v0);
+    }
+    if (v1 != kOutside) {
+      sum += w * constrain(v1 - x, ps, pshift);
+      lo = min(lo, v1);
+      hi = max(hi, v1);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int d2 = h == 0 ? (d + 2) & 7 : (d + 6) & 7;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int w = k == 0 ? 2 : 1;
+      const int o = tap_dr(d2, k) * ts + tap_dc(d2, k);
+      const int v0 = t[base + o], v1 = t[base - o];
+      if (v0 != kOutside) {
+        sum += w * constrain(v0 - x, ss, sshift);
+        lo = min(lo, v0);
+        hi = max(hi, v0);
+      }
+      if (v1 != kOutside) {
+        sum += w * constrain(v1 - x, ss, sshift);
+        lo = min(lo, v1);
+        hi = max(hi, v1);
+      }
+    }
+  }
+  const int y = x + ((sum + 8 - (sum < 0 ? 1 : 0)) >> 4);
+  return min(hi, max(lo, y));
+}
+
+}  // namespace cdef

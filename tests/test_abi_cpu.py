@@ -1,0 +1,92 @@
+"""The C-ABI library loads without a GPU, exports every declared symbol, and
+rejects bad host-side arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "cdef.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cdef_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1602_05975_amd import cdef
+    return cdef.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1602_05975_amd import cdef
+    names = _declared_symbols()
+    assert "cdef_search_strengths" in names and "cdef_find_dir" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(cdef.EXPORTS)
+    assert lib.cdef_abi_version() == 1
+
+
+def test_status_strings(lib):
+    from paper_1602_05975_amd import cdef
+    for s in (0, -1, -2, -3, -4, 7):
+        assert isinstance(cdef.status_str(s), str) and cdef.status_str(s)
+
+
+def _frame(w=64, h=64, bd=10, layout=1, stride=None, ptr=0x10000):
+    from paper_1602_05975_amd import cdef
+    f = cdef.CdefFrame()
+    f.width, f.height, f.bitdepth, f.layout = w, h, bd, layout
+    np_ = 3 if layout == 1 else 1
+    for p in range(np_):
+        pw = w if p == 0 else (w + 1) // 2
+        f.plane[p] = ptr + p * 0x100000
+        f.stride[p] = pw if stride is None else stride
+    return f
+
+
+def test_find_dir_argument_checks(lib):
+    P = 0x20000
+    assert lib.cdef_find_dir(None, P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame()), None, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(stride=3)), P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(w=0)), P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(bd=12)), P, P, None) == -2
+    assert lib.cdef_find_dir(C.byref(_frame(bd=9)), P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(layout=2)), P, P, None) == -1
+    f = _frame()
+    f.plane[1] = None
+    assert lib.cdef_find_dir(C.byref(f), P, P, None) == -1
+
+
+def test_search_argument_checks(lib):
+    P = 0x20000
+    r, s = _frame(), _frame(ptr=0x900000)
+    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 2, P, None, None, None) == -1
+    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 7, P, None, None, None) == -1
+    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 3, None, None, None, None) == -1
+    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 3, P, P, None, None) == -1
+    s2 = _frame(w=66, ptr=0x900000)
+    assert lib.cdef_search_strengths(C.byref(r), C.byref(s2), None, 3, P, None, None, None) == -1
+
+
+def test_filter_argument_checks(lib):
+    from paper_1602_05975_amd import cdef
+    P = 0x20000
+    f = _frame()
+    o = cdef.CdefFrameOut()
+    for p in range(3):
+        o.plane[p] = 0x4000000 + p * 0x100000
+        o.stride[p] = 64
+    assert lib.cdef_filter_frame(C.byref(f), C.byref(o), P, P, None, 2, P, None) == -1
+    assert lib.cdef_filter_frame(C.byref(f), None, P, P, None, 3, P, None) == -1
+    assert lib.cdef_filter_frame(C.byref(f), C.byref(o), P, P, None, 3, None, None) == -1
+    alias = cdef.CdefFrameOut()
+    for p in range(3):
+        alias.plane[p] = f.plane[p]
+        alias.stride[p] = f.stride[p]
+    assert lib.cdef_filter_frame(C.byref(f), C.byref(alias), P, P, None, 3, P, None) == -1
