@@ -1,0 +1,235 @@
+"""Benchmark of the CDEF hot path on one MI355X.
+
+A step is one pass of the whole path -- tile staging, direction search,
+per-block filter parameters, the constrained filter under all 64 strength
+pairs and the fused SSE reduction -- over one batch of eight synthetic
+3840x2160 10-bit 4:2:0 frames with 30 % of 8x8 blocks skipped, one
+cdef_search_strengths launch per frame.  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of the fused search (frozen formula, independent of the
+# kernel's instruction count): element operations per plane sample that is
+# filtered (12 tap differences/magnitudes/clamp bounds 48, 15 primary
+# strengths x 4 taps x 6 = 360, 3 secondary strengths x 8 taps x 6 = 144,
+# 64 pairs x 8 = 512), per skipped sample (difference, square, accumulate),
+# and per luma pixel for the direction search.
+OPS_PER_FILTERED_SAMPLE = 1064
+OPS_PER_SKIPPED_SAMPLE = 3
+OPS_PER_LUMA_PX_DIRSEARCH = 10
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T int32 lane-ops/s;
+# packed 16-bit instructions do two element operations per lane.
+PEAK_PACKED_I16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["k_search.hip", "cdef_device.hpp"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1602_05975_amd", "csrc", s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def frame_work(fr):
+    """(algorithmic ops, algorithmic HBM bytes) of one fused search launch."""
+    filtered = skipped = 0
+    sk = fr.skip.astype(bool)
+    for p in range(fr.nplanes):
+        w, h = fr.plane_dims(p)
+        bs = 8 if p == 0 else 4
+        full = np.repeat(np.repeat(sk, bs, axis=0), bs, axis=1)[:h, :w]
+        n_sk = int(full.sum())
+        skipped += n_sk
+        filtered += w * h - n_sk
+    ops = (OPS_PER_FILTERED_SAMPLE * filtered + OPS_PER_SKIPPED_SAMPLE * skipped
+           + OPS_PER_LUMA_PX_DIRSEARCH * fr.width * fr.height)
+    samples = filtered + skipped
+    nfb = fr.fb_rows * fr.fb_cols
+    nblk = fr.blk_rows * fr.blk_cols
+    bytes_ = 2 * 2 * samples + nblk + nfb * 64 * 8 * fr.nplanes + 5 * nblk
+    return ops, bytes_
+
+
+def cpu_baseline(fr, fb_rows: int = 6):
+    """The oracle, as it stands, on the first `fb_rows` filter-block rows of
+    one frame (direction search of those rows + the search of their filter
+    blocks), on all host cores the box gives this process (max 16)."""
+    from oracle import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(16, cores))
+    rows = min(fr.height, 64 * fb_rows)
+    t0 = time.perf_counter()
+    d, v = oracle.find_dir(np.ascontiguousarray(fr.recon[0][:rows]), fr.bitdepth)
+    t_dir = time.perf_counter() - t0
+    dfull = np.zeros((fr.blk_rows, fr.blk_cols), np.uint8)
+    vfull = np.zeros((fr.blk_rows, fr.blk_cols), np.int32)
+    dfull[:d.shape[0]] = d
+    vfull[:v.shape[0]] = v
+    fbs = [(by, bx) for by in range(fb_rows) for bx in range(fr.fb_cols)]
+    t0 = time.perf_counter()
+    oracle.search_fbs(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, dfull, vfull,
+                      fr.skip, fr.damping, fbs, threads=cores)
+    t_search = time.perf_counter() - t0
+    px = rows * fr.width
+    return {
+        "value": px / (t_dir + t_search) / 1e6,
+        "unit": "Mpixel/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{len(fbs)} filter blocks ({fb_rows} rows of 64) of one 3840x2160 10-bit "
+                  f"4:2:0 frame, 30% skip: direction search + all-pair search, "
+                  f"{t_dir + t_search:.1f} s wall",
+    }
+
+
+def load_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, valid
+    only while the kernel sources are unchanged since they were taken."""
+    path = os.path.join(ROOT, "profiles", "k_search_4k_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(frames shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1602_05975_amd import cdef, synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cdef.load()
+
+    log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
+    frames = synth.config2(args.frames)
+    ops = sum(frame_work(f)[0] for f in frames)
+    algo_bytes = sum(frame_work(f)[1] for f in frames)
+
+    dev = torch.device("cuda:0")
+    jobs = []
+    for fr in frames:
+        rec = cdef.Frame.from_numpy(fr.recon, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
+        src = cdef.Frame.from_numpy(fr.src, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
+        skip = torch.from_numpy(fr.skip).to(dev)
+        sse = torch.empty((fr.nplanes, fr.fb_rows, fr.fb_cols, 16, 4), dtype=torch.int64,
+                          device=dev)
+        d = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.uint8, device=dev)
+        v = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.int32, device=dev)
+        jobs.append((rec, src, skip, fr.damping, sse, d, v))
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for k, (rec, src, skip, D, sse, d, v) in enumerate(jobs):
+            if events is not None:
+                events[k][0].record(stream)
+            cdef.cdef_search_strengths(rec, src, skip, D, sse, d, v, stream)
+            if events is not None:
+                events[k][1].record(stream)
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+           for _ in jobs] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in st] for st in ev])
+
+    px_per_step = sum(f.width * f.height for f in frames)
+    ms_per_step = wall * 1e3 / args.steps
+    value = px_per_step * args.steps / wall / 1e6
+    avg_launch_s = float(launch_ms.mean()) / 1e3
+    achieved = ops / len(frames) / avg_launch_s / 1e12
+    traffic = load_traffic()
+    result = {
+        "metric": "Mpixel/s for dir+filter+all-strength SSE search, 4K 10-bit; p99 frame latency",
+        "value": round(value, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{len(frames)}x3840x2160 10-bit 4:2:0 frames, 30% of 8x8 blocks "
+                        "skipped, damping 3: fused direction search + filter under all 64 "
+                        "(primary, secondary) strength pairs + per-64x64 SSE, one launch "
+                        "per frame",
+            "frames_per_step": len(frames),
+            "luma_px_per_step": px_per_step,
+        },
+        "frame_latency_ms": {
+            "p50": round(float(np.percentile(launch_ms, 50)), 4),
+            "p99": round(float(np.percentile(launch_ms, 99)), 4),
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(PEAK_PACKED_I16_TOPS, 1),
+            "unit": "TOP/s",
+            "frac": round(achieved / PEAK_PACKED_I16_TOPS, 4),
+            "traffic": traffic,
+            "kernel": "k_search",
+            "algorithmic_ops_per_launch": int(ops / len(frames)),
+            "hbm_gbs_algorithmic": round(algo_bytes / len(frames) / avg_launch_s / 1e9, 1),
+            "hbm_peak_gbs": PEAK_HBM_GBS,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(frames[0])
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -26,7 +26,7 @@ constexpr uint16_t kOutside = 0x8000;
 // line 22.5 degrees clockwise on screen (row index grows downward).
 
 // Line number of pixel (i, j) of an 8x8 block for direction d.
-__host__ __device__ constexpr int line_key(int d, int i, int j) {
+__host__ __device__ __forceinline__ constexpr int line_key(int d, int i, int j) {
   return d == 0 ? i + j
        : d == 1 ? i + (j >> 1)
        : d == 2 ? i
@@ -37,77 +37,106 @@ __host__ __device__ constexpr int line_key(int d, int i, int j) {
                 : j + (i >> 1);
 }
 
-// Number of pixels on line k of direction d in a full 8x8 block.
-__host__ __device__ constexpr int line_count(int d, int k) {
-  int n = 0;
-  for (int i = 0; i < 8; ++i)
-    for (int j = 0; j < 8; ++j) n += line_key(d, i, j) == k ? 1 : 0;
-  return n;
-}
-
 // Row/column offset of the inner (t = 0) and outer (t = 1) tap along d.
-__host__ __device__ constexpr int tap_dr(int d, int t) {
+__host__ __device__ __forceinline__ constexpr int tap_dr(int d, int t) {
   return t == 0 ? (d == 0 ? -1 : d <= 3 ? 0 : 1)
                 : (d == 0 ? -2 : d == 1 ? -1 : d == 2 ? 0 : d == 3 ? 1 : 2);
 }
-__host__ __device__ constexpr int tap_dc(int d, int t) {
+__host__ __device__ __forceinline__ constexpr int tap_dc(int d, int t) {
   return t == 0 ? (d <= 4 ? 1 : 0)
                 : (d <= 4 ? 2 : d == 5 ? 1 : d == 6 ? 0 : -1);
 }
 
 __device__ __forceinline__ int floor_log2(int v) { return 31 - __clz(v); }  // v >= 1
 
-// 840 / n for n = 1..8 (840 is the least common multiple of 1..8).
+// 840 / n for n = 1..8 (840 is the least common multiple of 1..8), looked
+// up branch-free from 10-bit fields of two constants; n = 0 gives 0.
 __device__ __forceinline__ int inv840(int n) {
-  return n == 1 ? 840 : n == 2 ? 420 : n == 3 ? 280 : n == 4 ? 210
-       : n == 5 ? 168 : n == 6 ? 140 : n == 7 ? 120 : 105;
+  constexpr uint64_t lo = 840ull << 10 | 420ull << 20 | 280ull << 30 | 210ull << 40 |
+                          168ull << 50;
+  constexpr uint64_t hi = 140ull | 120ull << 10 | 105ull << 20;
+  return n <= 5 ? (int)((lo >> (10 * n)) & 1023) : (int)((hi >> (10 * (n - 6))) & 1023);
 }
 
-// Algorithm 1 on a full 8x8 block of centred 8-bit values: the 840-scaled
-// s_d of Eq. (5) for all eight directions.  All loops unroll; line sums and
-// counts are compile-time positions.
-__device__ __forceinline__ void dir_costs_full(const int (&x)[64], int (&cost)[8]) {
-#pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    int part[15];
-#pragma unroll
-    for (int k = 0; k < 15; ++k) part[k] = 0;
-#pragma unroll
+// Number of pixels on every line of every direction of a full 8x8 block,
+// evaluated by the compiler.
+struct LineCounts {
+  int n[8][15];
+};
+__host__ __device__ constexpr LineCounts make_line_counts() {
+  LineCounts t{};
+  for (int d = 0; d < 8; ++d)
     for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) t.n[d][line_key(d, i, j)] += 1;
+  return t;
+}
+
+// Algorithm 1 for one direction D of a full 8x8 block of centred 8-bit
+// values: the 840-scaled s_D of Eq. (5).  D is a template parameter so that
+// every line index and every 840 / N is a compile-time constant.
+template <int D>
+__device__ __forceinline__ int dir_cost_full(const int (&x)[64]) {
+  constexpr LineCounts kN = make_line_counts();
+  int part[15];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) part[line_key(d, i, j)] += x[i * 8 + j];
-    int c = 0;
+  for (int k = 0; k < 15; ++k) part[k] = 0;
 #pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      const int n = line_count(d, k);
-      if (n > 0) c += __mul24(__mul24(part[k], part[k]), 840 / (n > 0 ? n : 1));
-    }
-    cost[d] = c;
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) part[line_key(D, i, j)] += x[i * 8 + j];
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    const int n = kN.n[D][k];
+    if (n > 0) c += __mul24(__mul24(part[k], part[k]), 840 / (n > 0 ? n : 1));
   }
+  return c;
+}
+
+__device__ __forceinline__ void dir_costs_full(const int (&x)[64], int (&cost)[8]) {
+  cost[0] = dir_cost_full<0>(x);
+  cost[1] = dir_cost_full<1>(x);
+  cost[2] = dir_cost_full<2>(x);
+  cost[3] = dir_cost_full<3>(x);
+  cost[4] = dir_cost_full<4>(x);
+  cost[5] = dir_cost_full<5>(x);
+  cost[6] = dir_cost_full<6>(x);
+  cost[7] = dir_cost_full<7>(x);
 }
 
 // The same for a block cut by the frame edge: only the top-left bw x bh
-// pixels exist, and line lengths are counted.
-__device__ __forceinline__ void dir_costs_partial(const int (&x)[64], int bw, int bh, int (&cost)[8]) {
+// pixels exist, and line lengths are counted (840 / N stays exact).
+template <int D>
+__device__ __forceinline__ int dir_cost_partial(const int (&x)[64], int bw, int bh) {
+  int part[15], cnt[15];
 #pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    int part[15], cnt[15];
+  for (int k = 0; k < 15; ++k) part[k] = cnt[k] = 0;
 #pragma unroll
-    for (int k = 0; k < 15; ++k) part[k] = cnt[k] = 0;
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) {
+      const bool in = i < bh && j < bw;
+      part[line_key(D, i, j)] += in ? x[i * 8 + j] : 0;
+      cnt[line_key(D, i, j)] += in ? 1 : 0;
+    }
+  int c = 0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const bool in = i < bh && j < bw;
-        part[line_key(d, i, j)] += in ? x[i * 8 + j] : 0;
-        cnt[line_key(d, i, j)] += in ? 1 : 0;
-      }
-    int c = 0;
-#pragma unroll
-    for (int k = 0; k < 15; ++k)
-      if (cnt[k] > 0) c += __mul24(__mul24(part[k], part[k]), inv840(cnt[k]));
-    cost[d] = c;
+  for (int k = 0; k < 15; ++k) {
+    c += __mul24(__mul24(part[k], part[k]), inv840(cnt[k]));
   }
+  return c;
+}
+
+__device__ __forceinline__ void dir_costs_partial(const int (&x)[64], int bw, int bh,
+                                                  int (&cost)[8]) {
+  cost[0] = dir_cost_partial<0>(x, bw, bh);
+  cost[1] = dir_cost_partial<1>(x, bw, bh);
+  cost[2] = dir_cost_partial<2>(x, bw, bh);
+  cost[3] = dir_cost_partial<3>(x, bw, bh);
+  cost[4] = dir_cost_partial<4>(x, bw, bh);
+  cost[5] = dir_cost_partial<5>(x, bw, bh);
+  cost[6] = dir_cost_partial<6>(x, bw, bh);
+  cost[7] = dir_cost_partial<7>(x, bw, bh);
 }
 
 // Argmax with a strict '>' from d = 0, and the directional contrast
