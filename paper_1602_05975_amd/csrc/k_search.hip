@@ -42,6 +42,23 @@ constexpr int kLC0 = 8;  // tile column that holds frame column x0 (16-byte alig
 constexpr int kCS = 48;  // chroma recon tile row stride (36 used)
 constexpr int kCC0 = 8;
 
+// LDS offsets of the six tap positions (inner, outer along d; along d+2;
+// along d-2) in the luma tile, per direction.  Indexed with wave-uniform
+// directions, so the reads are scalar loads.
+struct TapTable {
+  int off[8][6];
+};
+__host__ __device__ constexpr TapTable make_tap_table(int stride) {
+  TapTable t{};
+  for (int d = 0; d < 8; ++d)
+    for (int k = 0; k < 6; ++k) {
+      const int dd = k < 2 ? d : k < 4 ? (d + 2) & 7 : (d + 6) & 7;
+      t.off[d][k] = tap_dr(dd, k & 1) * stride + tap_dc(dd, k & 1);
+    }
+  return t;
+}
+__constant__ TapTable kLumaTaps = make_tap_table(kLS);
+
 __device__ __forceinline__ s16x2 as_s(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
 __device__ __forceinline__ s16x2 as_s(u16x2 v) { return __builtin_bit_cast(s16x2, v); }
 __device__ __forceinline__ u16x2 as_u(s16x2 v) { return __builtin_bit_cast(u16x2, v); }
@@ -134,6 +151,8 @@ __device__ __forceinline__ int pair_one(const Taps &t, s16x2 P, int acc) {
 }
 
 // Luma task: 2 blocks (lo/hi half), per-block adjusted primary strengths.
+// The per-strength parameters are wave-uniform; they are built as 32-bit
+// scalars (low half: block A, high half: block B) so that they stay in SGPRs.
 template <int BD, int D>
 __device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t adjB,
                                           int (&acc)[64]) {
@@ -145,14 +164,29 @@ __device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t
   acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
 #pragma unroll
   for (int si = 1; si < 4; ++si) acc[si] = pair_one(t, Q[si], acc[si]);
+  uint32_t prev_sh = 0xFFFFFFFFu;
+  u16x2 a[4];
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
-    const int sa = (int)((adjA >> (4 * S)) & 15), sb = (int)((adjB >> (4 * S)) & 15);
-    const u16x2 s = pair_u(sa << c, sb << c);
-    const u16x2 sh = pair_u(sa ? D - floor_log2(sa) : 0, sb ? D - floor_log2(sb) : 0);
-    const s16x2 w1 = pair_s((sa & 1) ? 3 : 4, (sb & 1) ? 3 : 4);
-    const s16x2 w2 = pair_s((sa & 1) ? 3 : 2, (sb & 1) ? 3 : 2);
-    const s16x2 P = group_sum(t, 0, s, sh, w1, w2);
+    const uint32_t sa = (uint32_t)(adjA >> (4 * S)) & 15u, sb = (uint32_t)(adjB >> (4 * S)) & 15u;
+    const uint32_t sp = (sa << c) | (sb << (16 + c));
+    const uint32_t sha = sa ? (uint32_t)(D - floor_log2((int)sa)) : 0u;
+    const uint32_t shb = sb ? (uint32_t)(D - floor_log2((int)sb)) : 0u;
+    const uint32_t sh = sha | (shb << 16);
+    const uint32_t w1 = ((sa & 1) ? 3u : 4u) | (((sb & 1) ? 3u : 4u) << 16);
+    const uint32_t w2 = ((sa & 1) ? 3u : 2u) | (((sb & 1) ? 3u : 2u) << 16);
+    if (sh != prev_sh) {  // the shift changes at most a few times over S = 1..15
+      prev_sh = sh;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
+    }
+    s16x2 m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      m[k] = as_s(__builtin_elementwise_min(__builtin_elementwise_sub_sat(as_u(sp), a[k]), t.ad[k]));
+    const s16x2 inner = m[0] * t.sg[0] + m[1] * t.sg[1];
+    const s16x2 outer = m[2] * t.sg[2] + m[3] * t.sg[3];
+    const s16x2 P = inner * as_s(w1) + outer * as_s(w2);
     acc[4 * S] = pair_one(t, P, acc[4 * S]);
 #pragma unroll
     for (int si = 1; si < 4; ++si) acc[4 * S + si] = pair_both(t, P, Q[si], acc[4 * S + si]);
@@ -227,7 +261,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }  // namespace
 
 template <int BD, int D>
-__global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
+__global__ __launch_bounds__(256, 3) void k_search(const SearchArgs a) {
   __shared__ __align__(16) uint16_t ry[68 * kLS];
   __shared__ __align__(16) uint16_t sy[64 * 64];
   __shared__ __align__(16) uint16_t rc[2][36 * kCS];
@@ -377,10 +411,8 @@ __global__ __launch_bounds__(256) void k_search(const SearchArgs a) {
       int oA[6], oB[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const int ddA = k < 2 ? dA : k < 4 ? (dA + 2) & 7 : (dA + 6) & 7;
-        const int ddB = k < 2 ? dB : k < 4 ? (dB + 2) & 7 : (dB + 6) & 7;
-        oA[k] = tap_dr(ddA, k & 1) * kLS + tap_dc(ddA, k & 1);
-        oB[k] = tap_dr(ddB, k & 1) * kLS + tap_dc(ddB, k & 1);
+        oA[k] = kLumaTaps.off[dA][k];
+        oB[k] = kLumaTaps.off[dB][k];
       }
       const uint32_t xv = ((uint32_t)ry[bA] | ((uint32_t)ry[bB] << 16)) & vm;
       const uint32_t sv = ((uint32_t)sy[rA * 64 + cA] | ((uint32_t)sy[rB * 64 + cB] << 16)) & vm;
