@@ -3,11 +3,12 @@
 A step is one pass of the whole path -- tile staging, direction search,
 per-block filter parameters, the constrained filter under all 64 strength
 pairs and the fused SSE reduction -- over one batch of eight synthetic
-3840x2160 10-bit 4:2:0 frames with 30 % of 8x8 blocks skipped, one
-cdef_search_strengths launch per frame.  Inputs are resident in HBM before
+3840x2160 10-bit 4:2:0 frames with 30 % of 8x8 blocks skipped: one
+cdef_batch_launch over all their filter blocks (--per-frame: one
+cdef_search_strengths launch per frame).  Inputs are resident in HBM before
 the timed region.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--per-frame] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -36,7 +37,7 @@ OPS_PER_LUMA_PX_DIRSEARCH = 10
 # packed 16-bit instructions do two element operations per lane.
 PEAK_PACKED_I16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["k_search.hip", "cdef_device.hpp"]
+KERNEL_SOURCES = ["k_fused.hip", "cdef_device.hpp"]
 
 
 def log(msg):
@@ -106,10 +107,10 @@ def cpu_baseline(fr, fb_rows: int = 6):
     }
 
 
-def load_traffic():
+def load_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter runs, valid
     only while the kernel sources are unchanged since they were taken."""
-    path = os.path.join(ROOT, "profiles", "k_search_4k_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_4k_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -126,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-frame", action="store_true",
+                    help="one cdef_search_strengths launch per frame instead of one batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling HBM counters)")
@@ -169,8 +172,23 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
+    batch = None
+    if not args.per_frame:
+        batch = cdef.Batch()
+        for (rec, src, skip, D, sse, d, v) in jobs:
+            batch.add_search(rec, src, skip, D, sse, d, v)
+        batch.prepare(stream)
+        torch.cuda.synchronize()
 
+    # launches of one step, each bracketed by HIP events on the launch stream
     def step(events=None):
+        if batch is not None:
+            if events is not None:
+                events[0][0].record(stream)
+            batch.launch(stream)
+            if events is not None:
+                events[0][1].record(stream)
+            return
         for k, (rec, src, skip, D, sse, d, v) in enumerate(jobs):
             if events is not None:
                 events[k][0].record(stream)
@@ -178,18 +196,19 @@ def main():
             if events is not None:
                 events[k][1].record(stream)
 
+    launches_per_step = 1 if batch is not None else len(jobs)
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    log(f"timing {args.steps} steps")
+    log(f"timing {args.steps} steps ({launches_per_step} launch(es) per step)")
     ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-           for _ in jobs] for _ in range(args.steps)]
+           for _ in range(launches_per_step)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(ev[s])
+    for s_ in range(args.steps):
+        step(ev[s_])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = np.array([[e[0].elapsed_time(e[1]) for e in st] for st in ev])
@@ -198,8 +217,11 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = px_per_step * args.steps / wall / 1e6
     avg_launch_s = float(launch_ms.mean()) / 1e3
-    achieved = ops / len(frames) / avg_launch_s / 1e12
-    traffic = load_traffic()
+    ops_per_launch = ops / launches_per_step
+    bytes_per_launch = algo_bytes / launches_per_step
+    achieved = ops_per_launch / avg_launch_s / 1e12
+    frame_ms = launch_ms if batch is None else launch_ms  # a batch's frames finish together
+    traffic = load_traffic("k_fused_batch" if batch is not None else "k_fused_one")
     result = {
         "metric": "Mpixel/s for dir+filter+all-strength SSE search, 4K 10-bit; p99 frame latency",
         "value": round(value, 1),
@@ -216,14 +238,17 @@ def main():
         "config": {
             "workload": f"{len(frames)}x3840x2160 10-bit 4:2:0 frames, 30% of 8x8 blocks "
                         "skipped, damping 3: fused direction search + filter under all 64 "
-                        "(primary, secondary) strength pairs + per-64x64 SSE, one launch "
-                        "per frame",
+                        "(primary, secondary) strength pairs + per-64x64 SSE, "
+                        + ("one launch per frame" if batch is None else
+                           "one batched launch per step"),
             "frames_per_step": len(frames),
             "luma_px_per_step": px_per_step,
         },
         "frame_latency_ms": {
-            "p50": round(float(np.percentile(launch_ms, 50)), 4),
-            "p99": round(float(np.percentile(launch_ms, 99)), 4),
+            "p50": round(float(np.percentile(frame_ms, 50)), 4),
+            "p99": round(float(np.percentile(frame_ms, 99)), 4),
+            "note": "per-frame launch time" if batch is None else
+                    "batch launch time (all frames of a step complete together)",
         },
         "roofline": {
             "bound": "alu",
@@ -232,9 +257,9 @@ def main():
             "unit": "TOP/s",
             "frac": round(achieved / PEAK_PACKED_I16_TOPS, 4),
             "traffic": traffic,
-            "kernel": "k_search",
-            "algorithmic_ops_per_launch": int(ops / len(frames)),
-            "hbm_gbs_algorithmic": round(algo_bytes / len(frames) / avg_launch_s / 1e9, 1),
+            "kernel": "k_fused_batch" if batch is not None else "k_fused_one",
+            "algorithmic_ops_per_launch": int(ops_per_launch),
+            "hbm_gbs_algorithmic": round(bytes_per_launch / avg_launch_s / 1e9, 1),
             "hbm_peak_gbs": PEAK_HBM_GBS,
         },
     }

@@ -125,6 +125,59 @@ cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src
                                   const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
                                   uint8_t *dir, int32_t *var, void *stream);
 
+/* ---- Batches ----------------------------------------------------------------
+ * Many frames -- of any size, bit depth 8 or 10 and damping -- in one launch
+ * over all their 64x64 filter blocks.  Each job is either the strength
+ * search of cdef_search_strengths or the direction search + filter of one
+ * frame at its own per-filter-block strengths (cdef_find_dir followed by
+ * cdef_filter_frame, fused).  Results are bit-identical to the per-frame
+ * entry points. */
+enum { CDEF_MODE_SEARCH = 0, CDEF_MODE_FILTER = 1 };
+
+typedef struct {
+  cdef_frame recon;          /* input frame */
+  cdef_frame src;            /* search: the source frame; filter: ignored */
+  cdef_frame_out out;        /* filter: output planes (must not overlap recon); search: ignored */
+  const uint8_t *skip8x8;    /* NULL = no skipped block */
+  const cdef_strength *fb;   /* filter: per-filter-block strengths; search: ignored */
+  uint64_t *sse;             /* search: table as cdef_search_strengths; filter: ignored */
+  uint8_t *dir;              /* optional direction-search outputs (both or neither) */
+  int32_t *var;
+  int32_t damping;           /* luma D, 3..6 */
+  int32_t mode;              /* CDEF_MODE_SEARCH or CDEF_MODE_FILTER */
+} cdef_job;
+
+/* What cdef_batch_prepare leaves for cdef_batch_launch (host memory, owned by
+ * the caller; valid while the workspace is). */
+typedef struct {
+  const void *table;  /* device job table inside the workspace */
+  int32_t njobs;
+  int32_t nitems;     /* filter blocks over all jobs */
+  int32_t variant;    /* launch variant, 0 = default */
+  int32_t reserved;
+} cdef_batch_plan;
+
+/* Bytes of device workspace (and of pinned host staging, if used) for a
+ * batch of njobs; 0 for njobs < 1. */
+size_t cdef_batch_workspace_bytes(int32_t njobs);
+
+/* Validate every job on the host and upload the job table to `workspace`
+ * (device memory of at least cdef_batch_workspace_bytes(njobs) bytes).
+ * host_staging: pinned host memory of the same size, owned by the caller;
+ * the upload is then an asynchronous copy on `stream` and the caller must
+ * leave the staging untouched until the stream has passed it.  With
+ * host_staging NULL the upload is synchronous.  Errors: CDEF_E_INVAL for a
+ * bad job (its index is not reported), CDEF_E_NOMEM if the workspace is too
+ * small; nothing is enqueued on error. */
+cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_staging,
+                               void *workspace, size_t workspace_bytes, cdef_batch_plan *plan,
+                               void *stream);
+
+/* One launch over every filter block of a prepared batch.  Enqueues kernels
+ * only (no copies, no allocation), so it can be captured in a HIP graph and
+ * replayed while the workspace and all job buffers stay valid. */
+cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream);
+
 /* Human-readable name of a status code (static storage, never NULL). */
 const char *cdef_status_str(cdef_status s);
 

@@ -28,9 +28,14 @@ EXPORTS = (
     "cdef_find_dir",
     "cdef_filter_frame",
     "cdef_search_strengths",
+    "cdef_batch_workspace_bytes",
+    "cdef_batch_prepare",
+    "cdef_batch_launch",
     "cdef_status_str",
     "cdef_abi_version",
 )
+MODE_SEARCH = 0
+MODE_FILTER = 1
 
 
 class CdefFrame(C.Structure):
@@ -46,6 +51,31 @@ class CdefFrame(C.Structure):
 
 class CdefFrameOut(C.Structure):
     _fields_ = [("plane", C.c_void_p * 3), ("stride", C.c_int64 * 3)]
+
+
+class CdefJob(C.Structure):
+    _fields_ = [
+        ("recon", CdefFrame),
+        ("src", CdefFrame),
+        ("out", CdefFrameOut),
+        ("skip8x8", C.c_void_p),
+        ("fb", C.c_void_p),
+        ("sse", C.c_void_p),
+        ("dir", C.c_void_p),
+        ("var", C.c_void_p),
+        ("damping", C.c_int32),
+        ("mode", C.c_int32),
+    ]
+
+
+class CdefBatchPlan(C.Structure):
+    _fields_ = [
+        ("table", C.c_void_p),
+        ("njobs", C.c_int32),
+        ("nitems", C.c_int32),
+        ("variant", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
 
 
 class CdefError(RuntimeError):
@@ -75,6 +105,13 @@ def load(path: str = LIB_PATH):
     L.cdef_search_strengths.argtypes = [C.POINTER(CdefFrame), C.POINTER(CdefFrame), P,
                                         C.c_int32, P, P, P, P]
     L.cdef_search_strengths.restype = C.c_int
+    L.cdef_batch_workspace_bytes.argtypes = [C.c_int32]
+    L.cdef_batch_workspace_bytes.restype = C.c_size_t
+    L.cdef_batch_prepare.argtypes = [C.POINTER(CdefJob), C.c_int32, P, P, C.c_size_t,
+                                     C.POINTER(CdefBatchPlan), P]
+    L.cdef_batch_prepare.restype = C.c_int
+    L.cdef_batch_launch.argtypes = [C.POINTER(CdefBatchPlan), P]
+    L.cdef_batch_launch.restype = C.c_int
     L.cdef_status_str.argtypes = [C.c_int]
     L.cdef_status_str.restype = C.c_char_p
     L.cdef_abi_version.argtypes = []
@@ -201,3 +238,71 @@ def search_strengths(recon: Frame, src: Frame, skip, damping: int, want_dir=Fals
         v = torch.empty(recon.block_shape, dtype=torch.int32, device=dev)
     cdef_search_strengths(recon, src, skip, damping, sse, d, v, stream)
     return (sse, d, v) if want_dir else sse
+
+
+# ---- batches ------------------------------------------------------------------
+
+def _out_struct(out_planes) -> CdefFrameOut:
+    o = CdefFrameOut()
+    for p, t in enumerate(out_planes[:3]):
+        if t is not None:
+            o.plane[p] = t.data_ptr()
+            o.stride[p] = t.stride(0)
+    return o
+
+
+class Batch:
+    """A prepared set of jobs launched together (cdef_batch_prepare /
+    cdef_batch_launch).  Jobs keep references to their tensors; the device
+    workspace and pinned staging buffer live as long as the batch."""
+
+    def __init__(self):
+        self.jobs: list = []
+        self._keep: list = []
+        self.plan = CdefBatchPlan()
+        self.workspace = None
+        self.staging = None
+
+    def add_search(self, recon: Frame, src: Frame, skip, damping: int, sse, dir=None, var=None):
+        j = CdefJob()
+        j.recon, j.src = recon.c_struct(), src.c_struct()
+        j.skip8x8, j.sse = _ptr(skip), _ptr(sse)
+        j.dir, j.var = _ptr(dir), _ptr(var)
+        j.damping, j.mode = damping, MODE_SEARCH
+        self.jobs.append(j)
+        self._keep.append((recon, src, skip, sse, dir, var))
+        return len(self.jobs) - 1
+
+    def add_filter(self, recon: Frame, out_planes, skip, damping: int, fb, dir=None, var=None):
+        j = CdefJob()
+        j.recon = recon.c_struct()
+        j.out = _out_struct(out_planes)
+        j.skip8x8, j.fb = _ptr(skip), _ptr(fb)
+        j.dir, j.var = _ptr(dir), _ptr(var)
+        j.damping, j.mode = damping, MODE_FILTER
+        self.jobs.append(j)
+        self._keep.append((recon, out_planes, skip, fb, dir, var))
+        return len(self.jobs) - 1
+
+    def prepare(self, stream=None) -> None:
+        import torch
+        L = load()
+        n = len(self.jobs)
+        nbytes = L.cdef_batch_workspace_bytes(n)
+        dev = self._keep[0][0].planes[0].device
+        if self.workspace is None or self.workspace.numel() < nbytes:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            self.staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        arr = (CdefJob * n)(*self.jobs)
+        st = L.cdef_batch_prepare(arr, n, self.staging.data_ptr(), self.workspace.data_ptr(),
+                                  self.workspace.numel(), C.byref(self.plan),
+                                  _stream_handle(stream))
+        _check(st, "cdef_batch_prepare")
+
+    def launch(self, stream=None) -> None:
+        _check(load().cdef_batch_launch(C.byref(self.plan), _stream_handle(stream)),
+               "cdef_batch_launch")
+
+    @property
+    def nitems(self) -> int:
+        return self.plan.nitems

@@ -5,6 +5,8 @@
 #include "cdef_launch.hpp"
 
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
 
 namespace {
 
@@ -61,6 +63,65 @@ bool same_geometry(const cdef_frame *a, const cdef_frame *b) {
          a->layout == b->layout;
 }
 
+bool stride32(int64_t s) { return s >= 0 && s <= INT32_MAX; }
+
+// Host-side checks of one job plus its descriptor for the fused kernel.
+cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
+  FrameDesc r;
+  cdef_status st = check_frame(&j->recon, &r);
+  if (st != CDEF_OK) return st;
+  if (j->damping < 3 || j->damping > 6) return CDEF_E_INVAL;
+  if ((j->dir == nullptr) != (j->var == nullptr)) return CDEF_E_INVAL;
+  memset(o, 0, sizeof(*o));
+  for (int p = 0; p < r.nplanes; ++p) {
+    if (!stride32(r.stride[p])) return CDEF_E_UNSUPPORTED;
+    o->rec[p] = r.plane[p];
+    o->rstride[p] = (int32_t)r.stride[p];
+  }
+  if (j->mode == CDEF_MODE_SEARCH) {
+    FrameDesc s;
+    st = check_frame(&j->src, &s);
+    if (st != CDEF_OK) return st;
+    if (!same_geometry(&j->recon, &j->src) || !j->sse) return CDEF_E_INVAL;
+    for (int p = 0; p < s.nplanes; ++p) {
+      if (!stride32(s.stride[p])) return CDEF_E_UNSUPPORTED;
+      o->src[p] = s.plane[p];
+      o->sstride[p] = (int32_t)s.stride[p];
+    }
+  } else if (j->mode == CDEF_MODE_FILTER) {
+    if (!j->fb) return CDEF_E_INVAL;
+    for (int p = 0; p < r.nplanes; ++p) {
+      int w, h;
+      plane_dims(&j->recon, p, &w, &h);
+      if (!j->out.plane[p] || j->out.stride[p] < w) return CDEF_E_INVAL;
+      if (!stride32(j->out.stride[p])) return CDEF_E_UNSUPPORTED;
+      cdef_frame o2 = j->recon;
+      o2.stride[p] = j->out.stride[p];
+      for (int q = 0; q < r.nplanes; ++q)
+        if (ranges_overlap(j->out.plane[p], plane_bytes(&o2, p), j->recon.plane[q],
+                           plane_bytes(&j->recon, q)))
+          return CDEF_E_INVAL;
+      o->out[p] = j->out.plane[p];
+      o->ostride[p] = (int32_t)j->out.stride[p];
+    }
+  } else {
+    return CDEF_E_INVAL;
+  }
+  o->skip = j->skip8x8;
+  o->strengths = reinterpret_cast<const uint8_t *>(j->fb);
+  o->sse = j->sse;
+  o->dir = j->dir;
+  o->var = j->var;
+  o->width = r.width;
+  o->height = r.height;
+  o->bitdepth = r.bitdepth;
+  o->damping = j->damping;
+  o->nplanes = r.nplanes;
+  o->mode = j->mode;
+  cdef::fill_job_geometry(*o);
+  return CDEF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -103,16 +164,67 @@ cdef_status cdef_filter_frame(const cdef_frame *in, const cdef_frame_out *out, c
 cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src,
                                   const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
                                   uint8_t *dir, int32_t *var, void *stream) {
-  FrameDesc r, s;
-  cdef_status st = check_frame(recon, &r);
+  if (!recon || !src) return CDEF_E_INVAL;
+  cdef_job j;
+  memset(&j, 0, sizeof(j));
+  j.recon = *recon;
+  j.src = *src;
+  j.skip8x8 = skip8x8;
+  j.sse = sse;
+  j.dir = dir;
+  j.var = var;
+  j.damping = damping;
+  j.mode = CDEF_MODE_SEARCH;
+  cdef::JobDesc d;
+  const cdef_status st = make_job(&j, &d);
   if (st != CDEF_OK) return st;
-  st = check_frame(src, &s);
+  return from_hip(cdef::launch_fused_one(d, (hipStream_t)stream));
+}
+
+size_t cdef_batch_workspace_bytes(int32_t njobs) {
+  return njobs < 1 ? 0 : (size_t)njobs * sizeof(cdef::JobDesc);
+}
+
+cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_staging,
+                               void *workspace, size_t workspace_bytes, cdef_batch_plan *plan,
+                               void *stream) {
+  if (!jobs || njobs < 1 || !workspace || !plan) return CDEF_E_INVAL;
+  const size_t need = cdef_batch_workspace_bytes(njobs);
+  if (workspace_bytes < need) return CDEF_E_NOMEM;
+  cdef::JobDesc *table = host_staging ? (cdef::JobDesc *)host_staging
+                                      : (cdef::JobDesc *)malloc(need);
+  if (!table) return CDEF_E_NOMEM;
+  int64_t items = 0;
+  cdef_status st = CDEF_OK;
+  for (int32_t i = 0; i < njobs && st == CDEF_OK; ++i) {
+    st = make_job(&jobs[i], &table[i]);
+    if (st == CDEF_OK) {
+      table[i].item0 = (int32_t)items;
+      items += (int64_t)table[i].fbc * table[i].fbr;
+      if (items > INT32_MAX / 2) st = CDEF_E_UNSUPPORTED;
+    }
+  }
+  if (st == CDEF_OK) {
+    hipError_t e = host_staging
+                       ? hipMemcpyAsync(workspace, table, need, hipMemcpyHostToDevice,
+                                        (hipStream_t)stream)
+                       : hipMemcpy(workspace, table, need, hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = CDEF_E_HIP;
+  }
+  if (!host_staging) free(table);
   if (st != CDEF_OK) return st;
-  if (!same_geometry(recon, src)) return CDEF_E_INVAL;
-  if (!sse) return CDEF_E_INVAL;
-  if ((dir == nullptr) != (var == nullptr)) return CDEF_E_INVAL;
-  if (damping < 3 || damping > 6) return CDEF_E_INVAL;
-  return from_hip(cdef::launch_search(r, s, skip8x8, damping, sse, dir, var, (hipStream_t)stream));
+  plan->table = workspace;
+  plan->njobs = njobs;
+  plan->nitems = (int32_t)items;
+  plan->variant = 0;
+  plan->reserved = 0;
+  return CDEF_OK;
+}
+
+cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
+  if (!plan || !plan->table || plan->njobs < 1 || plan->nitems < 1) return CDEF_E_INVAL;
+  return from_hip(cdef::launch_fused_batch((const cdef::JobDesc *)plan->table, plan->njobs,
+                                           plan->nitems, plan->variant, (hipStream_t)stream));
 }
 
 const char *cdef_status_str(cdef_status s) {

@@ -15,13 +15,41 @@ struct FrameDesc {
   int nplanes;        // 1 (4:0:0) or 3 (4:2:0)
 };
 
+enum JobMode : int32_t { kModeSearch = 0, kModeFilter = 1 };
+
+// One frame of work as the fused kernel reads it (kernel argument for a
+// single frame, or an element of a device-resident table for a batch).
+// Strides are in samples and fit 32 bits (frames are at most 65536 wide).
+struct JobDesc {
+  const uint16_t *rec[3];
+  const uint16_t *src[3];  // search mode
+  uint16_t *out[3];        // filter mode
+  const uint8_t *skip;     // may be null
+  const uint8_t *strengths;  // filter mode: [fbr][fbc][4]
+  uint64_t *sse;           // search mode
+  uint8_t *dir;            // optional
+  int32_t *var;            // optional
+  int32_t rstride[3], sstride[3], ostride[3];
+  int32_t width, height, bitdepth, damping, nplanes, mode;
+  int32_t fbc, fbr, bcols, brows;
+  int32_t item0;  // first work item (filter block) of this job in the batch
+  int32_t pad;
+};
+
 hipError_t launch_find_dir(const FrameDesc &f, uint8_t *dir, int32_t *var, hipStream_t s);
 
 hipError_t launch_filter(const FrameDesc &in, uint16_t *const out[3], const int64_t out_stride[3],
                          const uint8_t *dir, const int32_t *var, const uint8_t *skip, int damping,
                          const uint8_t *strengths, hipStream_t s);
 
-hipError_t launch_search(const FrameDesc &rec, const FrameDesc &src, const uint8_t *skip,
-                         int damping, uint64_t *sse, uint8_t *dir, int32_t *var, hipStream_t s);
+// One frame, job descriptor passed by value.
+hipError_t launch_fused_one(const JobDesc &job, hipStream_t s);
+
+// Many frames: `jobs` is a device array of njobs descriptors (item0 set),
+// nitems the total number of filter blocks.
+hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
+                              hipStream_t s);
+
+void fill_job_geometry(JobDesc &j);
 
 }  // namespace cdef

@@ -1,0 +1,611 @@
+// Fused CDEF kernel over 64x64 filter blocks (Section 4), one workgroup of
+// four waves per filter block, in one of two modes:
+//
+//  * search (Section 5): direction search (Section 2, Algorithm 1), the
+//    constrained filter (Section 3) under all 64 (S^(p), S^(s)) pairs and the
+//    per-filter-block distortion D_{b,p} = ||s - d||^2 for every plane, with
+//    filtered pixels never leaving registers;
+//  * filter: direction search and the filter (Eq. 7-13) at the block's own
+//    strengths, writing the filtered planes.
+//
+// A launch covers the filter blocks of one frame or of a batch of frames of
+// any size, bit depth (8/10) and damping; workgroup ids are remapped so that
+// each XCD (one L2 each) walks a contiguous range of filter blocks and
+// neighbouring blocks share their halo lines in L2.
+//
+// Search decomposition per filter block:
+//  * recon tiles with a 2-pixel halo (the taps reach +-2) and source tiles are
+//    staged in LDS for luma and both 4:2:0 chroma planes;
+//  * wave 0 runs Algorithm 1 for the 64 luma 8x8 blocks, one block per lane,
+//    while waves 1-3 sum (x - s)^2 over skipped blocks (identical for every
+//    pair);
+//  * non-skipped blocks are compacted; a luma task is two 8x8 blocks held in
+//    the two 16-bit halves of every lane (lane = pixel), so the per-block
+//    strengths are wave-uniform scalars; a chroma task is eight 4x4 blocks;
+//    waves 0-1 take the Cb tasks and waves 2-3 the Cr tasks;
+//  * per task and lane the candidate-independent work (12 tap magnitudes and
+//    signs, clamp bounds) is done once; secondary sums for S^(s) = 1, 2, 4,
+//    the primary sum once per S^(p), and per pair one packed
+//    round/clamp/square-accumulate;
+//  * the 64 per-lane accumulators are reduced across the wave by a
+//    transposing butterfly built from lane swaps and DPP moves (lane k ends
+//    with pair k), then across waves in LDS.
+#include "cdef_device.hpp"
+#include "cdef_launch.hpp"
+
+namespace cdef {
+
+namespace {
+
+constexpr int kLS = 80;  // luma recon tile row stride in samples (68 used)
+constexpr int kLC0 = 8;  // tile column that holds frame column x0 (16-byte aligned)
+constexpr int kCS = 48;  // chroma recon tile row stride (36 used)
+constexpr int kCC0 = 8;
+
+// LDS offsets of the six tap positions (inner, outer along d; along d+2;
+// along d-2) in a tile of the given stride, per direction.
+struct TapTable {
+  int off[8][6];
+};
+__host__ __device__ constexpr TapTable make_tap_table(int stride) {
+  TapTable t{};
+  for (int d = 0; d < 8; ++d)
+    for (int k = 0; k < 6; ++k) {
+      const int dd = k < 2 ? d : k < 4 ? (d + 2) & 7 : (d + 6) & 7;
+      t.off[d][k] = tap_dr(dd, k & 1) * stride + tap_dc(dd, k & 1);
+    }
+  return t;
+}
+// Indexed with wave-uniform directions, so the reads are scalar loads.
+__constant__ TapTable kLumaTaps = make_tap_table(kLS);
+
+__device__ __forceinline__ s16x2 as_s(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ s16x2 as_s(u16x2 v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ u16x2 as_u(s16x2 v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ u16x2 as_u(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ s16x2 splat(int v) { return s16x2{(short)v, (short)v}; }
+__device__ __forceinline__ uint32_t splat32(uint32_t v) { return v | (v << 16); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return (uint64_t)(uint32_t)uniform((int)(uint32_t)v) |
+         ((uint64_t)(uint32_t)uniform((int)(uint32_t)(v >> 32)) << 32);
+}
+
+// Per-lane, candidate-independent state of one task: two samples per lane.
+struct Taps {
+  u16x2 ad[12];  // |x_tap - x| (out-of-frame taps: >= 31745)
+  s16x2 sg[12];  // sign of x_tap - x as +-1
+  s16x2 X;       // 16 (x - s) + 8: the rounding offset with the source folded in
+  s16x2 dxs;     // x - s
+  s16x2 lo, hi;  // clamp range minus s
+};
+
+// Tap order: primary +inner, -inner, +outer, -outer; then for the two
+// secondary directions d+2 and d-2 the same four.
+__device__ __forceinline__ void prepare(Taps &t, uint32_t xv, uint32_t sv, const uint32_t (&tp)[12]) {
+  const s16x2 X = as_s(xv);
+  s16x2 hi = X;
+  u16x2 lo = as_u(xv);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const s16x2 v = as_s(tp[k]);
+    const s16x2 d = v - X;
+    const s16x2 nd = X - v;
+    t.ad[k] = as_u(__builtin_elementwise_max(d, nd));
+    t.sg[k] = (d >> splat(15)) | splat(1);
+    hi = __builtin_elementwise_max(hi, v);        // kOutside is the most negative int16
+    lo = __builtin_elementwise_min(lo, as_u(v));  // and the largest uint16 here
+  }
+  const s16x2 S = as_s(sv);
+  t.dxs = X - S;
+  t.X = t.dxs * splat(16) + splat(8);
+  t.lo = as_s(lo) - S;
+  t.hi = hi - S;
+}
+
+// Weighted constrained sum over taps [k0, k0+4) with magnitudes already
+// shifted (a): f = sign * min(|d|, max(0, S - (|d| >> shift))).
+__device__ __forceinline__ s16x2 group_sum(const Taps &t, const u16x2 (&a)[4], int k0, uint32_t s,
+                                           uint32_t wi, uint32_t wo) {
+  s16x2 m[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    m[k] = as_s(__builtin_elementwise_min(__builtin_elementwise_sub_sat(as_u(s), a[k]),
+                                          t.ad[k0 + k]));
+  const s16x2 inner = m[0] * t.sg[k0] + m[1] * t.sg[k0 + 1];
+  const s16x2 outer = m[2] * t.sg[k0 + 2] + m[3] * t.sg[k0 + 3];
+  return inner * as_s(wi) + outer * as_s(wo);
+}
+
+// Secondary sum over the 8 secondary taps for strength `s` (scaled, both
+// halves) and shift `sh` (both halves); weights 2 (inner) and 1 (outer).
+__device__ __forceinline__ s16x2 secondary(const Taps &t, uint32_t s, uint32_t sh) {
+  s16x2 q = splat(0);
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    u16x2 a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = t.ad[4 + 4 * g + k] >> as_u(sh);
+    q = q + group_sum(t, a, 4 + 4 * g, s, splat32(2), splat32(1));
+  }
+  return q;
+}
+
+// One (S^(p), S^(s)) pair with both groups possibly active: round the sum
+// of P and Q ties-away-from-zero, add to x - s, clamp, square-accumulate.
+__device__ __forceinline__ int pair_both(const Taps &t, s16x2 P, s16x2 Q, int acc) {
+  const s16x2 sum = P + Q;
+  s16x2 y = (t.X + sum + (sum >> splat(15))) >> splat(4);
+  y = __builtin_elementwise_min(__builtin_elementwise_max(y, t.lo), t.hi);
+  return __builtin_amdgcn_sdot2(y, y, acc, false);
+}
+
+// A pair with only one tap group: its weights sum to 12/16 < 1, so the
+// result cannot leave the clamp range and the clamp is skipped.
+__device__ __forceinline__ int pair_one(const Taps &t, s16x2 P, int acc) {
+  const s16x2 y = (t.X + P + (P >> splat(15))) >> splat(4);
+  return __builtin_amdgcn_sdot2(y, y, acc, false);
+}
+
+// Secondary sums for S^(s) = 1, 2, 4 at damping `damp` (8-bit domain).
+__device__ __forceinline__ void secondaries(const Taps &t, int c, int damp, s16x2 (&Q)[4]) {
+  Q[1] = secondary(t, splat32(1u << c), splat32((uint32_t)damp));
+  Q[2] = secondary(t, splat32(2u << c), splat32((uint32_t)(damp - 1)));
+  Q[3] = secondary(t, splat32(4u << c), splat32((uint32_t)(damp - 2)));
+}
+
+// Luma task: 2 blocks (lo/hi half) with per-block adjusted primary
+// strengths (Eq. 13).  Per-strength parameters are wave-uniform 32-bit
+// scalars (low half: block A, high half: block B).
+__device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t adjB, int c, int D,
+                                          int (&acc)[64]) {
+  s16x2 Q[4];
+  secondaries(t, c, D, Q);
+  acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
+#pragma unroll
+  for (int si = 1; si < 4; ++si) acc[si] = pair_one(t, Q[si], acc[si]);
+  uint32_t prev_sh = 0xFFFFFFFFu;
+  u16x2 a[4];
+#pragma unroll
+  for (int S = 1; S < 16; ++S) {
+    const uint32_t sa = (uint32_t)(adjA >> (4 * S)) & 15u, sb = (uint32_t)(adjB >> (4 * S)) & 15u;
+    const uint32_t sp = (sa << c) | (sb << (16 + c));
+    const uint32_t sha = sa ? (uint32_t)(D - floor_log2((int)sa)) : 0u;
+    const uint32_t shb = sb ? (uint32_t)(D - floor_log2((int)sb)) : 0u;
+    const uint32_t sh = sha | (shb << 16);
+    const uint32_t w1 = ((sa & 1) ? 3u : 4u) | (((sb & 1) ? 3u : 4u) << 16);
+    const uint32_t w2 = ((sa & 1) ? 3u : 2u) | (((sb & 1) ? 3u : 2u) << 16);
+    if (sh != prev_sh) {  // the shift pair changes only a few times over S = 1..15
+      prev_sh = sh;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
+    }
+    const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
+    acc[4 * S] = pair_one(t, P, acc[4 * S]);
+#pragma unroll
+    for (int si = 1; si < 4; ++si) acc[4 * S + si] = pair_both(t, P, Q[si], acc[4 * S + si]);
+  }
+}
+
+// Chroma task: strengths are not adjusted (uniform over the plane); the
+// chroma damping is max(D - 1, floor(log2 S^(p))) for both tap groups, which
+// differs from D - 1 only for D = 3 and S^(p) >= 8.
+__device__ __forceinline__ void chroma_task(const Taps &t, int c, int D, int (&acc)[64]) {
+  s16x2 Q[4];
+  secondaries(t, c, D - 1, Q);
+  acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
+#pragma unroll
+  for (int si = 1; si < 4; ++si) acc[si] = pair_one(t, Q[si], acc[si]);
+  u16x2 a[4];
+#pragma unroll
+  for (int S = 1; S < 16; ++S) {
+    const int lg = S >= 8 ? 3 : S >= 4 ? 2 : S >= 2 ? 1 : 0;
+    if (S == 8 && D == 3) secondaries(t, c, 3, Q);  // chroma damping becomes 3
+    const int Dc = max(D - 1, lg);
+    if (S == 1 || S == 2 || S == 4 || S == 8 || (S == 8 && D == 3)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32((uint32_t)(Dc - lg)));
+    }
+    const uint32_t w1 = splat32((S & 1) ? 3u : 4u), w2 = splat32((S & 1) ? 3u : 2u);
+    const s16x2 P = group_sum(t, a, 0, splat32((uint32_t)S << c), w1, w2);
+    acc[4 * S] = pair_one(t, P, acc[4 * S]);
+#pragma unroll
+    for (int si = 1; si < 4; ++si) acc[4 * S + si] = pair_both(t, P, Q[si], acc[4 * S + si]);
+  }
+}
+
+// One butterfly level at lane distance 8, 4, 2 or 1: the partner lane (DPP
+// `ctrl`) lies in the other half of the group; each lane keeps one value of
+// every pair and adds the partner's copy of it.
+template <int DIST, int CTRL>
+__device__ __forceinline__ void dpp_level(uint32_t (&v)[64], bool up) {
+#pragma unroll
+  for (int i = 0; i < DIST; ++i) {
+    const uint32_t a = v[i], b = v[i + DIST];
+    const uint32_t send = up ? a : b;
+    const uint32_t keep = up ? b : a;
+    v[i] = keep + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)send, CTRL, 0xF, 0xF, false);
+  }
+}
+
+// Wave-wide sum of 64 per-lane accumulators; lane k returns the total of
+// accumulator k.  Each level halves the values kept per lane.
+__device__ __forceinline__ uint32_t reduce_transpose(const int (&acc)[64], int lane) {
+  uint32_t v[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) v[i] = (uint32_t)acc[i];
+  // distance 32: lanes 0-31 keep pair i, lanes 32-63 pair i + 32
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v[i], v[i + 32], false, false);
+    v[i] = r[0] + r[1];
+  }
+  // distance 16: odd rows of 16 keep pair i + 16
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v[i], v[i + 16], false, false);
+    v[i] = r[0] + r[1];
+  }
+  dpp_level<8, 0x140>(v, (lane & 8) != 0);  // row_mirror: 15 - l within a row
+  dpp_level<4, 0x141>(v, (lane & 4) != 0);  // row_half_mirror: 7 - l within 8
+  dpp_level<2, 0x4E>(v, (lane & 2) != 0);   // quad_perm [2,3,0,1]
+  dpp_level<1, 0xB1>(v, (lane & 1) != 0);   // quad_perm [1,0,3,2]
+  return v[0];
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += (uint32_t)__shfl_xor((int)v, m, 64);
+  return v;
+}
+
+// Workgroup id -> work item: hardware deals workgroups to the 8 XCDs
+// round-robin; give each XCD a contiguous range of items.
+__device__ __forceinline__ int xcd_item(int wg, int n) {
+  const int x = wg & 7, i = wg >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + i;
+}
+
+struct Smem {
+  uint16_t ry[68 * kLS];
+  uint16_t sy[64 * 64];
+  uint16_t rc[2][36 * kCS];
+  uint16_t sc[2][32 * 32];
+  uint64_t adj[64];
+  int32_t var[64];
+  uint32_t red[2][4][64];
+  uint32_t skipsse[3];
+  int16_t coff[8][6];
+  uint8_t dir[64];
+  uint8_t list[64];
+  uint8_t flag[64];  // bit 0: in frame, bit 1: skipped
+  int n;
+};
+
+// Stage the recon tiles (all modes) and, for the search, the source tiles;
+// per-block flags for the 64 luma blocks.
+__device__ __forceinline__ void stage_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid,
+                                           bool search) {
+  const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
+  stage_recon<64, 64, kLS, kLC0, 256>(sm.ry, J.rec[0], J.rstride[0], W, H, y0, x0, tid);
+  if (search) stage_interior<64, 64, 256>(sm.sy, J.src[0], J.sstride[0], W, H, y0, x0, tid);
+  if (J.nplanes == 3) {
+    const int cw = (W + 1) >> 1, ch = (H + 1) >> 1;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      stage_recon<32, 32, kCS, kCC0, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], cw, ch, y0 >> 1,
+                                          x0 >> 1, tid);
+      if (search)
+        stage_interior<32, 32, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], cw, ch, y0 >> 1,
+                                    x0 >> 1, tid);
+    }
+  }
+  if (tid < 48) {
+    const int d = tid / 6, k = tid - 6 * (tid / 6);
+    const int dd = k < 2 ? d : k < 4 ? (d + 2) & 7 : (d + 6) & 7;
+    sm.coff[d][k] = (int16_t)(tap_dr(dd, k & 1) * kCS + tap_dc(dd, k & 1));
+  }
+  if (tid < 64) {
+    const int by = fby * 8 + (tid >> 3), bx = fbx * 8 + (tid & 7);
+    const bool in = by < J.brows && bx < J.bcols;
+    const bool sk = in && J.skip && J.skip[(int64_t)by * J.bcols + bx];
+    sm.flag[tid] = (uint8_t)((in ? 1 : 0) | (sk ? 2 : 0));
+  }
+  if (tid < 3) sm.skipsse[tid] = 0;
+}
+
+// Algorithm 1 for the 64 luma blocks of the filter block, one per lane of
+// wave 0; Eq. (13) adjusted strengths; compaction of the blocks to filter.
+__device__ __forceinline__ void direction_search(Smem &sm, const JobDesc &J, int fby, int fbx,
+                                                 int lane) {
+  const int b = lane;
+  const int by = fby * 8 + (b >> 3), bx = fbx * 8 + (b & 7);
+  const int c = J.bitdepth - 8;
+  const bool in = sm.flag[b] & 1, sk = sm.flag[b] & 2;
+  int d = 0, v = 0;
+  if (in) {
+    const int bw = min(8, J.width - 8 * bx), bh = min(8, J.height - 8 * by);
+    int x[64];
+    const uint16_t *row0 = sm.ry + (2 + 8 * (b >> 3)) * kLS + kLC0 + 8 * (b & 7);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(row0 + i * kLS);
+      const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int px = (int)((w4[j >> 1] >> (16 * (j & 1))) & 0xFFFF);
+        x[i * 8 + j] = (px >> c) - 128;
+      }
+    }
+    int cost[8];
+    if (bw == 8 && bh == 8) {
+      dir_costs_full(x, cost);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (i >= bh || j >= bw) x[i * 8 + j] = 0;
+      dir_costs_partial(x, bw, bh, cost);
+    }
+    pick_direction(cost, d, v);
+    if (J.dir) {
+      J.dir[(int64_t)by * J.bcols + bx] = (uint8_t)d;
+      J.var[(int64_t)by * J.bcols + bx] = v;
+    }
+  }
+  sm.dir[b] = (uint8_t)d;
+  sm.var[b] = v;
+  sm.adj[b] = adjusted_strengths(v);
+  const bool active = in && !sk;
+  const uint64_t m = __ballot(active);
+  const int pos = __popcll(m & ((1ull << lane) - 1ull));
+  if (active) sm.list[pos] = (uint8_t)b;
+  if (lane == 0) sm.n = __popcll(m);
+}
+
+// Sum of (x - s)^2 over pixels of skipped blocks, for each plane; run by
+// threads t0.. of the workgroup (nt of them).
+__device__ __forceinline__ void skipped_sse(Smem &sm, const JobDesc &J, int fby, int fbx, int t,
+                                            int nt, int lane) {
+  const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
+  uint32_t e0 = 0, e1 = 0, e2 = 0;
+  for (int e = t; e < 64 * 64; e += nt) {
+    const int r = e >> 6, col = e & 63;
+    if ((sm.flag[(r >> 3) * 8 + (col >> 3)] & 2) && y0 + r < H && x0 + col < W) {
+      const int dd = (int)sm.ry[(r + 2) * kLS + kLC0 + col] - (int)sm.sy[e];
+      e0 += (uint32_t)(dd * dd);
+    }
+  }
+  if (J.nplanes == 3) {
+    const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+    for (int e = t; e < 32 * 32; e += nt) {
+      const int r = e >> 5, col = e & 31;
+      if ((sm.flag[(r >> 2) * 8 + (col >> 2)] & 2) && cy0 + r < ch && cx0 + col < cw) {
+        const int i = (r + 2) * kCS + kCC0 + col;
+        const int d1 = (int)sm.rc[0][i] - (int)sm.sc[0][e];
+        const int d2 = (int)sm.rc[1][i] - (int)sm.sc[1][e];
+        e1 += (uint32_t)(d1 * d1);
+        e2 += (uint32_t)(d2 * d2);
+      }
+    }
+  }
+  e0 = wave_sum(e0);
+  e1 = wave_sum(e1);
+  e2 = wave_sum(e2);
+  if (lane == 0) {
+    atomicAdd(&sm.skipsse[0], e0);
+    atomicAdd(&sm.skipsse[1], e1);
+    atomicAdd(&sm.skipsse[2], e2);
+  }
+}
+
+__device__ __forceinline__ void search_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
+  const int c = J.bitdepth - 8, D = J.damping;
+  const bool chroma = J.nplanes == 3;
+
+  stage_item(sm, J, fby, fbx, tid, true);
+  __syncthreads();
+  if (wave == 0)
+    direction_search(sm, J, fby, fbx, lane);
+  else
+    skipped_sse(sm, J, fby, fbx, tid - 64, 192, lane);
+  __syncthreads();
+  const int n = sm.n;
+
+  // luma: tasks of two 8x8 blocks, dealt round-robin to the four waves
+  {
+    int acc[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) acc[i] = 0;
+    const int ntask = (n + 1) >> 1;
+    const int r = lane >> 3, col = lane & 7;
+    for (int tk = wave; tk < ntask; tk += 4) {
+      const int A = uniform(sm.list[2 * tk]);
+      const bool hasB = 2 * tk + 1 < n;
+      const int B = hasB ? uniform(sm.list[2 * tk + 1]) : A;
+      const int dA = uniform(sm.dir[A]), dB = uniform(sm.dir[B]);
+      const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
+      const int rA = 8 * (A >> 3) + r, cA = 8 * (A & 7) + col;
+      const int rB = 8 * (B >> 3) + r, cB = 8 * (B & 7) + col;
+      const bool vA = y0 + rA < H && x0 + cA < W;
+      const bool vB = hasB && y0 + rB < H && x0 + cB < W;
+      const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
+      const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
+      const uint32_t xv = ((uint32_t)sm.ry[bA] | ((uint32_t)sm.ry[bB] << 16)) & vm;
+      const uint32_t sv =
+          ((uint32_t)sm.sy[rA * 64 + cA] | ((uint32_t)sm.sy[rB * 64 + cB] << 16)) & vm;
+      uint32_t tp[12];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int oA = kLumaTaps.off[dA][k], oB = kLumaTaps.off[dB][k];
+        const int slot = (k >> 1) * 4 + (k & 1) * 2;
+        tp[slot] = ((uint32_t)sm.ry[bA + oA] | ((uint32_t)sm.ry[bB + oB] << 16)) & vm;
+        tp[slot + 1] = ((uint32_t)sm.ry[bA - oA] | ((uint32_t)sm.ry[bB - oB] << 16)) & vm;
+      }
+      Taps t;
+      prepare(t, xv, sv, tp);
+      luma_task(t, adjA, adjB, c, D, acc);
+    }
+    sm.red[0][wave][lane] = reduce_transpose(acc, lane);
+  }
+
+  // chroma (4:2:0): tasks of eight 4x4 blocks (four per half); waves 0-1
+  // take Cb, waves 2-3 take Cr
+  if (chroma) {
+    const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+    const int p = wave >> 1;
+    const uint16_t *rt = sm.rc[p];
+    const uint16_t *st = sm.sc[p];
+    const int ntask = (n + 7) >> 3;
+    const int sub = lane >> 4, r = (lane >> 2) & 3, col = lane & 3;
+    int acc[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) acc[i] = 0;
+    for (int tk = wave & 1; tk < ntask; tk += 2) {
+      const int iL = 8 * tk + sub, iH = 8 * tk + 4 + sub;
+      const bool hasL = iL < n, hasH = iH < n;
+      const int L = hasL ? sm.list[iL] : 0, Hb = hasH ? sm.list[iH] : 0;
+      const int rL = 4 * (L >> 3) + r, cL = 4 * (L & 7) + col;
+      const int rH = 4 * (Hb >> 3) + r, cH = 4 * (Hb & 7) + col;
+      const bool vL = hasL && cy0 + rL < ch && cx0 + cL < cw;
+      const bool vH = hasH && cy0 + rH < ch && cx0 + cH < cw;
+      const uint32_t vm = (vL ? 0x0000FFFFu : 0u) | (vH ? 0xFFFF0000u : 0u);
+      const int bL = (rL + 2) * kCS + kCC0 + cL, bH = (rH + 2) * kCS + kCC0 + cH;
+      const int dL = sm.dir[L], dH = sm.dir[Hb];
+      const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
+      const uint32_t sv = ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm;
+      uint32_t tp[12];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int oL = sm.coff[dL][k], oH = sm.coff[dH][k];
+        const int slot = (k >> 1) * 4 + (k & 1) * 2;
+        tp[slot] = ((uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16)) & vm;
+        tp[slot + 1] = ((uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16)) & vm;
+      }
+      Taps t;
+      prepare(t, xv, sv, tp);
+      chroma_task(t, c, D, acc);
+    }
+    sm.red[1][wave][lane] = reduce_transpose(acc, lane);
+  }
+  __syncthreads();
+
+  const int64_t fbi = (int64_t)fby * J.fbc + fbx;
+  const int64_t plane_stride = (int64_t)J.fbr * J.fbc * 64;
+  if (tid < 64) {
+    const uint64_t s = (uint64_t)sm.red[0][0][tid] + sm.red[0][1][tid] + sm.red[0][2][tid] +
+                       sm.red[0][3][tid] + sm.skipsse[0];
+    J.sse[fbi * 64 + tid] = s;
+  } else if (chroma && tid < 192) {
+    const int p = (tid >> 6) - 1, k = tid & 63;
+    const uint64_t s =
+        (uint64_t)sm.red[1][2 * p][k] + sm.red[1][2 * p + 1][k] + sm.skipsse[1 + p];
+    J.sse[(1 + p) * plane_stride + fbi * 64 + k] = s;
+  }
+}
+
+// Filter mode: the block's own strengths (Section 3.2 ranges; bad values are
+// masked / clamped so the kernel stays defined), one pixel per lane.
+__device__ __forceinline__ void filter_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
+  const int c = J.bitdepth - 8, D = J.damping;
+  stage_item(sm, J, fby, fbx, tid, false);
+  __syncthreads();
+  if (wave == 0) direction_search(sm, J, fby, fbx, lane);
+  __syncthreads();
+  const uint8_t *st = J.strengths + 4 * ((int64_t)fby * J.fbc + fbx);
+  const int pri_y = st[0] & 15, sec_y = min((int)st[1], 4);
+  const int pri_uv = st[2] & 15, sec_uv = min((int)st[3], 4);
+  {
+    const int ss = sec_y << c, sshift = sec_y ? D - floor_log2(sec_y) : 0;
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e >> 6, col = e & 63;
+      if (y0 + r >= H || x0 + col >= W) continue;
+      const int b = (r >> 3) * 8 + (col >> 3);
+      const int base = (r + 2) * kLS + kLC0 + col;
+      int y = sm.ry[base];
+      if (!(sm.flag[b] & 2)) {
+        const int adj = (int)((sm.adj[b] >> (4 * pri_y)) & 15);  // Eq. (13)
+        y = filter_pixel(sm.ry, base, kLS, sm.dir[b], adj << c, adj ? D - floor_log2(adj) : 0,
+                         (adj & 1) ? 3 : 4, (adj & 1) ? 3 : 2, ss, sshift);
+      }
+      J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] = (uint16_t)y;
+    }
+  }
+  if (J.nplanes != 3) return;
+  const int Dc = pri_uv ? max(D - 1, floor_log2(pri_uv)) : D - 1;
+  const int ps = pri_uv << c, pshift = pri_uv ? Dc - floor_log2(pri_uv) : 0;
+  const int w1 = (pri_uv & 1) ? 3 : 4, w2 = (pri_uv & 1) ? 3 : 2;
+  const int ss = sec_uv << c, sshift = sec_uv ? Dc - floor_log2(sec_uv) : 0;
+  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  for (int e = tid; e < 2 * 32 * 32; e += 256) {
+    const int p = e >> 10, r = (e >> 5) & 31, col = e & 31;
+    if (cy0 + r >= ch || cx0 + col >= cw) continue;
+    const int b = (r >> 2) * 8 + (col >> 2);
+    const int base = (r + 2) * kCS + kCC0 + col;
+    const int y = (sm.flag[b] & 2) ? (int)sm.rc[p][base]
+                                   : filter_pixel(sm.rc[p], base, kCS, sm.dir[b], ps, pshift, w1,
+                                                  w2, ss, sshift);
+    J.out[1 + p][(int64_t)(cy0 + r) * J.ostride[1 + p] + cx0 + col] = (uint16_t)y;
+  }
+}
+
+__device__ __forceinline__ void run_item(Smem &sm, const JobDesc &J, int item, int tid) {
+  const int fby = item / J.fbc, fbx = item - fby * J.fbc;
+  if (J.mode == kModeSearch)
+    search_item(sm, J, fby, fbx, tid);
+  else
+    filter_item(sm, J, fby, fbx, tid);
+}
+
+}  // namespace
+
+// One frame; the descriptor is a kernel argument.
+__global__ __launch_bounds__(256, 3) void k_fused_one(const JobDesc J) {
+  __shared__ __align__(16) Smem sm;
+  run_item(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+}
+
+// A batch: descriptors in device memory, items numbered across jobs.
+__global__ __launch_bounds__(256, 3) void k_fused_batch(const JobDesc *__restrict__ jobs,
+                                                        int njobs) {
+  __shared__ __align__(16) Smem sm;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  int lo = 0, hi = njobs - 1;  // last job with item0 <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item0 <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const JobDesc &J = jobs[lo];
+  run_item(sm, J, item - J.item0, threadIdx.x);
+}
+
+void fill_job_geometry(JobDesc &j) {
+  j.bcols = (j.width + 7) / 8;
+  j.brows = (j.height + 7) / 8;
+  j.fbc = (j.width + 63) / 64;
+  j.fbr = (j.height + 63) / 64;
+}
+
+hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
+  const int grid = job.fbc * job.fbr;
+  hipLaunchKernelGGL(k_fused_one, dim3(grid), dim3(256), 0, s, job);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
+                              hipStream_t s) {
+  (void)variant;
+  hipLaunchKernelGGL(k_fused_batch, dim3(nitems), dim3(256), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+}  // namespace cdef

@@ -90,3 +90,34 @@ def test_filter_argument_checks(lib):
         alias.plane[p] = f.plane[p]
         alias.stride[p] = f.stride[p]
     assert lib.cdef_filter_frame(C.byref(f), C.byref(alias), P, P, None, 3, P, None) == -1
+
+
+def test_batch_argument_checks(lib):
+    from paper_1602_05975_amd import cdef
+    assert lib.cdef_batch_workspace_bytes(0) == 0
+    per = lib.cdef_batch_workspace_bytes(1)
+    assert per > 0 and lib.cdef_batch_workspace_bytes(5) == 5 * per
+    plan = cdef.CdefBatchPlan()
+    j = cdef.CdefJob()
+    j.recon = _frame()
+    j.src = _frame(ptr=0x900000)
+    j.sse = 0x5000000
+    j.damping = 3
+    j.mode = 0
+    jobs = (cdef.CdefJob * 1)(j)
+    W = 0x7000000
+    assert lib.cdef_batch_prepare(None, 1, None, W, per, C.byref(plan), None) == -1
+    assert lib.cdef_batch_prepare(jobs, 0, None, W, per, C.byref(plan), None) == -1
+    assert lib.cdef_batch_prepare(jobs, 1, None, W, per - 1, C.byref(plan), None) == -4
+    for field, bad in (("damping", 9), ("mode", 5), ("sse", None)):
+        jb = cdef.CdefJob.from_buffer_copy(j)
+        setattr(jb, field, bad)
+        assert lib.cdef_batch_prepare((cdef.CdefJob * 1)(jb), 1, None, W, per, C.byref(plan),
+                                      None) == -1, field
+    jf = cdef.CdefJob.from_buffer_copy(j)
+    jf.mode = 1  # filter without strengths or outputs
+    assert lib.cdef_batch_prepare((cdef.CdefJob * 1)(jf), 1, None, W, per, C.byref(plan),
+                                  None) == -1
+    empty = cdef.CdefBatchPlan()
+    assert lib.cdef_batch_launch(C.byref(empty), None) == -1
+    assert lib.cdef_batch_launch(None, None) == -1

@@ -1,0 +1,169 @@
+"""Batches through cdef_batch_prepare / cdef_batch_launch: bit-exact with the
+per-frame entry points and the oracle, for mixed sizes, bit depths, damping
+and both job modes, and under HIP graph capture and replay."""
+import numpy as np
+import pytest
+
+from helpers import gpu_frame, oracle_search, to_np_u16
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05975_amd import cdef
+    cdef.load()
+
+
+def _synth():
+    from paper_1602_05975_amd import synth
+    return synth
+
+
+def _alloc_search(fr):
+    import torch
+    sse = torch.full((fr.nplanes, fr.fb_rows, fr.fb_cols, 16, 4), -1, dtype=torch.int64,
+                     device="cuda")
+    d = torch.full((fr.blk_rows, fr.blk_cols), 255, dtype=torch.uint8, device="cuda")
+    v = torch.full((fr.blk_rows, fr.blk_cols), -1, dtype=torch.int32, device="cuda")
+    return sse, d, v
+
+
+def _mixed_frames():
+    s = _synth()
+    specs = [(200, 136, 10, 3, 0.3, "search"), (131, 67, 8, 5, 0.2, "filter"),
+             (426, 240, 10, 6, 0.0, "search"), (64, 64, 8, 4, 0.5, "search"),
+             (7, 5, 10, 3, 0.0, "filter"), (150, 70, 10, 4, 0.3, "filter"),
+             (96, 70, 8, 3, 0.1, "search")]
+    frames = []
+    for i, (w, h, bd, D, sk, mode) in enumerate(specs):
+        layout = s.LAYOUT_400 if i == 3 else s.LAYOUT_420
+        fr = s.make_frame(w, h, bd, layout, 31000 + i, skip_prob=sk, damping=D)
+        frames.append((fr, mode))
+    return frames
+
+
+def test_mixed_batch_matches_per_frame_and_oracle(oracle):
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    b = cdef.Batch()
+    outs = []
+    for k, (fr, mode) in enumerate(_mixed_frames()):
+        rec = gpu_frame(fr.recon, fr)
+        skip = torch.from_numpy(fr.skip).cuda()
+        if mode == "search":
+            src = gpu_frame(fr.src, fr)
+            sse, d, v = _alloc_search(fr)
+            b.add_search(rec, src, skip, fr.damping, sse, d, v)
+            outs.append((fr, mode, (sse, d, v), (rec, src, skip)))
+        else:
+            st = torch.from_numpy(s.random_strengths(fr, 500 + k)).cuda()
+            o = [torch.full_like(p, -1) for p in rec.planes[:fr.nplanes]]
+            d = torch.full((fr.blk_rows, fr.blk_cols), 255, dtype=torch.uint8, device="cuda")
+            v = torch.full((fr.blk_rows, fr.blk_cols), -1, dtype=torch.int32, device="cuda")
+            b.add_filter(rec, o, skip, fr.damping, st, d, v)
+            outs.append((fr, mode, (o, d, v), (rec, st, skip)))
+    b.prepare()
+    print(f"batch of {len(outs)} jobs, {b.nitems} filter blocks", flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for fr, mode, res, inp in outs:
+        od, ov = oracle.find_dir(fr.recon[0], fr.bitdepth)
+        if mode == "search":
+            sse, d, v = res
+            rec, src, skip = inp
+            ref_sse, ref_d, ref_v = cdef.search_strengths(rec, src, skip, fr.damping, want_dir=True)
+            torch.cuda.synchronize()
+            assert torch.equal(sse, ref_sse) and torch.equal(d, ref_d) and torch.equal(v, ref_v)
+            t, _, _, fbs = oracle_search(oracle, fr)
+            got = sse.cpu().numpy().view(np.uint64)
+            for k, (by, bx) in enumerate(fbs):
+                assert (got[:, by, bx] == t[k]).all(), (fr.width, fr.height, by, bx)
+        else:
+            o, d, v = res
+            rec, st, skip = inp
+            pd, pv = cdef.find_dir(rec)
+            ref = cdef.filter_frame(rec, pd, pv, skip, fr.damping, st)
+            torch.cuda.synchronize()
+            for p in range(fr.nplanes):
+                assert torch.equal(o[p], ref[p])
+            oref = oracle.filter_frame(fr.recon, fr.width, fr.height, fr.bitdepth, od, ov, fr.skip,
+                                       fr.damping, st.cpu().numpy())
+            for p in range(fr.nplanes):
+                assert (to_np_u16(o[p]) == oref[p]).all()
+        assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
+
+
+def test_config3_batch_matches_per_frame_launches(oracle):
+    # 64 frames, resolutions from 426x240 to 3840x2160, 8- and 10-bit, damping
+    # 3..6, full search: one launch vs 64 cdef_search_strengths launches.
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    frames = s.config3(64)
+    b = cdef.Batch()
+    res, ins = [], []
+    for fr in frames:
+        rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+        sse, d, v = _alloc_search(fr)
+        b.add_search(rec, src, None, fr.damping, sse, d, v)
+        res.append((sse, d, v))
+        ins.append((rec, src))
+    b.prepare()
+    print(f"config-3 batch: {b.nitems} filter blocks", flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for k, (fr, (sse, d, v), (rec, src)) in enumerate(zip(frames, res, ins)):
+        ref = cdef.search_strengths(rec, src, None, fr.damping)
+        torch.cuda.synchronize()
+        assert torch.equal(sse, ref), k
+        if k % 8 == 0:  # oracle on two sampled filter blocks of every eighth frame
+            fbs = [(int(rng.integers(0, fr.fb_rows)), int(rng.integers(0, fr.fb_cols))),
+                   (fr.fb_rows - 1, fr.fb_cols - 1)]
+            t, od, ov, _ = oracle_search(oracle, fr, skip=False, fbs=fbs)
+            got = sse.cpu().numpy().view(np.uint64)
+            for i, (by, bx) in enumerate(fbs):
+                assert (got[:, by, bx] == t[i]).all()
+            assert (d.cpu().numpy() == od).all()
+
+
+def test_batch_graph_capture_replays():
+    # The launch enqueues kernels only, so it can be captured; every replay,
+    # interleaved with eager work that clobbers the outputs, must reproduce
+    # the eager result.
+    import torch
+    from paper_1602_05975_amd import cdef
+    frs = [f for f, m in _mixed_frames() if m == "search"][:2]
+    b = cdef.Batch()
+    outs, ins = [], []
+    for fr in frs:
+        rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+        skip = torch.from_numpy(fr.skip).cuda()
+        sse, d, v = _alloc_search(fr)
+        b.add_search(rec, src, skip, fr.damping, sse, d, v)
+        outs.append(sse)
+        ins.append((rec, src, skip, fr.damping))
+    b.prepare()
+    torch.cuda.synchronize()
+    refs = [cdef.search_strengths(r, s_, sk, D) for (r, s_, sk, D) in ins]
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        b.launch(stream)  # warm up on the capture stream
+    stream.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        b.launch(stream)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(rep)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert torch.equal(o, r), rep
