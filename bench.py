@@ -120,6 +120,109 @@ def load_traffic(kernel):
     return t.get("hbm_bytes_per_launch")
 
 
+def _device_search_jobs(frames, dev):
+    import torch
+    from paper_1602_05975_amd import cdef
+    jobs = []
+    for fr in frames:
+        rec = cdef.Frame.from_numpy(fr.recon, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
+        src = cdef.Frame.from_numpy(fr.src, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
+        skip = torch.from_numpy(fr.skip).to(dev)
+        sse = torch.empty((fr.nplanes, fr.fb_rows, fr.fb_cols, 16, 4), dtype=torch.int64,
+                          device=dev)
+        d = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.uint8, device=dev)
+        v = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.int32, device=dev)
+        jobs.append((rec, src, skip, fr.damping, sse, d, v))
+    return jobs
+
+
+def _time_steps(fn, steps, warmup, stream):
+    """Wall time per step (ms) of `fn`, bracketed by device synchronization."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def run_batching(args):
+    """The 64-frame uneven batch (resolutions 426x240 .. 3840x2160, 8/10 bit,
+    damping 3..6, full search): 64 per-frame launches vs one batched launch,
+    tuned, eager and replayed from a captured HIP graph.  Results of all
+    paths are compared bit for bit before timing."""
+    import torch
+    from paper_1602_05975_amd import cdef, synth, tune
+    log("generating the 64-frame mixed batch")
+    frames = synth.config3(64)
+    dev = torch.device("cuda:0")
+    jobs = _device_search_jobs(frames, dev)
+    stream = torch.cuda.current_stream()
+    px = sum(f.width * f.height for f in frames)
+
+    def plain():
+        for (rec, src, skip, D, sse, d, v) in jobs:
+            cdef.cdef_search_strengths(rec, src, skip, D, sse, d, v, stream)
+
+    plain()
+    torch.cuda.synchronize()
+    ref = [j[4].clone() for j in jobs]
+
+    batch = cdef.Batch()
+    for (rec, src, skip, D, sse, d, v) in jobs:
+        batch.add_search(rec, src, skip, D, sse, d, v)
+    batch.prepare(stream)
+    torch.cuda.synchronize()
+    per_variant = tune.time_variants(batch, stream, reps=5)
+    best = min(per_variant, key=per_variant.get)
+    batch.plan.variant = best
+    for j in jobs:
+        j[4].zero_()
+    batch.launch(stream)
+    torch.cuda.synchronize()
+    exact = all(torch.equal(j[4], r) for j, r in zip(jobs, ref))
+
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        batch.launch(side)
+    side.synchronize()
+    with torch.cuda.graph(graph, stream=side):
+        batch.launch(side)
+    for j in jobs:
+        j[4].zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    exact = exact and all(torch.equal(j[4], r) for j, r in zip(jobs, ref))
+
+    steps, warm = max(3, args.steps // 3), 2
+    log(f"timing {steps} steps of each path")
+    t_plain = _time_steps(plain, steps, warm, stream)
+    t_batch = _time_steps(lambda: batch.launch(stream), steps, warm, stream)
+    t_graph = _time_steps(graph.replay, steps, warm, stream)
+    res = {
+        "workload": "64 frames, resolutions uniform over 426x240..3840x2160, 8/10-bit, "
+                    "damping 3..6, 4:2:0, full 64-pair search",
+        "luma_px_per_step": px,
+        "filter_blocks": batch.nitems,
+        "bit_exact_vs_per_frame": bool(exact),
+        "per_frame_launches": {"ms_per_step": round(t_plain, 4),
+                               "mpixel_s": round(px / t_plain / 1e3, 1)},
+        "batched_launch": {"ms_per_step": round(t_batch, 4),
+                           "mpixel_s": round(px / t_batch / 1e3, 1)},
+        "graph_replay": {"ms_per_step": round(t_graph, 4),
+                         "mpixel_s": round(px / t_graph / 1e3, 1)},
+        "speedup_graph_vs_per_frame": round(t_plain / t_graph, 3),
+        "tuned_variant": best,
+        "variant_ms": {tune.VARIANT_NAMES[k]: round(v, 4) for k, v in per_variant.items()},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -129,6 +232,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-frame", action="store_true",
                     help="one cdef_search_strengths launch per frame instead of one batch")
+    ap.add_argument("--workload", choices=["search4k", "batch", "serve"], default="search4k",
+                    help="search4k: the headline line (default); batch: 64 mixed frames, "
+                         "per-frame launches vs one tuned, graph-replayed batch; serve: "
+                         "Poisson request stream, continuous batching vs one request per "
+                         "launch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling HBM counters)")
@@ -152,6 +260,11 @@ def main():
         print(json.dumps({"copy_bytes": n, "reads": n, "writes": n}))
         return
     cdef.load()
+    if args.workload == "batch":
+        return run_batching(args)
+    if args.workload == "serve":
+        from paper_1602_05975_amd import serve
+        return serve.bench_main(args)
 
     log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
     frames = synth.config2(args.frames)

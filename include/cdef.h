@@ -153,9 +153,21 @@ typedef struct {
   const void *table;  /* device job table inside the workspace */
   int32_t njobs;
   int32_t nitems;     /* filter blocks over all jobs */
-  int32_t variant;    /* launch variant, 0 = default */
+  int32_t variant;    /* launch variant 0..CDEF_BATCH_VARIANTS-1 (see below), 0 = default */
   int32_t reserved;
 } cdef_batch_plan;
+
+/* Host-side checks of one job, exactly those cdef_batch_prepare applies to each
+ * of its jobs; enqueues nothing.  Lets a scheduler reject a bad request alone
+ * instead of failing the batch it would have joined. */
+cdef_status cdef_job_validate(const cdef_job *job);
+
+/* Launch variants a tuner may choose between (all bit-identical):
+ *   0: at most 3 waves per SIMD (168 VGPRs), XCD-contiguous filter-block order
+ *   1: at most 2 waves per SIMD (256 VGPRs), XCD-contiguous order
+ *   2: 3 waves per SIMD, plain order
+ *   3: 2 waves per SIMD, plain order */
+#define CDEF_BATCH_VARIANTS 4
 
 /* Bytes of device workspace (and of pinned host staging, if used) for a
  * batch of njobs; 0 for njobs < 1. */
@@ -173,9 +185,10 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
                                void *workspace, size_t workspace_bytes, cdef_batch_plan *plan,
                                void *stream);
 
-/* One launch over every filter block of a prepared batch.  Enqueues kernels
- * only (no copies, no allocation), so it can be captured in a HIP graph and
- * replayed while the workspace and all job buffers stay valid. */
+/* One launch over every filter block of a prepared batch, in launch variant
+ * plan->variant (CDEF_E_INVAL if out of range).  Enqueues kernels only (no
+ * copies, no allocation), so it can be captured in a HIP graph and replayed
+ * while the workspace and all job buffers stay valid. */
 cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream);
 
 /* Human-readable name of a status code (static storage, never NULL). */

@@ -31,6 +31,7 @@ EXPORTS = (
     "cdef_batch_workspace_bytes",
     "cdef_batch_prepare",
     "cdef_batch_launch",
+    "cdef_job_validate",
     "cdef_status_str",
     "cdef_abi_version",
 )
@@ -112,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.cdef_batch_prepare.restype = C.c_int
     L.cdef_batch_launch.argtypes = [C.POINTER(CdefBatchPlan), P]
     L.cdef_batch_launch.restype = C.c_int
+    L.cdef_job_validate.argtypes = [C.POINTER(CdefJob)]
+    L.cdef_job_validate.restype = C.c_int
     L.cdef_status_str.argtypes = [C.c_int]
     L.cdef_status_str.restype = C.c_char_p
     L.cdef_abi_version.argtypes = []
@@ -251,6 +254,32 @@ def _out_struct(out_planes) -> CdefFrameOut:
     return o
 
 
+def make_search_job(recon: Frame, src: Frame, skip, damping: int, sse, dir=None,
+                    var=None) -> CdefJob:
+    j = CdefJob()
+    j.recon, j.src = recon.c_struct(), src.c_struct()
+    j.skip8x8, j.sse = _ptr(skip), _ptr(sse)
+    j.dir, j.var = _ptr(dir), _ptr(var)
+    j.damping, j.mode = damping, MODE_SEARCH
+    return j
+
+
+def make_filter_job(recon: Frame, out_planes, skip, damping: int, fb, dir=None,
+                    var=None) -> CdefJob:
+    j = CdefJob()
+    j.recon = recon.c_struct()
+    j.out = _out_struct(out_planes)
+    j.skip8x8, j.fb = _ptr(skip), _ptr(fb)
+    j.dir, j.var = _ptr(dir), _ptr(var)
+    j.damping, j.mode = damping, MODE_FILTER
+    return j
+
+
+def validate_job(job: CdefJob) -> int:
+    """Status of the host-side checks of one job (no GPU work)."""
+    return load().cdef_job_validate(C.byref(job))
+
+
 class Batch:
     """A prepared set of jobs launched together (cdef_batch_prepare /
     cdef_batch_launch).  Jobs keep references to their tensors; the device
@@ -264,24 +293,17 @@ class Batch:
         self.staging = None
 
     def add_search(self, recon: Frame, src: Frame, skip, damping: int, sse, dir=None, var=None):
-        j = CdefJob()
-        j.recon, j.src = recon.c_struct(), src.c_struct()
-        j.skip8x8, j.sse = _ptr(skip), _ptr(sse)
-        j.dir, j.var = _ptr(dir), _ptr(var)
-        j.damping, j.mode = damping, MODE_SEARCH
-        self.jobs.append(j)
-        self._keep.append((recon, src, skip, sse, dir, var))
-        return len(self.jobs) - 1
+        return self.add_job(make_search_job(recon, src, skip, damping, sse, dir, var),
+                            (recon, src, skip, sse, dir, var))
 
     def add_filter(self, recon: Frame, out_planes, skip, damping: int, fb, dir=None, var=None):
-        j = CdefJob()
-        j.recon = recon.c_struct()
-        j.out = _out_struct(out_planes)
-        j.skip8x8, j.fb = _ptr(skip), _ptr(fb)
-        j.dir, j.var = _ptr(dir), _ptr(var)
-        j.damping, j.mode = damping, MODE_FILTER
-        self.jobs.append(j)
-        self._keep.append((recon, out_planes, skip, fb, dir, var))
+        return self.add_job(make_filter_job(recon, out_planes, skip, damping, fb, dir, var),
+                            (recon, out_planes, skip, fb, dir, var))
+
+    def add_job(self, job: "CdefJob", keep) -> int:
+        """Add a ready job; `keep` holds the tensors it points to."""
+        self.jobs.append(job)
+        self._keep.append(keep)
         return len(self.jobs) - 1
 
     def prepare(self, stream=None) -> None:
@@ -289,9 +311,8 @@ class Batch:
         L = load()
         n = len(self.jobs)
         nbytes = L.cdef_batch_workspace_bytes(n)
-        dev = self._keep[0][0].planes[0].device
         if self.workspace is None or self.workspace.numel() < nbytes:
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             self.staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
         arr = (CdefJob * n)(*self.jobs)
         st = L.cdef_batch_prepare(arr, n, self.staging.data_ptr(), self.workspace.data_ptr(),

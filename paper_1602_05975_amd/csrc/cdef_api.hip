@@ -181,6 +181,12 @@ cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src
   return from_hip(cdef::launch_fused_one(d, (hipStream_t)stream));
 }
 
+cdef_status cdef_job_validate(const cdef_job *job) {
+  if (!job) return CDEF_E_INVAL;
+  cdef::JobDesc d;
+  return make_job(job, &d);
+}
+
 size_t cdef_batch_workspace_bytes(int32_t njobs) {
   return njobs < 1 ? 0 : (size_t)njobs * sizeof(cdef::JobDesc);
 }
@@ -223,6 +229,7 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
 
 cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
   if (!plan || !plan->table || plan->njobs < 1 || plan->nitems < 1) return CDEF_E_INVAL;
+  if (plan->variant < 0 || plan->variant >= CDEF_BATCH_VARIANTS) return CDEF_E_INVAL;
   return from_hip(cdef::launch_fused_batch((const cdef::JobDesc *)plan->table, plan->njobs,
                                            plan->nitems, plan->variant, (hipStream_t)stream));
 }

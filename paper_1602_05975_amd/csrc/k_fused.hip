@@ -572,10 +572,13 @@ __global__ __launch_bounds__(256, 3) void k_fused_one(const JobDesc J) {
 }
 
 // A batch: descriptors in device memory, items numbered across jobs.
-__global__ __launch_bounds__(256, 3) void k_fused_batch(const JobDesc *__restrict__ jobs,
-                                                        int njobs) {
+// OCC bounds the waves per SIMD (and so the VGPR budget); XCD selects the
+// XCD-contiguous order of filter blocks.
+template <int OCC, bool XCD>
+__global__ __launch_bounds__(256, OCC) void k_fused_batch(const JobDesc *__restrict__ jobs,
+                                                          int njobs) {
   __shared__ __align__(16) Smem sm;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int item = XCD ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   int lo = 0, hi = njobs - 1;  // last job with item0 <= item
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -603,8 +606,12 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
 
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
                               hipStream_t s) {
-  (void)variant;
-  hipLaunchKernelGGL(k_fused_batch, dim3(nitems), dim3(256), 0, s, jobs, njobs);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_fused_batch<2, true>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
+    case 2: hipLaunchKernelGGL((k_fused_batch<3, false>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
+    case 3: hipLaunchKernelGGL((k_fused_batch<2, false>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
+    default: hipLaunchKernelGGL((k_fused_batch<3, true>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
+  }
   return hipGetLastError();
 }
 

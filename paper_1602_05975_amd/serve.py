@@ -1,0 +1,402 @@
+"""Continuous-batching CDEF server.
+
+Requests are frames that are already resident in device memory (as when
+CDEF runs inside a GPU codec pipeline: the reconstruction is produced on the
+device and the source was uploaded once), each asking either for the
+encoder's strength search or for the direction search + filter at given
+per-filter-block strengths.  The scheduler
+
+* validates each request on its own at submission (a bad request fails
+  alone and never joins a batch),
+* admits requests first-in first-out while the device bytes of their
+  outputs fit a budget (by default 90 % of the free device memory),
+* launches every admitted request not yet running as one batch
+  (cdef_batch_prepare + cdef_batch_launch) on the next free stream of a
+  small pool, without waiting for earlier batches, so requests that arrive
+  while others run join the next batch and batches overlap on the device,
+* retires batches by polling their completion events and releases their
+  budget.
+
+The same scheduler drives the plain path (one request per launch through the
+per-frame entry points, in arrival order on one stream) for comparison, and
+a test executor with no GPU.  Results are bit-identical whichever path or
+batch a request takes.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import json
+import sys
+import time
+from typing import Callable, Deque, Dict, List, Optional
+
+import numpy as np
+
+from . import cdef
+
+SEARCH = cdef.MODE_SEARCH
+FILTER = cdef.MODE_FILTER
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    mode: int
+    recon: "cdef.Frame"
+    src: Optional["cdef.Frame"] = None  # search
+    strengths: object = None            # filter: uint8 [fbr][fbc][4] device tensor
+    skip: object = None
+    damping: int = 3
+    arrival: float = 0.0                # host clock, seconds
+    # filled in by the server
+    status: int = 0
+    outputs: tuple = ()
+    out_bytes: int = 0
+    admitted: float = -1.0
+    done: float = -1.0
+    job: object = None
+    batch_id: int = -1
+
+    @property
+    def luma_px(self) -> int:
+        return self.recon.width * self.recon.height
+
+
+def output_bytes(req: Request) -> int:
+    """Device bytes a request's outputs occupy while it is in flight."""
+    f = req.recon
+    fbr, fbc = f.fb_shape
+    br, bc = f.block_shape
+    dv = br * bc * 5
+    if req.mode == SEARCH:
+        return f.nplanes * fbr * fbc * 64 * 8 + dv
+    w, h = f.width, f.height
+    px = w * h + (2 * ((w + 1) // 2) * ((h + 1) // 2) if f.nplanes == 3 else 0)
+    return 2 * px + dv
+
+
+class GpuBatchExecutor:
+    """Batches of requests through cdef_batch_prepare / cdef_batch_launch on a
+    pool of streams (default priority)."""
+
+    def __init__(self, n_streams: int = 2, variant: Optional[int] = None):
+        import torch
+        self.torch = torch
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.slots = [cdef.Batch() for _ in range(n_streams)]
+        self.busy = [None] * n_streams  # event of the batch running in each slot
+        self.variant = variant
+        self.t0_event = None
+
+    def set_epoch(self):
+        """Align device event times with the host clock."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+        self.t0_event.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        self.t0_host = time.perf_counter()
+
+    def allocate(self, req: Request):
+        torch = self.torch
+        f = req.recon
+        br, bc = f.block_shape
+        d = torch.empty((br, bc), dtype=torch.uint8, device="cuda")
+        v = torch.empty((br, bc), dtype=torch.int32, device="cuda")
+        if req.mode == SEARCH:
+            fbr, fbc = f.fb_shape
+            sse = torch.empty((f.nplanes, fbr, fbc, 16, 4), dtype=torch.int64, device="cuda")
+            req.outputs = (sse, d, v)
+            req.job = cdef.make_search_job(f, req.src, req.skip, req.damping, sse, d, v)
+        else:
+            outs = [torch.empty_like(p) for p in f.planes[:f.nplanes]]
+            req.outputs = (outs, d, v)
+            req.job = cdef.make_filter_job(f, outs, req.skip, req.damping, req.strengths, d, v)
+
+    def validate(self, req: Request) -> int:
+        return cdef.validate_job(req.job)
+
+    def free_slot(self) -> int:
+        for i, e in enumerate(self.busy):
+            if e is None:
+                return i
+        return -1
+
+    def launch(self, reqs: List[Request]):
+        i = self.free_slot()
+        assert i >= 0
+        b = self.slots[i]
+        b.jobs, b._keep = [], []
+        for r in reqs:
+            b.add_job(r.job, (r.recon, r.src, r.skip, r.strengths, r.outputs))
+        s = self.streams[i]
+        b.prepare(s)
+        if self.variant is not None:
+            b.plan.variant = self.variant
+        b.launch(s)
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(s)
+        self.busy[i] = ev
+        return i
+
+    def poll(self, handle) -> Optional[float]:
+        """Completion time (host clock) of a finished launch, else None."""
+        ev = self.busy[handle]
+        if ev is None or not ev.query():
+            return None
+        self.busy[handle] = None
+        return self.t0_host + self.t0_event.elapsed_time(ev) / 1e3
+
+    @property
+    def capacity(self) -> int:
+        return len(self.slots)
+
+
+class GpuPlainExecutor:
+    """One request per launch through the per-frame entry points, in order,
+    on one stream."""
+
+    in_order = True
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.Stream()
+        self.pending: Dict[int, object] = {}
+        self.next = 0
+        self.t0_event = None
+
+    set_epoch = GpuBatchExecutor.set_epoch
+    allocate = GpuBatchExecutor.allocate
+    validate = GpuBatchExecutor.validate
+
+    def launch(self, reqs: List[Request]):
+        assert len(reqs) == 1
+        r = reqs[0]
+        s = self.stream
+        if r.mode == SEARCH:
+            sse, d, v = r.outputs
+            cdef.cdef_search_strengths(r.recon, r.src, r.skip, r.damping, sse, d, v, s)
+        else:
+            outs, d, v = r.outputs
+            cdef.cdef_find_dir(r.recon, d, v, s)
+            cdef.cdef_filter_frame(r.recon, outs, d, v, r.skip, r.damping, r.strengths, s)
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(s)
+        h = self.next
+        self.next += 1
+        self.pending[h] = ev
+        return h
+
+    def poll(self, handle) -> Optional[float]:
+        ev = self.pending.get(handle)
+        if ev is None or not ev.query():
+            return None
+        del self.pending[handle]
+        return self.t0_host + self.t0_event.elapsed_time(ev) / 1e3
+
+    @property
+    def capacity(self) -> int:
+        return 1 << 30  # launches queue on the stream in order
+
+
+class Scheduler:
+    """Admission by output bytes, continuous batching, completion polling.
+    Executor-agnostic: it needs allocate / validate / launch / poll /
+    capacity."""
+
+    def __init__(self, executor, budget_bytes: int, max_batch: int = 256,
+                 batching: bool = True, clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.budget = budget_bytes
+        self.in_use = 0
+        self.max_batch = max_batch if batching else 1
+        self.queue: Deque[Request] = collections.deque()   # submitted, not admitted
+        self.ready: List[Request] = []                       # admitted, not launched
+        self.running: Dict[object, List[Request]] = {}
+        self.finished: List[Request] = []
+        self.rejected: List[Request] = []
+        self.clock = clock
+        self.nbatches = 0
+
+    def submit(self, req: Request) -> None:
+        self.queue.append(req)
+
+    def cancel(self, rid: int) -> bool:
+        """Withdraw a request that has not been admitted yet."""
+        for r in list(self.queue):
+            if r.rid == rid:
+                self.queue.remove(r)
+                return True
+        return False
+
+    def _admit(self, now: float) -> None:
+        while self.queue:
+            r = self.queue[0]
+            need = output_bytes(r)
+            if need > self.budget:  # can never fit: reject rather than block the queue
+                self.queue.popleft()
+                r.status = cdef.CDEF_E_NOMEM
+                self.rejected.append(r)
+                continue
+            if self.in_use + need > self.budget:
+                return
+            self.queue.popleft()
+            self.ex.allocate(r)
+            st = self.ex.validate(r)
+            if st != cdef.CDEF_OK:
+                r.status = st
+                r.outputs, r.job = (), None
+                self.rejected.append(r)
+                continue
+            r.out_bytes = need
+            r.admitted = now
+            self.in_use += need
+            self.ready.append(r)
+
+    def _retire(self) -> List[Request]:
+        done = []
+        in_order = getattr(self.ex, "in_order", False)
+        for h in list(self.running):
+            t = self.ex.poll(h)
+            if t is None:
+                if in_order:  # launches on one stream finish in order
+                    break
+                continue
+            for r in self.running.pop(h):
+                r.done = t
+                self.in_use -= r.out_bytes
+                done.append(r)
+        self.finished.extend(done)
+        return done
+
+    def step(self) -> List[Request]:
+        """One scheduling round; returns the requests completed in it."""
+        done = self._retire()
+        self._admit(self.clock())
+        while self.ready and len(self.running) < self.ex.capacity:
+            if getattr(self.ex, "free_slot", None) and self.ex.free_slot() < 0:
+                break
+            take, self.ready = self.ready[:self.max_batch], self.ready[self.max_batch:]
+            h = self.ex.launch(take)
+            for r in take:
+                r.batch_id = self.nbatches
+            self.nbatches += 1
+            self.running[h] = take
+        return done
+
+    @property
+    def idle(self) -> bool:
+        return not (self.queue or self.ready or self.running)
+
+
+def run_trace(sched: Scheduler, requests: List[Request], offsets: np.ndarray,
+              spin: float = 20e-6) -> float:
+    """Submit request k at start + offsets[k] (host clock) and run the
+    scheduler until all complete.  Returns the wall time."""
+    start = time.perf_counter()
+    k = 0
+    n = len(requests)
+    while k < n or not sched.idle:
+        now = time.perf_counter()
+        while k < n and start + offsets[k] <= now:
+            requests[k].arrival = start + offsets[k]
+            sched.submit(requests[k])
+            k += 1
+        sched.step()
+        if k < n and sched.idle:
+            time.sleep(max(0.0, min(spin, start + offsets[k] - time.perf_counter())))
+    return time.perf_counter() - start
+
+
+# ---- benchmark (bench.py --workload serve) ---------------------------------
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_request_pool(n_frames: int = 20, seed: int = 4):
+    """Device-resident frames of the mixed resolution / bit-depth set."""
+    import torch
+    from . import synth
+    rng = np.random.default_rng(seed)
+    pool = []
+    params = synth.mixed_frame_params(n_frames, 4)
+    for i, (w, h, bd, D) in enumerate(params):
+        fr = synth.make_frame(w, h, bd, synth.LAYOUT_420, synth.config_seed(4, i), damping=D)
+        rec = cdef.Frame.from_numpy(fr.recon, w, h, bd, fr.layout)
+        src = cdef.Frame.from_numpy(fr.src, w, h, bd, fr.layout)
+        st = torch.from_numpy(synth.random_strengths(fr, 70 + i)).cuda()
+        pool.append((fr, rec, src, st))
+    del rng
+    return pool
+
+
+def make_requests(pool, n: int, seed: int) -> List[Request]:
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n):
+        fr, rec, src, st = pool[int(rng.integers(0, len(pool)))]
+        mode = SEARCH if rng.random() < 0.5 else FILTER
+        reqs.append(Request(rid=k, mode=mode, recon=rec, src=src if mode == SEARCH else None,
+                            strengths=st if mode == FILTER else None, damping=fr.damping))
+    return reqs
+
+
+def _stats(reqs: List[Request], wall: float) -> dict:
+    lat = np.array([(r.done - r.arrival) * 1e3 for r in reqs])
+    px = sum(r.luma_px for r in reqs)
+    return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "mpixel_s": round(px / wall / 1e6, 1),
+            "requests": len(reqs)}
+
+
+def bench_main(args) -> None:
+    import torch
+    n_req = 2000
+    warm = 200
+    _log("building the request pool")
+    pool = make_request_pool()
+    budget = int(torch.cuda.mem_get_info()[0] * 0.9)
+
+    # sustainable rate of the plain path: all requests back to back
+    reqs = make_requests(pool, warm, 1)
+    ex = GpuPlainExecutor()
+    ex.set_epoch()
+    sch = Scheduler(ex, budget, batching=False)
+    run_trace(sch, reqs, np.zeros(len(reqs)))
+    reqs = make_requests(pool, n_req, 2)
+    ex.set_epoch()
+    sch = Scheduler(ex, budget, batching=False)
+    wall = run_trace(sch, reqs, np.zeros(len(reqs)))
+    plain_rate = n_req / wall
+    _log(f"plain path back-to-back: {plain_rate:.0f} requests/s")
+
+    out = {"workload": "Poisson arrivals of device-resident frames, resolutions uniform over "
+                       "426x240..3840x2160, 8/10-bit, 4:2:0, 50% strength search / 50% "
+                       "direction search + filter at random per-filter-block strengths",
+           "plain_capacity_req_s": round(plain_rate, 1), "rates": []}
+    for frac in (0.7, 0.3, 0.9, 1.2):
+        lam = frac * plain_rate
+        rng = np.random.default_rng(int(frac * 100))
+        offs = np.cumsum(rng.exponential(1.0 / lam, n_req + warm))
+        res = {"rate_fraction_of_plain": frac, "rate_req_s": round(lam, 1)}
+        for name, mk, batching in (("plain", GpuPlainExecutor, False),
+                                   ("batched", GpuBatchExecutor, True)):
+            ex = mk()
+            ex.set_epoch()
+            sch = Scheduler(ex, budget, batching=batching)
+            reqs = make_requests(pool, n_req + warm, 3)
+            wall = run_trace(sch, reqs, offs)
+            kept = sorted(sch.finished, key=lambda r: r.rid)[warm:]
+            span = max(r.done for r in kept) - min(r.arrival for r in kept)
+            st = _stats(kept, span)
+            st["batches"] = sch.nbatches
+            res[name] = st
+            _log(f"rate {frac:.1f}x {name}: {st}")
+        res["p99_gain"] = round(res["plain"]["p99_ms"] / res["batched"]["p99_ms"], 3)
+        out["rates"].append(res)
+    print(json.dumps(out), flush=True)

@@ -1,0 +1,103 @@
+"""The continuous-batching server on the GPU: every request's result is
+bit-identical to the same request computed alone through the per-frame
+entry points, whichever batch it joined, and a bad request fails alone."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05975_amd import cdef
+    cdef.load()
+
+
+def _pool():
+    import torch
+    from paper_1602_05975_amd import cdef, synth
+    pool = []
+    for i, (w, h, bd, D) in enumerate([(426, 240, 8, 3), (200, 136, 10, 4), (131, 67, 10, 6),
+                                       (640, 360, 10, 3), (96, 70, 8, 5)]):
+        fr = synth.make_frame(w, h, bd, synth.LAYOUT_420, 77000 + i, skip_prob=0.2, damping=D)
+        rec = cdef.Frame.from_numpy(fr.recon, w, h, bd, fr.layout)
+        src = cdef.Frame.from_numpy(fr.src, w, h, bd, fr.layout)
+        st = torch.from_numpy(synth.random_strengths(fr, 90 + i)).cuda()
+        skip = torch.from_numpy(fr.skip).cuda()
+        pool.append((fr, rec, src, st, skip))
+    return pool
+
+
+def _requests(pool, n, seed):
+    from paper_1602_05975_amd import serve
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n):
+        fr, rec, src, st, skip = pool[int(rng.integers(0, len(pool)))]
+        mode = serve.SEARCH if rng.random() < 0.5 else serve.FILTER
+        reqs.append(serve.Request(rid=k, mode=mode, recon=rec,
+                                  src=src if mode == serve.SEARCH else None,
+                                  strengths=st if mode == serve.FILTER else None,
+                                  skip=skip, damping=fr.damping))
+    return reqs
+
+
+def _alone(req):
+    from paper_1602_05975_amd import cdef, serve
+    if req.mode == serve.SEARCH:
+        return cdef.search_strengths(req.recon, req.src, req.skip, req.damping)
+    d, v = cdef.find_dir(req.recon)
+    return cdef.filter_frame(req.recon, d, v, req.skip, req.damping, req.strengths)
+
+
+@pytest.mark.parametrize("batching", [True, False])
+def test_served_results_equal_alone(batching):
+    import torch
+    from paper_1602_05975_amd import serve
+    pool = _pool()
+    reqs = _requests(pool, 120, 5)
+    ex = serve.GpuBatchExecutor() if batching else serve.GpuPlainExecutor()
+    ex.set_epoch()
+    sched = serve.Scheduler(ex, budget_bytes=64 << 20, batching=batching)
+    offs = np.cumsum(np.random.default_rng(6).exponential(1.0 / 4000.0, len(reqs)))
+    print(f"serving {len(reqs)} requests, batching={batching}", flush=True)
+    serve.run_trace(sched, reqs, offs)
+    torch.cuda.synchronize()
+    assert len(sched.finished) == len(reqs) and not sched.rejected
+    if batching:
+        assert sched.nbatches < len(reqs)
+    for r in sched.finished:
+        assert r.done >= r.arrival
+        ref = _alone(r)
+        torch.cuda.synchronize()
+        if r.mode == serve.SEARCH:
+            assert torch.equal(r.outputs[0], ref), r.rid
+        else:
+            for a, b in zip(r.outputs[0], ref):
+                assert torch.equal(a, b), r.rid
+
+
+def test_bad_request_fails_alone():
+    import torch
+    from paper_1602_05975_amd import serve
+    pool = _pool()
+    reqs = _requests(pool, 10, 8)
+    reqs[4].damping = 9  # invalid
+    ex = serve.GpuBatchExecutor()
+    ex.set_epoch()
+    sched = serve.Scheduler(ex, budget_bytes=64 << 20)
+    serve.run_trace(sched, reqs, np.zeros(len(reqs)))
+    torch.cuda.synchronize()
+    assert [r.rid for r in sched.rejected] == [4]
+    assert sorted(r.rid for r in sched.finished) == [0, 1, 2, 3, 5, 6, 7, 8, 9]
+    for r in sched.finished:
+        ref = _alone(r)
+        torch.cuda.synchronize()
+        got = r.outputs[0]
+        if r.mode == serve.SEARCH:
+            assert torch.equal(got, ref)
+        else:
+            assert all(torch.equal(a, b) for a, b in zip(got, ref))

@@ -1,0 +1,136 @@
+"""Scheduler logic of the serving loop, on the CPU with a fake executor and
+a virtual clock: admission by byte budget, first-in first-out order,
+rejection of bad or oversized requests without disturbing the others,
+cancellation, and batching of requests that arrive while others run."""
+import pytest
+
+from paper_1602_05975_amd import cdef, serve
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor:
+    """Completes a launch `cost` seconds after it starts, two at a time."""
+
+    capacity = 2
+
+    def __init__(self, clock, cost_per_px=1e-9):
+        self.clock, self.cost = clock, cost_per_px
+        self.running = {}
+        self.launches = []
+        self.n = 0
+
+    def allocate(self, req):
+        req.outputs = ("out",)
+        req.job = object()
+
+    def validate(self, req):
+        return cdef.CDEF_OK if 3 <= req.damping <= 6 else cdef.CDEF_E_INVAL
+
+    def free_slot(self):
+        return 0 if len(self.running) < self.capacity else -1
+
+    def launch(self, reqs):
+        h = self.n
+        self.n += 1
+        self.launches.append([r.rid for r in reqs])
+        self.running[h] = self.clock() + self.cost * sum(r.luma_px for r in reqs)
+        return h
+
+    def poll(self, h):
+        t = self.running.get(h)
+        if t is None or self.clock() < t:
+            return None
+        del self.running[h]
+        return t
+
+
+def _req(rid, w=64, h=64, mode=serve.SEARCH, damping=3):
+    f = cdef.Frame([None, None, None], w, h, 10, cdef.LAYOUT_420)
+    return serve.Request(rid=rid, mode=mode, recon=f, damping=damping)
+
+
+def _run(sched, clock, reqs, arrivals, dt=1e-6, limit=10.0):
+    k = 0
+    peak = 0
+    while k < len(reqs) or not sched.idle:
+        while k < len(reqs) and arrivals[k] <= clock.t:
+            reqs[k].arrival = arrivals[k]
+            sched.submit(reqs[k])
+            k += 1
+        sched.step()
+        peak = max(peak, sched.in_use)
+        assert sched.in_use <= sched.budget
+        clock.t += dt
+        assert clock.t < limit
+    return peak
+
+
+def test_budget_fifo_and_completion():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    need = serve.output_bytes(_req(0))
+    sched = serve.Scheduler(ex, budget_bytes=3 * need, clock=clock)
+    reqs = [_req(i) for i in range(20)]
+    peak = _run(sched, clock, reqs, [0.0] * 20)
+    assert peak <= 3 * need and peak > need
+    assert sorted(r.rid for r in sched.finished) == list(range(20))
+    order = [r.admitted for r in sorted(sched.finished, key=lambda r: r.rid)]
+    assert order == sorted(order)  # admitted first-in first-out
+    assert all(r.done >= r.arrival for r in sched.finished)
+
+
+def test_oversized_and_invalid_requests_fail_alone():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    small = serve.output_bytes(_req(0))
+    sched = serve.Scheduler(ex, budget_bytes=4 * small, clock=clock)
+    reqs = [_req(0), _req(1, w=4000, h=4000), _req(2, damping=9), _req(3), _req(4)]
+    _run(sched, clock, reqs, [0.0] * 5)
+    assert sorted(r.rid for r in sched.finished) == [0, 3, 4]
+    rej = {r.rid: r.status for r in sched.rejected}
+    assert rej == {1: cdef.CDEF_E_NOMEM, 2: cdef.CDEF_E_INVAL}
+    for launch in ex.launches:
+        assert 1 not in launch and 2 not in launch
+
+
+def test_cancel_before_admission():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    need = serve.output_bytes(_req(0))
+    sched = serve.Scheduler(ex, budget_bytes=need, clock=clock)
+    for i in range(4):
+        sched.submit(_req(i))
+    sched.step()  # admits and launches request 0 only (budget of one)
+    assert sched.cancel(2) and not sched.cancel(0)
+    while not sched.idle:
+        clock.t += 1e-5
+        sched.step()
+    assert sorted(r.rid for r in sched.finished) == [0, 1, 3]
+
+
+def test_requests_arriving_during_a_launch_join_the_next_batch():
+    clock = Clock()
+    ex = FakeExecutor(clock, cost_per_px=1e-7)  # a 64x64 request takes 0.4 ms
+    sched = serve.Scheduler(ex, budget_bytes=1 << 30, clock=clock)
+    reqs = [_req(i) for i in range(12)]
+    arrivals = [0.0] + [1e-4 * i for i in range(1, 12)]
+    _run(sched, clock, reqs, arrivals, dt=5e-6)
+    sizes = [len(b) for b in ex.launches]
+    assert sizes[0] == 1 and max(sizes) > 1 and sum(sizes) == 12
+    flat = [rid for b in ex.launches for rid in b]
+    assert flat == sorted(flat)  # batches keep arrival order
+
+
+def test_plain_mode_is_one_request_per_launch():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sched = serve.Scheduler(ex, budget_bytes=1 << 30, batching=False, clock=clock)
+    _run(sched, clock, [_req(i) for i in range(6)], [0.0] * 6)
+    assert all(len(b) == 1 for b in ex.launches) and len(ex.launches) == 6
