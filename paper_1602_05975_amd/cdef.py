@@ -306,14 +306,19 @@ class Batch:
         self._keep.append(keep)
         return len(self.jobs) - 1
 
-    def prepare(self, stream=None) -> None:
+    def reserve(self, njobs: int) -> None:
+        """Size the workspace and pinned staging for up to njobs jobs now, so
+        later prepares never allocate (pinned allocation blocks the host)."""
         import torch
-        L = load()
-        n = len(self.jobs)
-        nbytes = L.cdef_batch_workspace_bytes(n)
+        nbytes = load().cdef_batch_workspace_bytes(max(1, njobs))
         if self.workspace is None or self.workspace.numel() < nbytes:
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             self.staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+
+    def prepare(self, stream=None) -> None:
+        L = load()
+        n = len(self.jobs)
+        self.reserve(n)
         arr = (CdefJob * n)(*self.jobs)
         st = L.cdef_batch_prepare(arr, n, self.staging.data_ptr(), self.workspace.data_ptr(),
                                   self.workspace.numel(), C.byref(self.plan),
