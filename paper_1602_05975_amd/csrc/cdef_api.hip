@@ -119,6 +119,15 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
   o->nplanes = r.nplanes;
   o->mode = j->mode;
   cdef::fill_job_geometry(*o);
+  // 16-byte staging is possible when every plane read starts 16-byte aligned
+  // and every row pitch keeps it so
+  bool al = true;
+  for (int p = 0; p < r.nplanes; ++p) {
+    al = al && ((uintptr_t)o->rec[p] & 15) == 0 && (o->rstride[p] & 7) == 0;
+    if (j->mode == CDEF_MODE_SEARCH)
+      al = al && ((uintptr_t)o->src[p] & 15) == 0 && (o->sstride[p] & 7) == 0;
+  }
+  o->flags = al ? cdef::kAligned16 : 0;
   return CDEF_OK;
 }
 

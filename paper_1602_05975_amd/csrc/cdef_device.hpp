@@ -173,17 +173,26 @@ __device__ __forceinline__ uint64_t adjusted_strengths(int var) {
 // Copies rows y0-2 .. y0+TH+1 and columns x0-2 .. x0+TW+1 of a plane into an
 // LDS tile whose column COL0 holds frame column x0.  Positions outside the
 // plane get kOutside.  Threads walk consecutive columns, so global reads
-// coalesce.
+// coalesce; the trip count is a compile-time constant so that every load is
+// issued before the first LDS store (no load-to-store serialization).
 template <int TH, int TW, int STRIDE, int COL0, int NT>
 __device__ __forceinline__ void stage_recon(uint16_t *lds, const uint16_t *plane, int64_t stride,
                                             int pw, int ph, int y0, int x0, int tid) {
-  constexpr int W = TW + 4, N = (TH + 4) * W;
-  for (int e = tid; e < N; e += NT) {
+  constexpr int W = TW + 4, N = (TH + 4) * W, ITER = (N + NT - 1) / NT;
+  uint16_t v[ITER];
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int e = tid + k * NT;
     const int r = e / W, c = e - r * W;
     const int y = y0 - 2 + r, x = x0 - 2 + c;
-    uint16_t v = kOutside;
-    if (y >= 0 && y < ph && x >= 0 && x < pw) v = plane[(int64_t)y * stride + x];
-    lds[r * STRIDE + COL0 - 2 + c] = v;
+    v[k] = kOutside;
+    if (e < N && y >= 0 && y < ph && x >= 0 && x < pw) v[k] = plane[(int64_t)y * stride + x];
+  }
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int e = tid + k * NT;
+    const int r = e / W, c = e - r * W;
+    if (e < N) lds[r * STRIDE + COL0 - 2 + c] = v[k];
   }
 }
 
@@ -192,10 +201,44 @@ template <int TH, int TW, int NT>
 __device__ __forceinline__ void stage_interior(uint16_t *lds, const uint16_t *plane,
                                                int64_t stride, int pw, int ph, int y0, int x0,
                                                int tid) {
-  for (int e = tid; e < TH * TW; e += NT) {
+  constexpr int ITER = (TH * TW + NT - 1) / NT;
+  uint16_t v[ITER];
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int e = tid + k * NT;
     const int r = e / TW, c = e - r * TW;
     const int y = y0 + r, x = x0 + c;
-    lds[e] = (y < ph && x < pw) ? plane[(int64_t)y * stride + x] : (uint16_t)0;
+    v[k] = (e < TH * TW && y < ph && x < pw) ? plane[(int64_t)y * stride + x] : (uint16_t)0;
+  }
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int e = tid + k * NT;
+    if (e < TH * TW) lds[e] = v[k];
+  }
+}
+
+// Fast staging of ROWS rows of Q 16-byte chunks each, from a plane whose base
+// and row pitch are 16-byte aligned, into LDS rows of LSTRIDE samples: row r,
+// chunk q reads plane[(y0 + r) * stride + xs + 8 q .. + 7], xs a multiple of 8.
+// The caller guarantees that the whole rectangle lies inside the plane.
+template <int ROWS, int Q, int LSTRIDE, int NT>
+__device__ __forceinline__ void stage_rows16(uint16_t *lds, const uint16_t *plane, int64_t stride,
+                                             int y0, int xs, int tid) {
+  constexpr int N = ROWS * Q, ITER = (N + NT - 1) / NT;
+  uint4 v[ITER];
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int e = tid + k * NT;
+    const int r = e / Q, q = e - r * Q;
+    v[k] = make_uint4(0, 0, 0, 0);
+    if (e < N)
+      v[k] = *reinterpret_cast<const uint4 *>(plane + (int64_t)(y0 + r) * stride + xs + 8 * q);
+  }
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int e = tid + k * NT;
+    const int r = e / Q, q = e - r * Q;
+    if (e < N) *reinterpret_cast<uint4 *>(lds + r * LSTRIDE + 8 * q) = v[k];
   }
 }
 

@@ -16,6 +16,7 @@ struct FrameDesc {
 };
 
 enum JobMode : int32_t { kModeSearch = 0, kModeFilter = 1 };
+enum JobFlags : int32_t { kAligned16 = 1 };
 
 // One frame of work as the fused kernel reads it (kernel argument for a
 // single frame, or an element of a device-resident table for a batch).
@@ -33,7 +34,7 @@ struct JobDesc {
   int32_t width, height, bitdepth, damping, nplanes, mode;
   int32_t fbc, fbr, bcols, brows;
   int32_t item0;  // first work item (filter block) of this job in the batch
-  int32_t pad;
+  int32_t flags;  // bit 0: every plane's base and row pitch are 16-byte aligned
 };
 
 hipError_t launch_find_dir(const FrameDesc &f, uint8_t *dir, int32_t *var, hipStream_t s);

@@ -284,21 +284,42 @@ struct Smem {
 };
 
 // Stage the recon tiles (all modes) and, for the search, the source tiles;
-// per-block flags for the 64 luma blocks.
+// per-block flags for the 64 luma blocks.  Filter blocks whose tiles (with
+// the 16-byte-rounded halo) lie inside aligned planes take 16-byte loads;
+// the rest go sample by sample with the frame-edge sentinel.
 __device__ __forceinline__ void stage_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid,
                                            bool search) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
-  stage_recon<64, 64, kLS, kLC0, 256>(sm.ry, J.rec[0], J.rstride[0], W, H, y0, x0, tid);
-  if (search) stage_interior<64, 64, 256>(sm.sy, J.src[0], J.sstride[0], W, H, y0, x0, tid);
-  if (J.nplanes == 3) {
-    const int cw = (W + 1) >> 1, ch = (H + 1) >> 1;
+  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  const bool chroma = J.nplanes == 3;
+  const bool fast = (J.flags & kAligned16) && y0 >= 2 && y0 + 66 <= H && x0 >= 8 &&
+                    x0 + 72 <= W &&
+                    (!chroma || (cy0 >= 2 && cy0 + 34 <= ch && cx0 >= 8 && cx0 + 40 <= cw));
+  if (fast) {
+    // luma: 68 rows of columns x0-8 .. x0+71 (the tile's full 80-sample rows)
+    stage_rows16<68, 10, kLS, 256>(sm.ry, J.rec[0], J.rstride[0], y0 - 2, x0 - kLC0, tid);
+    if (search) stage_rows16<64, 8, 64, 256>(sm.sy, J.src[0], J.sstride[0], y0, x0, tid);
+    if (chroma) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      stage_recon<32, 32, kCS, kCC0, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], cw, ch, y0 >> 1,
-                                          x0 >> 1, tid);
-      if (search)
-        stage_interior<32, 32, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], cw, ch, y0 >> 1,
-                                    x0 >> 1, tid);
+      for (int p = 0; p < 2; ++p) {
+        stage_rows16<36, 6, kCS, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], cy0 - 2,
+                                      cx0 - kCC0, tid);
+        if (search)
+          stage_rows16<32, 4, 32, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], cy0, cx0, tid);
+      }
+    }
+  } else {
+    stage_recon<64, 64, kLS, kLC0, 256>(sm.ry, J.rec[0], J.rstride[0], W, H, y0, x0, tid);
+    if (search) stage_interior<64, 64, 256>(sm.sy, J.src[0], J.sstride[0], W, H, y0, x0, tid);
+    if (chroma) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        stage_recon<32, 32, kCS, kCC0, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], cw, ch,
+                                            cy0, cx0, tid);
+        if (search)
+          stage_interior<32, 32, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], cw, ch, cy0,
+                                      cx0, tid);
+      }
     }
   }
   if (tid < 48) {
