@@ -191,6 +191,45 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
  * while the workspace and all job buffers stay valid. */
 cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream);
 
+/* ---- Preset selection -------------------------------------------------------
+ * Section 5, Eq. (15): choose the frame's presets from a strength-search SSE
+ * table.  Candidates are the 64 pairs, numbered p = S^(p) * 4 + index of
+ * S^(s) (order 0, 1, 2, 4) as in the table.  D^luma_{b,p} is plane 0,
+ * D^chroma_{b,p} the sum of planes 1 and 2 (0 for 4:0:0).  For luma and for
+ * chroma a greedy sequence of 8 presets is built, each step adding the
+ * candidate not yet chosen that most lowers sum_b min over the chosen set
+ * (lowest p on ties).  For N = 1, 2, 4, 8 the first N are then re-optimized
+ * one preset at a time, for up to refine_passes passes: a slot takes the
+ * candidate, not among the other slots, that gives the smallest distortion,
+ * when that is strictly smaller.  The cost of Eq. (15),
+ *   J(N) = lambda * B * log2(N) + D^luma(N) + D^chroma(N),  B = fb_rows * fb_cols,
+ * is evaluated in double precision in exactly that order, and the smallest N
+ * of minimal J is chosen.  Each filter block gets, for luma and for chroma,
+ * the slot (0..N-1) of its smallest distortion in the chosen set (lowest slot
+ * on ties).  As Eq. (15) is printed, the luma and chroma slots of a block are
+ * chosen independently. */
+typedef struct {
+  int32_t n;              /* chosen number of presets N*: 1, 2, 4 or 8 */
+  int32_t reserved;
+  int32_t luma[4][8];     /* preset candidates for N = 1, 2, 4, 8; slots >= N hold -1 */
+  int32_t chroma[4][8];
+  uint64_t dist_luma[4];  /* sum over blocks of the minimum luma distortion, N = 1, 2, 4, 8 */
+  uint64_t dist_chroma[4];
+  double cost[4];         /* J(N) for N = 1, 2, 4, 8 */
+} cdef_preset_result;
+
+/* sse:       device, uint64 [nplanes][fb_rows][fb_cols][16][4] (cdef_search_strengths).
+ * lambda:    rate multiplier, finite and >= 0.  refine_passes: 0..16.
+ * result:    device pointer, written by the kernels.
+ * fb_luma, fb_chroma: device uint8 [fb_rows][fb_cols], the slots for N*.
+ * Errors: CDEF_E_INVAL for null pointers, nplanes not 1 or 3, sizes < 1,
+ * a bad lambda or refine_passes; CDEF_E_UNSUPPORTED for more than 2^24
+ * filter blocks.  Two kernel launches on `stream`, no allocation. */
+cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
+                                int32_t fb_cols, double lambda, int32_t refine_passes,
+                                cdef_preset_result *result, uint8_t *fb_luma,
+                                uint8_t *fb_chroma, void *stream);
+
 /* Human-readable name of a status code (static storage, never NULL). */
 const char *cdef_status_str(cdef_status s);
 

@@ -322,3 +322,118 @@ void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame 
     }
   }
 }
+
+/* ---- Section 5, Eq. (15): choosing the presets ---------------------------------
+ * R17 Eq. (15) takes the minimum over P_luma and over P_chroma separately, as
+ *     printed; B is the number of filter blocks.  The "optimal preset to add"
+ *     is a candidate not yet in the set; ties go to the lowest candidate index
+ *     (S^(p) * 4 + index of S^(s)).  Re-optimization replaces one preset at a
+ *     time by the best candidate not among the others, only when that strictly
+ *     lowers the distortion. */
+
+static uint64_t group_d(const uint64_t *sse, int nplanes, int nfb, int g, int b, int p) {
+  if (g == 0) return sse[(int64_t)b * 64 + p];
+  if (nplanes < 3) return 0;
+  return sse[((int64_t)nfb + b) * 64 + p] + sse[((int64_t)2 * nfb + b) * 64 + p];
+}
+
+/* sum over blocks of the minimum distortion over set[0..n), with slot `skip`
+ * replaced by candidate `with` (skip < 0: no replacement; with < 0: slot dropped) */
+static uint64_t set_distortion(const uint64_t *sse, int nplanes, int nfb, int g, const int *set,
+                               int n, int skip, int with) {
+  uint64_t total = 0;
+  for (int b = 0; b < nfb; b++) {
+    uint64_t m = UINT64_MAX;
+    for (int i = 0; i < n; i++) {
+      int p = i == skip ? with : set[i];
+      if (p < 0) continue;
+      uint64_t d = group_d(sse, nplanes, nfb, g, b, p);
+      if (d < m) m = d;
+    }
+    total += m;
+  }
+  return total;
+}
+
+static int in_set(const int *set, int n, int p, int except) {
+  for (int i = 0; i < n; i++)
+    if (i != except && set[i] == p) return 1;
+  return 0;
+}
+
+void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
+                                int refine_passes, int32_t *n_chosen, int32_t *sets_l,
+                                int32_t *sets_c, uint64_t *dist, double *cost, uint8_t *fb_l,
+                                uint8_t *fb_c) {
+  static const int NS[4] = {1, 2, 4, 8};
+  int best_sets[2][4][8];
+  for (int g = 0; g < 2; g++) {
+    int greedy[8];
+    for (int step = 0; step < 8; step++) {
+      int best = -1;
+      uint64_t bestd = UINT64_MAX;
+      for (int p = 0; p < 64; p++) {
+        if (in_set(greedy, step, p, -1)) continue;
+        greedy[step] = p;
+        uint64_t d = set_distortion(sse, nplanes, nfb, g, greedy, step + 1, -1, -1);
+        if (best < 0 || d < bestd) {
+          bestd = d;
+          best = p;
+        }
+      }
+      greedy[step] = best;
+    }
+    for (int k = 0; k < 4; k++) {
+      int n = NS[k], set[8];
+      for (int i = 0; i < 8; i++) set[i] = i < n ? greedy[i] : -1;
+      for (int pass = 0; pass < refine_passes; pass++) {
+        int changed = 0;
+        for (int i = 0; i < n; i++) {
+          uint64_t curd = set_distortion(sse, nplanes, nfb, g, set, n, -1, -1);
+          int bestp = set[i];
+          uint64_t bestd = curd;
+          for (int p = 0; p < 64; p++) {
+            if (in_set(set, n, p, i)) continue;
+            uint64_t d = set_distortion(sse, nplanes, nfb, g, set, n, i, p);
+            if (d < bestd) {
+              bestd = d;
+              bestp = p;
+            }
+          }
+          if (bestp != set[i]) {
+            set[i] = bestp;
+            changed = 1;
+          }
+        }
+        if (!changed) break;
+      }
+      for (int i = 0; i < 8; i++) best_sets[g][k][i] = set[i];
+      dist[g * 4 + k] = set_distortion(sse, nplanes, nfb, g, set, n, -1, -1);
+    }
+  }
+  int chosen = 0;
+  for (int k = 0; k < 4; k++) {
+    cost[k] = lambda * (double)nfb * (double)k + (double)(dist[k] + dist[4 + k]);
+    if (cost[k] < cost[chosen]) chosen = k;
+  }
+  *n_chosen = NS[chosen];
+  for (int k = 0; k < 4; k++)
+    for (int i = 0; i < 8; i++) {
+      sets_l[k * 8 + i] = best_sets[0][k][i];
+      sets_c[k * 8 + i] = best_sets[1][k][i];
+    }
+  for (int b = 0; b < nfb; b++) {
+    for (int g = 0; g < 2; g++) {
+      int bi = 0;
+      uint64_t bd = UINT64_MAX;
+      for (int i = 0; i < NS[chosen]; i++) {
+        uint64_t d = group_d(sse, nplanes, nfb, g, b, best_sets[g][chosen][i]);
+        if (d < bd) {
+          bd = d;
+          bi = i;
+        }
+      }
+      (g == 0 ? fb_l : fb_c)[b] = (uint8_t)bi;
+    }
+  }
+}

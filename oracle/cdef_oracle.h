@@ -92,6 +92,23 @@ void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame 
                         const uint8_t *skip, int damping, uint64_t *sse,
                         uint8_t *dir, int32_t *var);
 
+/* Section 5, Eq. (15): preset selection on an SSE table sse
+ * [nplanes][nfb][64] (as cdef_oracle_search, filter blocks flattened).
+ * Luma distortion D^l[b][p] = plane 0; chroma D^c[b][p] = planes 1 + 2 (0 for
+ * nplanes = 1).  For each group a greedy sequence of 8 presets is built (each
+ * step adds the candidate that most lowers sum_b min over the set, lowest
+ * candidate index on ties); for N = 1, 2, 4, 8 the greedy prefix is then
+ * re-optimized one preset at a time for up to refine_passes passes (a slot
+ * takes the best candidate given the others, only on a strict improvement).
+ * J(N) = lambda * B * log2(N) + D^l(N) + D^c(N) with B = nfb; the smallest N
+ * of minimal J is chosen.  Outputs: n_chosen; sets_l/sets_c [4][8] (slot
+ * entries >= N are -1); dist [2][4] (luma, chroma; N = 1, 2, 4, 8); cost[4];
+ * per-block preset slots fb_l / fb_c (lowest slot on ties) for N*. */
+void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
+                                int refine_passes, int32_t *n_chosen, int32_t *sets_l,
+                                int32_t *sets_c, uint64_t *dist, double *cost, uint8_t *fb_l,
+                                uint8_t *fb_c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,9 @@ def lib():
         L.cdef_oracle_search.argtypes = [C.POINTER(OracleFrame), C.POINTER(OracleFrame), P,
                                          C.c_int, P, P, P]
         L.cdef_oracle_search.restype = None
+        L.cdef_oracle_select_presets.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_int, P, P,
+                                                 P, P, P, P, P]
+        L.cdef_oracle_select_presets.restype = None
         _lib = L
     return _lib
 
@@ -181,3 +184,24 @@ def search(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, h
     t = search_fbs(recon, src, width, height, bitdepth, d, v, skip, damping, fbs, threads)
     sse = t.reshape(fbr, fbc, len(recon), 16, 4).transpose(2, 0, 1, 3, 4)
     return np.ascontiguousarray(sse), d, v
+
+
+def select_presets(sse: np.ndarray, lam: float, refine_passes: int = 0) -> dict:
+    """Eq. (15) preset selection on an SSE table [nplanes][fbr][fbc][16][4]."""
+    sse = np.ascontiguousarray(sse, dtype=np.uint64)
+    nplanes = sse.shape[0]
+    nfb = int(np.prod(sse.shape[1:3]))
+    n = np.zeros(1, np.int32)
+    sl = np.zeros((4, 8), np.int32)
+    sc = np.zeros((4, 8), np.int32)
+    dist = np.zeros((2, 4), np.uint64)
+    cost = np.zeros(4, np.float64)
+    fl = np.zeros(nfb, np.uint8)
+    fc = np.zeros(nfb, np.uint8)
+    lib().cdef_oracle_select_presets(sse.ctypes.data, nplanes, nfb, float(lam), refine_passes,
+                                     n.ctypes.data, sl.ctypes.data, sc.ctypes.data,
+                                     dist.ctypes.data, cost.ctypes.data, fl.ctypes.data,
+                                     fc.ctypes.data)
+    shape = sse.shape[1:3]
+    return {"n": int(n[0]), "luma": sl, "chroma": sc, "dist": dist, "cost": cost,
+            "fb_luma": fl.reshape(shape), "fb_chroma": fc.reshape(shape)}

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcdef_hip.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["cdef_api.hip", "k_plain.hip", "k_fused.hip"]
+SOURCES = ["cdef_api.hip", "k_plain.hip", "k_fused.hip", "k_presets.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -32,6 +32,7 @@ EXPORTS = (
     "cdef_batch_prepare",
     "cdef_batch_launch",
     "cdef_job_validate",
+    "cdef_select_presets",
     "cdef_status_str",
     "cdef_abi_version",
 )
@@ -79,6 +80,18 @@ class CdefBatchPlan(C.Structure):
     ]
 
 
+class CdefPresetResult(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("reserved", C.c_int32),
+        ("luma", (C.c_int32 * 8) * 4),
+        ("chroma", (C.c_int32 * 8) * 4),
+        ("dist_luma", C.c_uint64 * 4),
+        ("dist_chroma", C.c_uint64 * 4),
+        ("cost", C.c_double * 4),
+    ]
+
+
 class CdefError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {status_str(status)} ({status})")
@@ -115,6 +128,9 @@ def load(path: str = LIB_PATH):
     L.cdef_batch_launch.restype = C.c_int
     L.cdef_job_validate.argtypes = [C.POINTER(CdefJob)]
     L.cdef_job_validate.restype = C.c_int
+    L.cdef_select_presets.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                      P, P, P, P]
+    L.cdef_select_presets.restype = C.c_int
     L.cdef_status_str.argtypes = [C.c_int]
     L.cdef_status_str.restype = C.c_char_p
     L.cdef_abi_version.argtypes = []
@@ -332,3 +348,33 @@ class Batch:
     @property
     def nitems(self) -> int:
         return self.plan.nitems
+
+
+# ---- preset selection (Section 5, Eq. 15) -------------------------------------
+
+def cdef_select_presets(sse, lam: float, refine_passes: int, result, fb_luma, fb_chroma,
+                        stream=None) -> None:
+    nplanes, fbr, fbc = sse.shape[0], sse.shape[1], sse.shape[2]
+    st = load().cdef_select_presets(_ptr(sse), nplanes, fbr, fbc, float(lam), refine_passes,
+                                    _ptr(result), _ptr(fb_luma), _ptr(fb_chroma),
+                                    _stream_handle(stream))
+    _check(st, "cdef_select_presets")
+
+
+def select_presets(sse, lam: float, refine_passes: int = 0, stream=None) -> dict:
+    """Run the preset selection on a device SSE table and return the result
+    (this reads the result back, so it synchronizes the stream)."""
+    import numpy as np
+    import torch
+    dev = sse.device
+    fbr, fbc = sse.shape[1], sse.shape[2]
+    res = torch.zeros(C.sizeof(CdefPresetResult), dtype=torch.uint8, device=dev)
+    fl = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
+    fc = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
+    cdef_select_presets(sse, lam, refine_passes, res, fl, fc, stream)
+    r = CdefPresetResult.from_buffer_copy(res.cpu().numpy().tobytes())
+    return {"n": r.n, "luma": np.array(r.luma, dtype=np.int32),
+            "chroma": np.array(r.chroma, dtype=np.int32),
+            "dist": np.array([list(r.dist_luma), list(r.dist_chroma)], dtype=np.uint64),
+            "cost": np.array(list(r.cost)), "fb_luma": fl.cpu().numpy(),
+            "fb_chroma": fc.cpu().numpy()}

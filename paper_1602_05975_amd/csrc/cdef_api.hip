@@ -4,9 +4,15 @@
 #include "../../include/cdef.h"
 #include "cdef_launch.hpp"
 
+#include <math.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+static_assert(sizeof(cdef_preset_result) == sizeof(cdef::PresetResult), "preset result layout");
+static_assert(offsetof(cdef_preset_result, cost) == offsetof(cdef::PresetResult, cost),
+              "preset result layout");
 
 namespace {
 
@@ -241,6 +247,22 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
   if (plan->variant < 0 || plan->variant >= CDEF_BATCH_VARIANTS) return CDEF_E_INVAL;
   return from_hip(cdef::launch_fused_batch((const cdef::JobDesc *)plan->table, plan->njobs,
                                            plan->nitems, plan->variant, (hipStream_t)stream));
+}
+
+cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
+                                int32_t fb_cols, double lambda, int32_t refine_passes,
+                                cdef_preset_result *result, uint8_t *fb_luma,
+                                uint8_t *fb_chroma, void *stream) {
+  if (!sse || !result || !fb_luma || !fb_chroma) return CDEF_E_INVAL;
+  if (nplanes != 1 && nplanes != 3) return CDEF_E_INVAL;
+  if (fb_rows < 1 || fb_cols < 1) return CDEF_E_INVAL;
+  if (!(lambda >= 0.0) || !isfinite(lambda)) return CDEF_E_INVAL;
+  if (refine_passes < 0 || refine_passes > 16) return CDEF_E_INVAL;
+  const int64_t nfb = (int64_t)fb_rows * fb_cols;
+  if (nfb > (1 << 24)) return CDEF_E_UNSUPPORTED;
+  return from_hip(cdef::launch_select_presets(sse, nplanes, (int)nfb, lambda, refine_passes,
+                                              reinterpret_cast<cdef::PresetResult *>(result),
+                                              fb_luma, fb_chroma, (hipStream_t)stream));
 }
 
 const char *cdef_status_str(cdef_status s) {

@@ -53,4 +53,16 @@ hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int va
 
 void fill_job_geometry(JobDesc &j);
 
+// Result of the preset selection; same layout as cdef_preset_result.
+struct PresetResult {
+  int32_t n, reserved;
+  int32_t luma[4][8], chroma[4][8];
+  uint64_t dist_luma[4], dist_chroma[4];
+  double cost[4];
+};
+
+hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
+                                 int refine, PresetResult *out, uint8_t *fb_luma,
+                                 uint8_t *fb_chroma, hipStream_t s);
+
 }  // namespace cdef

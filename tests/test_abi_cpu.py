@@ -121,3 +121,21 @@ def test_batch_argument_checks(lib):
     empty = cdef.CdefBatchPlan()
     assert lib.cdef_batch_launch(C.byref(empty), None) == -1
     assert lib.cdef_batch_launch(None, None) == -1
+
+
+def test_select_presets_argument_checks(lib):
+    P = C.c_void_p(0x10000)
+    f = lib.cdef_select_presets
+    assert f(None, 3, 2, 2, 1.0, 0, P, P, P, None) == -1
+    assert f(P, 3, 2, 2, 1.0, 0, None, P, P, None) == -1
+    assert f(P, 3, 2, 2, 1.0, 0, P, None, P, None) == -1
+    assert f(P, 3, 2, 2, 1.0, 0, P, P, None, None) == -1
+    assert f(P, 2, 2, 2, 1.0, 0, P, P, P, None) == -1
+    assert f(P, 3, 0, 2, 1.0, 0, P, P, P, None) == -1
+    assert f(P, 3, 2, -1, 1.0, 0, P, P, P, None) == -1
+    assert f(P, 3, 2, 2, -1.0, 0, P, P, P, None) == -1
+    assert f(P, 3, 2, 2, float("nan"), 0, P, P, P, None) == -1
+    assert f(P, 3, 2, 2, float("inf"), 0, P, P, P, None) == -1
+    assert f(P, 3, 2, 2, 1.0, -1, P, P, P, None) == -1
+    assert f(P, 3, 2, 2, 1.0, 17, P, P, P, None) == -1
+    assert f(P, 1, 4097, 4097, 1.0, 0, P, P, P, None) == -2
