@@ -218,17 +218,29 @@ typedef struct {
   double cost[4];         /* J(N) for N = 1, 2, 4, 8 */
 } cdef_preset_result;
 
+/* Bytes of device workspace cdef_select_presets needs (the same for every
+ * table size; under 1 MiB). */
+size_t cdef_select_presets_workspace_bytes(void);
+
 /* sse:       device, uint64 [nplanes][fb_rows][fb_cols][16][4] (cdef_search_strengths).
  * lambda:    rate multiplier, finite and >= 0.  refine_passes: 0..16.
- * result:    device pointer, written by the kernels.
+ * result:    device pointer, written by the kernels.  result->n == 0 reports
+ *            that the selection could not complete (its workgroups could not
+ *            all run within a second, e.g. behind other work filling the
+ *            device); the other fields are then undefined.
  * fb_luma, fb_chroma: device uint8 [fb_rows][fb_cols], the slots for N*.
- * Errors: CDEF_E_INVAL for null pointers, nplanes not 1 or 3, sizes < 1,
- * a bad lambda or refine_passes; CDEF_E_UNSUPPORTED for more than 2^24
- * filter blocks.  Two kernel launches on `stream`, no allocation. */
+ * workspace: device memory of cdef_select_presets_workspace_bytes() bytes,
+ *            256-byte aligned, owned by the caller; it must not be shared by
+ *            calls that may run at the same time.
+ * Errors: CDEF_E_INVAL for null pointers, a short or misaligned workspace,
+ * nplanes not 1 or 3, sizes < 1, a bad lambda or refine_passes;
+ * CDEF_E_UNSUPPORTED for more than 2^24 filter blocks.  Three kernel launches
+ * on `stream`, no allocation, no host synchronization. */
 cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
                                 int32_t fb_cols, double lambda, int32_t refine_passes,
                                 cdef_preset_result *result, uint8_t *fb_luma,
-                                uint8_t *fb_chroma, void *stream);
+                                uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
+                                void *stream);
 
 /* Human-readable name of a status code (static storage, never NULL). */
 const char *cdef_status_str(cdef_status s);

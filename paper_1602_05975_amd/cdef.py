@@ -33,6 +33,7 @@ EXPORTS = (
     "cdef_batch_launch",
     "cdef_job_validate",
     "cdef_select_presets",
+    "cdef_select_presets_workspace_bytes",
     "cdef_status_str",
     "cdef_abi_version",
 )
@@ -129,7 +130,9 @@ def load(path: str = LIB_PATH):
     L.cdef_job_validate.argtypes = [C.POINTER(CdefJob)]
     L.cdef_job_validate.restype = C.c_int
     L.cdef_select_presets.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
-                                      P, P, P, P]
+                                      P, P, P, P, C.c_size_t, P]
+    L.cdef_select_presets_workspace_bytes.argtypes = []
+    L.cdef_select_presets_workspace_bytes.restype = C.c_size_t
     L.cdef_select_presets.restype = C.c_int
     L.cdef_status_str.argtypes = [C.c_int]
     L.cdef_status_str.restype = C.c_char_p
@@ -353,15 +356,22 @@ class Batch:
 # ---- preset selection (Section 5, Eq. 15) -------------------------------------
 
 def cdef_select_presets(sse, lam: float, refine_passes: int, result, fb_luma, fb_chroma,
-                        stream=None) -> None:
+                        workspace, stream=None) -> None:
     nplanes, fbr, fbc = sse.shape[0], sse.shape[1], sse.shape[2]
     st = load().cdef_select_presets(_ptr(sse), nplanes, fbr, fbc, float(lam), refine_passes,
                                     _ptr(result), _ptr(fb_luma), _ptr(fb_chroma),
+                                    _ptr(workspace), workspace.numel() * workspace.element_size(),
                                     _stream_handle(stream))
     _check(st, "cdef_select_presets")
 
 
-def select_presets(sse, lam: float, refine_passes: int = 0, stream=None) -> dict:
+def preset_workspace(device="cuda"):
+    import torch
+    n = load().cdef_select_presets_workspace_bytes()
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def select_presets(sse, lam: float, refine_passes: int = 0, stream=None, workspace=None) -> dict:
     """Run the preset selection on a device SSE table and return the result
     (this reads the result back, so it synchronizes the stream)."""
     import numpy as np
@@ -371,8 +381,11 @@ def select_presets(sse, lam: float, refine_passes: int = 0, stream=None) -> dict
     res = torch.zeros(C.sizeof(CdefPresetResult), dtype=torch.uint8, device=dev)
     fl = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
     fc = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
-    cdef_select_presets(sse, lam, refine_passes, res, fl, fc, stream)
+    ws = preset_workspace(dev) if workspace is None else workspace
+    cdef_select_presets(sse, lam, refine_passes, res, fl, fc, ws, stream)
     r = CdefPresetResult.from_buffer_copy(res.cpu().numpy().tobytes())
+    if r.n == 0:
+        raise CdefError("cdef_select_presets: the selection did not complete")
     return {"n": r.n, "luma": np.array(r.luma, dtype=np.int32),
             "chroma": np.array(r.chroma, dtype=np.int32),
             "dist": np.array([list(r.dist_luma), list(r.dist_chroma)], dtype=np.uint64),

@@ -249,11 +249,16 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
                                            plan->nitems, plan->variant, (hipStream_t)stream));
 }
 
+size_t cdef_select_presets_workspace_bytes(void) { return cdef::preset_workspace_bytes(); }
+
 cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
                                 int32_t fb_cols, double lambda, int32_t refine_passes,
                                 cdef_preset_result *result, uint8_t *fb_luma,
-                                uint8_t *fb_chroma, void *stream) {
-  if (!sse || !result || !fb_luma || !fb_chroma) return CDEF_E_INVAL;
+                                uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
+                                void *stream) {
+  if (!sse || !result || !fb_luma || !fb_chroma || !workspace) return CDEF_E_INVAL;
+  if (workspace_bytes < cdef::preset_workspace_bytes() || ((uintptr_t)workspace & 255))
+    return CDEF_E_INVAL;
   if (nplanes != 1 && nplanes != 3) return CDEF_E_INVAL;
   if (fb_rows < 1 || fb_cols < 1) return CDEF_E_INVAL;
   if (!(lambda >= 0.0) || !isfinite(lambda)) return CDEF_E_INVAL;
@@ -262,7 +267,8 @@ cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb
   if (nfb > (1 << 24)) return CDEF_E_UNSUPPORTED;
   return from_hip(cdef::launch_select_presets(sse, nplanes, (int)nfb, lambda, refine_passes,
                                               reinterpret_cast<cdef::PresetResult *>(result),
-                                              fb_luma, fb_chroma, (hipStream_t)stream));
+                                              fb_luma, fb_chroma, workspace,
+                                              (hipStream_t)stream));
 }
 
 const char *cdef_status_str(cdef_status s) {

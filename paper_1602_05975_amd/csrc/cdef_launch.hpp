@@ -61,8 +61,9 @@ struct PresetResult {
   double cost[4];
 };
 
+size_t preset_workspace_bytes();
 hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
                                  int refine, PresetResult *out, uint8_t *fb_luma,
-                                 uint8_t *fb_chroma, hipStream_t s);
+                                 uint8_t *fb_chroma, void *workspace, hipStream_t s);
 
 }  // namespace cdef

@@ -10,10 +10,25 @@
 // D^luma(N) + D^chroma(N), the smallest N of minimal J wins, and every filter
 // block gets the slot of its smallest distortion (lowest slot on ties).
 //
-// One workgroup of 1024 threads per group: thread (p = t % 64, q = t / 64)
-// sums min(m_b, D_{b,p}) over blocks b = q mod 16, where m_b, the minimum
-// over the presets held fixed, is staged in LDS 4096 blocks at a time; the
-// 16 partial sums per candidate are added in LDS.
+// Layout of the work.  Each group (luma, chroma) is spread over G workgroups;
+// workgroup w owns a contiguous slice of about 64 filter blocks and keeps its
+// slice of D (chroma already summed) in LDS.  Every step of the search is a
+// "round": each workgroup evaluates, for up to three candidate sets at once,
+// the 64 partial sums sum_{b in slice} min(m_b, D_{b,p}) (m_b the minimum over
+// the presets held fixed), adds them atomically into the round's totals in
+// the workspace and waits until all G workgroups of its group have done so.
+// Every workgroup then reads the same integer totals and takes the same
+// decisions without further communication.  The greedy
+// takes 8 rounds; the refinements of N = 2, 4 and 8 advance together, one
+// slot per round.  Two facts keep this exact with fewer rounds: the N = 1
+// refinement can never change the set (the greedy first pick is the exact
+// minimum of the same sums, lowest index first), and a refined set's
+// distortion is the smaller of the two costs compared at its last slot
+// decision, so it needs no extra evaluation.
+//
+// Waits are bounded in time: a workgroup that waited more than a second marks
+// the selection failed and leaves, every other one leaves at its next wait,
+// and the result then reports n = 0.
 #include "cdef_launch.hpp"
 
 #include <stdint.h>
@@ -22,172 +37,383 @@ namespace cdef {
 
 namespace {
 
-constexpr int kChunk = 4096;
-constexpr int kNT = 1024;
+constexpr int kNT = 256;        // threads per workgroup
+constexpr int kSlice = 64;      // filter blocks per workgroup kept in LDS
+constexpr int kMaxG = 128;      // workgroups per group
+constexpr int kQ = 3;           // candidate sets evaluated per round
+constexpr uint64_t kWaitTicks = 100000000ull;  // 1 s of the 100 MHz wall clock
 
-__device__ __forceinline__ uint64_t dist_of(const uint64_t *sse, int nplanes, int nfb, int g,
-                                            int b, int p) {
+struct PresetWork {
+  uint32_t arrive[2];  // per-group arrival counters (G per round)
+  uint32_t failed;
+  uint32_t pad[61];
+  uint64_t total[3][2][kQ][64];  // [round mod 3][group][set][p]
+};
+
+__device__ __forceinline__ uint64_t group_dist(const uint64_t *sse, int nfb, int g, int b, int p) {
   if (g == 0) return sse[(int64_t)b * 64 + p];
-  if (nplanes < 3) return 0;
   return sse[((int64_t)nfb + b) * 64 + p] + sse[((int64_t)2 * nfb + b) * 64 + p];
 }
 
-struct PresetSmem {
-  uint64_t m[kChunk];
-  uint64_t part[16][64];
-  uint64_t cost[64];
+struct Query {
   int set[8];
-  int greedy[8];
-  int changed;
+  int n, excl;
 };
 
-// cost[p] = sum_b min(min_{i < n, i != excl} D_{b,S[i]}, D_{b,p}) for all 64 p.
-__device__ void evaluate(PresetSmem &sm, const uint64_t *sse, int nplanes, int nfb, int g,
-                         const int *S, int n, int excl) {
-  const int tid = threadIdx.x, p = tid & 63, q = tid >> 6;
-  uint64_t acc = 0;
-  for (int c0 = 0; c0 < nfb; c0 += kChunk) {
-    const int cn = min(kChunk, nfb - c0);
-    for (int i = tid; i < cn; i += kNT) {
-      uint64_t mm = UINT64_MAX;
-      for (int k = 0; k < n; ++k) {
-        if (k == excl) continue;
-        const uint64_t d = dist_of(sse, nplanes, nfb, g, c0 + i, S[k]);
-        mm = d < mm ? d : mm;
-      }
-      sm.m[i] = mm;
-    }
-    __syncthreads();
-    for (int i = q; i < cn; i += 16) {
-      const uint64_t d = dist_of(sse, nplanes, nfb, g, c0 + i, p);
-      acc += d < sm.m[i] ? d : sm.m[i];
-    }
-    __syncthreads();
-  }
-  sm.part[q][p] = acc;
-  __syncthreads();
-  if (tid < 64) {
-    uint64_t s = 0;
-    for (int k = 0; k < 16; ++k) s += sm.part[k][tid];
-    sm.cost[tid] = s;
-  }
-  __syncthreads();
-}
+struct CoopSmem {
+  uint64_t d[kSlice][64];
+  uint64_t m[kQ][kSlice];
+  uint64_t red[4][kQ][64];
+  uint64_t cost[kQ][64];
+  uint64_t best_cost[kQ];
+  int best_p[kQ];
+  Query q[kQ];
+  int qowner[kQ];  // refinement (0: N = 2, 1: N = 4, 2: N = 8) of each query
+  int nq, last, ok;
+  // search state, identical in every workgroup of the group
+  int step;
+  int greedy[8];
+  uint64_t greedy_cost[8];
+  int rset[3][8];
+  int slot[3], pass[3], changed[3], done[3];
+  uint64_t rdist[3];
+};
 
-__device__ __forceinline__ bool in_set(const int *S, int n, int p, int except) {
-  for (int i = 0; i < n; ++i)
-    if (i != except && S[i] == p) return true;
+__device__ __forceinline__ bool excluded(const Query &q, int p) {
+  for (int i = 0; i < q.n; ++i)
+    if (i != q.excl && q.set[i] == p) return true;
   return false;
 }
 
-__global__ __launch_bounds__(kNT) void k_preset_search(const uint64_t *__restrict__ sse,
-                                                       int nplanes, int nfb, int refine,
-                                                       PresetResult *out) {
-  __shared__ PresetSmem sm;
-  const int g = blockIdx.x, tid = threadIdx.x;
-  for (int step = 0; step < 8; ++step) {
-    evaluate(sm, sse, nplanes, nfb, g, sm.greedy, step, -1);
-    if (tid == 0) {
-      int best = -1;
-      for (int p = 0; p < 64; ++p) {
-        if (in_set(sm.greedy, step, p, -1)) continue;
-        if (best < 0 || sm.cost[p] < sm.cost[best]) best = p;
+// Lexicographic (cost, p) minimum over the 64 lanes of a wave; excluded
+// candidates carry UINT64_MAX and an index past 63.
+__device__ __forceinline__ void wave_argmin(uint64_t &c, int &p) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint64_t oc = __shfl_xor(c, off, 64);
+    const int op = __shfl_xor(p, off, 64);
+    if (oc < c || (oc == c && op < p)) {
+      c = oc;
+      p = op;
+    }
+  }
+}
+
+// The workgroup's partial sums for this round are in sm.red.  They are added
+// atomically into the round's totals, then the workgroup counts its arrival
+// and waits for the group's other workgroups.  Totals rotate over three
+// buffers: the last arrival of round r clears the buffer of round r - 1
+// (= r + 2 mod 3), which every workgroup has read before arriving at round r
+// and none adds to before round r + 2.  Everything that passes between
+// workgroups (totals, counters, the failure flag) is accessed only by
+// device-scope atomics, so ordering needs no cache write-back or
+// invalidation: each wave waits until its own atomics have returned before
+// the arrival is counted, and totals are read only after the count is seen
+// complete.  On return sm.cost holds the group's totals; false if the wait
+// timed out.
+__device__ bool round_totals(CoopSmem &sm, PresetWork *work, int g, int G, int nq,
+                             uint32_t round) {
+  const int tid = threadIdx.x, s = tid >> 6, lane = tid & 63;
+  const uint32_t buf = round % 3;
+  uint64_t before = 0;
+  if (tid < nq * 64) {
+    const uint64_t v =
+        sm.red[0][s][lane] + sm.red[1][s][lane] + sm.red[2][s][lane] + sm.red[3][s][lane];
+    before = __hip_atomic_fetch_add(&work->total[buf][g][s][lane], v, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // consuming the returned value makes the wave wait for the add to complete
+  __asm__ volatile("" : : "v"(before));
+  __syncthreads();
+  if (tid == 0) {
+    const uint32_t target = (uint32_t)G * (round + 1);
+    const uint32_t old =
+        __hip_atomic_fetch_add(&work->arrive[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    if (old + 1 != target) {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&work->arrive[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+             target) {
+        if (__hip_atomic_load(&work->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            wall_clock64() - t0 > kWaitTicks) {
+          __hip_atomic_store(&work->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      sm.greedy[step] = best;
+    }
+    sm.last = old + 1 == target;
+    sm.ok = ok;
+  }
+  __syncthreads();
+  if (!sm.ok) return false;
+  if (tid < nq * 64)
+    sm.cost[s][lane] = __hip_atomic_load(&work->total[buf][g][s][lane], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  if (sm.last && tid < kQ * 64)
+    __hip_atomic_store(&work->total[(round + 2) % 3][g][s][lane], (uint64_t)0, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  // the clearing stores complete before this workgroup's next arrival
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  return true;
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict__ sse,
+                                                     int nplanes, int nfb, int G, int refine,
+                                                     PresetWork *work, PresetResult *out) {
+  __shared__ CoopSmem sm;
+  const int g = blockIdx.x / G, w = blockIdx.x % G, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  if (g == 1 && nplanes == 1) {
+    // all-zero chroma: every candidate ties, so the greedy takes 0, 1, ..., 7
+    // and no refinement finds a strict improvement
+    if (w == 0 && tid < 32) {
+      const int k = tid >> 3, i = tid & 7;
+      out->chroma[k][i] = i < (1 << k) ? i : -1;
+      if (i == 0) out->dist_chroma[k] = 0;
+    }
+    return;
+  }
+  const int per = (nfb + G - 1) / G;
+  const int b0 = min(nfb, w * per), cnt = min(nfb, b0 + per) - b0;
+
+  if (LDS) {
+    for (int i = tid; i < cnt * 64; i += kNT)
+      sm.d[i >> 6][i & 63] = group_dist(sse, nfb, g, b0 + (i >> 6), i & 63);
+  }
+  if (tid == 0) {
+    sm.step = 0;
+    for (int r = 0; r < 3; ++r) sm.done[r] = 0;
+  }
+  __syncthreads();
+
+  for (uint32_t round = 0;; ++round) {
+    // ---- the candidate sets evaluated in this round
+    if (tid == 0) {
+      int nq = 0;
+      if (sm.step < 8) {
+        Query &q = sm.q[0];
+        for (int i = 0; i < 8; ++i) q.set[i] = sm.greedy[i];
+        q.n = sm.step;
+        q.excl = -1;
+        sm.qowner[0] = -1;
+        nq = 1;
+      } else {
+        for (int r = 0; r < 3; ++r) {
+          if (sm.done[r]) continue;
+          Query &q = sm.q[nq];
+          for (int i = 0; i < 8; ++i) q.set[i] = sm.rset[r][i];
+          q.n = 2 << r;
+          q.excl = sm.slot[r];
+          sm.qowner[nq] = r;
+          ++nq;
+        }
+      }
+      sm.nq = nq;
     }
     __syncthreads();
-  }
-  for (int k = 0; k < 4; ++k) {
-    const int n = 1 << k;
-    if (tid < 8) sm.set[tid] = tid < n ? sm.greedy[tid] : -1;
-    __syncthreads();
-    for (int pass = 0; pass < refine; ++pass) {
-      if (tid == 0) sm.changed = 0;
+    const int nq = sm.nq;
+    if (nq == 0) break;
+
+    // ---- partial sums: thread (p = lane, row = wave) over blocks row, row + 4, ...
+    uint64_t acc[kQ] = {0, 0, 0};
+    if (LDS) {
+      for (int i = tid; i < nq * cnt; i += kNT) {
+        const int s = i / cnt, bl = i - s * cnt;
+        const Query &q = sm.q[s];
+        uint64_t mm = UINT64_MAX;
+        for (int k = 0; k < q.n; ++k) {
+          if (k == q.excl) continue;
+          const uint64_t d = sm.d[bl][q.set[k]];
+          mm = d < mm ? d : mm;
+        }
+        sm.m[s][bl] = mm;
+      }
       __syncthreads();
-      for (int i = 0; i < n; ++i) {
-        evaluate(sm, sse, nplanes, nfb, g, sm.set, n, i);
-        if (tid == 0) {
-          int bp = sm.set[i];
-          uint64_t bd = sm.cost[bp];
-          for (int p = 0; p < 64; ++p) {
-            if (in_set(sm.set, n, p, i)) continue;
-            if (sm.cost[p] < bd) {
-              bd = sm.cost[p];
-              bp = p;
-            }
-          }
-          if (bp != sm.set[i]) {
-            sm.set[i] = bp;
-            sm.changed = 1;
+      for (int bl = wave; bl < cnt; bl += 4) {
+        const uint64_t d = sm.d[bl][lane];
+#pragma unroll
+        for (int s = 0; s < kQ; ++s) {
+          if (s < nq) {
+            const uint64_t mm = sm.m[s][bl];
+            acc[s] += d < mm ? d : mm;
           }
         }
-        __syncthreads();
       }
-      // every thread reads the flag before thread 0 may clear it again
-      const int changed = sm.changed;
-      __syncthreads();
-      if (!changed) break;
+    } else {
+      for (int bl = wave; bl < cnt; bl += 4) {
+        const uint64_t d = group_dist(sse, nfb, g, b0 + bl, lane);
+        for (int s = 0; s < nq; ++s) {
+          const Query &q = sm.q[s];
+          uint64_t mm = UINT64_MAX;
+          for (int k = 0; k < q.n; ++k) {
+            if (k == q.excl) continue;
+            const uint64_t e = group_dist(sse, nfb, g, b0 + bl, q.set[k]);
+            mm = e < mm ? e : mm;
+          }
+          acc[s] += d < mm ? d : mm;
+        }
+      }
     }
-    evaluate(sm, sse, nplanes, nfb, g, sm.set, n, -1);
+#pragma unroll
+    for (int s = 0; s < kQ; ++s) sm.red[wave][s][lane] = acc[s];
+    __syncthreads();
+    if (!round_totals(sm, work, g, G, nq, round)) return;
+
+    // ---- one decision per candidate set
+    if (wave < nq) {
+      const Query &q = sm.q[wave];
+      uint64_t c = sm.cost[wave][lane];
+      int p = lane;
+      if (excluded(q, lane)) {
+        c = UINT64_MAX;
+        p = 64;
+      }
+      wave_argmin(c, p);
+      if (lane == 0) {
+        sm.best_cost[wave] = c;
+        sm.best_p[wave] = p;
+      }
+    }
+    __syncthreads();
+
+    // ---- state update (thread 0; every workgroup does the same)
     if (tid == 0) {
-      uint64_t *dist = g == 0 ? out->dist_luma : out->dist_chroma;
-      int32_t *sets = g == 0 ? &out->luma[0][0] : &out->chroma[0][0];
-      dist[k] = sm.cost[sm.set[0]];  // min(m_b, D_{b,S[0]}) = m_b
-      for (int i = 0; i < 8; ++i) sets[k * 8 + i] = sm.set[i];
+      if (sm.step < 8) {
+        sm.greedy[sm.step] = sm.best_p[0];
+        sm.greedy_cost[sm.step] = sm.best_cost[0];
+        if (++sm.step == 8) {
+          for (int r = 0; r < 3; ++r) {
+            const int n = 2 << r;
+            for (int i = 0; i < 8; ++i) sm.rset[r][i] = i < n ? sm.greedy[i] : -1;
+            sm.slot[r] = sm.pass[r] = sm.changed[r] = 0;
+            sm.rdist[r] = sm.greedy_cost[n - 1];
+            sm.done[r] = refine == 0;
+          }
+        }
+      } else {
+        for (int s = 0; s < nq; ++s) {
+          const int r = sm.qowner[s], n = 2 << r, i = sm.slot[r];
+          const uint64_t cur = sm.cost[s][sm.rset[r][i]];
+          if (sm.best_cost[s] < cur) {
+            sm.rset[r][i] = sm.best_p[s];
+            sm.changed[r] = 1;
+            sm.rdist[r] = sm.best_cost[s];
+          } else {
+            sm.rdist[r] = cur;
+          }
+          if (++sm.slot[r] == n) {
+            sm.slot[r] = 0;
+            ++sm.pass[r];
+            if (!sm.changed[r] || sm.pass[r] == refine) sm.done[r] = 1;
+            sm.changed[r] = 0;
+          }
+        }
+      }
     }
     __syncthreads();
   }
+
+  if (w == 0 && tid == 0) {
+    int32_t *sets = g == 0 ? &out->luma[0][0] : &out->chroma[0][0];
+    uint64_t *dist = g == 0 ? out->dist_luma : out->dist_chroma;
+    sets[0] = sm.greedy[0];
+    for (int i = 1; i < 8; ++i) sets[i] = -1;
+    dist[0] = sm.greedy_cost[0];
+    for (int r = 0; r < 3; ++r) {
+      for (int i = 0; i < 8; ++i) sets[(r + 1) * 8 + i] = sm.rset[r][i];
+      dist[r + 1] = sm.rdist[r];
+    }
+  }
+}
+
+// Counters and the totals of rounds 0 and 1 start at zero.
+__global__ void k_preset_reset(PresetWork *work) {
+  const int t = threadIdx.x;
+  if (t < 2) work->arrive[t] = 0;
+  if (t == 0) work->failed = 0;
+  uint64_t *tot = &work->total[0][0][0][0];
+  for (int i = t; i < 2 * 2 * kQ * 64; i += blockDim.x) tot[i] = 0;
 }
 
 __global__ __launch_bounds__(kNT) void k_preset_finish(const uint64_t *__restrict__ sse,
                                                        int nplanes, int nfb, double lambda,
-                                                       PresetResult *out, uint8_t *fb_luma,
-                                                       uint8_t *fb_chroma) {
+                                                       const PresetWork *work, PresetResult *out,
+                                                       uint8_t *fb_luma, uint8_t *fb_chroma) {
   __shared__ int chosen;
+  if (work->failed) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) out->n = 0;
+    return;
+  }
   if (threadIdx.x == 0) {
     // J(N) is evaluated as written, one rounding per operation (no fused
     // multiply-add), so that equal inputs give the same choice everywhere.
 #pragma clang fp contract(off)
+    double cost[4];
     int c = 0;
     for (int k = 0; k < 4; ++k) {
-      out->cost[k] = lambda * (double)nfb * (double)k +
-                     (double)(out->dist_luma[k] + out->dist_chroma[k]);
-      if (out->cost[k] < out->cost[c]) c = k;
+      cost[k] = lambda * (double)nfb * (double)k +
+                (double)(out->dist_luma[k] + out->dist_chroma[k]);
+      if (cost[k] < cost[c]) c = k;
     }
-    out->n = 1 << c;
-    out->reserved = 0;
+    if (blockIdx.x == 0) {
+      for (int k = 0; k < 4; ++k) out->cost[k] = cost[k];
+      out->n = 1 << c;
+      out->reserved = 0;
+    }
     chosen = c;
   }
   __syncthreads();
   const int c = chosen, n = 1 << c;
-  for (int b = blockIdx.x * kNT + threadIdx.x; b < nfb; b += gridDim.x * kNT) {
-    for (int g = 0; g < 2; ++g) {
-      const int32_t *sets = g == 0 ? &out->luma[c][0] : &out->chroma[c][0];
-      int bi = 0;
+  const int b = blockIdx.x * kNT + threadIdx.x;
+  if (b >= nfb) return;
+  for (int g = 0; g < 2; ++g) {
+    const int32_t *sets = g == 0 ? &out->luma[c][0] : &out->chroma[c][0];
+    int bi = 0;
+    if (g == 0 || nplanes == 3) {
       uint64_t bd = UINT64_MAX;
       for (int i = 0; i < n; ++i) {
-        const uint64_t d = dist_of(sse, nplanes, nfb, g, b, sets[i]);
+        const uint64_t d = group_dist(sse, nfb, g, b, sets[i]);
         if (d < bd) {
           bd = d;
           bi = i;
         }
       }
-      (g == 0 ? fb_luma : fb_chroma)[b] = (uint8_t)bi;
     }
+    (g == 0 ? fb_luma : fb_chroma)[b] = (uint8_t)bi;
   }
 }
 
 }  // namespace
 
+size_t preset_workspace_bytes() { return sizeof(PresetWork); }
+
+int preset_groups(int nfb) { return min(kMaxG, (nfb + kSlice - 1) / kSlice); }
+
 hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
                                  int refine, PresetResult *out, uint8_t *fb_luma,
-                                 uint8_t *fb_chroma, hipStream_t s) {
-  hipLaunchKernelGGL(k_preset_search, dim3(2), dim3(kNT), 0, s, sse, nplanes, nfb, refine, out);
+                                 uint8_t *fb_chroma, void *workspace, hipStream_t s) {
+  PresetWork *work = static_cast<PresetWork *>(workspace);
+  const int G = preset_groups(nfb);
+  const int per = (nfb + G - 1) / G;
+  hipLaunchKernelGGL(k_preset_reset, dim3(1), dim3(256), 0, s, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // one workgroup: every thread of it needs the chosen N computed by thread 0
-  hipLaunchKernelGGL(k_preset_finish, dim3(1), dim3(kNT), 0, s, sse, nplanes, nfb, lambda, out,
-                     fb_luma, fb_chroma);
+  // 2 G <= 256 workgroups of 256 threads: all of them fit on the device at
+  // once, so every wait for the last arrival of a round ends.
+  if (per <= kSlice)
+    hipLaunchKernelGGL(k_preset_coop<true>, dim3(2 * G), dim3(kNT), 0, s, sse, nplanes, nfb, G,
+                       refine, work, out);
+  else
+    hipLaunchKernelGGL(k_preset_coop<false>, dim3(2 * G), dim3(kNT), 0, s, sse, nplanes, nfb, G,
+                       refine, work, out);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_preset_finish, dim3((nfb + kNT - 1) / kNT), dim3(kNT), 0, s, sse, nplanes,
+                     nfb, lambda, work, out, fb_luma, fb_chroma);
   return hipGetLastError();
 }
 

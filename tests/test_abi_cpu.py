@@ -125,17 +125,27 @@ def test_batch_argument_checks(lib):
 
 def test_select_presets_argument_checks(lib):
     P = C.c_void_p(0x10000)
+    W = C.c_void_p(0x20000)
+    n = lib.cdef_select_presets_workspace_bytes()
+    assert 0 < n < (1 << 20)
     f = lib.cdef_select_presets
-    assert f(None, 3, 2, 2, 1.0, 0, P, P, P, None) == -1
-    assert f(P, 3, 2, 2, 1.0, 0, None, P, P, None) == -1
-    assert f(P, 3, 2, 2, 1.0, 0, P, None, P, None) == -1
-    assert f(P, 3, 2, 2, 1.0, 0, P, P, None, None) == -1
-    assert f(P, 2, 2, 2, 1.0, 0, P, P, P, None) == -1
-    assert f(P, 3, 0, 2, 1.0, 0, P, P, P, None) == -1
-    assert f(P, 3, 2, -1, 1.0, 0, P, P, P, None) == -1
-    assert f(P, 3, 2, 2, -1.0, 0, P, P, P, None) == -1
-    assert f(P, 3, 2, 2, float("nan"), 0, P, P, P, None) == -1
-    assert f(P, 3, 2, 2, float("inf"), 0, P, P, P, None) == -1
-    assert f(P, 3, 2, 2, 1.0, -1, P, P, P, None) == -1
-    assert f(P, 3, 2, 2, 1.0, 17, P, P, P, None) == -1
-    assert f(P, 1, 4097, 4097, 1.0, 0, P, P, P, None) == -2
+
+    def call(sse=P, npl=3, fbr=2, fbc=2, lam=1.0, ref=0, res=P, fl=P, fc=P, ws=W, wsb=n):
+        return f(sse, npl, fbr, fbc, lam, ref, res, fl, fc, ws, wsb, None)
+
+    assert call(sse=None) == -1
+    assert call(res=None) == -1
+    assert call(fl=None) == -1
+    assert call(fc=None) == -1
+    assert call(ws=None) == -1
+    assert call(wsb=n - 1) == -1
+    assert call(ws=C.c_void_p(0x20008)) == -1
+    assert call(npl=2) == -1
+    assert call(fbr=0) == -1
+    assert call(fbc=-1) == -1
+    assert call(lam=-1.0) == -1
+    assert call(lam=float("nan")) == -1
+    assert call(lam=float("inf")) == -1
+    assert call(ref=-1) == -1
+    assert call(ref=17) == -1
+    assert call(npl=1, fbr=4097, fbc=4097) == -2

@@ -49,9 +49,10 @@ def test_hand_table(oracle):
 
 @pytest.mark.parametrize("nplanes,fbr,fbc,ties", [
     (3, 1, 1, False), (1, 3, 7, False), (3, 5, 9, True), (3, 17, 30, False),
-    (1, 64, 70, True), (3, 65, 70, False)])
+    (1, 64, 70, True), (3, 65, 70, False), (3, 68, 120, False), (3, 96, 100, True)])
 def test_random_tables(oracle, nplanes, fbr, fbc, ties):
-    # 64 x 70 and 65 x 70 blocks cross the 4096-block staging chunk
+    # up to 64 blocks per workgroup, 128 workgroups per group: 68 x 120 blocks
+    # (an 8K frame) fill every slice; 96 x 100 blocks no longer fit in LDS
     rng = np.random.default_rng(nplanes * 1000 + fbr * 37 + fbc)
     top = 5 if ties else 1 << 30
     sse = rng.integers(0, top, size=(nplanes, fbr, fbc, 16, 4)).astype(np.uint64)
@@ -77,9 +78,10 @@ def test_device_outputs_stay_on_device():
     res = torch.zeros(360, dtype=torch.uint8, device="cuda")
     fl = torch.full((2, 3), 255, dtype=torch.uint8, device="cuda")
     fc = torch.full((2, 3), 255, dtype=torch.uint8, device="cuda")
+    ws = cdef.preset_workspace()
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        cdef.cdef_select_presets(sse, 1e3, 2, res, fl, fc, s)
+        cdef.cdef_select_presets(sse, 1e3, 2, res, fl, fc, ws, s)
     s.synchronize()
     n = int(res[:4].cpu().numpy().view(np.int32)[0])
     assert n in (1, 2, 4, 8)
