@@ -53,6 +53,16 @@
  *  R15 skip = 1 marks an 8x8 block with no coded residual: it is copied, and
  *      so is its co-located chroma.
  *  R16 SSE counts in-frame pixels only and is per plane.
+ *  R18 A preset holds, per plane group, a skip condition bit (Section 4),
+ *      passed as bit 7 of the secondary-strength byte.  A filter block whose
+ *      in-frame 8x8 blocks are all skipped is not filtered under any preset.
+ *      Otherwise a skipped 8x8 block is filtered only when the bit is set.
+ *      Strengths (0, 0) with the bit set stand for S^(p) = 19, S^(s) = 7 with
+ *      the bit set.  19 goes through Eq. (13) and the weight parity rule like
+ *      any primary strength; since D may never be lower than floor(log2 S),
+ *      a luma block whose adjusted strength reaches 16..19 takes
+ *      floor(log2 S) = 4 as its damping for both tap groups, as the chroma
+ *      rule R13 does.
  */
 #include "cdef_oracle.h"
 
@@ -215,6 +225,7 @@ static block_params params_for(int plane, int bitdepth, int damping, int pri, in
   if (plane == 0) {
     s = cdef_oracle_adjust_strength(pri, var);
     d = damping;
+    if (s > 0 && floor_log2(s) > d) d = floor_log2(s); /* R18 */
   } else {
     s = pri;
     d = cdef_oracle_chroma_damping(damping, pri);
@@ -234,6 +245,28 @@ static void plane_geometry(const cdef_oracle_frame *f, int plane, int *pw, int *
   *ph = plane == 0 ? f->height : (f->height + 1) / 2;
 }
 
+/* R18: the preset of one plane group from a strengths entry. */
+static void preset_of(const uint8_t *st, int plane, int *pri, int *sec, int *skipcond) {
+  int sb = plane == 0 ? st[1] : st[3];
+  *pri = plane == 0 ? st[0] : st[2];
+  *sec = sb & 0x7f;
+  *skipcond = sb >> 7;
+  if (*pri == 0 && *sec == 0 && *skipcond) {
+    *pri = 19;
+    *sec = 7;
+  }
+}
+
+/* R18: every in-frame 8x8 block of filter block (fby, fbx) is skipped. */
+static int fb_skipped(const cdef_oracle_frame *f, const uint8_t *skip, int fby, int fbx) {
+  if (!skip) return 0;
+  int bcols = (f->width + 7) / 8, brows = (f->height + 7) / 8;
+  for (int by = 8 * fby; by < imin(8 * fby + 8, brows); by++)
+    for (int bx = 8 * fbx; bx < imin(8 * fbx + 8, bcols); bx++)
+      if (!skip[by * bcols + bx]) return 0;
+  return 1;
+}
+
 void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3],
                               const int64_t out_stride[3], const uint8_t *dir,
                               const int32_t *var, const uint8_t *skip, int damping,
@@ -248,13 +281,13 @@ void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3
       for (int j = 0; j < pw; j++) {
         int b = (i / bs) * bcols + (j / bs);
         int x = in->plane[p][(int64_t)i * in->stride[p] + j];
+        const uint8_t *st = strengths + 4 * ((i / fs) * fbcols + (j / fs));
+        int pri, sec, skipcond;
+        preset_of(st, p, &pri, &sec, &skipcond);
         int y;
-        if (skip && skip[b]) {
+        if (fb_skipped(in, skip, i / fs, j / fs) || (skip && skip[b] && !skipcond)) {
           y = x;
         } else {
-          const uint8_t *st = strengths + 4 * ((i / fs) * fbcols + (j / fs));
-          int pri = p == 0 ? st[0] : st[2];
-          int sec = p == 0 ? st[1] : st[3];
           block_params bp = params_for(p, in->bitdepth, damping, pri, sec, var[b]);
           y = cdef_oracle_filter_pixel(in->plane[p], in->stride[p], pw, ph, i, j, dir[b],
                                        bp.pri_s, bp.pri_d, bp.w1, bp.w2, bp.sec_s, bp.sec_d);
@@ -269,41 +302,58 @@ void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3
 
 static const int SEC_STRENGTHS[4] = {0, 1, 2, 4};
 
-void cdef_oracle_search_fb(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
-                           const uint8_t *dir, const int32_t *var, const uint8_t *skip,
-                           int damping, int fby, int fbx, uint64_t *sse) {
+/* Section 5: every candidate filters the whole filter block, as the filter
+ * would with that preset (R18), and sums squared errors against the source.
+ * Candidate (skip condition bit k, S^(p), S^(s) index) is at
+ * sse[((p * nskip + k) * 16 + S^(p)) * 4 + index]. */
+void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+                            const uint8_t *dir, const int32_t *var, const uint8_t *skip,
+                            int damping, int nskip, int fby, int fbx, uint64_t *sse) {
   int bcols = (recon->width + 7) / 8;
+  int all_skipped = fb_skipped(recon, skip, fby, fbx);
   for (int p = 0; p < recon->nplanes; p++) {
     int pw, ph, ss;
     plane_geometry(recon, p, &pw, &ph, &ss);
     int bs = 8 >> ss, fs = 64 >> ss;
     int i0 = fby * fs, j0 = fbx * fs;
     int i1 = imin(i0 + fs, ph), j1 = imin(j0 + fs, pw);
-    for (int pri = 0; pri < 16; pri++) {
-      for (int si = 0; si < 4; si++) {
-        uint64_t acc = 0;
-        for (int i = i0; i < i1; i++) {
-          for (int j = j0; j < j1; j++) {
-            int b = (i / bs) * bcols + (j / bs);
-            int x = recon->plane[p][(int64_t)i * recon->stride[p] + j];
-            int y;
-            if (skip && skip[b]) {
-              y = x;
-            } else {
-              block_params bp =
-                  params_for(p, recon->bitdepth, damping, pri, SEC_STRENGTHS[si], var[b]);
-              y = cdef_oracle_filter_pixel(recon->plane[p], recon->stride[p], pw, ph, i, j,
-                                           dir[b], bp.pri_s, bp.pri_d, bp.w1, bp.w2,
-                                           bp.sec_s, bp.sec_d);
+    for (int k = 0; k < nskip; k++) {
+      for (int pri_sig = 0; pri_sig < 16; pri_sig++) {
+        for (int si = 0; si < 4; si++) {
+          uint8_t st[4] = {(uint8_t)pri_sig, (uint8_t)(SEC_STRENGTHS[si] | (k << 7)),
+                           (uint8_t)pri_sig, (uint8_t)(SEC_STRENGTHS[si] | (k << 7))};
+          int pri, sec, skipcond;
+          preset_of(st, p, &pri, &sec, &skipcond);
+          uint64_t acc = 0;
+          for (int i = i0; i < i1; i++) {
+            for (int j = j0; j < j1; j++) {
+              int b = (i / bs) * bcols + (j / bs);
+              int x = recon->plane[p][(int64_t)i * recon->stride[p] + j];
+              int y;
+              if (all_skipped || (skip && skip[b] && !skipcond)) {
+                y = x;
+              } else {
+                block_params bp = params_for(p, recon->bitdepth, damping, pri, sec, var[b]);
+                y = cdef_oracle_filter_pixel(recon->plane[p], recon->stride[p], pw, ph, i, j,
+                                             dir[b], bp.pri_s, bp.pri_d, bp.w1, bp.w2,
+                                             bp.sec_s, bp.sec_d);
+              }
+              int64_t e =
+                  (int64_t)y - (int64_t)src->plane[p][(int64_t)i * src->stride[p] + j];
+              acc += (uint64_t)(e * e);
             }
-            int64_t e = (int64_t)y - (int64_t)src->plane[p][(int64_t)i * src->stride[p] + j];
-            acc += (uint64_t)(e * e);
           }
+          sse[((p * nskip + k) * 16 + pri_sig) * 4 + si] = acc;
         }
-        sse[(p * 16 + pri) * 4 + si] = acc;
       }
     }
   }
+}
+
+void cdef_oracle_search_fb(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+                           const uint8_t *dir, const int32_t *var, const uint8_t *skip,
+                           int damping, int fby, int fbx, uint64_t *sse) {
+  cdef_oracle_search_fb2(recon, src, dir, var, skip, damping, 1, fby, fbx, sse);
 }
 
 void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
@@ -327,27 +377,29 @@ void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame 
  * R17 Eq. (15) takes the minimum over P_luma and over P_chroma separately, as
  *     printed; B is the number of filter blocks.  The "optimal preset to add"
  *     is a candidate not yet in the set; ties go to the lowest candidate index
- *     (S^(p) * 4 + index of S^(s)).  Re-optimization replaces one preset at a
+ *     (skip condition bit * 64 + S^(p) * 4 + index of S^(s); 64 candidates
+ *     without the bit, 128 with it).  Re-optimization replaces one preset at a
  *     time by the best candidate not among the others, only when that strictly
  *     lowers the distortion. */
 
-static uint64_t group_d(const uint64_t *sse, int nplanes, int nfb, int g, int b, int p) {
-  if (g == 0) return sse[(int64_t)b * 64 + p];
+static uint64_t group_d(const uint64_t *sse, int nplanes, int nfb, int nc, int g, int b,
+                        int p) {
+  if (g == 0) return sse[(int64_t)b * nc + p];
   if (nplanes < 3) return 0;
-  return sse[((int64_t)nfb + b) * 64 + p] + sse[((int64_t)2 * nfb + b) * 64 + p];
+  return sse[((int64_t)nfb + b) * nc + p] + sse[((int64_t)2 * nfb + b) * nc + p];
 }
 
 /* sum over blocks of the minimum distortion over set[0..n), with slot `skip`
  * replaced by candidate `with` (skip < 0: no replacement; with < 0: slot dropped) */
-static uint64_t set_distortion(const uint64_t *sse, int nplanes, int nfb, int g, const int *set,
-                               int n, int skip, int with) {
+static uint64_t set_distortion(const uint64_t *sse, int nplanes, int nfb, int nc, int g,
+                               const int *set, int n, int skip, int with) {
   uint64_t total = 0;
   for (int b = 0; b < nfb; b++) {
     uint64_t m = UINT64_MAX;
     for (int i = 0; i < n; i++) {
       int p = i == skip ? with : set[i];
       if (p < 0) continue;
-      uint64_t d = group_d(sse, nplanes, nfb, g, b, p);
+      uint64_t d = group_d(sse, nplanes, nfb, nc, g, b, p);
       if (d < m) m = d;
     }
     total += m;
@@ -361,8 +413,8 @@ static int in_set(const int *set, int n, int p, int except) {
   return 0;
 }
 
-void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
-                                int refine_passes, int32_t *n_chosen, int32_t *sets_l,
+void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
+                                double lambda, int refine_passes, int32_t *n_chosen, int32_t *sets_l,
                                 int32_t *sets_c, uint64_t *dist, double *cost, uint8_t *fb_l,
                                 uint8_t *fb_c) {
   static const int NS[4] = {1, 2, 4, 8};
@@ -372,10 +424,10 @@ void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, doubl
     for (int step = 0; step < 8; step++) {
       int best = -1;
       uint64_t bestd = UINT64_MAX;
-      for (int p = 0; p < 64; p++) {
+      for (int p = 0; p < ncand; p++) {
         if (in_set(greedy, step, p, -1)) continue;
         greedy[step] = p;
-        uint64_t d = set_distortion(sse, nplanes, nfb, g, greedy, step + 1, -1, -1);
+        uint64_t d = set_distortion(sse, nplanes, nfb, ncand, g, greedy, step + 1, -1, -1);
         if (best < 0 || d < bestd) {
           bestd = d;
           best = p;
@@ -389,12 +441,12 @@ void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, doubl
       for (int pass = 0; pass < refine_passes; pass++) {
         int changed = 0;
         for (int i = 0; i < n; i++) {
-          uint64_t curd = set_distortion(sse, nplanes, nfb, g, set, n, -1, -1);
+          uint64_t curd = set_distortion(sse, nplanes, nfb, ncand, g, set, n, -1, -1);
           int bestp = set[i];
           uint64_t bestd = curd;
-          for (int p = 0; p < 64; p++) {
+          for (int p = 0; p < ncand; p++) {
             if (in_set(set, n, p, i)) continue;
-            uint64_t d = set_distortion(sse, nplanes, nfb, g, set, n, i, p);
+            uint64_t d = set_distortion(sse, nplanes, nfb, ncand, g, set, n, i, p);
             if (d < bestd) {
               bestd = d;
               bestp = p;
@@ -408,7 +460,7 @@ void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, doubl
         if (!changed) break;
       }
       for (int i = 0; i < 8; i++) best_sets[g][k][i] = set[i];
-      dist[g * 4 + k] = set_distortion(sse, nplanes, nfb, g, set, n, -1, -1);
+      dist[g * 4 + k] = set_distortion(sse, nplanes, nfb, ncand, g, set, n, -1, -1);
     }
   }
   int chosen = 0;
@@ -427,7 +479,7 @@ void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, doubl
       int bi = 0;
       uint64_t bd = UINT64_MAX;
       for (int i = 0; i < NS[chosen]; i++) {
-        uint64_t d = group_d(sse, nplanes, nfb, g, b, best_sets[g][chosen][i]);
+        uint64_t d = group_d(sse, nplanes, nfb, ncand, g, b, best_sets[g][chosen][i]);
         if (d < bd) {
           bd = d;
           bi = i;

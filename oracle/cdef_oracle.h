@@ -73,7 +73,9 @@ int cdef_oracle_filter_pixel(const uint16_t *p, int64_t stride, int pw, int ph, 
 /* Filter a whole frame (Sections 3-4).  dir/var from cdef_oracle_find_dir,
  * skip [ceil(h/8)][ceil(w/8)] (NULL = no skipped blocks), strengths
  * [ceil(h/64)][ceil(w/64)][4] = (pri_y, sec_y, pri_uv, sec_uv) in the 8-bit
- * domain, damping = luma D (3..6). */
+ * domain, bit 7 of sec_y / sec_uv = the luma / chroma skip condition bit
+ * (with strengths 0, 0 it selects the (19, 7) preset), damping = luma D
+ * (3..6).  A filter block whose 8x8 blocks are all skipped is copied. */
 void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3],
                               const int64_t out_stride[3], const uint8_t *dir,
                               const int32_t *var, const uint8_t *skip, int damping,
@@ -86,6 +88,12 @@ void cdef_oracle_search_fb(const cdef_oracle_frame *recon, const cdef_oracle_fra
                            const uint8_t *dir, const int32_t *var, const uint8_t *skip,
                            int damping, int fby, int fbx, uint64_t *sse);
 
+/* The same with nskip = 2: also the 64 presets with the skip condition bit
+ * set (Section 5, 128 combinations).  sse is [nplanes][nskip][16][4]. */
+void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+                            const uint8_t *dir, const int32_t *var, const uint8_t *skip,
+                            int damping, int nskip, int fby, int fbx, uint64_t *sse);
+
 /* The whole-frame search: find_dir, then every filter block.
  * sse is [nplanes][ceil(h/64)][ceil(w/64)][16][4]; dir/var as find_dir. */
 void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
@@ -93,7 +101,8 @@ void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame 
                         uint8_t *dir, int32_t *var);
 
 /* Section 5, Eq. (15): preset selection on an SSE table sse
- * [nplanes][nfb][64] (as cdef_oracle_search, filter blocks flattened).
+ * [nplanes][nfb][ncand] (as cdef_oracle_search / search_fb2, filter blocks
+ * flattened; ncand = 64 or 128).
  * Luma distortion D^l[b][p] = plane 0; chroma D^c[b][p] = planes 1 + 2 (0 for
  * nplanes = 1).  For each group a greedy sequence of 8 presets is built (each
  * step adds the candidate that most lowers sum_b min over the set, lowest
@@ -104,8 +113,8 @@ void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame 
  * of minimal J is chosen.  Outputs: n_chosen; sets_l/sets_c [4][8] (slot
  * entries >= N are -1); dist [2][4] (luma, chroma; N = 1, 2, 4, 8); cost[4];
  * per-block preset slots fb_l / fb_c (lowest slot on ties) for N*. */
-void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
-                                int refine_passes, int32_t *n_chosen, int32_t *sets_l,
+void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
+                                double lambda, int refine_passes, int32_t *n_chosen, int32_t *sets_l,
                                 int32_t *sets_c, uint64_t *dist, double *cost, uint8_t *fb_l,
                                 uint8_t *fb_c);
 

@@ -62,8 +62,11 @@ def lib():
         L.cdef_oracle_search.argtypes = [C.POINTER(OracleFrame), C.POINTER(OracleFrame), P,
                                          C.c_int, P, P, P]
         L.cdef_oracle_search.restype = None
-        L.cdef_oracle_select_presets.argtypes = [P, C.c_int, C.c_int, C.c_double, C.c_int, P, P,
-                                                 P, P, P, P, P]
+        L.cdef_oracle_search_fb2.argtypes = [C.POINTER(OracleFrame), C.POINTER(OracleFrame), P,
+                                             P, P, C.c_int, C.c_int, C.c_int, C.c_int, P]
+        L.cdef_oracle_search_fb2.restype = None
+        L.cdef_oracle_select_presets.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
+                                                 P, P, P, P, P, P, P]
         L.cdef_oracle_select_presets.restype = None
         _lib = L
     return _lib
@@ -145,8 +148,9 @@ def filter_frame(planes: Sequence[np.ndarray], width: int, height: int, bitdepth
 
 def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, height: int,
                bitdepth: int, dir: np.ndarray, var: np.ndarray, skip: Optional[np.ndarray],
-               damping: int, fbs, threads: int = 1) -> np.ndarray:
-    """SSE tables [len(fbs)][nplanes][16][4] for the listed (fby, fbx) blocks.
+               damping: int, fbs, threads: int = 1, full: bool = False) -> np.ndarray:
+    """SSE tables [len(fbs)][nplanes][16][4] for the listed (fby, fbx) blocks,
+    or [len(fbs)][nplanes][2][16][4] with full=True (skip condition bit 0, 1).
 
     dir/var must come from find_dir (the oracle's own).  ctypes releases the
     GIL during the call, so a thread pool runs filter blocks in parallel."""
@@ -158,13 +162,14 @@ def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: in
     var = np.ascontiguousarray(var, dtype=np.int32)
     sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
     fbs = list(fbs)
-    out = np.zeros((len(fbs), len(recon), 16, 4), dtype=np.uint64)
+    nskip = 2 if full else 1
+    out = np.zeros((len(fbs), len(recon), nskip, 16, 4), dtype=np.uint64)
     L = lib()
 
     def one(k):
         by, bx = fbs[k]
-        L.cdef_oracle_search_fb(C.byref(fr), C.byref(fs), dir.ctypes.data, var.ctypes.data,
-                                _ptr(sk), damping, by, bx, out[k].ctypes.data)
+        L.cdef_oracle_search_fb2(C.byref(fr), C.byref(fs), dir.ctypes.data, var.ctypes.data,
+                                 _ptr(sk), damping, nskip, by, bx, out[k].ctypes.data)
 
     if threads <= 1:
         for k in range(len(fbs)):
@@ -172,25 +177,31 @@ def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: in
     else:
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(one, range(len(fbs))))
-    return out
+    return out if full else out[:, :, 0]
 
 
 def search(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, height: int,
-           bitdepth: int, skip: Optional[np.ndarray], damping: int, threads: int = 1):
-    """Whole-frame search: (sse [nplanes][fbr][fbc][16][4], dir, var)."""
+           bitdepth: int, skip: Optional[np.ndarray], damping: int, threads: int = 1,
+           full: bool = False):
+    """Whole-frame search: (sse, dir, var); sse is [nplanes][fbr][fbc][16][4],
+    or [nplanes][fbr][fbc][2][16][4] with full=True."""
     d, v = find_dir(recon[0], bitdepth)
     fbr, fbc = (height + 63) // 64, (width + 63) // 64
     fbs = [(by, bx) for by in range(fbr) for bx in range(fbc)]
-    t = search_fbs(recon, src, width, height, bitdepth, d, v, skip, damping, fbs, threads)
-    sse = t.reshape(fbr, fbc, len(recon), 16, 4).transpose(2, 0, 1, 3, 4)
+    t = search_fbs(recon, src, width, height, bitdepth, d, v, skip, damping, fbs, threads, full)
+    t = t.reshape((fbr, fbc, len(recon)) + t.shape[2:])
+    sse = np.moveaxis(t, 2, 0)
     return np.ascontiguousarray(sse), d, v
 
 
 def select_presets(sse: np.ndarray, lam: float, refine_passes: int = 0) -> dict:
-    """Eq. (15) preset selection on an SSE table [nplanes][fbr][fbc][16][4]."""
+    """Eq. (15) preset selection on an SSE table [nplanes][fbr][fbc][16][4]
+    (64 candidates) or [nplanes][fbr][fbc][2][16][4] (128 candidates)."""
     sse = np.ascontiguousarray(sse, dtype=np.uint64)
     nplanes = sse.shape[0]
     nfb = int(np.prod(sse.shape[1:3]))
+    ncand = int(np.prod(sse.shape[3:]))
+    assert ncand in (64, 128)
     n = np.zeros(1, np.int32)
     sl = np.zeros((4, 8), np.int32)
     sc = np.zeros((4, 8), np.int32)
@@ -198,8 +209,8 @@ def select_presets(sse: np.ndarray, lam: float, refine_passes: int = 0) -> dict:
     cost = np.zeros(4, np.float64)
     fl = np.zeros(nfb, np.uint8)
     fc = np.zeros(nfb, np.uint8)
-    lib().cdef_oracle_select_presets(sse.ctypes.data, nplanes, nfb, float(lam), refine_passes,
-                                     n.ctypes.data, sl.ctypes.data, sc.ctypes.data,
+    lib().cdef_oracle_select_presets(sse.ctypes.data, nplanes, nfb, ncand, float(lam),
+                                     refine_passes, n.ctypes.data, sl.ctypes.data, sc.ctypes.data,
                                      dist.ctypes.data, cost.ctypes.data, fl.ctypes.data,
                                      fc.ctypes.data)
     shape = sse.shape[1:3]
