@@ -72,13 +72,19 @@ typedef struct {
   int64_t stride[3];
 } cdef_frame_out;
 
-/* Strengths of one 64x64 filter block, 8-bit domain.  Section 3.2 gives the
- * ranges: pri 0..15, sec in {0, 1, 2, 4}.  They are read on the device; a
- * value out of range is a contract violation (the kernel masks pri to 4
- * bits and treats sec > 4 as 4, and stays memory-safe). */
+/* The preset of one 64x64 filter block, 8-bit domain (Sections 3.2 and 4).
+ * Strength ranges: pri 0..15, sec in {0, 1, 2, 4}.  Bit 7 of sec_y / sec_uv
+ * is the luma / chroma skip condition bit (CDEF_SKIP_CONDITION): with it, the
+ * block's skipped 8x8 blocks are filtered too, and strengths (0, 0) then mean
+ * S^(p) = 19, S^(s) = 7.  A filter block whose in-frame 8x8 blocks are all
+ * skipped is never filtered.  The bytes are read on the device; a value out
+ * of range is a contract violation (the kernel masks pri to 4 bits and
+ * treats sec > 4 as 4, and stays memory-safe). */
 typedef struct {
   uint8_t pri_y, sec_y, pri_uv, sec_uv;
 } cdef_strength;
+
+#define CDEF_SKIP_CONDITION 0x80
 
 /* Direction search, Section 2 and Algorithm 1, on the luma plane of `f`.
  *   dir[b]: the direction 0..7 that minimizes E_d^2 of Eq. (2) (ties go to
@@ -98,9 +104,13 @@ cdef_status cdef_find_dir(const cdef_frame *f, uint8_t *dir, int32_t *var, void 
  *   in, out:  same geometry; out must not overlap in.
  *   dir, var: from cdef_find_dir on `in`.
  *   skip8x8:  1 = block has no coded residual and is copied (its co-located
- *             chroma too); NULL means no block is skipped.
+ *             chroma too) unless its filter block's preset has the skip
+ *             condition bit; NULL means no block is skipped.
  *   damping:  luma D, 3..6; chroma uses max(D - 1, floor(log2 pri_uv)).
- *   fb:       per-filter-block strengths [ceil(h/64)][ceil(w/64)].
+ *   fb:       per-filter-block presets [ceil(h/64)][ceil(w/64)].
+ * A luma block whose adjusted primary strength reaches 16..19 (only the
+ * (19, 7) preset can) uses damping max(D, floor(log2 S)), since D may never be
+ * below floor(log2 S) (Section 3.2).
  * Out-of-frame taps are ignored (Section 3.2); every output pixel is computed
  * from unfiltered input.
  * Errors: as cdef_find_dir, plus CDEF_E_INVAL for damping outside 3..6, a null
@@ -125,26 +135,36 @@ cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src
                                   const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
                                   uint8_t *dir, int32_t *var, void *stream);
 
+/* The full encoder search of Section 5: the 16 x 4 x 2 = 128 combinations of
+ * S^(p), S^(s) and the skip condition bit.  Entry (k, S^(p), S^(s)) is the SSE
+ * of the filter block filtered as cdef_filter_frame would with that preset
+ * (k = 1: skip condition bit set; (1, 0, 0) is the (19, 7) preset).
+ *   sse: uint64 [nplanes][ceil(h/64)][ceil(w/64)][2][16][4].
+ * Other arguments and errors as cdef_search_strengths. */
+cdef_status cdef_search_strengths128(const cdef_frame *recon, const cdef_frame *src,
+                                     const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
+                                     uint8_t *dir, int32_t *var, void *stream);
+
 /* ---- Batches ----------------------------------------------------------------
  * Many frames -- of any size, bit depth 8 or 10 and damping -- in one launch
- * over all their 64x64 filter blocks.  Each job is either the strength
- * search of cdef_search_strengths or the direction search + filter of one
- * frame at its own per-filter-block strengths (cdef_find_dir followed by
- * cdef_filter_frame, fused).  Results are bit-identical to the per-frame
+ * over all their 64x64 filter blocks.  Each job is the strength search of
+ * cdef_search_strengths, the full search of cdef_search_strengths128, or the
+ * direction search + filter of one frame at its own per-filter-block presets
+ * (cdef_find_dir followed by cdef_filter_frame, fused).  Results are bit-identical to the per-frame
  * entry points. */
-enum { CDEF_MODE_SEARCH = 0, CDEF_MODE_FILTER = 1 };
+enum { CDEF_MODE_SEARCH = 0, CDEF_MODE_FILTER = 1, CDEF_MODE_SEARCH128 = 2 };
 
 typedef struct {
   cdef_frame recon;          /* input frame */
-  cdef_frame src;            /* search: the source frame; filter: ignored */
+  cdef_frame src;            /* searches: the source frame; filter: ignored */
   cdef_frame_out out;        /* filter: output planes (must not overlap recon); search: ignored */
   const uint8_t *skip8x8;    /* NULL = no skipped block */
   const cdef_strength *fb;   /* filter: per-filter-block strengths; search: ignored */
-  uint64_t *sse;             /* search: table as cdef_search_strengths; filter: ignored */
+  uint64_t *sse;             /* searches: table as cdef_search_strengths(128); filter: ignored */
   uint8_t *dir;              /* optional direction-search outputs (both or neither) */
   int32_t *var;
   int32_t damping;           /* luma D, 3..6 */
-  int32_t mode;              /* CDEF_MODE_SEARCH or CDEF_MODE_FILTER */
+  int32_t mode;              /* CDEF_MODE_SEARCH, CDEF_MODE_SEARCH128 or CDEF_MODE_FILTER */
 } cdef_job;
 
 /* What cdef_batch_prepare leaves for cdef_batch_launch (host memory, owned by
@@ -193,8 +213,10 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream);
 
 /* ---- Preset selection -------------------------------------------------------
  * Section 5, Eq. (15): choose the frame's presets from a strength-search SSE
- * table.  Candidates are the 64 pairs, numbered p = S^(p) * 4 + index of
- * S^(s) (order 0, 1, 2, 4) as in the table.  D^luma_{b,p} is plane 0,
+ * table.  Candidates are numbered as the table's last dimensions: p =
+ * S^(p) * 4 + index of S^(s) (order 0, 1, 2, 4) for the 64-combination table
+ * of cdef_search_strengths, plus 64 * skip condition bit for the 128 of
+ * cdef_search_strengths128.  D^luma_{b,p} is plane 0,
  * D^chroma_{b,p} the sum of planes 1 and 2 (0 for 4:0:0).  For luma and for
  * chroma a greedy sequence of 8 presets is built, each step adding the
  * candidate not yet chosen that most lowers sum_b min over the chosen set
@@ -211,7 +233,7 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream);
 typedef struct {
   int32_t n;              /* chosen number of presets N*: 1, 2, 4 or 8 */
   int32_t reserved;
-  int32_t luma[4][8];     /* preset candidates for N = 1, 2, 4, 8; slots >= N hold -1 */
+  int32_t luma[4][8];     /* candidates chosen for N = 1, 2, 4, 8; slots >= N hold -1 */
   int32_t chroma[4][8];
   uint64_t dist_luma[4];  /* sum over blocks of the minimum luma distortion, N = 1, 2, 4, 8 */
   uint64_t dist_chroma[4];
@@ -222,7 +244,9 @@ typedef struct {
  * table size; under 1 MiB). */
 size_t cdef_select_presets_workspace_bytes(void);
 
-/* sse:       device, uint64 [nplanes][fb_rows][fb_cols][16][4] (cdef_search_strengths).
+/* sse:       device, uint64 [nplanes][fb_rows][fb_cols][ncand] as written by
+ *            cdef_search_strengths (ncand = 64) or cdef_search_strengths128
+ *            (ncand = 128).
  * lambda:    rate multiplier, finite and >= 0.  refine_passes: 0..16.
  * result:    device pointer, written by the kernels.  result->n == 0 reports
  *            that the selection could not complete (its workgroups could not
@@ -233,11 +257,13 @@ size_t cdef_select_presets_workspace_bytes(void);
  *            256-byte aligned, owned by the caller; it must not be shared by
  *            calls that may run at the same time.
  * Errors: CDEF_E_INVAL for null pointers, a short or misaligned workspace,
- * nplanes not 1 or 3, sizes < 1, a bad lambda or refine_passes;
+ * nplanes not 1 or 3, ncand not 64 or 128, sizes < 1, a bad lambda or
+ * refine_passes;
  * CDEF_E_UNSUPPORTED for more than 2^24 filter blocks.  Three kernel launches
  * on `stream`, no allocation, no host synchronization. */
 cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
-                                int32_t fb_cols, double lambda, int32_t refine_passes,
+                                int32_t fb_cols, int32_t ncand, double lambda,
+                                int32_t refine_passes,
                                 cdef_preset_result *result, uint8_t *fb_luma,
                                 uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
                                 void *stream);

@@ -28,6 +28,7 @@ EXPORTS = (
     "cdef_find_dir",
     "cdef_filter_frame",
     "cdef_search_strengths",
+    "cdef_search_strengths128",
     "cdef_batch_workspace_bytes",
     "cdef_batch_prepare",
     "cdef_batch_launch",
@@ -39,6 +40,8 @@ EXPORTS = (
 )
 MODE_SEARCH = 0
 MODE_FILTER = 1
+MODE_SEARCH128 = 2
+SKIP_CONDITION = 0x80  # bit 7 of a secondary-strength byte
 
 
 class CdefFrame(C.Structure):
@@ -120,6 +123,8 @@ def load(path: str = LIB_PATH):
     L.cdef_search_strengths.argtypes = [C.POINTER(CdefFrame), C.POINTER(CdefFrame), P,
                                         C.c_int32, P, P, P, P]
     L.cdef_search_strengths.restype = C.c_int
+    L.cdef_search_strengths128.argtypes = L.cdef_search_strengths.argtypes
+    L.cdef_search_strengths128.restype = C.c_int
     L.cdef_batch_workspace_bytes.argtypes = [C.c_int32]
     L.cdef_batch_workspace_bytes.restype = C.c_size_t
     L.cdef_batch_prepare.argtypes = [C.POINTER(CdefJob), C.c_int32, P, P, C.c_size_t,
@@ -129,8 +134,8 @@ def load(path: str = LIB_PATH):
     L.cdef_batch_launch.restype = C.c_int
     L.cdef_job_validate.argtypes = [C.POINTER(CdefJob)]
     L.cdef_job_validate.restype = C.c_int
-    L.cdef_select_presets.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
-                                      P, P, P, P, C.c_size_t, P]
+    L.cdef_select_presets.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                      C.c_int32, P, P, P, P, C.c_size_t, P]
     L.cdef_select_presets_workspace_bytes.argtypes = []
     L.cdef_select_presets_workspace_bytes.restype = C.c_size_t
     L.cdef_select_presets.restype = C.c_int
@@ -231,6 +236,14 @@ def cdef_search_strengths(recon: Frame, src: Frame, skip, damping: int, sse, dir
     _check(st, "cdef_search_strengths")
 
 
+def cdef_search_strengths128(recon: Frame, src: Frame, skip, damping: int, sse, dir=None,
+                             var=None, stream=None) -> None:
+    st = load().cdef_search_strengths128(C.byref(recon.c_struct()), C.byref(src.c_struct()),
+                                         _ptr(skip), damping, _ptr(sse), _ptr(dir), _ptr(var),
+                                         _stream_handle(stream))
+    _check(st, "cdef_search_strengths128")
+
+
 # ---- allocating conveniences -------------------------------------------------
 
 def find_dir(frame: Frame, stream=None):
@@ -249,16 +262,21 @@ def filter_frame(frame: Frame, dir, var, skip, damping: int, fb, stream=None):
     return outs
 
 
-def search_strengths(recon: Frame, src: Frame, skip, damping: int, want_dir=False, stream=None):
+def search_strengths(recon: Frame, src: Frame, skip, damping: int, want_dir=False, stream=None,
+                     full=False):
+    """SSE table [nplanes][fbr][fbc][16][4], or with full=True the 128
+    combinations [nplanes][fbr][fbc][2][16][4] (skip condition bit 0, 1)."""
     import torch
     dev = recon.planes[0].device
     fbr, fbc = recon.fb_shape
-    sse = torch.empty((recon.nplanes, fbr, fbc, 16, 4), dtype=torch.int64, device=dev)
+    shape = (recon.nplanes, fbr, fbc) + ((2, 16, 4) if full else (16, 4))
+    sse = torch.empty(shape, dtype=torch.int64, device=dev)
     d = v = None
     if want_dir:
         d = torch.empty(recon.block_shape, dtype=torch.uint8, device=dev)
         v = torch.empty(recon.block_shape, dtype=torch.int32, device=dev)
-    cdef_search_strengths(recon, src, skip, damping, sse, d, v, stream)
+    fn = cdef_search_strengths128 if full else cdef_search_strengths
+    fn(recon, src, skip, damping, sse, d, v, stream)
     return (sse, d, v) if want_dir else sse
 
 
@@ -274,12 +292,12 @@ def _out_struct(out_planes) -> CdefFrameOut:
 
 
 def make_search_job(recon: Frame, src: Frame, skip, damping: int, sse, dir=None,
-                    var=None) -> CdefJob:
+                    var=None, full=False) -> CdefJob:
     j = CdefJob()
     j.recon, j.src = recon.c_struct(), src.c_struct()
     j.skip8x8, j.sse = _ptr(skip), _ptr(sse)
     j.dir, j.var = _ptr(dir), _ptr(var)
-    j.damping, j.mode = damping, MODE_SEARCH
+    j.damping, j.mode = damping, MODE_SEARCH128 if full else MODE_SEARCH
     return j
 
 
@@ -311,8 +329,9 @@ class Batch:
         self.workspace = None
         self.staging = None
 
-    def add_search(self, recon: Frame, src: Frame, skip, damping: int, sse, dir=None, var=None):
-        return self.add_job(make_search_job(recon, src, skip, damping, sse, dir, var),
+    def add_search(self, recon: Frame, src: Frame, skip, damping: int, sse, dir=None, var=None,
+                   full=False):
+        return self.add_job(make_search_job(recon, src, skip, damping, sse, dir, var, full),
                             (recon, src, skip, sse, dir, var))
 
     def add_filter(self, recon: Frame, out_planes, skip, damping: int, fb, dir=None, var=None):
@@ -357,8 +376,13 @@ class Batch:
 
 def cdef_select_presets(sse, lam: float, refine_passes: int, result, fb_luma, fb_chroma,
                         workspace, stream=None) -> None:
+    """sse: [nplanes][fbr][fbc][16][4] (64 candidates) or [..][2][16][4] (128)."""
     nplanes, fbr, fbc = sse.shape[0], sse.shape[1], sse.shape[2]
-    st = load().cdef_select_presets(_ptr(sse), nplanes, fbr, fbc, float(lam), refine_passes,
+    ncand = 1
+    for n in sse.shape[3:]:
+        ncand *= n
+    st = load().cdef_select_presets(_ptr(sse), nplanes, fbr, fbc, ncand, float(lam),
+                                    refine_passes,
                                     _ptr(result), _ptr(fb_luma), _ptr(fb_chroma),
                                     _ptr(workspace), workspace.numel() * workspace.element_size(),
                                     _stream_handle(stream))

@@ -13,6 +13,9 @@
 static_assert(sizeof(cdef_preset_result) == sizeof(cdef::PresetResult), "preset result layout");
 static_assert(offsetof(cdef_preset_result, cost) == offsetof(cdef::PresetResult, cost),
               "preset result layout");
+static_assert(CDEF_MODE_SEARCH == cdef::kModeSearch && CDEF_MODE_FILTER == cdef::kModeFilter &&
+                  CDEF_MODE_SEARCH128 == cdef::kModeSearchFull,
+              "job modes");
 
 namespace {
 
@@ -84,7 +87,8 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
     o->rec[p] = r.plane[p];
     o->rstride[p] = (int32_t)r.stride[p];
   }
-  if (j->mode == CDEF_MODE_SEARCH) {
+  const bool search = j->mode == CDEF_MODE_SEARCH || j->mode == CDEF_MODE_SEARCH128;
+  if (search) {
     FrameDesc s;
     st = check_frame(&j->src, &s);
     if (st != CDEF_OK) return st;
@@ -130,8 +134,7 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
   bool al = true;
   for (int p = 0; p < r.nplanes; ++p) {
     al = al && ((uintptr_t)o->rec[p] & 15) == 0 && (o->rstride[p] & 7) == 0;
-    if (j->mode == CDEF_MODE_SEARCH)
-      al = al && ((uintptr_t)o->src[p] & 15) == 0 && (o->sstride[p] & 7) == 0;
+    if (search) al = al && ((uintptr_t)o->src[p] & 15) == 0 && (o->sstride[p] & 7) == 0;
   }
   o->flags = al ? cdef::kAligned16 : 0;
   return CDEF_OK;
@@ -176,9 +179,11 @@ cdef_status cdef_filter_frame(const cdef_frame *in, const cdef_frame_out *out, c
                                       (hipStream_t)stream));
 }
 
-cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src,
-                                  const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
-                                  uint8_t *dir, int32_t *var, void *stream) {
+namespace {
+
+cdef_status search_one(const cdef_frame *recon, const cdef_frame *src, const uint8_t *skip8x8,
+                       int32_t damping, uint64_t *sse, uint8_t *dir, int32_t *var, int32_t mode,
+                       void *stream) {
   if (!recon || !src) return CDEF_E_INVAL;
   cdef_job j;
   memset(&j, 0, sizeof(j));
@@ -189,11 +194,25 @@ cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src
   j.dir = dir;
   j.var = var;
   j.damping = damping;
-  j.mode = CDEF_MODE_SEARCH;
+  j.mode = mode;
   cdef::JobDesc d;
   const cdef_status st = make_job(&j, &d);
   if (st != CDEF_OK) return st;
   return from_hip(cdef::launch_fused_one(d, (hipStream_t)stream));
+}
+
+}  // namespace
+
+cdef_status cdef_search_strengths(const cdef_frame *recon, const cdef_frame *src,
+                                  const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
+                                  uint8_t *dir, int32_t *var, void *stream) {
+  return search_one(recon, src, skip8x8, damping, sse, dir, var, CDEF_MODE_SEARCH, stream);
+}
+
+cdef_status cdef_search_strengths128(const cdef_frame *recon, const cdef_frame *src,
+                                     const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
+                                     uint8_t *dir, int32_t *var, void *stream) {
+  return search_one(recon, src, skip8x8, damping, sse, dir, var, CDEF_MODE_SEARCH128, stream);
 }
 
 cdef_status cdef_job_validate(const cdef_job *job) {
@@ -252,7 +271,8 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
 size_t cdef_select_presets_workspace_bytes(void) { return cdef::preset_workspace_bytes(); }
 
 cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
-                                int32_t fb_cols, double lambda, int32_t refine_passes,
+                                int32_t fb_cols, int32_t ncand, double lambda,
+                                int32_t refine_passes,
                                 cdef_preset_result *result, uint8_t *fb_luma,
                                 uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
                                 void *stream) {
@@ -260,12 +280,14 @@ cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb
   if (workspace_bytes < cdef::preset_workspace_bytes() || ((uintptr_t)workspace & 255))
     return CDEF_E_INVAL;
   if (nplanes != 1 && nplanes != 3) return CDEF_E_INVAL;
+  if (ncand != 64 && ncand != 128) return CDEF_E_INVAL;
   if (fb_rows < 1 || fb_cols < 1) return CDEF_E_INVAL;
   if (!(lambda >= 0.0) || !isfinite(lambda)) return CDEF_E_INVAL;
   if (refine_passes < 0 || refine_passes > 16) return CDEF_E_INVAL;
   const int64_t nfb = (int64_t)fb_rows * fb_cols;
   if (nfb > (1 << 24)) return CDEF_E_UNSUPPORTED;
-  return from_hip(cdef::launch_select_presets(sse, nplanes, (int)nfb, lambda, refine_passes,
+  return from_hip(cdef::launch_select_presets(sse, nplanes, (int)nfb, ncand, lambda,
+                                              refine_passes,
                                               reinterpret_cast<cdef::PresetResult *>(result),
                                               fb_luma, fb_chroma, workspace,
                                               (hipStream_t)stream));

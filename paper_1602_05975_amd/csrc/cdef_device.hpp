@@ -169,6 +169,41 @@ __device__ __forceinline__ uint64_t adjusted_strengths(int var) {
   return t;
 }
 
+// Eq. (13) for one signaled strength s (0..19).
+__device__ __forceinline__ int adjust_strength(int s, int var) {
+  if (var < 1024) return 0;
+  const int q = var >> 16;
+  const int i = q == 0 ? 0 : min(floor_log2(q), 12);
+  return (s * (4 + i) + 8) >> 4;
+}
+
+// Section 4: the preset of one plane group from its two strength bytes:
+// primary in the low 4 bits, secondary in bits 0-6 (values above 4 act as
+// 4), the skip condition bit in bit 7.  Strengths 0, 0 with the bit set
+// stand for S^(p) = 19, S^(s) = 7.
+struct Preset {
+  int pri, sec;
+  bool skipcond;
+};
+__device__ __forceinline__ Preset decode_preset(int pri_byte, int sec_byte) {
+  Preset p;
+  p.pri = pri_byte & 15;
+  p.sec = min(sec_byte & 0x7f, 4);
+  p.skipcond = (sec_byte & 0x80) != 0;
+  if (p.pri == 0 && p.sec == 0 && p.skipcond) {
+    p.pri = 19;
+    p.sec = 7;
+  }
+  return p;
+}
+
+// Luma damping of a block filtered with adjusted primary strength s: D,
+// raised to floor(log2 s) when lower (D may never be below it; only the
+// strength 19 of the special preset can reach 16 and up).
+__device__ __forceinline__ int luma_damping(int D, int s) {
+  return s > 0 ? max(D, floor_log2(s)) : D;
+}
+
 // ---- Tile staging ---------------------------------------------------------
 // Copies rows y0-2 .. y0+TH+1 and columns x0-2 .. x0+TW+1 of a plane into an
 // LDS tile whose column COL0 holds frame column x0.  Positions outside the

@@ -15,7 +15,7 @@ struct FrameDesc {
   int nplanes;        // 1 (4:0:0) or 3 (4:2:0)
 };
 
-enum JobMode : int32_t { kModeSearch = 0, kModeFilter = 1 };
+enum JobMode : int32_t { kModeSearch = 0, kModeFilter = 1, kModeSearchFull = 2 };
 enum JobFlags : int32_t { kAligned16 = 1 };
 
 // One frame of work as the fused kernel reads it (kernel argument for a
@@ -27,7 +27,7 @@ struct JobDesc {
   uint16_t *out[3];        // filter mode
   const uint8_t *skip;     // may be null
   const uint8_t *strengths;  // filter mode: [fbr][fbc][4]
-  uint64_t *sse;           // search mode
+  uint64_t *sse;           // search modes: [nplanes][fbr][fbc][64] (full: [..][2][64])
   uint8_t *dir;            // optional
   int32_t *var;            // optional
   int32_t rstride[3], sstride[3], ostride[3];
@@ -62,8 +62,8 @@ struct PresetResult {
 };
 
 size_t preset_workspace_bytes();
-hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
-                                 int refine, PresetResult *out, uint8_t *fb_luma,
+hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
+                                 double lambda, int refine, PresetResult *out, uint8_t *fb_luma,
                                  uint8_t *fb_chroma, void *workspace, hipStream_t s);
 
 }  // namespace cdef

@@ -4,7 +4,9 @@
 //  * search (Section 5): direction search (Section 2, Algorithm 1), the
 //    constrained filter (Section 3) under all 64 (S^(p), S^(s)) pairs and the
 //    per-filter-block distortion D_{b,p} = ||s - d||^2 for every plane, with
-//    filtered pixels never leaving registers;
+//    filtered pixels never leaving registers; the full search adds the 64
+//    presets with the skip condition bit set (Section 4: skipped 8x8 blocks
+//    filtered too; strengths 0, 0 standing for 19, 7), 128 in all;
 //  * filter: direction search and the filter (Eq. 7-13) at the block's own
 //    strengths, writing the filtered planes.
 //
@@ -29,7 +31,15 @@
 //    round/clamp/square-accumulate;
 //  * the 64 per-lane accumulators are reduced across the wave by a
 //    transposing butterfly built from lane swaps and DPP moves (lane k ends
-//    with pair k), then across waves in LDS.
+//    with pair k), then across waves in LDS;
+//  * the full search runs the same tasks a second time over the skipped
+//    blocks, into separate sums, and evaluates (19, 7) in the slot of the
+//    pair (0, 0), whose unfiltered distortion is summed while wave 0 runs
+//    the direction search.  By
+//    8x8 block the distortion splits: with the bit, D = (blocks with residual
+//    at p) + (skipped blocks at p); without it, (blocks with residual at p) +
+//    (skipped blocks unfiltered); a filter block with every block skipped
+//    is never filtered.
 #include "cdef_device.hpp"
 #include "cdef_launch.hpp"
 
@@ -155,14 +165,51 @@ __device__ __forceinline__ void secondaries(const Taps &t, int c, int damp, s16x
   Q[3] = secondary(t, splat32(4u << c), splat32((uint32_t)(damp - 2)));
 }
 
+// The special preset (Section 4) on a luma task: S^(p) = 19 adjusted per
+// block by Eq. (13) (a19A, a19B), S^(s) = 7, each block's damping raised to
+// floor(log2 S) when lower.
+__device__ __forceinline__ int luma_special(const Taps &t, int a19A, int a19B, int c, int D,
+                                            int acc) {
+  const int dA = luma_damping(D, a19A), dB = luma_damping(D, a19B);
+  const uint32_t sp = ((uint32_t)a19A << c) | ((uint32_t)a19B << (16 + c));
+  const uint32_t sh = (uint32_t)(a19A ? dA - floor_log2(a19A) : 0) |
+                      ((uint32_t)(a19B ? dB - floor_log2(a19B) : 0) << 16);
+  const uint32_t w1 = ((a19A & 1) ? 3u : 4u) | (((a19B & 1) ? 3u : 4u) << 16);
+  const uint32_t w2 = ((a19A & 1) ? 3u : 2u) | (((a19B & 1) ? 3u : 2u) << 16);
+  u16x2 a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
+  const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
+  const s16x2 Q = secondary(t, splat32(7u << c), (uint32_t)(dA - 2) | ((uint32_t)(dB - 2) << 16));
+  return pair_both(t, P, Q, acc);
+}
+
+// The special preset on a chroma task: 19 (odd: weights 3, 3) and 7 at the
+// chroma damping max(D - 1, floor(log2 19) = 4).
+__device__ __forceinline__ int chroma_special(const Taps &t, int c, int D, int acc) {
+  const int Dc = max(D - 1, 4);
+  u16x2 a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32((uint32_t)(Dc - 4)));
+  const s16x2 P = group_sum(t, a, 0, splat32(19u << c), splat32(3), splat32(3));
+  const s16x2 Q = secondary(t, splat32(7u << c), splat32((uint32_t)(Dc - 2)));
+  return pair_both(t, P, Q, acc);
+}
+
 // Luma task: 2 blocks (lo/hi half) with per-block adjusted primary
 // strengths (Eq. 13).  Per-strength parameters are wave-uniform 32-bit
 // scalars (low half: block A, high half: block B).
-__device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t adjB, int c, int D,
-                                          int (&acc)[64]) {
+template <bool FULL>
+__device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t adjB, int a19A,
+                                          int a19B, int c, int D, int (&acc)[64]) {
+  // pair (0, 0) filters nothing; in the full search its slot carries the
+  // special preset instead (the unfiltered distortion is summed elsewhere)
+  if (FULL)
+    acc[0] = luma_special(t, a19A, a19B, c, D, acc[0]);
+  else
+    acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
   s16x2 Q[4];
   secondaries(t, c, D, Q);
-  acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
 #pragma unroll
   for (int si = 1; si < 4; ++si) acc[si] = pair_one(t, Q[si], acc[si]);
   uint32_t prev_sh = 0xFFFFFFFFu;
@@ -191,10 +238,14 @@ __device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t
 // Chroma task: strengths are not adjusted (uniform over the plane); the
 // chroma damping is max(D - 1, floor(log2 S^(p))) for both tap groups, which
 // differs from D - 1 only for D = 3 and S^(p) >= 8.
+template <bool FULL>
 __device__ __forceinline__ void chroma_task(const Taps &t, int c, int D, int (&acc)[64]) {
+  if (FULL)
+    acc[0] = chroma_special(t, c, D, acc[0]);
+  else
+    acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
   s16x2 Q[4];
   secondaries(t, c, D - 1, Q);
-  acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
 #pragma unroll
   for (int si = 1; si < 4; ++si) acc[si] = pair_one(t, Q[si], acc[si]);
   u16x2 a[4];
@@ -274,13 +325,16 @@ struct Smem {
   uint16_t sc[2][32 * 32];
   uint64_t adj[64];
   int32_t var[64];
-  uint32_t red[2][4][64];
-  uint32_t skipsse[3];
+  uint32_t red[2][4][64];   // [luma, chroma][wave][pair]: blocks with residual
+  uint32_t red2[2][4][64];  // the same over skipped blocks (full search)
+  uint32_t skipsse[3];      // per plane: sum of (x - s)^2 over skipped blocks
+  uint32_t allsse[3];       // the same over every in-frame pixel (full search)
   int16_t coff[8][6];
   uint8_t dir[64];
-  uint8_t list[64];
-  uint8_t flag[64];  // bit 0: in frame, bit 1: skipped
-  int n;
+  uint8_t list[64];   // blocks with residual, then (full search) skipped blocks
+  uint8_t adj19[64];  // Eq. (13) applied to 19 (full search)
+  uint8_t flag[64];   // bit 0: in frame, bit 1: skipped
+  int n, nsk;
 };
 
 // Stage the recon tiles (all modes) and, for the search, the source tiles;
@@ -334,10 +388,13 @@ __device__ __forceinline__ void stage_item(Smem &sm, const JobDesc &J, int fby, 
     sm.flag[tid] = (uint8_t)((in ? 1 : 0) | (sk ? 2 : 0));
   }
   if (tid < 3) sm.skipsse[tid] = 0;
+  if (tid < 3) sm.allsse[tid] = 0;
 }
 
 // Algorithm 1 for the 64 luma blocks of the filter block, one per lane of
-// wave 0; Eq. (13) adjusted strengths; compaction of the blocks to filter.
+// wave 0; Eq. (13) adjusted strengths; compaction of the blocks to filter
+// (the full search lists the skipped in-frame blocks after them).
+template <bool FULL>
 __device__ __forceinline__ void direction_search(Smem &sm, const JobDesc &J, int fby, int fbx,
                                                  int lane) {
   const int b = lane;
@@ -380,198 +437,248 @@ __device__ __forceinline__ void direction_search(Smem &sm, const JobDesc &J, int
   sm.var[b] = v;
   sm.adj[b] = adjusted_strengths(v);
   const bool active = in && !sk;
+  const uint64_t below = (1ull << lane) - 1ull;
   const uint64_t m = __ballot(active);
-  const int pos = __popcll(m & ((1ull << lane) - 1ull));
-  if (active) sm.list[pos] = (uint8_t)b;
+  if (active) sm.list[__popcll(m & below)] = (uint8_t)b;
+  if (FULL) {
+    sm.adj19[b] = (uint8_t)adjust_strength(19, v);
+    const bool skipped = in && sk;
+    const uint64_t ms = __ballot(skipped);
+    if (skipped) sm.list[__popcll(m) + __popcll(ms & below)] = (uint8_t)b;
+    if (lane == 0) sm.nsk = __popcll(ms);
+  }
   if (lane == 0) sm.n = __popcll(m);
 }
 
-// Sum of (x - s)^2 over pixels of skipped blocks, for each plane; run by
-// threads t0.. of the workgroup (nt of them).
+// Sum of (x - s)^2 over pixels of skipped blocks, for each plane, and in
+// the full search also over every in-frame pixel; run by threads t0.. of
+// the workgroup (nt of them).
+template <bool FULL>
 __device__ __forceinline__ void skipped_sse(Smem &sm, const JobDesc &J, int fby, int fbx, int t,
                                             int nt, int lane) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
-  uint32_t e0 = 0, e1 = 0, e2 = 0;
-  for (int e = t; e < 64 * 64; e += nt) {
-    const int r = e >> 6, col = e & 63;
-    if ((sm.flag[(r >> 3) * 8 + (col >> 3)] & 2) && y0 + r < H && x0 + col < W) {
-      const int dd = (int)sm.ry[(r + 2) * kLS + kLC0 + col] - (int)sm.sy[e];
-      e0 += (uint32_t)(dd * dd);
+  uint32_t e[3] = {0, 0, 0}, a[3] = {0, 0, 0};
+  for (int i = t; i < 64 * 64; i += nt) {
+    const int r = i >> 6, col = i & 63;
+    if (y0 + r < H && x0 + col < W) {
+      const int dd = (int)sm.ry[(r + 2) * kLS + kLC0 + col] - (int)sm.sy[i];
+      const uint32_t q = (uint32_t)(dd * dd);
+      if (sm.flag[(r >> 3) * 8 + (col >> 3)] & 2) e[0] += q;
+      a[0] += q;
     }
   }
   if (J.nplanes == 3) {
     const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
-    for (int e = t; e < 32 * 32; e += nt) {
-      const int r = e >> 5, col = e & 31;
-      if ((sm.flag[(r >> 2) * 8 + (col >> 2)] & 2) && cy0 + r < ch && cx0 + col < cw) {
-        const int i = (r + 2) * kCS + kCC0 + col;
-        const int d1 = (int)sm.rc[0][i] - (int)sm.sc[0][e];
-        const int d2 = (int)sm.rc[1][i] - (int)sm.sc[1][e];
-        e1 += (uint32_t)(d1 * d1);
-        e2 += (uint32_t)(d2 * d2);
+    for (int i = t; i < 32 * 32; i += nt) {
+      const int r = i >> 5, col = i & 31;
+      if (cy0 + r < ch && cx0 + col < cw) {
+        const int k = (r + 2) * kCS + kCC0 + col;
+        const int d1 = (int)sm.rc[0][k] - (int)sm.sc[0][i];
+        const int d2 = (int)sm.rc[1][k] - (int)sm.sc[1][i];
+        const uint32_t q1 = (uint32_t)(d1 * d1), q2 = (uint32_t)(d2 * d2);
+        if (sm.flag[(r >> 2) * 8 + (col >> 2)] & 2) {
+          e[1] += q1;
+          e[2] += q2;
+        }
+        a[1] += q1;
+        a[2] += q2;
       }
     }
   }
-  e0 = wave_sum(e0);
-  e1 = wave_sum(e1);
-  e2 = wave_sum(e2);
-  if (lane == 0) {
-    atomicAdd(&sm.skipsse[0], e0);
-    atomicAdd(&sm.skipsse[1], e1);
-    atomicAdd(&sm.skipsse[2], e2);
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const uint32_t es = wave_sum(e[p]);
+    if (lane == 0) atomicAdd(&sm.skipsse[p], es);
+    if (FULL) {
+      const uint32_t as = wave_sum(a[p]);
+      if (lane == 0) atomicAdd(&sm.allsse[p], as);
+    }
   }
 }
 
+// Luma tasks over list entries [first, first + count): two 8x8 blocks per
+// task, dealt round-robin to the four waves; per-wave pair totals go to
+// red[wave][pair].
+template <bool FULL>
+__device__ __forceinline__ void luma_tasks(Smem &sm, const JobDesc &J, int first, int count,
+                                           int y0, int x0, int wave, int lane, uint32_t *red) {
+  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
+  int acc[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) acc[i] = 0;
+  const int ntask = (count + 1) >> 1;
+  const int r = lane >> 3, col = lane & 7;
+  for (int tk = wave; tk < ntask; tk += 4) {
+    const int A = uniform(sm.list[first + 2 * tk]);
+    const bool hasB = 2 * tk + 1 < count;
+    const int B = hasB ? uniform(sm.list[first + 2 * tk + 1]) : A;
+    const int dA = uniform(sm.dir[A]), dB = uniform(sm.dir[B]);
+    const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
+    const int rA = 8 * (A >> 3) + r, cA = 8 * (A & 7) + col;
+    const int rB = 8 * (B >> 3) + r, cB = 8 * (B & 7) + col;
+    const bool vA = y0 + rA < H && x0 + cA < W;
+    const bool vB = hasB && y0 + rB < H && x0 + cB < W;
+    const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
+    const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
+    const uint32_t xv = ((uint32_t)sm.ry[bA] | ((uint32_t)sm.ry[bB] << 16)) & vm;
+    const uint32_t sv =
+        ((uint32_t)sm.sy[rA * 64 + cA] | ((uint32_t)sm.sy[rB * 64 + cB] << 16)) & vm;
+    uint32_t tp[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int oA = kLumaTaps.off[dA][k], oB = kLumaTaps.off[dB][k];
+      const int slot = (k >> 1) * 4 + (k & 1) * 2;
+      tp[slot] = ((uint32_t)sm.ry[bA + oA] | ((uint32_t)sm.ry[bB + oB] << 16)) & vm;
+      tp[slot + 1] = ((uint32_t)sm.ry[bA - oA] | ((uint32_t)sm.ry[bB - oB] << 16)) & vm;
+    }
+    Taps t;
+    prepare(t, xv, sv, tp);
+    const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
+    luma_task<FULL>(t, adjA, adjB, a19A, a19B, c, D, acc);
+  }
+  red[wave * 64 + lane] = reduce_transpose(acc, lane);
+}
+
+// Chroma (4:2:0) tasks over list entries [first, first + count): eight 4x4
+// blocks per task (four per half); waves 0-1 take Cb, waves 2-3 Cr.
+template <bool FULL>
+__device__ __forceinline__ void chroma_tasks(Smem &sm, const JobDesc &J, int first, int count,
+                                             int y0, int x0, int wave, int lane, uint32_t *red) {
+  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
+  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  const int p = wave >> 1;
+  const uint16_t *rt = sm.rc[p];
+  const uint16_t *st = sm.sc[p];
+  const int ntask = (count + 7) >> 3;
+  const int sub = lane >> 4, r = (lane >> 2) & 3, col = lane & 3;
+  int acc[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) acc[i] = 0;
+  for (int tk = wave & 1; tk < ntask; tk += 2) {
+    const int iL = 8 * tk + sub, iH = 8 * tk + 4 + sub;
+    const bool hasL = iL < count, hasH = iH < count;
+    const int L = hasL ? sm.list[first + iL] : 0, Hb = hasH ? sm.list[first + iH] : 0;
+    const int rL = 4 * (L >> 3) + r, cL = 4 * (L & 7) + col;
+    const int rH = 4 * (Hb >> 3) + r, cH = 4 * (Hb & 7) + col;
+    const bool vL = hasL && cy0 + rL < ch && cx0 + cL < cw;
+    const bool vH = hasH && cy0 + rH < ch && cx0 + cH < cw;
+    const uint32_t vm = (vL ? 0x0000FFFFu : 0u) | (vH ? 0xFFFF0000u : 0u);
+    const int bL = (rL + 2) * kCS + kCC0 + cL, bH = (rH + 2) * kCS + kCC0 + cH;
+    const int dL = sm.dir[L], dH = sm.dir[Hb];
+    const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
+    const uint32_t sv = ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm;
+    uint32_t tp[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int oL = sm.coff[dL][k], oH = sm.coff[dH][k];
+      const int slot = (k >> 1) * 4 + (k & 1) * 2;
+      tp[slot] = ((uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16)) & vm;
+      tp[slot + 1] = ((uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16)) & vm;
+    }
+    Taps t;
+    prepare(t, xv, sv, tp);
+    chroma_task<FULL>(t, c, D, acc);
+  }
+  red[wave * 64 + lane] = reduce_transpose(acc, lane);
+}
+
+template <bool FULL>
 __device__ __forceinline__ void search_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
-  const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
-  const int c = J.bitdepth - 8, D = J.damping;
+  const int y0 = fby * 64, x0 = fbx * 64;
   const bool chroma = J.nplanes == 3;
 
   stage_item(sm, J, fby, fbx, tid, true);
   __syncthreads();
   if (wave == 0)
-    direction_search(sm, J, fby, fbx, lane);
+    direction_search<FULL>(sm, J, fby, fbx, lane);
   else
-    skipped_sse(sm, J, fby, fbx, tid - 64, 192, lane);
+    skipped_sse<FULL>(sm, J, fby, fbx, tid - 64, 192, lane);
   __syncthreads();
   const int n = sm.n;
 
-  // luma: tasks of two 8x8 blocks, dealt round-robin to the four waves
-  {
-    int acc[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) acc[i] = 0;
-    const int ntask = (n + 1) >> 1;
-    const int r = lane >> 3, col = lane & 7;
-    for (int tk = wave; tk < ntask; tk += 4) {
-      const int A = uniform(sm.list[2 * tk]);
-      const bool hasB = 2 * tk + 1 < n;
-      const int B = hasB ? uniform(sm.list[2 * tk + 1]) : A;
-      const int dA = uniform(sm.dir[A]), dB = uniform(sm.dir[B]);
-      const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
-      const int rA = 8 * (A >> 3) + r, cA = 8 * (A & 7) + col;
-      const int rB = 8 * (B >> 3) + r, cB = 8 * (B & 7) + col;
-      const bool vA = y0 + rA < H && x0 + cA < W;
-      const bool vB = hasB && y0 + rB < H && x0 + cB < W;
-      const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
-      const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
-      const uint32_t xv = ((uint32_t)sm.ry[bA] | ((uint32_t)sm.ry[bB] << 16)) & vm;
-      const uint32_t sv =
-          ((uint32_t)sm.sy[rA * 64 + cA] | ((uint32_t)sm.sy[rB * 64 + cB] << 16)) & vm;
-      uint32_t tp[12];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int oA = kLumaTaps.off[dA][k], oB = kLumaTaps.off[dB][k];
-        const int slot = (k >> 1) * 4 + (k & 1) * 2;
-        tp[slot] = ((uint32_t)sm.ry[bA + oA] | ((uint32_t)sm.ry[bB + oB] << 16)) & vm;
-        tp[slot + 1] = ((uint32_t)sm.ry[bA - oA] | ((uint32_t)sm.ry[bB - oB] << 16)) & vm;
-      }
-      Taps t;
-      prepare(t, xv, sv, tp);
-      luma_task(t, adjA, adjB, c, D, acc);
-    }
-    sm.red[0][wave][lane] = reduce_transpose(acc, lane);
-  }
-
-  // chroma (4:2:0): tasks of eight 4x4 blocks (four per half); waves 0-1
-  // take Cb, waves 2-3 take Cr
-  if (chroma) {
-    const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
-    const int p = wave >> 1;
-    const uint16_t *rt = sm.rc[p];
-    const uint16_t *st = sm.sc[p];
-    const int ntask = (n + 7) >> 3;
-    const int sub = lane >> 4, r = (lane >> 2) & 3, col = lane & 3;
-    int acc[64];
-#pragma unroll
-    for (int i = 0; i < 64; ++i) acc[i] = 0;
-    for (int tk = wave & 1; tk < ntask; tk += 2) {
-      const int iL = 8 * tk + sub, iH = 8 * tk + 4 + sub;
-      const bool hasL = iL < n, hasH = iH < n;
-      const int L = hasL ? sm.list[iL] : 0, Hb = hasH ? sm.list[iH] : 0;
-      const int rL = 4 * (L >> 3) + r, cL = 4 * (L & 7) + col;
-      const int rH = 4 * (Hb >> 3) + r, cH = 4 * (Hb & 7) + col;
-      const bool vL = hasL && cy0 + rL < ch && cx0 + cL < cw;
-      const bool vH = hasH && cy0 + rH < ch && cx0 + cH < cw;
-      const uint32_t vm = (vL ? 0x0000FFFFu : 0u) | (vH ? 0xFFFF0000u : 0u);
-      const int bL = (rL + 2) * kCS + kCC0 + cL, bH = (rH + 2) * kCS + kCC0 + cH;
-      const int dL = sm.dir[L], dH = sm.dir[Hb];
-      const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
-      const uint32_t sv = ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm;
-      uint32_t tp[12];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int oL = sm.coff[dL][k], oH = sm.coff[dH][k];
-        const int slot = (k >> 1) * 4 + (k & 1) * 2;
-        tp[slot] = ((uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16)) & vm;
-        tp[slot + 1] = ((uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16)) & vm;
-      }
-      Taps t;
-      prepare(t, xv, sv, tp);
-      chroma_task(t, c, D, acc);
-    }
-    sm.red[1][wave][lane] = reduce_transpose(acc, lane);
+  luma_tasks<FULL>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[0][0][0]);
+  if (chroma) chroma_tasks<FULL>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[1][0][0]);
+  // skipped blocks matter only where some block has residual
+  if (FULL && n > 0) {
+    const int nsk = sm.nsk;
+    luma_tasks<FULL>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[0][0][0]);
+    if (chroma) chroma_tasks<FULL>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[1][0][0]);
   }
   __syncthreads();
 
   const int64_t fbi = (int64_t)fby * J.fbc + fbx;
-  const int64_t plane_stride = (int64_t)J.fbr * J.fbc * 64;
+  const int64_t nfb = (int64_t)J.fbr * J.fbc;
+  int P = -1, k = tid & 63;
+  uint64_t A = 0, Bf = 0;
   if (tid < 64) {
-    const uint64_t s = (uint64_t)sm.red[0][0][tid] + sm.red[0][1][tid] + sm.red[0][2][tid] +
-                       sm.red[0][3][tid] + sm.skipsse[0];
-    J.sse[fbi * 64 + tid] = s;
+    P = 0;
+    A = (uint64_t)sm.red[0][0][k] + sm.red[0][1][k] + sm.red[0][2][k] + sm.red[0][3][k];
+    if (FULL)
+      Bf = (uint64_t)sm.red2[0][0][k] + sm.red2[0][1][k] + sm.red2[0][2][k] + sm.red2[0][3][k];
   } else if (chroma && tid < 192) {
-    const int p = (tid >> 6) - 1, k = tid & 63;
-    const uint64_t s =
-        (uint64_t)sm.red[1][2 * p][k] + sm.red[1][2 * p + 1][k] + sm.skipsse[1 + p];
-    J.sse[(1 + p) * plane_stride + fbi * 64 + k] = s;
+    const int p = (tid >> 6) - 1;
+    P = 1 + p;
+    A = (uint64_t)sm.red[1][2 * p][k] + sm.red[1][2 * p + 1][k];
+    if (FULL) Bf = (uint64_t)sm.red2[1][2 * p][k] + sm.red2[1][2 * p + 1][k];
+  }
+  if (P < 0) return;
+  const uint64_t U = sm.skipsse[P];
+  if (!FULL) {
+    J.sse[(P * nfb + fbi) * 64 + k] = A + U;
+  } else {
+    // slot 0 holds the special preset; (0, 0) itself is the unfiltered sum
+    uint64_t *o = J.sse + (P * nfb + fbi) * 128;
+    o[k] = k == 0 ? (uint64_t)sm.allsse[P] : A + U;
+    o[64 + k] = n > 0 ? A + Bf : U;  // every block skipped: nothing is filtered
   }
 }
 
-// Filter mode: the block's own strengths (Section 3.2 ranges; bad values are
-// masked / clamped so the kernel stays defined), one pixel per lane.
+// Filter mode: the block's own preset (Section 3.2 ranges, Section 4 skip
+// rules; bad values are masked / clamped so the kernel stays defined), one
+// pixel per lane.
 __device__ __forceinline__ void filter_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid) {
-  const int lane = tid & 63, wave = tid >> 6;
+  const int wave = tid >> 6, lane = tid & 63;
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int c = J.bitdepth - 8, D = J.damping;
   stage_item(sm, J, fby, fbx, tid, false);
   __syncthreads();
-  if (wave == 0) direction_search(sm, J, fby, fbx, lane);
+  if (wave == 0) direction_search<false>(sm, J, fby, fbx, lane);
   __syncthreads();
   const uint8_t *st = J.strengths + 4 * ((int64_t)fby * J.fbc + fbx);
-  const int pri_y = st[0] & 15, sec_y = min((int)st[1], 4);
-  const int pri_uv = st[2] & 15, sec_uv = min((int)st[3], 4);
-  {
-    const int ss = sec_y << c, sshift = sec_y ? D - floor_log2(sec_y) : 0;
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int r = e >> 6, col = e & 63;
-      if (y0 + r >= H || x0 + col >= W) continue;
-      const int b = (r >> 3) * 8 + (col >> 3);
-      const int base = (r + 2) * kLS + kLC0 + col;
-      int y = sm.ry[base];
-      if (!(sm.flag[b] & 2)) {
-        const int adj = (int)((sm.adj[b] >> (4 * pri_y)) & 15);  // Eq. (13)
-        y = filter_pixel(sm.ry, base, kLS, sm.dir[b], adj << c, adj ? D - floor_log2(adj) : 0,
-                         (adj & 1) ? 3 : 4, (adj & 1) ? 3 : 2, ss, sshift);
-      }
-      J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] = (uint16_t)y;
+  const Preset py = decode_preset(st[0], st[1]);
+  const Preset pc = decode_preset(st[2], st[3]);
+  const bool fb_skipped = sm.n == 0;  // no block with residual: not filtered
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e >> 6, col = e & 63;
+    if (y0 + r >= H || x0 + col >= W) continue;
+    const int b = (r >> 3) * 8 + (col >> 3);
+    const int base = (r + 2) * kLS + kLC0 + col;
+    int y = sm.ry[base];
+    if (!fb_skipped && (!(sm.flag[b] & 2) || py.skipcond)) {
+      const int adj = adjust_strength(py.pri, sm.var[b]);  // Eq. (13)
+      const int Dl = luma_damping(D, adj);
+      y = filter_pixel(sm.ry, base, kLS, sm.dir[b], adj << c, adj ? Dl - floor_log2(adj) : 0,
+                       (adj & 1) ? 3 : 4, (adj & 1) ? 3 : 2, py.sec << c,
+                       py.sec ? Dl - floor_log2(py.sec) : 0);
     }
+    J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] = (uint16_t)y;
   }
   if (J.nplanes != 3) return;
-  const int Dc = pri_uv ? max(D - 1, floor_log2(pri_uv)) : D - 1;
-  const int ps = pri_uv << c, pshift = pri_uv ? Dc - floor_log2(pri_uv) : 0;
-  const int w1 = (pri_uv & 1) ? 3 : 4, w2 = (pri_uv & 1) ? 3 : 2;
-  const int ss = sec_uv << c, sshift = sec_uv ? Dc - floor_log2(sec_uv) : 0;
+  const int Dc = pc.pri ? max(D - 1, floor_log2(pc.pri)) : D - 1;
+  const int ps = pc.pri << c, pshift = pc.pri ? Dc - floor_log2(pc.pri) : 0;
+  const int w1 = (pc.pri & 1) ? 3 : 4, w2 = (pc.pri & 1) ? 3 : 2;
+  const int ss = pc.sec << c, sshift = pc.sec ? Dc - floor_log2(pc.sec) : 0;
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
   for (int e = tid; e < 2 * 32 * 32; e += 256) {
     const int p = e >> 10, r = (e >> 5) & 31, col = e & 31;
     if (cy0 + r >= ch || cx0 + col >= cw) continue;
     const int b = (r >> 2) * 8 + (col >> 2);
     const int base = (r + 2) * kCS + kCC0 + col;
-    const int y = (sm.flag[b] & 2) ? (int)sm.rc[p][base]
-                                   : filter_pixel(sm.rc[p], base, kCS, sm.dir[b], ps, pshift, w1,
-                                                  w2, ss, sshift);
+    const bool filt = !fb_skipped && (!(sm.flag[b] & 2) || pc.skipcond);
+    const int y = filt ? filter_pixel(sm.rc[p], base, kCS, sm.dir[b], ps, pshift, w1, w2, ss,
+                                      sshift)
+                       : (int)sm.rc[p][base];
     J.out[1 + p][(int64_t)(cy0 + r) * J.ostride[1 + p] + cx0 + col] = (uint16_t)y;
   }
 }
@@ -579,7 +686,9 @@ __device__ __forceinline__ void filter_item(Smem &sm, const JobDesc &J, int fby,
 __device__ __forceinline__ void run_item(Smem &sm, const JobDesc &J, int item, int tid) {
   const int fby = item / J.fbc, fbx = item - fby * J.fbc;
   if (J.mode == kModeSearch)
-    search_item(sm, J, fby, fbx, tid);
+    search_item<false>(sm, J, fby, fbx, tid);
+  else if (J.mode == kModeSearchFull)
+    search_item<true>(sm, J, fby, fbx, tid);
   else
     filter_item(sm, J, fby, fbx, tid);
 }

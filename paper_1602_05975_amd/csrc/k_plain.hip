@@ -60,28 +60,29 @@ constexpr int kLC0 = 8;  // tile column of frame column x0
 constexpr int kCS = 48;  // chroma tile row stride (36 used)
 constexpr int kCC0 = 8;
 
-// Section 3.2: secondary strength domain {0, 1, 2, 4}; larger values are
-// clamped to 4 so that a bad input stays well defined.
-__device__ __forceinline__ int sanitize_sec(int s) { return min(s, 4); }
-
 // One workgroup per 64x64 filter block; every pixel reads unfiltered input
-// from the LDS tile, so no ordering between blocks matters.
+// from the LDS tile, so no ordering between blocks matters.  Section 4: a
+// skipped 8x8 block is filtered only under a preset with the skip condition
+// bit, and a filter block whose blocks are all skipped is not filtered.
 template <int BD>
 __global__ __launch_bounds__(256) void k_filter(const FilterArgs a) {
   __shared__ __align__(16) uint16_t ry[68 * kLS];
   __shared__ __align__(16) uint16_t rc[36 * kCS];
-  __shared__ int s_par[64][6];  // per 8x8 block: dir, ps, pshift, w1|w2<<8, skip, unused
+  // per 8x8 block: dir, primary strength, primary shift, w1 | w2 << 8,
+  // skipped, secondary shift (luma)
+  __shared__ int s_par[64][6];
   constexpr int c = BD - 8;
   const int tid = threadIdx.x;
   const int fby = blockIdx.x / a.fbc, fbx = blockIdx.x - fby * a.fbc;
   const int y0 = fby * 64, x0 = fbx * 64;
   const int W = a.width, H = a.height;
   const uint8_t *st = a.strengths + 4 * blockIdx.x;
-  const int pri_y = st[0] & 15, sec_y = sanitize_sec(st[1]);
-  const int pri_uv = st[2] & 15, sec_uv = sanitize_sec(st[3]);
+  const Preset py = decode_preset(st[0], st[1]);
+  const Preset pc = decode_preset(st[2], st[3]);
   const int D = a.damping;
 
   stage_recon<64, 64, kLS, kLC0, 256>(ry, a.in[0], a.istride[0], W, H, y0, x0, tid);
+  int active = 0;
   if (tid < 64) {
     const int by = fby * 8 + (tid >> 3), bx = fbx * 8 + (tid & 7);
     int d = 0, sk = 1, v = 0;
@@ -90,39 +91,43 @@ __global__ __launch_bounds__(256) void k_filter(const FilterArgs a) {
       d = a.dir[b];
       v = a.var[b];
       sk = a.skip ? (a.skip[b] != 0) : 0;
+      active = !sk;
     }
-    const int adj = (int)((adjusted_strengths(v) >> (4 * pri_y)) & 15);  // Eq. (13)
+    const int adj = adjust_strength(py.pri, v);  // Eq. (13)
+    const int Dl = luma_damping(D, adj);
     s_par[tid][0] = d & 7;
     s_par[tid][1] = adj << c;
-    s_par[tid][2] = adj ? D - floor_log2(adj) : 0;
+    s_par[tid][2] = adj ? Dl - floor_log2(adj) : 0;
     s_par[tid][3] = (adj & 1) ? (3 | (3 << 8)) : (4 | (2 << 8));
     s_par[tid][4] = sk;
+    s_par[tid][5] = py.sec ? Dl - floor_log2(py.sec) : 0;
   }
-  __syncthreads();
+  // a filter block with no block left to filter is copied
+  const bool fb_skipped = !__syncthreads_or(active);
   {
-    const int ss = sec_y << c, sshift = sec_y ? D - floor_log2(sec_y) : 0;
+    const int ss = py.sec << c;
     for (int e = tid; e < 64 * 64; e += 256) {
       const int r = e >> 6, col = e & 63;
       if (y0 + r >= H || x0 + col >= W) continue;
       const int b = (r >> 3) * 8 + (col >> 3);
       const int base = (r + 2) * kLS + kLC0 + col;
       int y;
-      if (s_par[b][4]) {
+      if (fb_skipped || (s_par[b][4] && !py.skipcond)) {
         y = ry[base];
       } else {
         const int w12 = s_par[b][3];
         y = filter_pixel(ry, base, kLS, s_par[b][0], s_par[b][1], s_par[b][2], w12 & 255,
-                         w12 >> 8, ss, sshift);
+                         w12 >> 8, ss, s_par[b][5]);
       }
       a.out[0][(int64_t)(y0 + r) * a.ostride[0] + x0 + col] = (uint16_t)y;
     }
   }
   if (a.nplanes == 1) return;
   // Chroma (4:2:0): unadjusted strength, damping max(D - 1, floor(log2 S)).
-  const int Dc = pri_uv ? max(D - 1, floor_log2(pri_uv)) : D - 1;
-  const int ps = pri_uv << c, pshift = pri_uv ? Dc - floor_log2(pri_uv) : 0;
-  const int w1 = (pri_uv & 1) ? 3 : 4, w2 = (pri_uv & 1) ? 3 : 2;
-  const int ss = sec_uv << c, sshift = sec_uv ? Dc - floor_log2(sec_uv) : 0;
+  const int Dc = pc.pri ? max(D - 1, floor_log2(pc.pri)) : D - 1;
+  const int ps = pc.pri << c, pshift = pc.pri ? Dc - floor_log2(pc.pri) : 0;
+  const int w1 = (pc.pri & 1) ? 3 : 4, w2 = (pc.pri & 1) ? 3 : 2;
+  const int ss = pc.sec << c, sshift = pc.sec ? Dc - floor_log2(pc.sec) : 0;
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
   for (int p = 1; p < 3; ++p) {
     __syncthreads();
@@ -133,9 +138,10 @@ __global__ __launch_bounds__(256) void k_filter(const FilterArgs a) {
       if (cy0 + r >= ch || cx0 + col >= cw) continue;
       const int b = (r >> 2) * 8 + (col >> 2);
       const int base = (r + 2) * kCS + kCC0 + col;
-      const int y = s_par[b][4] ? (int)rc[base]
-                                : filter_pixel(rc, base, kCS, s_par[b][0], ps, pshift, w1, w2,
-                                               ss, sshift);
+      const int y = (fb_skipped || (s_par[b][4] && !pc.skipcond))
+                        ? (int)rc[base]
+                        : filter_pixel(rc, base, kCS, s_par[b][0], ps, pshift, w1, w2, ss,
+                                       sshift);
       a.out[p][(int64_t)(cy0 + r) * a.ostride[p] + cx0 + col] = (uint16_t)y;
     }
   }

@@ -1,7 +1,8 @@
 // Preset selection on the strength-search table (Section 5, Eq. 15).
 //
-// D^luma_{b,p} is the luma SSE of filter block b under pair p (p = S^(p) * 4
-// + index of S^(s)); D^chroma_{b,p} is the Cb + Cr SSE.  For each group a
+// D^luma_{b,p} is the luma SSE of filter block b under candidate p (p =
+// skip condition bit * 64 + S^(p) * 4 + index of S^(s); 64 candidates
+// without the bit, 128 with it); D^chroma_{b,p} is the Cb + Cr SSE.  For each group a
 // greedy sequence of 8 presets is built, each step adding the candidate not
 // yet chosen that most lowers sum_b min over the set (lowest index on ties);
 // for N = 1, 2, 4, 8 the greedy prefix is re-optimized one preset at a time
@@ -11,10 +12,10 @@
 // block gets the slot of its smallest distortion (lowest slot on ties).
 //
 // Layout of the work.  Each group (luma, chroma) is spread over G workgroups;
-// workgroup w owns a contiguous slice of about 64 filter blocks and keeps its
-// slice of D (chroma already summed) in LDS.  Every step of the search is a
+// workgroup w owns a contiguous slice of filter blocks (96 at 64 candidates,
+// 48 at 128) and keeps its slice of D (chroma already summed) in LDS.  Every step of the search is a
 // "round": each workgroup evaluates, for up to three candidate sets at once,
-// the 64 partial sums sum_{b in slice} min(m_b, D_{b,p}) (m_b the minimum over
+// the partial sums sum_{b in slice} min(m_b, D_{b,p}) (m_b the minimum over
 // the presets held fixed), adds them atomically into the round's totals in
 // the workspace and waits until all G workgroups of its group have done so.
 // Every workgroup then reads the same integer totals and takes the same
@@ -38,21 +39,26 @@ namespace cdef {
 namespace {
 
 constexpr int kNT = 256;        // threads per workgroup
-constexpr int kSlice = 64;      // filter blocks per workgroup kept in LDS
+constexpr int kLdsEntries = 6144;  // D values per workgroup kept in LDS
 constexpr int kMaxG = 128;      // workgroups per group
 constexpr int kQ = 3;           // candidate sets evaluated per round
+constexpr int kMaxNC = 128;     // candidates
 constexpr uint64_t kWaitTicks = 100000000ull;  // 1 s of the 100 MHz wall clock
+
+template <int NC>
+constexpr int slice_blocks() { return kLdsEntries / NC; }
 
 struct PresetWork {
   uint32_t arrive[2];  // per-group arrival counters (G per round)
   uint32_t failed;
   uint32_t pad[61];
-  uint64_t total[3][2][kQ][64];  // [round mod 3][group][set][p]
+  uint64_t total[3][2][kQ][kMaxNC];  // [round mod 3][group][set][p]
 };
 
+template <int NC>
 __device__ __forceinline__ uint64_t group_dist(const uint64_t *sse, int nfb, int g, int b, int p) {
-  if (g == 0) return sse[(int64_t)b * 64 + p];
-  return sse[((int64_t)nfb + b) * 64 + p] + sse[((int64_t)2 * nfb + b) * 64 + p];
+  if (g == 0) return sse[(int64_t)b * NC + p];
+  return sse[((int64_t)nfb + b) * NC + p] + sse[((int64_t)2 * nfb + b) * NC + p];
 }
 
 struct Query {
@@ -60,11 +66,13 @@ struct Query {
   int n, excl;
 };
 
+template <int NC>
 struct CoopSmem {
-  uint64_t d[kSlice][64];
+  static constexpr int kSlice = slice_blocks<NC>(), kRows = kNT / NC;
+  uint64_t d[kSlice][NC];
   uint64_t m[kQ][kSlice];
-  uint64_t red[4][kQ][64];
-  uint64_t cost[kQ][64];
+  uint64_t red[kRows][kQ][NC];
+  uint64_t cost[kQ][NC];
   uint64_t best_cost[kQ];
   int best_p[kQ];
   Query q[kQ];
@@ -85,17 +93,21 @@ __device__ __forceinline__ bool excluded(const Query &q, int p) {
   return false;
 }
 
+__device__ __forceinline__ void argmin2(uint64_t &c, int &p, uint64_t oc, int op) {
+  if (oc < c || (oc == c && op < p)) {
+    c = oc;
+    p = op;
+  }
+}
+
 // Lexicographic (cost, p) minimum over the 64 lanes of a wave; excluded
-// candidates carry UINT64_MAX and an index past 63.
+// candidates carry UINT64_MAX and an index past the last candidate.
 __device__ __forceinline__ void wave_argmin(uint64_t &c, int &p) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const uint64_t oc = __shfl_xor(c, off, 64);
     const int op = __shfl_xor(p, off, 64);
-    if (oc < c || (oc == c && op < p)) {
-      c = oc;
-      p = op;
-    }
+    argmin2(c, p, oc, op);
   }
 }
 
@@ -111,18 +123,22 @@ __device__ __forceinline__ void wave_argmin(uint64_t &c, int &p) {
 // the arrival is counted, and totals are read only after the count is seen
 // complete.  On return sm.cost holds the group's totals; false if the wait
 // timed out.
-__device__ bool round_totals(CoopSmem &sm, PresetWork *work, int g, int G, int nq,
+template <int NC>
+__device__ bool round_totals(CoopSmem<NC> &sm, PresetWork *work, int g, int G, int nq,
                              uint32_t round) {
-  const int tid = threadIdx.x, s = tid >> 6, lane = tid & 63;
+  constexpr int R = CoopSmem<NC>::kRows;
+  const int tid = threadIdx.x;
   const uint32_t buf = round % 3;
   uint64_t before = 0;
-  if (tid < nq * 64) {
-    const uint64_t v =
-        sm.red[0][s][lane] + sm.red[1][s][lane] + sm.red[2][s][lane] + sm.red[3][s][lane];
-    before = __hip_atomic_fetch_add(&work->total[buf][g][s][lane], v, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = tid; i < nq * NC; i += kNT) {
+    const int s = i / NC, p = i % NC;
+    uint64_t v = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v += sm.red[r][s][p];
+    before += __hip_atomic_fetch_add(&work->total[buf][g][s][p], v, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
   }
-  // consuming the returned value makes the wave wait for the add to complete
+  // consuming the returned values makes the wave wait for the adds to complete
   __asm__ volatile("" : : "v"(before));
   __syncthreads();
   if (tid == 0) {
@@ -148,25 +164,29 @@ __device__ bool round_totals(CoopSmem &sm, PresetWork *work, int g, int G, int n
   }
   __syncthreads();
   if (!sm.ok) return false;
-  if (tid < nq * 64)
-    sm.cost[s][lane] = __hip_atomic_load(&work->total[buf][g][s][lane], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-  if (sm.last && tid < kQ * 64)
-    __hip_atomic_store(&work->total[(round + 2) % 3][g][s][lane], (uint64_t)0, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = tid; i < nq * NC; i += kNT)
+    sm.cost[i / NC][i % NC] = __hip_atomic_load(&work->total[buf][g][i / NC][i % NC],
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (sm.last)
+    for (int i = tid; i < kQ * NC; i += kNT)
+      __hip_atomic_store(&work->total[(round + 2) % 3][g][i / NC][i % NC], (uint64_t)0,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   // the clearing stores complete before this workgroup's next arrival
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   return true;
 }
 
-template <bool LDS>
+template <int NC, bool LDS>
 __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict__ sse,
                                                      int nplanes, int nfb, int G, int refine,
                                                      PresetWork *work, PresetResult *out) {
-  __shared__ CoopSmem sm;
+  using Smem = CoopSmem<NC>;
+  constexpr int R = Smem::kRows;
+  __shared__ Smem sm;
   const int g = blockIdx.x / G, w = blockIdx.x % G, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int pc = tid % NC, row = tid / NC;  // candidate and block row of this thread
   if (g == 1 && nplanes == 1) {
     // all-zero chroma: every candidate ties, so the greedy takes 0, 1, ..., 7
     // and no refinement finds a strict improvement
@@ -181,8 +201,8 @@ __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict_
   const int b0 = min(nfb, w * per), cnt = min(nfb, b0 + per) - b0;
 
   if (LDS) {
-    for (int i = tid; i < cnt * 64; i += kNT)
-      sm.d[i >> 6][i & 63] = group_dist(sse, nfb, g, b0 + (i >> 6), i & 63);
+    for (int i = tid; i < cnt * NC; i += kNT)
+      sm.d[i / NC][i % NC] = group_dist<NC>(sse, nfb, g, b0 + i / NC, i % NC);
   }
   if (tid == 0) {
     sm.step = 0;
@@ -218,7 +238,7 @@ __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict_
     const int nq = sm.nq;
     if (nq == 0) break;
 
-    // ---- partial sums: thread (p = lane, row = wave) over blocks row, row + 4, ...
+    // ---- partial sums: thread (candidate pc, row) over blocks row, row + R, ...
     uint64_t acc[kQ] = {0, 0, 0};
     if (LDS) {
       for (int i = tid; i < nq * cnt; i += kNT) {
@@ -233,8 +253,8 @@ __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict_
         sm.m[s][bl] = mm;
       }
       __syncthreads();
-      for (int bl = wave; bl < cnt; bl += 4) {
-        const uint64_t d = sm.d[bl][lane];
+      for (int bl = row; bl < cnt; bl += R) {
+        const uint64_t d = sm.d[bl][pc];
 #pragma unroll
         for (int s = 0; s < kQ; ++s) {
           if (s < nq) {
@@ -244,14 +264,14 @@ __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict_
         }
       }
     } else {
-      for (int bl = wave; bl < cnt; bl += 4) {
-        const uint64_t d = group_dist(sse, nfb, g, b0 + bl, lane);
+      for (int bl = row; bl < cnt; bl += R) {
+        const uint64_t d = group_dist<NC>(sse, nfb, g, b0 + bl, pc);
         for (int s = 0; s < nq; ++s) {
           const Query &q = sm.q[s];
           uint64_t mm = UINT64_MAX;
           for (int k = 0; k < q.n; ++k) {
             if (k == q.excl) continue;
-            const uint64_t e = group_dist(sse, nfb, g, b0 + bl, q.set[k]);
+            const uint64_t e = group_dist<NC>(sse, nfb, g, b0 + bl, q.set[k]);
             mm = e < mm ? e : mm;
           }
           acc[s] += d < mm ? d : mm;
@@ -259,18 +279,20 @@ __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict_
       }
     }
 #pragma unroll
-    for (int s = 0; s < kQ; ++s) sm.red[wave][s][lane] = acc[s];
+    for (int s = 0; s < kQ; ++s) sm.red[row][s][pc] = acc[s];
     __syncthreads();
-    if (!round_totals(sm, work, g, G, nq, round)) return;
+    if (!round_totals<NC>(sm, work, g, G, nq, round)) return;
 
-    // ---- one decision per candidate set
+    // ---- one decision per candidate set: wave s scans the NC candidates,
+    // NC / 64 per lane
     if (wave < nq) {
       const Query &q = sm.q[wave];
-      uint64_t c = sm.cost[wave][lane];
-      int p = lane;
-      if (excluded(q, lane)) {
-        c = UINT64_MAX;
-        p = 64;
+      uint64_t c = UINT64_MAX;
+      int p = NC;
+#pragma unroll
+      for (int h = 0; h < NC / 64; ++h) {
+        const int cand = lane + 64 * h;
+        if (!excluded(q, cand)) argmin2(c, p, sm.cost[wave][cand], cand);
       }
       wave_argmin(c, p);
       if (lane == 0) {
@@ -336,9 +358,10 @@ __global__ void k_preset_reset(PresetWork *work) {
   if (t < 2) work->arrive[t] = 0;
   if (t == 0) work->failed = 0;
   uint64_t *tot = &work->total[0][0][0][0];
-  for (int i = t; i < 2 * 2 * kQ * 64; i += blockDim.x) tot[i] = 0;
+  for (int i = t; i < 2 * 2 * kQ * kMaxNC; i += blockDim.x) tot[i] = 0;
 }
 
+template <int NC>
 __global__ __launch_bounds__(kNT) void k_preset_finish(const uint64_t *__restrict__ sse,
                                                        int nplanes, int nfb, double lambda,
                                                        const PresetWork *work, PresetResult *out,
@@ -376,7 +399,7 @@ __global__ __launch_bounds__(kNT) void k_preset_finish(const uint64_t *__restric
     if (g == 0 || nplanes == 3) {
       uint64_t bd = UINT64_MAX;
       for (int i = 0; i < n; ++i) {
-        const uint64_t d = group_dist(sse, nfb, g, b, sets[i]);
+        const uint64_t d = group_dist<NC>(sse, nfb, g, b, sets[i]);
         if (d < bd) {
           bd = d;
           bi = i;
@@ -391,13 +414,14 @@ __global__ __launch_bounds__(kNT) void k_preset_finish(const uint64_t *__restric
 
 size_t preset_workspace_bytes() { return sizeof(PresetWork); }
 
-int preset_groups(int nfb) { return min(kMaxG, (nfb + kSlice - 1) / kSlice); }
+namespace {
 
-hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, double lambda,
-                                 int refine, PresetResult *out, uint8_t *fb_luma,
-                                 uint8_t *fb_chroma, void *workspace, hipStream_t s) {
-  PresetWork *work = static_cast<PresetWork *>(workspace);
-  const int G = preset_groups(nfb);
+template <int NC>
+hipError_t select_presets_nc(const uint64_t *sse, int nplanes, int nfb, double lambda, int refine,
+                             PresetResult *out, uint8_t *fb_luma, uint8_t *fb_chroma,
+                             PresetWork *work, hipStream_t s) {
+  constexpr int kSlice = slice_blocks<NC>();
+  const int G = min(kMaxG, (nfb + kSlice - 1) / kSlice);
   const int per = (nfb + G - 1) / G;
   hipLaunchKernelGGL(k_preset_reset, dim3(1), dim3(256), 0, s, work);
   hipError_t e = hipGetLastError();
@@ -405,16 +429,29 @@ hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, doub
   // 2 G <= 256 workgroups of 256 threads: all of them fit on the device at
   // once, so every wait for the last arrival of a round ends.
   if (per <= kSlice)
-    hipLaunchKernelGGL(k_preset_coop<true>, dim3(2 * G), dim3(kNT), 0, s, sse, nplanes, nfb, G,
-                       refine, work, out);
+    hipLaunchKernelGGL((k_preset_coop<NC, true>), dim3(2 * G), dim3(kNT), 0, s, sse, nplanes, nfb,
+                       G, refine, work, out);
   else
-    hipLaunchKernelGGL(k_preset_coop<false>, dim3(2 * G), dim3(kNT), 0, s, sse, nplanes, nfb, G,
-                       refine, work, out);
+    hipLaunchKernelGGL((k_preset_coop<NC, false>), dim3(2 * G), dim3(kNT), 0, s, sse, nplanes,
+                       nfb, G, refine, work, out);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_preset_finish, dim3((nfb + kNT - 1) / kNT), dim3(kNT), 0, s, sse, nplanes,
-                     nfb, lambda, work, out, fb_luma, fb_chroma);
+  hipLaunchKernelGGL(k_preset_finish<NC>, dim3((nfb + kNT - 1) / kNT), dim3(kNT), 0, s, sse,
+                     nplanes, nfb, lambda, work, out, fb_luma, fb_chroma);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
+                                 double lambda, int refine, PresetResult *out, uint8_t *fb_luma,
+                                 uint8_t *fb_chroma, void *workspace, hipStream_t s) {
+  PresetWork *work = static_cast<PresetWork *>(workspace);
+  if (ncand == 128)
+    return select_presets_nc<128>(sse, nplanes, nfb, lambda, refine, out, fb_luma, fb_chroma,
+                                  work, s);
+  return select_presets_nc<64>(sse, nplanes, nfb, lambda, refine, out, fb_luma, fb_chroma, work,
+                               s);
 }
 
 }  // namespace cdef

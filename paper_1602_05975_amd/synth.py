@@ -179,6 +179,23 @@ def random_strengths(frame: Frame, seed: int) -> np.ndarray:
     return out
 
 
+def random_presets(frame: Frame, seed: int, p_skipcond: float = 0.5,
+                   p_special: float = 0.15) -> np.ndarray:
+    """Per-FB presets as random_strengths, with the skip condition bit (bit 7
+    of each secondary byte) set with probability p_skipcond and, per plane
+    group, the (0, 0)-with-bit preset (strengths 19, 7) with p_special."""
+    out = random_strengths(frame, seed)
+    rng = np.random.Generator(np.random.PCG64([seed, 13]))
+    shape = (frame.fb_rows, frame.fb_cols)
+    for pri, sec in ((0, 1), (2, 3)):
+        bit = rng.random(shape) < p_skipcond
+        special = rng.random(shape) < p_special
+        out[..., pri][special] = 0
+        out[..., sec][special] = 0
+        out[..., sec] |= ((bit | special).astype(np.uint8) << 7)
+    return out
+
+
 def config0() -> Frame:
     """352x288 8-bit luma, filtered with (pri 4, sec 2) and damping 5."""
     return make_frame(352, 288, 8, LAYOUT_400, config_seed(0, 0), damping=5)

@@ -18,20 +18,23 @@ def to_np_u16(t):
     return t.cpu().numpy().view(np.uint16)
 
 
-def gpu_search(fr, skip=True, damping=None):
+def gpu_search(fr, skip=True, damping=None, full=False):
+    """GPU SSE table ([nplanes][fbr][fbc][16][4], or [..][2][16][4] with
+    full=True), dir and var, as numpy arrays."""
     import torch
     from paper_1602_05975_amd import cdef
     rec = gpu_frame(fr.recon, fr)
     src = gpu_frame(fr.src, fr)
     sk = torch.from_numpy(fr.skip).cuda() if skip else None
     sse, d, v = cdef.search_strengths(rec, src, sk, fr.damping if damping is None else damping,
-                                      want_dir=True)
+                                      want_dir=True, full=full)
     torch.cuda.synchronize()
     return sse.cpu().numpy().view(np.uint64), d.cpu().numpy(), v.cpu().numpy()
 
 
-def oracle_search(oracle, fr, skip=True, damping=None, fbs=None):
-    """Oracle SSE tables.  fbs: list of (fby, fbx) (default all)."""
+def oracle_search(oracle, fr, skip=True, damping=None, fbs=None, full=False):
+    """Oracle SSE tables [len(fbs)][nplanes][(2,)16][4].  fbs: list of
+    (fby, fbx) (default all)."""
     sk = fr.skip if skip else None
     D = fr.damping if damping is None else damping
     d, v = oracle.find_dir(fr.recon[0], fr.bitdepth)
@@ -39,5 +42,5 @@ def oracle_search(oracle, fr, skip=True, damping=None, fbs=None):
     if fbs is None:
         fbs = [(by, bx) for by in range(fbr) for bx in range(fbc)]
     t = oracle.search_fbs(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, d, v, sk, D, fbs,
-                          threads=ORACLE_THREADS)
+                          threads=ORACLE_THREADS, full=full)
     return t, d, v, fbs

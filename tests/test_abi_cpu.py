@@ -63,15 +63,18 @@ def test_find_dir_argument_checks(lib):
     assert lib.cdef_find_dir(C.byref(f), P, P, None) == -1
 
 
-def test_search_argument_checks(lib):
+@pytest.mark.parametrize("name", ["cdef_search_strengths", "cdef_search_strengths128"])
+def test_search_argument_checks(lib, name):
+    f = getattr(lib, name)
     P = 0x20000
     r, s = _frame(), _frame(ptr=0x900000)
-    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 2, P, None, None, None) == -1
-    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 7, P, None, None, None) == -1
-    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 3, None, None, None, None) == -1
-    assert lib.cdef_search_strengths(C.byref(r), C.byref(s), None, 3, P, P, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 2, P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 7, P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 3, None, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 3, P, P, None, None) == -1
     s2 = _frame(w=66, ptr=0x900000)
-    assert lib.cdef_search_strengths(C.byref(r), C.byref(s2), None, 3, P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s2), None, 3, P, None, None, None) == -1
+    assert f(None, C.byref(s), None, 3, P, None, None, None) == -1
 
 
 def test_filter_argument_checks(lib):
@@ -130,8 +133,8 @@ def test_select_presets_argument_checks(lib):
     assert 0 < n < (1 << 20)
     f = lib.cdef_select_presets
 
-    def call(sse=P, npl=3, fbr=2, fbc=2, lam=1.0, ref=0, res=P, fl=P, fc=P, ws=W, wsb=n):
-        return f(sse, npl, fbr, fbc, lam, ref, res, fl, fc, ws, wsb, None)
+    def call(sse=P, npl=3, fbr=2, fbc=2, nc=64, lam=1.0, ref=0, res=P, fl=P, fc=P, ws=W, wsb=n):
+        return f(sse, npl, fbr, fbc, nc, lam, ref, res, fl, fc, ws, wsb, None)
 
     assert call(sse=None) == -1
     assert call(res=None) == -1
@@ -141,6 +144,7 @@ def test_select_presets_argument_checks(lib):
     assert call(wsb=n - 1) == -1
     assert call(ws=C.c_void_p(0x20008)) == -1
     assert call(npl=2) == -1
+    assert call(nc=0) == -1 and call(nc=65) == -1 and call(nc=256) == -1
     assert call(fbr=0) == -1
     assert call(fbc=-1) == -1
     assert call(lam=-1.0) == -1
@@ -149,3 +153,4 @@ def test_select_presets_argument_checks(lib):
     assert call(ref=-1) == -1
     assert call(ref=17) == -1
     assert call(npl=1, fbr=4097, fbc=4097) == -2
+    assert call(npl=1, fbr=4097, fbc=4097, nc=128) == -2
