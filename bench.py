@@ -33,6 +33,11 @@ sys.path.insert(0, ROOT)
 OPS_PER_FILTERED_SAMPLE = 1064
 OPS_PER_SKIPPED_SAMPLE = 3
 OPS_PER_LUMA_PX_DIRSEARCH = 10
+# The 128-combination search adds, per filtered sample, the (19, 7) preset
+# (4 primary taps x 6 + 8 secondary taps x 6 + 8 to combine), and per sample
+# the unfiltered difference, square and accumulate over the whole block.
+OPS_PER_SPECIAL_SAMPLE = 80
+OPS_PER_SAMPLE_UNFILTERED = 3
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T int32 lane-ops/s;
 # packed 16-bit instructions do two element operations per lane.
 PEAK_PACKED_I16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -52,23 +57,38 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def frame_work(fr):
-    """(algorithmic ops, algorithmic HBM bytes) of one fused search launch."""
+def frame_work(fr, full=False):
+    """(algorithmic ops, algorithmic HBM bytes) of one fused search launch
+    (full: the 128-combination search, where the skipped blocks of filter
+    blocks with residual are filtered under every preset too)."""
     filtered = skipped = 0
     sk = fr.skip.astype(bool)
+    fb_all = np.zeros((fr.fb_rows, fr.fb_cols), bool)
+    for by in range(fr.fb_rows):
+        for bx in range(fr.fb_cols):
+            fb_all[by, bx] = sk[8 * by:8 * by + 8, 8 * bx:8 * bx + 8].all()
     for p in range(fr.nplanes):
         w, h = fr.plane_dims(p)
         bs = 8 if p == 0 else 4
-        full = np.repeat(np.repeat(sk, bs, axis=0), bs, axis=1)[:h, :w]
-        n_sk = int(full.sum())
+        fs = 64 if p == 0 else 32
+        if full:  # every sample of a filter block with residual is filtered
+            allsk = np.repeat(np.repeat(fb_all, fs, axis=0), fs, axis=1)[:h, :w]
+            n_sk = int(allsk.sum())
+        else:
+            px_sk = np.repeat(np.repeat(sk, bs, axis=0), bs, axis=1)[:h, :w]
+            n_sk = int(px_sk.sum())
         skipped += n_sk
         filtered += w * h - n_sk
-    ops = (OPS_PER_FILTERED_SAMPLE * filtered + OPS_PER_SKIPPED_SAMPLE * skipped
+    per_filtered = OPS_PER_FILTERED_SAMPLE + (OPS_PER_SPECIAL_SAMPLE if full else 0)
+    ops = (per_filtered * filtered + OPS_PER_SKIPPED_SAMPLE * skipped
            + OPS_PER_LUMA_PX_DIRSEARCH * fr.width * fr.height)
     samples = filtered + skipped
+    if full:
+        ops += OPS_PER_SAMPLE_UNFILTERED * samples
     nfb = fr.fb_rows * fr.fb_cols
     nblk = fr.blk_rows * fr.blk_cols
-    bytes_ = 2 * 2 * samples + nblk + nfb * 64 * 8 * fr.nplanes + 5 * nblk
+    ncand = 128 if full else 64
+    bytes_ = 2 * 2 * samples + nblk + nfb * ncand * 8 * fr.nplanes + 5 * nblk
     return ops, bytes_
 
 
@@ -223,6 +243,74 @@ def run_batching(args):
     print(json.dumps(res), flush=True)
 
 
+def run_presets(args):
+    """Preset selection (Eq. 15) on the strength-search tables of the eight
+    4K frames, 64 and 128 candidates, without and with two refinement
+    passes: device time per frame from HIP events, and the oracle's time on
+    one table."""
+    import torch
+    from paper_1602_05975_amd import cdef, synth
+    from oracle import oracle
+    log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
+    frames = synth.config2(args.frames)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    tables = {64: [], 128: []}
+    for fr in frames:
+        rec = cdef.Frame.from_numpy(fr.recon, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
+        src = cdef.Frame.from_numpy(fr.src, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
+        skip = torch.from_numpy(fr.skip).to(dev)
+        for nc in (64, 128):
+            tables[nc].append(cdef.search_strengths(rec, src, skip, fr.damping, full=nc == 128))
+    torch.cuda.synchronize()
+    lam = 2.0e4
+    res = torch.zeros(360, dtype=torch.uint8, device=dev)
+    ws = cdef.preset_workspace(dev)
+    fbr, fbc = frames[0].fb_rows, frames[0].fb_cols
+    fl = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
+    fc = torch.empty_like(fl)
+    out = {"workload": f"{args.frames} tables of 3840x2160 10-bit 4:2:0 frames "
+                       f"({fbr}x{fbc} filter blocks, 3 planes), lambda {lam}",
+           "cases": []}
+    for nc in (64, 128):
+        for refine in (0, 2):
+            def one(t):
+                cdef.cdef_select_presets(t, lam, refine, res, fl, fc, ws, stream)
+            for t in tables[nc][:2]:
+                one(t)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+            for k in range(args.steps):
+                t = tables[nc][k % len(tables[nc])]
+                ev[k][0].record(stream)
+                one(t)
+                ev[k][1].record(stream)
+            torch.cuda.synchronize()
+            us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+            table = tables[nc][0].cpu().numpy().view(np.uint64)
+            t0 = time.perf_counter()
+            ref = oracle.select_presets(table, lam, refine)
+            t_cpu = time.perf_counter() - t0
+            cdef.cdef_select_presets(tables[nc][0], lam, refine, res, fl, fc, ws, stream)
+            torch.cuda.synchronize()
+            r = cdef.CdefPresetResult.from_buffer_copy(res.cpu().numpy().tobytes())
+            exact = (r.n == ref["n"] and np.array_equal(np.array(r.luma), ref["luma"])
+                     and np.array_equal(np.array(r.chroma), ref["chroma"])
+                     and np.array_equal(fl.cpu().numpy(), ref["fb_luma"])
+                     and np.array_equal(fc.cpu().numpy(), ref["fb_chroma"]))
+            table_bytes = table.nbytes
+            out["cases"].append({
+                "candidates": nc, "refine_passes": refine, "chosen_n": int(r.n),
+                "us_per_frame_p50": round(float(np.percentile(us, 50)), 1),
+                "us_per_frame_mean": round(float(us.mean()), 1),
+                "table_bytes": int(table_bytes),
+                "table_read_gbs": round(table_bytes / (us.mean() * 1e-6) / 1e9, 1),
+                "oracle_ms_1_thread": round(t_cpu * 1e3, 1),
+                "bit_exact_vs_oracle": bool(exact)})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -232,8 +320,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-frame", action="store_true",
                     help="one cdef_search_strengths launch per frame instead of one batch")
-    ap.add_argument("--workload", choices=["search4k", "batch", "serve"], default="search4k",
-                    help="search4k: the headline line (default); batch: 64 mixed frames, "
+    ap.add_argument("--workload", choices=["search4k", "search128", "presets", "batch", "serve"],
+                    default="search4k",
+                    help="search4k: the headline line (default); search128: the same frames "
+                         "under the 128-combination search; presets: Eq. (15) preset "
+                         "selection on their tables; batch: 64 mixed frames, "
                          "per-frame launches vs one tuned, graph-replayed batch; serve: "
                          "Poisson request stream, continuous batching vs one request per "
                          "launch")
@@ -265,11 +356,14 @@ def main():
     if args.workload == "serve":
         from paper_1602_05975_amd import serve
         return serve.bench_main(args)
+    if args.workload == "presets":
+        return run_presets(args)
+    full = args.workload == "search128"
 
     log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
     frames = synth.config2(args.frames)
-    ops = sum(frame_work(f)[0] for f in frames)
-    algo_bytes = sum(frame_work(f)[1] for f in frames)
+    ops = sum(frame_work(f, full)[0] for f in frames)
+    algo_bytes = sum(frame_work(f, full)[1] for f in frames)
 
     dev = torch.device("cuda:0")
     jobs = []
@@ -277,19 +371,20 @@ def main():
         rec = cdef.Frame.from_numpy(fr.recon, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
         src = cdef.Frame.from_numpy(fr.src, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
         skip = torch.from_numpy(fr.skip).to(dev)
-        sse = torch.empty((fr.nplanes, fr.fb_rows, fr.fb_cols, 16, 4), dtype=torch.int64,
-                          device=dev)
+        shape = (fr.nplanes, fr.fb_rows, fr.fb_cols) + ((2, 16, 4) if full else (16, 4))
+        sse = torch.empty(shape, dtype=torch.int64, device=dev)
         d = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.uint8, device=dev)
         v = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.int32, device=dev)
         jobs.append((rec, src, skip, fr.damping, sse, d, v))
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
+    search_one = cdef.cdef_search_strengths128 if full else cdef.cdef_search_strengths
     batch = None
     if not args.per_frame:
         batch = cdef.Batch()
         for (rec, src, skip, D, sse, d, v) in jobs:
-            batch.add_search(rec, src, skip, D, sse, d, v)
+            batch.add_search(rec, src, skip, D, sse, d, v, full=full)
         batch.prepare(stream)
         torch.cuda.synchronize()
 
@@ -305,7 +400,7 @@ def main():
         for k, (rec, src, skip, D, sse, d, v) in enumerate(jobs):
             if events is not None:
                 events[k][0].record(stream)
-            cdef.cdef_search_strengths(rec, src, skip, D, sse, d, v, stream)
+            search_one(rec, src, skip, D, sse, d, v, stream)
             if events is not None:
                 events[k][1].record(stream)
 
@@ -334,9 +429,13 @@ def main():
     bytes_per_launch = algo_bytes / launches_per_step
     achieved = ops_per_launch / avg_launch_s / 1e12
     frame_ms = launch_ms if batch is None else launch_ms  # a batch's frames finish together
-    traffic = load_traffic("k_fused_batch" if batch is not None else "k_fused_one")
+    kname = "k_fused_batch" if batch is not None else "k_fused_one"
+    traffic = load_traffic(kname + ("_full" if full else ""))
+    what = ("all 128 (primary, secondary, skip condition) presets" if full else
+            "all 64 (primary, secondary) strength pairs")
     result = {
-        "metric": "Mpixel/s for dir+filter+all-strength SSE search, 4K 10-bit; p99 frame latency",
+        "metric": ("Mpixel/s for dir+filter+128-combination SSE search, 4K 10-bit" if full else
+                   "Mpixel/s for dir+filter+all-strength SSE search, 4K 10-bit; p99 frame latency"),
         "value": round(value, 1),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -350,8 +449,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{len(frames)}x3840x2160 10-bit 4:2:0 frames, 30% of 8x8 blocks "
-                        "skipped, damping 3: fused direction search + filter under all 64 "
-                        "(primary, secondary) strength pairs + per-64x64 SSE, "
+                        f"skipped, damping 3: fused direction search + filter under {what} "
+                        "+ per-64x64 SSE, "
                         + ("one launch per frame" if batch is None else
                            "one batched launch per step"),
             "frames_per_step": len(frames),
@@ -370,13 +469,13 @@ def main():
             "unit": "TOP/s",
             "frac": round(achieved / PEAK_PACKED_I16_TOPS, 4),
             "traffic": traffic,
-            "kernel": "k_fused_batch" if batch is not None else "k_fused_one",
+            "kernel": kname,
             "algorithmic_ops_per_launch": int(ops_per_launch),
             "hbm_gbs_algorithmic": round(bytes_per_launch / avg_launch_s / 1e9, 1),
             "hbm_peak_gbs": PEAK_HBM_GBS,
         },
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not full:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(frames[0])
     print(json.dumps(result), flush=True)
