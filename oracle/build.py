@@ -13,7 +13,7 @@ CFLAGS = ["-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared"]
 
 def build(extra_flags=(), out=LIB):
     src = os.path.join(HERE, "cdef_oracle.c")
-    cmd = ["gcc", *CFLAGS, *extra_flags, src, "-o", out + ".tmp"]
+    cmd = ["gcc", *CFLAGS, *extra_flags, src, "-o", out + ".tmp", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out

@@ -63,9 +63,17 @@
  *      a luma block whose adjusted strength reaches 16..19 takes
  *      floor(log2 S) = 4 as its damping for both tap groups, as the chroma
  *      rule R13 does.
+ *  R19 Eq. (14): the "8x8 block" is CDEF's filtering unit (an 8x8 luma
+ *      block; at 4:2:0 its co-located 4x4 chroma block), over its in-frame
+ *      pixels; sigma^2 are population variances (divided by the pixel
+ *      count); C1 = 6.25 and C2 = 312.5 at 8 bits scale by 4^(b-8) and
+ *      16^(b-8), the factors by which variances and their products grow, so
+ *      that the weight of a frame does not change when every sample is
+ *      multiplied by 2^(b-8).  Evaluated in double precision.
  */
 #include "cdef_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 
 /* ---- Section 2: direction search ---------------------------------------- */
@@ -345,6 +353,75 @@ void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_fr
           }
           sse[((p * nskip + k) * 16 + pri_sig) * 4 + si] = acc;
         }
+      }
+    }
+  }
+}
+
+/* Section 5, Eq. (14), R19: the contrast-weighted distortion of one filter
+ * block for the 64 pairs (skip condition bit off).  Each pair filters the
+ * whole block into a scratch copy, then every filtering unit contributes
+ * (sigma_s^2 + sigma_d^2 + C1) / (2 sqrt(sigma_s^2 sigma_d^2 + C2)) ||s - d||^2. */
+void cdef_oracle_search_fb_weighted(const cdef_oracle_frame *recon,
+                                    const cdef_oracle_frame *src, const uint8_t *dir,
+                                    const int32_t *var, const uint8_t *skip, int damping,
+                                    int fby, int fbx, double *dist) {
+  int bcols = (recon->width + 7) / 8;
+  int c = recon->bitdepth - 8;
+  double C1 = 6.25 * pow(4.0, c), C2 = 312.5 * pow(16.0, c);
+  int all_skipped = fb_skipped(recon, skip, fby, fbx);
+  int filtered[64 * 64];
+  for (int p = 0; p < recon->nplanes; p++) {
+    int pw, ph, ss;
+    plane_geometry(recon, p, &pw, &ph, &ss);
+    int bs = 8 >> ss, fs = 64 >> ss;
+    int i0 = fby * fs, j0 = fbx * fs;
+    int i1 = imin(i0 + fs, ph), j1 = imin(j0 + fs, pw);
+    for (int pri = 0; pri < 16; pri++) {
+      for (int si = 0; si < 4; si++) {
+        for (int i = i0; i < i1; i++) {
+          for (int j = j0; j < j1; j++) {
+            int b = (i / bs) * bcols + (j / bs);
+            int x = recon->plane[p][(int64_t)i * recon->stride[p] + j];
+            int y = x;
+            if (!all_skipped && !(skip && skip[b])) {
+              block_params bp =
+                  params_for(p, recon->bitdepth, damping, pri, SEC_STRENGTHS[si], var[b]);
+              y = cdef_oracle_filter_pixel(recon->plane[p], recon->stride[p], pw, ph, i, j,
+                                           dir[b], bp.pri_s, bp.pri_d, bp.w1, bp.w2,
+                                           bp.sec_s, bp.sec_d);
+            }
+            filtered[(i - i0) * 64 + (j - j0)] = y;
+          }
+        }
+        double total = 0.0;
+        for (int ui = i0; ui < i1; ui += bs) {
+          for (int uj = j0; uj < j1; uj += bs) {
+            int n = 0;
+            double ms = 0.0, md = 0.0;
+            for (int i = ui; i < imin(ui + bs, i1); i++)
+              for (int j = uj; j < imin(uj + bs, j1); j++) {
+                ms += src->plane[p][(int64_t)i * src->stride[p] + j];
+                md += filtered[(i - i0) * 64 + (j - j0)];
+                n++;
+              }
+            ms /= n;
+            md /= n;
+            double vs = 0.0, vd = 0.0, e2 = 0.0;
+            for (int i = ui; i < imin(ui + bs, i1); i++)
+              for (int j = uj; j < imin(uj + bs, j1); j++) {
+                double sv = src->plane[p][(int64_t)i * src->stride[p] + j];
+                double dv = filtered[(i - i0) * 64 + (j - j0)];
+                vs += (sv - ms) * (sv - ms);
+                vd += (dv - md) * (dv - md);
+                e2 += (sv - dv) * (sv - dv);
+              }
+            vs /= n;
+            vd /= n;
+            total += (vs + vd + C1) / (2.0 * sqrt(vs * vd + C2)) * e2;
+          }
+        }
+        dist[(p * 16 + pri) * 4 + si] = total;
       }
     }
   }

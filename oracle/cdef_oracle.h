@@ -13,7 +13,8 @@
  *   Section 3.2, Eq. (13) ..................... strength ranges, bit depth,
  *                                               chroma damping, adjustment
  *   Section 4 ................................. 64x64 filter blocks, skip
- *   Section 5 ................................. per-filter-block SSE D_{b,p}
+ *   Section 5 ................................. per-filter-block SSE D_{b,p},
+ *                                               Eq. (14) weighting, Eq. (15) presets
  *
  * Readings of points where the paper is silent or garbled are listed in the
  * source file next to the code that takes them.
@@ -93,6 +94,15 @@ void cdef_oracle_search_fb(const cdef_oracle_frame *recon, const cdef_oracle_fra
 void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
                             const uint8_t *dir, const int32_t *var, const uint8_t *skip,
                             int damping, int nskip, int fby, int fbx, uint64_t *sse);
+
+/* Section 5, Eq. (14): the contrast-weighted distortion of filter block
+ * (fby, fbx) for the 64 pairs (skip condition bit off), summed over the
+ * block's filtering units (8x8 luma, 4x4 chroma at 4:2:0); C1 = 6.25 * 4^(b-8),
+ * C2 = 312.5 * 16^(b-8).  dist is double [nplanes][16][4]. */
+void cdef_oracle_search_fb_weighted(const cdef_oracle_frame *recon,
+                                    const cdef_oracle_frame *src, const uint8_t *dir,
+                                    const int32_t *var, const uint8_t *skip, int damping,
+                                    int fby, int fbx, double *dist);
 
 /* The whole-frame search: find_dir, then every filter block.
  * sse is [nplanes][ceil(h/64)][ceil(w/64)][16][4]; dir/var as find_dir. */

@@ -65,6 +65,10 @@ def lib():
         L.cdef_oracle_search_fb2.argtypes = [C.POINTER(OracleFrame), C.POINTER(OracleFrame), P,
                                              P, P, C.c_int, C.c_int, C.c_int, C.c_int, P]
         L.cdef_oracle_search_fb2.restype = None
+        L.cdef_oracle_search_fb_weighted.argtypes = [C.POINTER(OracleFrame),
+                                                     C.POINTER(OracleFrame), P, P, P, C.c_int,
+                                                     C.c_int, C.c_int, P]
+        L.cdef_oracle_search_fb_weighted.restype = None
         L.cdef_oracle_select_presets.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
                                                  P, P, P, P, P, P, P]
         L.cdef_oracle_select_presets.restype = None
@@ -192,6 +196,37 @@ def search(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, h
     t = t.reshape((fbr, fbc, len(recon)) + t.shape[2:])
     sse = np.moveaxis(t, 2, 0)
     return np.ascontiguousarray(sse), d, v
+
+
+def search_fbs_weighted(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int,
+                        height: int, bitdepth: int, dir: np.ndarray, var: np.ndarray,
+                        skip: Optional[np.ndarray], damping: int, fbs,
+                        threads: int = 1) -> np.ndarray:
+    """Eq. (14) distortion tables, float64 [len(fbs)][nplanes][16][4]."""
+    recon = [np.ascontiguousarray(p, dtype=np.uint16) for p in recon]
+    src = [np.ascontiguousarray(p, dtype=np.uint16) for p in src]
+    fr = _frame(recon, width, height, bitdepth)
+    fs = _frame(src, width, height, bitdepth)
+    dir = np.ascontiguousarray(dir, dtype=np.uint8)
+    var = np.ascontiguousarray(var, dtype=np.int32)
+    sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
+    fbs = list(fbs)
+    out = np.zeros((len(fbs), len(recon), 16, 4), dtype=np.float64)
+    L = lib()
+
+    def one(k):
+        by, bx = fbs[k]
+        L.cdef_oracle_search_fb_weighted(C.byref(fr), C.byref(fs), dir.ctypes.data,
+                                         var.ctypes.data, _ptr(sk), damping, by, bx,
+                                         out[k].ctypes.data)
+
+    if threads <= 1:
+        for k in range(len(fbs)):
+            one(k)
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, range(len(fbs))))
+    return out
 
 
 def select_presets(sse: np.ndarray, lam: float, refine_passes: int = 0) -> dict:
