@@ -38,6 +38,12 @@ OPS_PER_LUMA_PX_DIRSEARCH = 10
 # the unfiltered difference, square and accumulate over the whole block.
 OPS_PER_SPECIAL_SAMPLE = 80
 OPS_PER_SAMPLE_UNFILTERED = 3
+# The weighted search (Eq. 14) keeps the 7 per-pair operations before the
+# square and, per pair, forms d = e + s, d^2 and e^2 and sums d, d^2, e^2
+# over the unit (13 instead of 8), and takes 6 source/reconstruction moments
+# per sample; the per-unit double-precision weights are not counted.
+OPS_PER_FILTERED_SAMPLE_W = OPS_PER_FILTERED_SAMPLE + 64 * (13 - 8)
+OPS_PER_SAMPLE_MOMENTS = 6
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T int32 lane-ops/s;
 # packed 16-bit instructions do two element operations per lane.
 PEAK_PACKED_I16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -57,7 +63,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def frame_work(fr, full=False):
+def frame_work(fr, full=False, weighted=False):
     """(algorithmic ops, algorithmic HBM bytes) of one fused search launch
     (full: the 128-combination search, where the skipped blocks of filter
     blocks with residual are filtered under every preset too)."""
@@ -80,11 +86,15 @@ def frame_work(fr, full=False):
         skipped += n_sk
         filtered += w * h - n_sk
     per_filtered = OPS_PER_FILTERED_SAMPLE + (OPS_PER_SPECIAL_SAMPLE if full else 0)
+    if weighted:
+        per_filtered = OPS_PER_FILTERED_SAMPLE_W
     ops = (per_filtered * filtered + OPS_PER_SKIPPED_SAMPLE * skipped
            + OPS_PER_LUMA_PX_DIRSEARCH * fr.width * fr.height)
     samples = filtered + skipped
     if full:
         ops += OPS_PER_SAMPLE_UNFILTERED * samples
+    if weighted:
+        ops += OPS_PER_SAMPLE_MOMENTS * samples
     nfb = fr.fb_rows * fr.fb_cols
     nblk = fr.blk_rows * fr.blk_cols
     ncand = 128 if full else 64
@@ -320,10 +330,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-frame", action="store_true",
                     help="one cdef_search_strengths launch per frame instead of one batch")
-    ap.add_argument("--workload", choices=["search4k", "search128", "presets", "batch", "serve"],
+    ap.add_argument("--workload", choices=["search4k", "search128", "weighted", "presets", "batch",
+                                           "serve"],
                     default="search4k",
                     help="search4k: the headline line (default); search128: the same frames "
-                         "under the 128-combination search; presets: Eq. (15) preset "
+                         "under the 128-combination search; weighted: the same frames with the "
+                         "Eq. (14) distortion; presets: Eq. (15) preset "
                          "selection on their tables; batch: 64 mixed frames, "
                          "per-frame launches vs one tuned, graph-replayed batch; serve: "
                          "Poisson request stream, continuous batching vs one request per "
@@ -359,11 +371,12 @@ def main():
     if args.workload == "presets":
         return run_presets(args)
     full = args.workload == "search128"
+    weighted = args.workload == "weighted"
 
     log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
     frames = synth.config2(args.frames)
-    ops = sum(frame_work(f, full)[0] for f in frames)
-    algo_bytes = sum(frame_work(f, full)[1] for f in frames)
+    ops = sum(frame_work(f, full, weighted)[0] for f in frames)
+    algo_bytes = sum(frame_work(f, full, weighted)[1] for f in frames)
 
     dev = torch.device("cuda:0")
     jobs = []
@@ -372,19 +385,20 @@ def main():
         src = cdef.Frame.from_numpy(fr.src, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
         skip = torch.from_numpy(fr.skip).to(dev)
         shape = (fr.nplanes, fr.fb_rows, fr.fb_cols) + ((2, 16, 4) if full else (16, 4))
-        sse = torch.empty(shape, dtype=torch.int64, device=dev)
+        sse = torch.empty(shape, dtype=torch.float64 if weighted else torch.int64, device=dev)
         d = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.uint8, device=dev)
         v = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.int32, device=dev)
         jobs.append((rec, src, skip, fr.damping, sse, d, v))
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
-    search_one = cdef.cdef_search_strengths128 if full else cdef.cdef_search_strengths
+    search_one = (cdef.cdef_search_weighted if weighted else
+                  cdef.cdef_search_strengths128 if full else cdef.cdef_search_strengths)
     batch = None
     if not args.per_frame:
         batch = cdef.Batch()
         for (rec, src, skip, D, sse, d, v) in jobs:
-            batch.add_search(rec, src, skip, D, sse, d, v, full=full)
+            batch.add_search(rec, src, skip, D, sse, d, v, full=full, weighted=weighted)
         batch.prepare(stream)
         torch.cuda.synchronize()
 
@@ -430,11 +444,15 @@ def main():
     achieved = ops_per_launch / avg_launch_s / 1e12
     frame_ms = launch_ms if batch is None else launch_ms  # a batch's frames finish together
     kname = "k_fused_batch" if batch is not None else "k_fused_one"
-    traffic = load_traffic(kname + ("_full" if full else ""))
+    traffic = load_traffic(kname + ("_full" if full else "_weighted" if weighted else ""))
     what = ("all 128 (primary, secondary, skip condition) presets" if full else
             "all 64 (primary, secondary) strength pairs")
+    if weighted:
+        what += " with the Eq. (14) contrast-weighted distortion (float64 table)"
     result = {
         "metric": ("Mpixel/s for dir+filter+128-combination SSE search, 4K 10-bit" if full else
+                   "Mpixel/s for dir+filter+all-strength Eq. (14) weighted search, 4K 10-bit"
+                   if weighted else
                    "Mpixel/s for dir+filter+all-strength SSE search, 4K 10-bit; p99 frame latency"),
         "value": round(value, 1),
         "unit": "Mpixel/s",
@@ -475,7 +493,7 @@ def main():
             "hbm_peak_gbs": PEAK_HBM_GBS,
         },
     }
-    if not args.no_cpu_baseline and not full:
+    if not args.no_cpu_baseline and not full and not weighted:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(frames[0])
     print(json.dumps(result), flush=True)

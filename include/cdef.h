@@ -145,14 +145,36 @@ cdef_status cdef_search_strengths128(const cdef_frame *recon, const cdef_frame *
                                      const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
                                      uint8_t *dir, int32_t *var, void *stream);
 
+/* The strength search with the contrast-weighted distortion of Section 5,
+ * Eq. (14), instead of the SSE: for every filter block, plane and pair,
+ *   sum over filtering units of
+ *   (sigma_s^2 + sigma_d^2 + C1) / (2 sqrt(sigma_s^2 sigma_d^2 + C2)) ||s - d||^2,
+ * where a filtering unit is an 8x8 luma block or its co-located 4x4 chroma
+ * block (4:2:0), sigma^2 are population variances over the unit's in-frame
+ * pixels, and C1 = 6.25 * 4^(b-8), C2 = 312.5 * 16^(b-8).  The moments are
+ * summed exactly in integers and the weight is evaluated in double
+ * precision (relative difference to a direct double evaluation ~1e-15).
+ *   dist: double [nplanes][ceil(h/64)][ceil(w/64)][16][4] (skip condition
+ *         bit off: skipped units enter unfiltered).
+ * Other arguments and errors as cdef_search_strengths. */
+cdef_status cdef_search_weighted(const cdef_frame *recon, const cdef_frame *src,
+                                 const uint8_t *skip8x8, int32_t damping, double *dist,
+                                 uint8_t *dir, int32_t *var, void *stream);
+
 /* ---- Batches ----------------------------------------------------------------
  * Many frames -- of any size, bit depth 8 or 10 and damping -- in one launch
  * over all their 64x64 filter blocks.  Each job is the strength search of
- * cdef_search_strengths, the full search of cdef_search_strengths128, or the
- * direction search + filter of one frame at its own per-filter-block presets
- * (cdef_find_dir followed by cdef_filter_frame, fused).  Results are bit-identical to the per-frame
+ * cdef_search_strengths, the full search of cdef_search_strengths128, the
+ * weighted search of cdef_search_weighted, or the direction search + filter
+ * of one frame at its own per-filter-block presets (cdef_find_dir followed by
+ * cdef_filter_frame, fused).  Results are bit-identical to the per-frame
  * entry points. */
-enum { CDEF_MODE_SEARCH = 0, CDEF_MODE_FILTER = 1, CDEF_MODE_SEARCH128 = 2 };
+enum {
+  CDEF_MODE_SEARCH = 0,
+  CDEF_MODE_FILTER = 1,
+  CDEF_MODE_SEARCH128 = 2,
+  CDEF_MODE_SEARCH_WEIGHTED = 3
+};
 
 typedef struct {
   cdef_frame recon;          /* input frame */
@@ -160,11 +182,13 @@ typedef struct {
   cdef_frame_out out;        /* filter: output planes (must not overlap recon); search: ignored */
   const uint8_t *skip8x8;    /* NULL = no skipped block */
   const cdef_strength *fb;   /* filter: per-filter-block strengths; search: ignored */
-  uint64_t *sse;             /* searches: table as cdef_search_strengths(128); filter: ignored */
+  uint64_t *sse;             /* searches: table as cdef_search_strengths(128); weighted: the
+                                double table of cdef_search_weighted; filter: ignored */
   uint8_t *dir;              /* optional direction-search outputs (both or neither) */
   int32_t *var;
   int32_t damping;           /* luma D, 3..6 */
-  int32_t mode;              /* CDEF_MODE_SEARCH, CDEF_MODE_SEARCH128 or CDEF_MODE_FILTER */
+  int32_t mode;              /* CDEF_MODE_SEARCH, CDEF_MODE_SEARCH128, CDEF_MODE_SEARCH_WEIGHTED
+                                or CDEF_MODE_FILTER */
 } cdef_job;
 
 /* What cdef_batch_prepare leaves for cdef_batch_launch (host memory, owned by
@@ -174,7 +198,8 @@ typedef struct {
   int32_t njobs;
   int32_t nitems;     /* filter blocks over all jobs */
   int32_t variant;    /* launch variant 0..CDEF_BATCH_VARIANTS-1 (see below), 0 = default */
-  int32_t reserved;
+  int32_t flags;      /* set by cdef_batch_prepare (bit 0: a job is a weighted search, whose
+                         kernels run at 2 waves per SIMD whatever the variant); keep */
 } cdef_batch_plan;
 
 /* Host-side checks of one job, exactly those cdef_batch_prepare applies to each

@@ -29,6 +29,7 @@ EXPORTS = (
     "cdef_filter_frame",
     "cdef_search_strengths",
     "cdef_search_strengths128",
+    "cdef_search_weighted",
     "cdef_batch_workspace_bytes",
     "cdef_batch_prepare",
     "cdef_batch_launch",
@@ -41,6 +42,7 @@ EXPORTS = (
 MODE_SEARCH = 0
 MODE_FILTER = 1
 MODE_SEARCH128 = 2
+MODE_SEARCH_WEIGHTED = 3
 SKIP_CONDITION = 0x80  # bit 7 of a secondary-strength byte
 
 
@@ -80,7 +82,7 @@ class CdefBatchPlan(C.Structure):
         ("njobs", C.c_int32),
         ("nitems", C.c_int32),
         ("variant", C.c_int32),
-        ("reserved", C.c_int32),
+        ("flags", C.c_int32),
     ]
 
 
@@ -125,6 +127,8 @@ def load(path: str = LIB_PATH):
     L.cdef_search_strengths.restype = C.c_int
     L.cdef_search_strengths128.argtypes = L.cdef_search_strengths.argtypes
     L.cdef_search_strengths128.restype = C.c_int
+    L.cdef_search_weighted.argtypes = L.cdef_search_strengths.argtypes
+    L.cdef_search_weighted.restype = C.c_int
     L.cdef_batch_workspace_bytes.argtypes = [C.c_int32]
     L.cdef_batch_workspace_bytes.restype = C.c_size_t
     L.cdef_batch_prepare.argtypes = [C.POINTER(CdefJob), C.c_int32, P, P, C.c_size_t,
@@ -244,6 +248,14 @@ def cdef_search_strengths128(recon: Frame, src: Frame, skip, damping: int, sse, 
     _check(st, "cdef_search_strengths128")
 
 
+def cdef_search_weighted(recon: Frame, src: Frame, skip, damping: int, dist, dir=None, var=None,
+                         stream=None) -> None:
+    st = load().cdef_search_weighted(C.byref(recon.c_struct()), C.byref(src.c_struct()),
+                                     _ptr(skip), damping, _ptr(dist), _ptr(dir), _ptr(var),
+                                     _stream_handle(stream))
+    _check(st, "cdef_search_weighted")
+
+
 # ---- allocating conveniences -------------------------------------------------
 
 def find_dir(frame: Frame, stream=None):
@@ -263,19 +275,22 @@ def filter_frame(frame: Frame, dir, var, skip, damping: int, fb, stream=None):
 
 
 def search_strengths(recon: Frame, src: Frame, skip, damping: int, want_dir=False, stream=None,
-                     full=False):
+                     full=False, weighted=False):
     """SSE table [nplanes][fbr][fbc][16][4], or with full=True the 128
-    combinations [nplanes][fbr][fbc][2][16][4] (skip condition bit 0, 1)."""
+    combinations [nplanes][fbr][fbc][2][16][4] (skip condition bit 0, 1), or
+    with weighted=True the Eq. (14) distortion as float64 [..][16][4]."""
     import torch
     dev = recon.planes[0].device
     fbr, fbc = recon.fb_shape
     shape = (recon.nplanes, fbr, fbc) + ((2, 16, 4) if full else (16, 4))
-    sse = torch.empty(shape, dtype=torch.int64, device=dev)
+    sse = torch.empty(shape, dtype=torch.float64 if weighted else torch.int64, device=dev)
     d = v = None
     if want_dir:
         d = torch.empty(recon.block_shape, dtype=torch.uint8, device=dev)
         v = torch.empty(recon.block_shape, dtype=torch.int32, device=dev)
-    fn = cdef_search_strengths128 if full else cdef_search_strengths
+    assert not (full and weighted), "the weighted search covers the 64 pairs"
+    fn = (cdef_search_weighted if weighted else
+          cdef_search_strengths128 if full else cdef_search_strengths)
     fn(recon, src, skip, damping, sse, d, v, stream)
     return (sse, d, v) if want_dir else sse
 
@@ -292,12 +307,13 @@ def _out_struct(out_planes) -> CdefFrameOut:
 
 
 def make_search_job(recon: Frame, src: Frame, skip, damping: int, sse, dir=None,
-                    var=None, full=False) -> CdefJob:
+                    var=None, full=False, weighted=False) -> CdefJob:
     j = CdefJob()
     j.recon, j.src = recon.c_struct(), src.c_struct()
     j.skip8x8, j.sse = _ptr(skip), _ptr(sse)
     j.dir, j.var = _ptr(dir), _ptr(var)
-    j.damping, j.mode = damping, MODE_SEARCH128 if full else MODE_SEARCH
+    j.damping = damping
+    j.mode = MODE_SEARCH_WEIGHTED if weighted else MODE_SEARCH128 if full else MODE_SEARCH
     return j
 
 
@@ -330,8 +346,9 @@ class Batch:
         self.staging = None
 
     def add_search(self, recon: Frame, src: Frame, skip, damping: int, sse, dir=None, var=None,
-                   full=False):
-        return self.add_job(make_search_job(recon, src, skip, damping, sse, dir, var, full),
+                   full=False, weighted=False):
+        return self.add_job(make_search_job(recon, src, skip, damping, sse, dir, var, full,
+                                            weighted),
                             (recon, src, skip, sse, dir, var))
 
     def add_filter(self, recon: Frame, out_planes, skip, damping: int, fb, dir=None, var=None):

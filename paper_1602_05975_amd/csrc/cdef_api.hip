@@ -14,7 +14,8 @@ static_assert(sizeof(cdef_preset_result) == sizeof(cdef::PresetResult), "preset 
 static_assert(offsetof(cdef_preset_result, cost) == offsetof(cdef::PresetResult, cost),
               "preset result layout");
 static_assert(CDEF_MODE_SEARCH == cdef::kModeSearch && CDEF_MODE_FILTER == cdef::kModeFilter &&
-                  CDEF_MODE_SEARCH128 == cdef::kModeSearchFull,
+                  CDEF_MODE_SEARCH128 == cdef::kModeSearchFull &&
+                  CDEF_MODE_SEARCH_WEIGHTED == cdef::kModeSearchWeighted,
               "job modes");
 
 namespace {
@@ -87,7 +88,8 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
     o->rec[p] = r.plane[p];
     o->rstride[p] = (int32_t)r.stride[p];
   }
-  const bool search = j->mode == CDEF_MODE_SEARCH || j->mode == CDEF_MODE_SEARCH128;
+  const bool search = j->mode == CDEF_MODE_SEARCH || j->mode == CDEF_MODE_SEARCH128 ||
+                      j->mode == CDEF_MODE_SEARCH_WEIGHTED;
   if (search) {
     FrameDesc s;
     st = check_frame(&j->src, &s);
@@ -215,6 +217,13 @@ cdef_status cdef_search_strengths128(const cdef_frame *recon, const cdef_frame *
   return search_one(recon, src, skip8x8, damping, sse, dir, var, CDEF_MODE_SEARCH128, stream);
 }
 
+cdef_status cdef_search_weighted(const cdef_frame *recon, const cdef_frame *src,
+                                 const uint8_t *skip8x8, int32_t damping, double *dist,
+                                 uint8_t *dir, int32_t *var, void *stream) {
+  return search_one(recon, src, skip8x8, damping, reinterpret_cast<uint64_t *>(dist), dir, var,
+                    CDEF_MODE_SEARCH_WEIGHTED, stream);
+}
+
 cdef_status cdef_job_validate(const cdef_job *job) {
   if (!job) return CDEF_E_INVAL;
   cdef::JobDesc d;
@@ -235,8 +244,10 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
                                       : (cdef::JobDesc *)malloc(need);
   if (!table) return CDEF_E_NOMEM;
   int64_t items = 0;
+  int32_t flags = 0;
   cdef_status st = CDEF_OK;
   for (int32_t i = 0; i < njobs && st == CDEF_OK; ++i) {
+    if (jobs[i].mode == CDEF_MODE_SEARCH_WEIGHTED) flags |= 1;
     st = make_job(&jobs[i], &table[i]);
     if (st == CDEF_OK) {
       table[i].item0 = (int32_t)items;
@@ -257,7 +268,7 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
   plan->njobs = njobs;
   plan->nitems = (int32_t)items;
   plan->variant = 0;
-  plan->reserved = 0;
+  plan->flags = flags;
   return CDEF_OK;
 }
 
@@ -265,7 +276,8 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
   if (!plan || !plan->table || plan->njobs < 1 || plan->nitems < 1) return CDEF_E_INVAL;
   if (plan->variant < 0 || plan->variant >= CDEF_BATCH_VARIANTS) return CDEF_E_INVAL;
   return from_hip(cdef::launch_fused_batch((const cdef::JobDesc *)plan->table, plan->njobs,
-                                           plan->nitems, plan->variant, (hipStream_t)stream));
+                                           plan->nitems, plan->variant, (plan->flags & 1) != 0,
+                                           (hipStream_t)stream));
 }
 
 size_t cdef_select_presets_workspace_bytes(void) { return cdef::preset_workspace_bytes(); }

@@ -15,7 +15,12 @@ struct FrameDesc {
   int nplanes;        // 1 (4:0:0) or 3 (4:2:0)
 };
 
-enum JobMode : int32_t { kModeSearch = 0, kModeFilter = 1, kModeSearchFull = 2 };
+enum JobMode : int32_t {
+  kModeSearch = 0,
+  kModeFilter = 1,
+  kModeSearchFull = 2,
+  kModeSearchWeighted = 3
+};
 enum JobFlags : int32_t { kAligned16 = 1 };
 
 // One frame of work as the fused kernel reads it (kernel argument for a
@@ -27,7 +32,8 @@ struct JobDesc {
   uint16_t *out[3];        // filter mode
   const uint8_t *skip;     // may be null
   const uint8_t *strengths;  // filter mode: [fbr][fbc][4]
-  uint64_t *sse;           // search modes: [nplanes][fbr][fbc][64] (full: [..][2][64])
+  uint64_t *sse;           // search modes: [nplanes][fbr][fbc][64] (full: [..][2][64];
+                           // weighted: double [..][64])
   uint8_t *dir;            // optional
   int32_t *var;            // optional
   int32_t rstride[3], sstride[3], ostride[3];
@@ -48,8 +54,9 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s);
 
 // Many frames: `jobs` is a device array of njobs descriptors (item0 set),
 // nitems the total number of filter blocks.
+// weighted: some job is a weighted search (kernels built for it).
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              hipStream_t s);
+                              bool weighted, hipStream_t s);
 
 void fill_job_geometry(JobDesc &j);
 

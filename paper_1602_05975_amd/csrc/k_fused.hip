@@ -7,6 +7,8 @@
 //    filtered pixels never leaving registers; the full search adds the 64
 //    presets with the skip condition bit set (Section 4: skipped 8x8 blocks
 //    filtered too; strengths 0, 0 standing for 19, 7), 128 in all;
+//  * weighted search (Section 5, Eq. 14): the 64 pairs with the
+//    contrast-weighted distortion instead of the SSE;
 //  * filter: direction search and the filter (Eq. 7-13) at the block's own
 //    strengths, writing the filtered planes.
 //
@@ -143,19 +145,17 @@ __device__ __forceinline__ s16x2 secondary(const Taps &t, uint32_t s, uint32_t s
 }
 
 // One (S^(p), S^(s)) pair with both groups possibly active: round the sum
-// of P and Q ties-away-from-zero, add to x - s, clamp, square-accumulate.
-__device__ __forceinline__ int pair_both(const Taps &t, s16x2 P, s16x2 Q, int acc) {
+// of P and Q ties-away-from-zero, add to x - s, clamp; returns y - s.
+__device__ __forceinline__ s16x2 err_both(const Taps &t, s16x2 P, s16x2 Q) {
   const s16x2 sum = P + Q;
-  s16x2 y = (t.X + sum + (sum >> splat(15))) >> splat(4);
-  y = __builtin_elementwise_min(__builtin_elementwise_max(y, t.lo), t.hi);
-  return __builtin_amdgcn_sdot2(y, y, acc, false);
+  const s16x2 y = (t.X + sum + (sum >> splat(15))) >> splat(4);
+  return __builtin_elementwise_min(__builtin_elementwise_max(y, t.lo), t.hi);
 }
 
 // A pair with only one tap group: its weights sum to 12/16 < 1, so the
 // result cannot leave the clamp range and the clamp is skipped.
-__device__ __forceinline__ int pair_one(const Taps &t, s16x2 P, int acc) {
-  const s16x2 y = (t.X + P + (P >> splat(15))) >> splat(4);
-  return __builtin_amdgcn_sdot2(y, y, acc, false);
+__device__ __forceinline__ s16x2 err_one(const Taps &t, s16x2 P) {
+  return (t.X + P + (P >> splat(15))) >> splat(4);
 }
 
 // Secondary sums for S^(s) = 1, 2, 4 at damping `damp` (8-bit domain).
@@ -168,8 +168,7 @@ __device__ __forceinline__ void secondaries(const Taps &t, int c, int damp, s16x
 // The special preset (Section 4) on a luma task: S^(p) = 19 adjusted per
 // block by Eq. (13) (a19A, a19B), S^(s) = 7, each block's damping raised to
 // floor(log2 S) when lower.
-__device__ __forceinline__ int luma_special(const Taps &t, int a19A, int a19B, int c, int D,
-                                            int acc) {
+__device__ __forceinline__ s16x2 luma_special(const Taps &t, int a19A, int a19B, int c, int D) {
   const int dA = luma_damping(D, a19A), dB = luma_damping(D, a19B);
   const uint32_t sp = ((uint32_t)a19A << c) | ((uint32_t)a19B << (16 + c));
   const uint32_t sh = (uint32_t)(a19A ? dA - floor_log2(a19A) : 0) |
@@ -181,37 +180,38 @@ __device__ __forceinline__ int luma_special(const Taps &t, int a19A, int a19B, i
   for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
   const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
   const s16x2 Q = secondary(t, splat32(7u << c), (uint32_t)(dA - 2) | ((uint32_t)(dB - 2) << 16));
-  return pair_both(t, P, Q, acc);
+  return err_both(t, P, Q);
 }
 
 // The special preset on a chroma task: 19 (odd: weights 3, 3) and 7 at the
 // chroma damping max(D - 1, floor(log2 19) = 4).
-__device__ __forceinline__ int chroma_special(const Taps &t, int c, int D, int acc) {
+__device__ __forceinline__ s16x2 chroma_special(const Taps &t, int c, int D) {
   const int Dc = max(D - 1, 4);
   u16x2 a[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32((uint32_t)(Dc - 4)));
   const s16x2 P = group_sum(t, a, 0, splat32(19u << c), splat32(3), splat32(3));
   const s16x2 Q = secondary(t, splat32(7u << c), splat32((uint32_t)(Dc - 2)));
-  return pair_both(t, P, Q, acc);
+  return err_both(t, P, Q);
 }
 
 // Luma task: 2 blocks (lo/hi half) with per-block adjusted primary
 // strengths (Eq. 13).  Per-strength parameters are wave-uniform 32-bit
-// scalars (low half: block A, high half: block B).
-template <bool FULL>
-__device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t adjB, int a19A,
-                                          int a19B, int c, int D, int (&acc)[64]) {
+// scalars (low half: block A, high half: block B).  Each pair's y - s goes
+// to sink(pair, e), pair = S^(p) * 4 + index of S^(s).
+template <bool FULL, class Sink>
+__device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_t adjB, int a19A,
+                                           int a19B, int c, int D, Sink &&sink) {
   // pair (0, 0) filters nothing; in the full search its slot carries the
   // special preset instead (the unfiltered distortion is summed elsewhere)
   if (FULL)
-    acc[0] = luma_special(t, a19A, a19B, c, D, acc[0]);
+    sink(0, luma_special(t, a19A, a19B, c, D));
   else
-    acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
+    sink(0, t.dxs);
   s16x2 Q[4];
   secondaries(t, c, D, Q);
 #pragma unroll
-  for (int si = 1; si < 4; ++si) acc[si] = pair_one(t, Q[si], acc[si]);
+  for (int si = 1; si < 4; ++si) sink(si, err_one(t, Q[si]));
   uint32_t prev_sh = 0xFFFFFFFFu;
   u16x2 a[4];
 #pragma unroll
@@ -229,25 +229,25 @@ __device__ __forceinline__ void luma_task(const Taps &t, uint64_t adjA, uint64_t
       for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
     }
     const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
-    acc[4 * S] = pair_one(t, P, acc[4 * S]);
+    sink(4 * S, err_one(t, P));
 #pragma unroll
-    for (int si = 1; si < 4; ++si) acc[4 * S + si] = pair_both(t, P, Q[si], acc[4 * S + si]);
+    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both(t, P, Q[si]));
   }
 }
 
 // Chroma task: strengths are not adjusted (uniform over the plane); the
 // chroma damping is max(D - 1, floor(log2 S^(p))) for both tap groups, which
 // differs from D - 1 only for D = 3 and S^(p) >= 8.
-template <bool FULL>
-__device__ __forceinline__ void chroma_task(const Taps &t, int c, int D, int (&acc)[64]) {
+template <bool FULL, class Sink>
+__device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, Sink &&sink) {
   if (FULL)
-    acc[0] = chroma_special(t, c, D, acc[0]);
+    sink(0, chroma_special(t, c, D));
   else
-    acc[0] = __builtin_amdgcn_sdot2(t.dxs, t.dxs, acc[0], false);
+    sink(0, t.dxs);
   s16x2 Q[4];
   secondaries(t, c, D - 1, Q);
 #pragma unroll
-  for (int si = 1; si < 4; ++si) acc[si] = pair_one(t, Q[si], acc[si]);
+  for (int si = 1; si < 4; ++si) sink(si, err_one(t, Q[si]));
   u16x2 a[4];
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
@@ -260,20 +260,28 @@ __device__ __forceinline__ void chroma_task(const Taps &t, int c, int D, int (&a
     }
     const uint32_t w1 = splat32((S & 1) ? 3u : 4u), w2 = splat32((S & 1) ? 3u : 2u);
     const s16x2 P = group_sum(t, a, 0, splat32((uint32_t)S << c), w1, w2);
-    acc[4 * S] = pair_one(t, P, acc[4 * S]);
+    sink(4 * S, err_one(t, P));
 #pragma unroll
-    for (int si = 1; si < 4; ++si) acc[4 * S + si] = pair_both(t, P, Q[si], acc[4 * S + si]);
+    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both(t, P, Q[si]));
   }
 }
 
+// Square-accumulate sink of the SSE searches.
+struct SquareSum {
+  int (&acc)[64];
+  __device__ __forceinline__ void operator()(int k, s16x2 e) const {
+    acc[k] = __builtin_amdgcn_sdot2(e, e, acc[k], false);
+  }
+};
+
 // One butterfly level at lane distance 8, 4, 2 or 1: the partner lane (DPP
-// `ctrl`) lies in the other half of the group; each lane keeps one value of
-// every pair and adds the partner's copy of it.
-template <int DIST, int CTRL>
+// `ctrl`) lies in the other half of the group; of the values v[0, 2 HALF)
+// each lane keeps one half (the upper if `up`) and adds the partner's copy.
+template <int HALF, int CTRL>
 __device__ __forceinline__ void dpp_level(uint32_t (&v)[64], bool up) {
 #pragma unroll
-  for (int i = 0; i < DIST; ++i) {
-    const uint32_t a = v[i], b = v[i + DIST];
+  for (int i = 0; i < HALF; ++i) {
+    const uint32_t a = v[i], b = v[i + HALF];
     const uint32_t send = up ? a : b;
     const uint32_t keep = up ? b : a;
     v[i] = keep + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)send, CTRL, 0xF, 0xF, false);
@@ -303,6 +311,37 @@ __device__ __forceinline__ uint32_t reduce_transpose(const int (&acc)[64], int l
   dpp_level<2, 0x4E>(v, (lane & 2) != 0);   // quad_perm [2,3,0,1]
   dpp_level<1, 0xB1>(v, (lane & 1) != 0);   // quad_perm [1,0,3,2]
   return v[0];
+}
+
+// The same butterfly on values already in 32-bit registers (consumed).
+__device__ __forceinline__ uint32_t reduce_transpose_u(uint32_t (&v)[64], int lane) {
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v[i], v[i + 32], false, false);
+    v[i] = r[0] + r[1];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v[i], v[i + 16], false, false);
+    v[i] = r[0] + r[1];
+  }
+  dpp_level<8, 0x140>(v, (lane & 8) != 0);
+  dpp_level<4, 0x141>(v, (lane & 4) != 0);
+  dpp_level<2, 0x4E>(v, (lane & 2) != 0);
+  dpp_level<1, 0xB1>(v, (lane & 1) != 0);
+  return v[0];
+}
+
+// Sums within each row of 16 lanes: 64 values per lane in, and lane l of a
+// row returns the row's totals of values 4 (l mod 16) .. 4 (l mod 16) + 3.
+__device__ __forceinline__ void reduce_rows_transpose(uint32_t (&v)[64], int lane,
+                                                      uint32_t (&out)[4]) {
+  dpp_level<32, 0x140>(v, (lane & 8) != 0);
+  dpp_level<16, 0x141>(v, (lane & 4) != 0);
+  dpp_level<8, 0x4E>(v, (lane & 2) != 0);
+  dpp_level<4, 0xB1>(v, (lane & 1) != 0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[j] = v[j];
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -335,6 +374,11 @@ struct Smem {
   uint8_t adj19[64];  // Eq. (13) applied to 19 (full search)
   uint8_t flag[64];   // bit 0: in frame, bit 1: skipped
   int n, nsk;
+  // weighted search: per plane and filtering unit (8x8 luma, 4x4 chroma)
+  // n, sum s, sum s^2, sum x, sum x^2, sum x s over in-frame pixels
+  uint32_t ustat[6][3][64];
+  double skipw[3];          // Eq. (14) over skipped units, per plane
+  double wred[2][4][64];    // per wave and pair: Eq. (14) over its tasks' units
 };
 
 // Stage the recon tiles (all modes) and, for the search, the source tiles;
@@ -534,7 +578,7 @@ __device__ __forceinline__ void luma_tasks(Smem &sm, const JobDesc &J, int first
     Taps t;
     prepare(t, xv, sv, tp);
     const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
-    luma_task<FULL>(t, adjA, adjB, a19A, a19B, c, D, acc);
+    luma_pairs<FULL>(t, adjA, adjB, a19A, a19B, c, D, SquareSum{acc});
   }
   red[wave * 64 + lane] = reduce_transpose(acc, lane);
 }
@@ -577,7 +621,7 @@ __device__ __forceinline__ void chroma_tasks(Smem &sm, const JobDesc &J, int fir
     }
     Taps t;
     prepare(t, xv, sv, tp);
-    chroma_task<FULL>(t, c, D, acc);
+    chroma_pairs<FULL>(t, c, D, SquareSum{acc});
   }
   red[wave * 64 + lane] = reduce_transpose(acc, lane);
 }
@@ -634,6 +678,304 @@ __device__ __forceinline__ void search_item(Smem &sm, const JobDesc &J, int fby,
   }
 }
 
+// ---- Weighted search (Eq. 14) ---------------------------------------------
+
+// Eq. (14) for one filtering unit from exact integer moments: n pixels,
+// sums of s, s^2, d, d^2 and the unit's SSE.  With V = n sum x^2 - (sum x)^2
+// = n^2 sigma^2, the weight is (Vs + Vd + C1 n^2) / (2 sqrt(Vs Vd + C2 n^4)).
+__device__ __forceinline__ double eq14(int n, uint32_t ss, uint32_t ss2, uint32_t sd, uint32_t sd2,
+                                       uint32_t sse, double C1, double C2) {
+  const double nn = (double)n * (double)n;
+  const double vs = (double)((int64_t)n * ss2 - (int64_t)ss * ss);
+  const double vd = (double)((int64_t)n * sd2 - (int64_t)sd * sd);
+  return (vs + vd + C1 * nn) / (2.0 * sqrt(vs * vd + C2 * nn * nn)) * (double)sse;
+}
+
+// Per-unit moments of the source and the unfiltered reconstruction, one
+// unit row (8 or 4 pixels) per step; run by threads t0.. (nt of them) while
+// wave 0 runs the direction search.  Unit rows are dealt so that
+// neighbouring threads add into different units.
+__device__ __forceinline__ void unit_stats(Smem &sm, const JobDesc &J, int fby, int fbx, int t,
+                                           int nt) {
+  const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
+  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  const int nrows = J.nplanes == 3 ? 1024 : 512;
+  for (int k = t; k < nrows; k += nt) {
+    int P, u, row;
+    if (k < 512) {
+      P = 0;
+      u = k & 63;
+      row = k >> 6;
+    } else {
+      P = 1 + ((k - 512) >> 8);
+      u = k & 63;
+      row = ((k - 512) >> 6) & 3;
+    }
+    uint32_t cnt = 0, a = 0, a2 = 0, b = 0, b2 = 0, ab = 0;
+    if (P == 0) {
+      const int r = 8 * (u >> 3) + row, c0 = 8 * (u & 7);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (y0 + r < H && x0 + c0 + j < W) {
+          const uint32_t sv = sm.sy[r * 64 + c0 + j], xv = sm.ry[(r + 2) * kLS + kLC0 + c0 + j];
+          ++cnt;
+          a += sv;
+          a2 += sv * sv;
+          b += xv;
+          b2 += xv * xv;
+          ab += xv * sv;
+        }
+      }
+    } else {
+      const int r = 4 * (u >> 3) + row, c0 = 4 * (u & 7);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (cy0 + r < ch && cx0 + c0 + j < cw) {
+          const uint32_t sv = sm.sc[P - 1][r * 32 + c0 + j];
+          const uint32_t xv = sm.rc[P - 1][(r + 2) * kCS + kCC0 + c0 + j];
+          ++cnt;
+          a += sv;
+          a2 += sv * sv;
+          b += xv;
+          b2 += xv * xv;
+          ab += xv * sv;
+        }
+      }
+    }
+    if (cnt) {
+      atomicAdd(&sm.ustat[0][P][u], cnt);
+      atomicAdd(&sm.ustat[1][P][u], a);
+      atomicAdd(&sm.ustat[2][P][u], a2);
+      atomicAdd(&sm.ustat[3][P][u], b);
+      atomicAdd(&sm.ustat[4][P][u], b2);
+      atomicAdd(&sm.ustat[5][P][u], ab);
+    }
+  }
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Keeps every pair's y - s of a task.
+struct StoreErr {
+  s16x2 (&e)[64];
+  __device__ __forceinline__ void operator()(int k, s16x2 v) const { e[k] = v; }
+};
+
+// The five per-pair moments of a task, summed over the lanes of each unit
+// (all 64 lanes for luma, each row of 16 for chroma): sum d packed (low
+// half: block of the low halves; each half stays below 2^16), sum d^2 and
+// sum (d - s)^2 for either half.
+template <bool ROWS>
+struct Moments {
+  static constexpr int K = ROWS ? 4 : 1;
+  uint32_t sd[K], d2lo[K], d2hi[K], e2lo[K], e2hi[K];
+};
+
+template <bool ROWS>
+__device__ __forceinline__ void reduce_chunk(uint32_t (&v)[64], int lane, uint32_t (&o)[ROWS ? 4 : 1]) {
+  if constexpr (ROWS)
+    reduce_rows_transpose(v, lane, o);
+  else
+    o[0] = reduce_transpose_u(v, lane);
+}
+
+template <bool ROWS>
+__device__ __forceinline__ void task_moments(const s16x2 (&ev)[64], uint32_t sv, int lane,
+                                             Moments<ROWS> &m) {
+  const s16x2 s = as_s(sv);
+  const u16x2 lo = u16x2{0xFFFF, 0}, hi = u16x2{0, 0xFFFF};
+  uint32_t v[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s);
+  reduce_chunk<ROWS>(v, lane, m.sd);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const u16x2 d = as_u(ev[i] + s);
+    v[i] = __builtin_amdgcn_udot2(d, d & lo, 0u, false);
+  }
+  reduce_chunk<ROWS>(v, lane, m.d2lo);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const u16x2 d = as_u(ev[i] + s);
+    v[i] = __builtin_amdgcn_udot2(d, d & hi, 0u, false);
+  }
+  reduce_chunk<ROWS>(v, lane, m.d2hi);
+#pragma unroll
+  for (int i = 0; i < 64; ++i)
+    v[i] = (uint32_t)__builtin_amdgcn_sdot2(ev[i], ev[i] & as_s(lo), 0, false);
+  reduce_chunk<ROWS>(v, lane, m.e2lo);
+#pragma unroll
+  for (int i = 0; i < 64; ++i)
+    v[i] = (uint32_t)__builtin_amdgcn_sdot2(ev[i], ev[i] & as_s(hi), 0, false);
+  reduce_chunk<ROWS>(v, lane, m.e2hi);
+}
+
+// Luma tasks of the weighted search; lane k accumulates pair k.
+__device__ __forceinline__ void luma_tasks_w(Smem &sm, const JobDesc &J, int n, int y0, int x0,
+                                             int wave, int lane, double C1, double C2) {
+  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
+  double accw = 0.0;
+  const int ntask = (n + 1) >> 1;
+  const int r = lane >> 3, col = lane & 7;
+  for (int tk = wave; tk < ntask; tk += 4) {
+    const int A = uniform(sm.list[2 * tk]);
+    const bool hasB = 2 * tk + 1 < n;
+    const int B = hasB ? uniform(sm.list[2 * tk + 1]) : A;
+    const int dA = uniform(sm.dir[A]), dB = uniform(sm.dir[B]);
+    const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
+    const int rA = 8 * (A >> 3) + r, cA = 8 * (A & 7) + col;
+    const int rB = 8 * (B >> 3) + r, cB = 8 * (B & 7) + col;
+    const bool vA = y0 + rA < H && x0 + cA < W;
+    const bool vB = hasB && y0 + rB < H && x0 + cB < W;
+    const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
+    const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
+    const uint32_t xv = ((uint32_t)sm.ry[bA] | ((uint32_t)sm.ry[bB] << 16)) & vm;
+    const uint32_t sv =
+        ((uint32_t)sm.sy[rA * 64 + cA] | ((uint32_t)sm.sy[rB * 64 + cB] << 16)) & vm;
+    uint32_t tp[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int oA = kLumaTaps.off[dA][k], oB = kLumaTaps.off[dB][k];
+      const int slot = (k >> 1) * 4 + (k & 1) * 2;
+      tp[slot] = ((uint32_t)sm.ry[bA + oA] | ((uint32_t)sm.ry[bB + oB] << 16)) & vm;
+      tp[slot + 1] = ((uint32_t)sm.ry[bA - oA] | ((uint32_t)sm.ry[bB - oB] << 16)) & vm;
+    }
+    s16x2 ev[64];
+    {
+      Taps t;
+      prepare(t, xv, sv, tp);
+      luma_pairs<false>(t, adjA, adjB, 0, 0, c, D, StoreErr{ev});
+    }
+    Moments<false> m;
+    task_moments<false>(ev, sv, lane, m);
+    accw += eq14((int)sm.ustat[0][0][A], sm.ustat[1][0][A], sm.ustat[2][0][A], m.sd[0] & 0xFFFF,
+                 m.d2lo[0], m.e2lo[0], C1, C2);
+    if (hasB)
+      accw += eq14((int)sm.ustat[0][0][B], sm.ustat[1][0][B], sm.ustat[2][0][B], m.sd[0] >> 16,
+                   m.d2hi[0], m.e2hi[0], C1, C2);
+  }
+  sm.wred[0][wave][lane] = accw;
+}
+
+// Chroma tasks of the weighted search: each row of 16 lanes holds one 4x4
+// unit per half; lane l of a row accumulates pairs 4 (l mod 16) + j.
+__device__ __forceinline__ void chroma_tasks_w(Smem &sm, const JobDesc &J, int n, int y0, int x0,
+                                               int wave, int lane, double C1, double C2) {
+  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
+  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  const int p = wave >> 1;
+  const uint16_t *rt = sm.rc[p];
+  const uint16_t *st = sm.sc[p];
+  const int ntask = (n + 7) >> 3;
+  const int sub = lane >> 4, r = (lane >> 2) & 3, col = lane & 3;
+  double accw[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int tk = wave & 1; tk < ntask; tk += 2) {
+    const int iL = 8 * tk + sub, iH = 8 * tk + 4 + sub;
+    const bool hasL = iL < n, hasH = iH < n;
+    const int L = hasL ? sm.list[iL] : 0, Hb = hasH ? sm.list[iH] : 0;
+    const int rL = 4 * (L >> 3) + r, cL = 4 * (L & 7) + col;
+    const int rH = 4 * (Hb >> 3) + r, cH = 4 * (Hb & 7) + col;
+    const bool vL = hasL && cy0 + rL < ch && cx0 + cL < cw;
+    const bool vH = hasH && cy0 + rH < ch && cx0 + cH < cw;
+    const uint32_t vm = (vL ? 0x0000FFFFu : 0u) | (vH ? 0xFFFF0000u : 0u);
+    const int bL = (rL + 2) * kCS + kCC0 + cL, bH = (rH + 2) * kCS + kCC0 + cH;
+    const int dL = sm.dir[L], dH = sm.dir[Hb];
+    const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
+    const uint32_t sv = ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm;
+    uint32_t tp[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int oL = sm.coff[dL][k], oH = sm.coff[dH][k];
+      const int slot = (k >> 1) * 4 + (k & 1) * 2;
+      tp[slot] = ((uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16)) & vm;
+      tp[slot + 1] = ((uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16)) & vm;
+    }
+    s16x2 ev[64];
+    {
+      Taps t;
+      prepare(t, xv, sv, tp);
+      chroma_pairs<false>(t, c, D, StoreErr{ev});
+    }
+    Moments<true> m;
+    task_moments<true>(ev, sv, lane, m);
+    const int P = 1 + p;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (hasL)
+        accw[j] += eq14((int)sm.ustat[0][P][L], sm.ustat[1][P][L], sm.ustat[2][P][L],
+                        m.sd[j] & 0xFFFF, m.d2lo[j], m.e2lo[j], C1, C2);
+      if (hasH)
+        accw[j] += eq14((int)sm.ustat[0][P][Hb], sm.ustat[1][P][Hb], sm.ustat[2][P][Hb],
+                        m.sd[j] >> 16, m.d2hi[j], m.e2hi[j], C1, C2);
+    }
+  }
+  // the four rows hold the same pairs for different units
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    accw[j] += __shfl_xor(accw[j], 16, 64);
+    accw[j] += __shfl_xor(accw[j], 32, 64);
+  }
+  if (lane < 16)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sm.wred[1][wave][4 * lane + j] = accw[j];
+}
+
+__device__ __forceinline__ void search_item_weighted(Smem &sm, const JobDesc &J, int fby, int fbx,
+                                                     int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int y0 = fby * 64, x0 = fbx * 64;
+  const bool chroma = J.nplanes == 3;
+  const int c = J.bitdepth - 8;
+  // C1 = 6.25 and C2 = 312.5 at 8 bits, scaled like variances and their
+  // products (exact powers of two)
+  const double C1 = 6.25 * (double)(1 << (2 * c)), C2 = 312.5 * (double)(1 << (4 * c));
+
+  stage_item(sm, J, fby, fbx, tid, true);
+  for (int i = tid; i < 6 * 3 * 64; i += 256) (&sm.ustat[0][0][0])[i] = 0;
+  __syncthreads();
+  if (wave == 0)
+    direction_search<false>(sm, J, fby, fbx, lane);
+  else
+    unit_stats(sm, J, fby, fbx, tid - 64, 192);
+  __syncthreads();
+  const int n = sm.n;
+
+  // skipped units are not filtered under any pair: wave P sums plane P's
+  if (wave < 3) {
+    const int P = wave, u = lane;
+    double w = 0.0;
+    if ((P == 0 || chroma) && (sm.flag[u] & 2)) {
+      const uint32_t cnt = sm.ustat[0][P][u];
+      const uint32_t ss = sm.ustat[1][P][u], ss2 = sm.ustat[2][P][u];
+      const uint32_t sx = sm.ustat[3][P][u], sx2 = sm.ustat[4][P][u], sxs = sm.ustat[5][P][u];
+      if (cnt) w = eq14((int)cnt, ss, ss2, sx, sx2, sx2 + ss2 - 2 * sxs, C1, C2);
+    }
+    w = wave_sum_f64(w);
+    if (lane == 0) sm.skipw[P] = w;
+  }
+
+  luma_tasks_w(sm, J, n, y0, x0, wave, lane, C1, C2);
+  if (chroma) chroma_tasks_w(sm, J, n, y0, x0, wave, lane, C1, C2);
+  __syncthreads();
+
+  const int64_t fbi = (int64_t)fby * J.fbc + fbx;
+  const int64_t nfb = (int64_t)J.fbr * J.fbc;
+  double *out = reinterpret_cast<double *>(J.sse);
+  const int k = tid & 63;
+  if (tid < 64) {
+    out[fbi * 64 + k] = sm.wred[0][0][k] + sm.wred[0][1][k] + sm.wred[0][2][k] +
+                        sm.wred[0][3][k] + sm.skipw[0];
+  } else if (chroma && tid < 192) {
+    const int p = (tid >> 6) - 1;
+    out[((1 + p) * nfb + fbi) * 64 + k] =
+        sm.wred[1][2 * p][k] + sm.wred[1][2 * p + 1][k] + sm.skipw[1 + p];
+  }
+}
+
 // Filter mode: the block's own preset (Section 3.2 ranges, Section 4 skip
 // rules; bad values are masked / clamped so the kernel stays defined), one
 // pixel per lane.
@@ -683,12 +1025,17 @@ __device__ __forceinline__ void filter_item(Smem &sm, const JobDesc &J, int fby,
   }
 }
 
+// W: the kernel also carries the weighted search (it needs more registers,
+// so it is compiled into kernels of its own).
+template <bool W>
 __device__ __forceinline__ void run_item(Smem &sm, const JobDesc &J, int item, int tid) {
   const int fby = item / J.fbc, fbx = item - fby * J.fbc;
   if (J.mode == kModeSearch)
     search_item<false>(sm, J, fby, fbx, tid);
   else if (J.mode == kModeSearchFull)
     search_item<true>(sm, J, fby, fbx, tid);
+  else if (W && J.mode == kModeSearchWeighted)
+    search_item_weighted(sm, J, fby, fbx, tid);
   else
     filter_item(sm, J, fby, fbx, tid);
 }
@@ -698,13 +1045,19 @@ __device__ __forceinline__ void run_item(Smem &sm, const JobDesc &J, int item, i
 // One frame; the descriptor is a kernel argument.
 __global__ __launch_bounds__(256, 3) void k_fused_one(const JobDesc J) {
   __shared__ __align__(16) Smem sm;
-  run_item(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+  run_item<false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+}
+
+// One frame of the weighted search (2 waves per SIMD: 256 VGPRs).
+__global__ __launch_bounds__(256, 2) void k_fused_one_w(const JobDesc J) {
+  __shared__ __align__(16) Smem sm;
+  run_item<true>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 // A batch: descriptors in device memory, items numbered across jobs.
 // OCC bounds the waves per SIMD (and so the VGPR budget); XCD selects the
 // XCD-contiguous order of filter blocks.
-template <int OCC, bool XCD>
+template <int OCC, bool XCD, bool W>
 __global__ __launch_bounds__(256, OCC) void k_fused_batch(const JobDesc *__restrict__ jobs,
                                                           int njobs) {
   __shared__ __align__(16) Smem sm;
@@ -718,7 +1071,7 @@ __global__ __launch_bounds__(256, OCC) void k_fused_batch(const JobDesc *__restr
       hi = mid - 1;
   }
   const JobDesc &J = jobs[lo];
-  run_item(sm, J, item - J.item0, threadIdx.x);
+  run_item<W>(sm, J, item - J.item0, threadIdx.x);
 }
 
 void fill_job_geometry(JobDesc &j) {
@@ -730,17 +1083,28 @@ void fill_job_geometry(JobDesc &j) {
 
 hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
   const int grid = job.fbc * job.fbr;
-  hipLaunchKernelGGL(k_fused_one, dim3(grid), dim3(256), 0, s, job);
+  if (job.mode == kModeSearchWeighted)
+    hipLaunchKernelGGL(k_fused_one_w, dim3(grid), dim3(256), 0, s, job);
+  else
+    hipLaunchKernelGGL(k_fused_one, dim3(grid), dim3(256), 0, s, job);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              hipStream_t s) {
+                              bool weighted, hipStream_t s) {
+  const dim3 g(nitems), b(256);
+  if (weighted) {  // 2 waves per SIMD; the variant picks the block order
+    if (variant == 0 || variant == 1)
+      hipLaunchKernelGGL((k_fused_batch<2, true, true>), g, b, 0, s, jobs, njobs);
+    else
+      hipLaunchKernelGGL((k_fused_batch<2, false, true>), g, b, 0, s, jobs, njobs);
+    return hipGetLastError();
+  }
   switch (variant) {
-    case 1: hipLaunchKernelGGL((k_fused_batch<2, true>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
-    case 2: hipLaunchKernelGGL((k_fused_batch<3, false>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
-    case 3: hipLaunchKernelGGL((k_fused_batch<2, false>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
-    default: hipLaunchKernelGGL((k_fused_batch<3, true>), dim3(nitems), dim3(256), 0, s, jobs, njobs); break;
+    case 1: hipLaunchKernelGGL((k_fused_batch<2, true, false>), g, b, 0, s, jobs, njobs); break;
+    case 2: hipLaunchKernelGGL((k_fused_batch<3, false, false>), g, b, 0, s, jobs, njobs); break;
+    case 3: hipLaunchKernelGGL((k_fused_batch<2, false, false>), g, b, 0, s, jobs, njobs); break;
+    default: hipLaunchKernelGGL((k_fused_batch<3, true, false>), g, b, 0, s, jobs, njobs); break;
   }
   return hipGetLastError();
 }

@@ -63,7 +63,8 @@ def test_find_dir_argument_checks(lib):
     assert lib.cdef_find_dir(C.byref(f), P, P, None) == -1
 
 
-@pytest.mark.parametrize("name", ["cdef_search_strengths", "cdef_search_strengths128"])
+@pytest.mark.parametrize("name", ["cdef_search_strengths", "cdef_search_strengths128",
+                                  "cdef_search_weighted"])
 def test_search_argument_checks(lib, name):
     f = getattr(lib, name)
     P = 0x20000
