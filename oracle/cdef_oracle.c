@@ -70,6 +70,11 @@
  *      16^(b-8), the factors by which variances and their products grow, so
  *      that the weight of a frame does not change when every sample is
  *      multiplied by 2^(b-8).  Evaluated in double precision.
+ *  R20 4:2:2 (chroma subsampled horizontally only): chroma is not filtered
+ *      (Section 4) and so is copied, and the searches cover luma only.
+ *  R21 4:4:4: each 8x8 chroma block takes the direction and skip flag of the
+ *      co-located 8x8 luma block; chroma filter blocks are 64x64; strengths
+ *      and damping follow the chroma rules of R13 as at 4:2:0.
  */
 #include "cdef_oracle.h"
 
@@ -247,10 +252,18 @@ static block_params params_for(int plane, int bitdepth, int damping, int pri, in
   return bp;
 }
 
-static void plane_geometry(const cdef_oracle_frame *f, int plane, int *pw, int *ph, int *ss) {
-  *ss = plane == 0 ? 0 : 1;
-  *pw = plane == 0 ? f->width : (f->width + 1) / 2;
-  *ph = plane == 0 ? f->height : (f->height + 1) / 2;
+/* Subsampling of a plane: chroma halves the width at 4:2:0 and 4:2:2 and
+ * the height at 4:2:0. */
+static void plane_geometry(const cdef_oracle_frame *f, int plane, int *pw, int *ph, int *ssx,
+                           int *ssy) {
+  *ssx = plane > 0 && (f->layout == CDEF_ORACLE_420 || f->layout == CDEF_ORACLE_422);
+  *ssy = plane > 0 && f->layout == CDEF_ORACLE_420;
+  *pw = (f->width + *ssx) >> *ssx;
+  *ph = (f->height + *ssy) >> *ssy;
+}
+
+int cdef_oracle_search_planes(const cdef_oracle_frame *f) {
+  return f->nplanes == 3 && f->layout != CDEF_ORACLE_422 ? 3 : 1;
 }
 
 /* R18: the preset of one plane group from a strengths entry. */
@@ -282,18 +295,19 @@ void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3
   int bcols = (in->width + 7) / 8;
   int fbcols = (in->width + 63) / 64;
   for (int p = 0; p < in->nplanes; p++) {
-    int pw, ph, ss;
-    plane_geometry(in, p, &pw, &ph, &ss);
-    int bs = 8 >> ss, fs = 64 >> ss;
+    int pw, ph, ssx, ssy;
+    plane_geometry(in, p, &pw, &ph, &ssx, &ssy);
+    int bw = 8 >> ssx, bh = 8 >> ssy, fw = 64 >> ssx, fh = 64 >> ssy;
     for (int i = 0; i < ph; i++) {
       for (int j = 0; j < pw; j++) {
-        int b = (i / bs) * bcols + (j / bs);
+        int b = (i / bh) * bcols + (j / bw);
         int x = in->plane[p][(int64_t)i * in->stride[p] + j];
-        const uint8_t *st = strengths + 4 * ((i / fs) * fbcols + (j / fs));
+        const uint8_t *st = strengths + 4 * ((i / fh) * fbcols + (j / fw));
         int pri, sec, skipcond;
         preset_of(st, p, &pri, &sec, &skipcond);
         int y;
-        if (fb_skipped(in, skip, i / fs, j / fs) || (skip && skip[b] && !skipcond)) {
+        if ((p > 0 && in->layout == CDEF_ORACLE_422) || /* R20 */
+            fb_skipped(in, skip, i / fh, j / fw) || (skip && skip[b] && !skipcond)) {
           y = x;
         } else {
           block_params bp = params_for(p, in->bitdepth, damping, pri, sec, var[b]);
@@ -319,12 +333,12 @@ void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_fr
                             int damping, int nskip, int fby, int fbx, uint64_t *sse) {
   int bcols = (recon->width + 7) / 8;
   int all_skipped = fb_skipped(recon, skip, fby, fbx);
-  for (int p = 0; p < recon->nplanes; p++) {
-    int pw, ph, ss;
-    plane_geometry(recon, p, &pw, &ph, &ss);
-    int bs = 8 >> ss, fs = 64 >> ss;
-    int i0 = fby * fs, j0 = fbx * fs;
-    int i1 = imin(i0 + fs, ph), j1 = imin(j0 + fs, pw);
+  for (int p = 0; p < cdef_oracle_search_planes(recon); p++) {
+    int pw, ph, ssx, ssy;
+    plane_geometry(recon, p, &pw, &ph, &ssx, &ssy);
+    int bw = 8 >> ssx, bh = 8 >> ssy, fw = 64 >> ssx, fh = 64 >> ssy;
+    int i0 = fby * fh, j0 = fbx * fw;
+    int i1 = imin(i0 + fh, ph), j1 = imin(j0 + fw, pw);
     for (int k = 0; k < nskip; k++) {
       for (int pri_sig = 0; pri_sig < 16; pri_sig++) {
         for (int si = 0; si < 4; si++) {
@@ -335,7 +349,7 @@ void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_fr
           uint64_t acc = 0;
           for (int i = i0; i < i1; i++) {
             for (int j = j0; j < j1; j++) {
-              int b = (i / bs) * bcols + (j / bs);
+              int b = (i / bh) * bcols + (j / bw);
               int x = recon->plane[p][(int64_t)i * recon->stride[p] + j];
               int y;
               if (all_skipped || (skip && skip[b] && !skipcond)) {
@@ -371,17 +385,17 @@ void cdef_oracle_search_fb_weighted(const cdef_oracle_frame *recon,
   double C1 = 6.25 * pow(4.0, c), C2 = 312.5 * pow(16.0, c);
   int all_skipped = fb_skipped(recon, skip, fby, fbx);
   int filtered[64 * 64];
-  for (int p = 0; p < recon->nplanes; p++) {
-    int pw, ph, ss;
-    plane_geometry(recon, p, &pw, &ph, &ss);
-    int bs = 8 >> ss, fs = 64 >> ss;
-    int i0 = fby * fs, j0 = fbx * fs;
-    int i1 = imin(i0 + fs, ph), j1 = imin(j0 + fs, pw);
+  for (int p = 0; p < cdef_oracle_search_planes(recon); p++) {
+    int pw, ph, ssx, ssy;
+    plane_geometry(recon, p, &pw, &ph, &ssx, &ssy);
+    int bw = 8 >> ssx, bh = 8 >> ssy, fw = 64 >> ssx, fh = 64 >> ssy;
+    int i0 = fby * fh, j0 = fbx * fw;
+    int i1 = imin(i0 + fh, ph), j1 = imin(j0 + fw, pw);
     for (int pri = 0; pri < 16; pri++) {
       for (int si = 0; si < 4; si++) {
         for (int i = i0; i < i1; i++) {
           for (int j = j0; j < j1; j++) {
-            int b = (i / bs) * bcols + (j / bs);
+            int b = (i / bh) * bcols + (j / bw);
             int x = recon->plane[p][(int64_t)i * recon->stride[p] + j];
             int y = x;
             if (!all_skipped && !(skip && skip[b])) {
@@ -395,12 +409,12 @@ void cdef_oracle_search_fb_weighted(const cdef_oracle_frame *recon,
           }
         }
         double total = 0.0;
-        for (int ui = i0; ui < i1; ui += bs) {
-          for (int uj = j0; uj < j1; uj += bs) {
+        for (int ui = i0; ui < i1; ui += bh) {
+          for (int uj = j0; uj < j1; uj += bw) {
             int n = 0;
             double ms = 0.0, md = 0.0;
-            for (int i = ui; i < imin(ui + bs, i1); i++)
-              for (int j = uj; j < imin(uj + bs, j1); j++) {
+            for (int i = ui; i < imin(ui + bh, i1); i++)
+              for (int j = uj; j < imin(uj + bw, j1); j++) {
                 ms += src->plane[p][(int64_t)i * src->stride[p] + j];
                 md += filtered[(i - i0) * 64 + (j - j0)];
                 n++;
@@ -408,8 +422,8 @@ void cdef_oracle_search_fb_weighted(const cdef_oracle_frame *recon,
             ms /= n;
             md /= n;
             double vs = 0.0, vd = 0.0, e2 = 0.0;
-            for (int i = ui; i < imin(ui + bs, i1); i++)
-              for (int j = uj; j < imin(uj + bs, j1); j++) {
+            for (int i = ui; i < imin(ui + bh, i1); i++)
+              for (int j = uj; j < imin(uj + bw, j1); j++) {
                 double sv = src->plane[p][(int64_t)i * src->stride[p] + j];
                 double dv = filtered[(i - i0) * 64 + (j - j0)];
                 vs += (sv - ms) * (sv - ms);
@@ -443,7 +457,7 @@ void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame 
   for (int by = 0; by < fbr; by++) {
     for (int bx = 0; bx < fbc; bx++) {
       cdef_oracle_search_fb(recon, src, dir, var, skip, damping, by, bx, tmp);
-      for (int p = 0; p < recon->nplanes; p++)
+      for (int p = 0; p < cdef_oracle_search_planes(recon); p++)
         for (int k = 0; k < 64; k++)
           sse[(((int64_t)p * fbr + by) * fbc + bx) * 64 + k] = tmp[p * 64 + k];
     }

@@ -31,14 +31,19 @@
 extern "C" {
 #endif
 
-/* One frame.  nplanes = 1 (luma only) or 3 (4:2:0: chroma planes are
- * ceil(width/2) x ceil(height/2)).  bitdepth 8..12. */
+/* Chroma layouts. */
+enum { CDEF_ORACLE_400 = 0, CDEF_ORACLE_420 = 1, CDEF_ORACLE_422 = 2, CDEF_ORACLE_444 = 3 };
+
+/* One frame.  nplanes = 1 (4:0:0) or 3; chroma planes are ceil(width/2) x
+ * ceil(height/2) at 4:2:0, ceil(width/2) x height at 4:2:2, width x height
+ * at 4:4:4.  bitdepth 8..12. */
 typedef struct {
   const uint16_t *plane[3];
   int64_t stride[3];
   int32_t width, height; /* luma size */
   int32_t bitdepth;
   int32_t nplanes;
+  int32_t layout;
 } cdef_oracle_frame;
 
 /* Line number k of pixel (i, j) (row i, column j, 0..7) of an 8x8 block for
@@ -81,6 +86,10 @@ void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3
                               const int64_t out_stride[3], const uint8_t *dir,
                               const int32_t *var, const uint8_t *skip, int damping,
                               const uint8_t *strengths);
+
+/* Planes that the searches cover: luma only at 4:0:0 and 4:2:2 (whose chroma
+ * is never filtered), all three otherwise. */
+int cdef_oracle_search_planes(const cdef_oracle_frame *f);
 
 /* Section 5: SSE of one 64x64 filter block (fby, fbx) for every plane and
  * every (S^(p) = 0..15, S^(s) in {0,1,2,4}) pair, filtering the block in full

@@ -24,7 +24,11 @@ class OracleFrame(C.Structure):
         ("height", C.c_int32),
         ("bitdepth", C.c_int32),
         ("nplanes", C.c_int32),
+        ("layout", C.c_int32),
     ]
+
+
+LAYOUT_400, LAYOUT_420, LAYOUT_422, LAYOUT_444 = 0, 1, 2, 3
 
 
 _lib = None
@@ -80,14 +84,34 @@ def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data
 
 
-def _frame(planes: Sequence[np.ndarray], width: int, height: int, bitdepth: int) -> OracleFrame:
+def infer_layout(planes: Sequence[np.ndarray], width: int, height: int) -> int:
+    """Layout from the plane shapes (4:2:0 when shapes do not tell apart)."""
+    if len(planes) == 1:
+        return LAYOUT_400
+    h, w = planes[1].shape
+    if (h, w) == ((height + 1) // 2, (width + 1) // 2):
+        return LAYOUT_420
+    if (h, w) == (height, (width + 1) // 2):
+        return LAYOUT_422
+    assert (h, w) == (height, width), "chroma planes match no layout"
+    return LAYOUT_444
+
+
+def _frame(planes: Sequence[np.ndarray], width: int, height: int, bitdepth: int,
+           layout: Optional[int] = None) -> OracleFrame:
     f = OracleFrame()
     for p, a in enumerate(planes):
         assert a.dtype == np.uint16 and a.flags.c_contiguous
         f.plane[p] = a.ctypes.data
         f.stride[p] = a.shape[1]
     f.width, f.height, f.bitdepth, f.nplanes = width, height, bitdepth, len(planes)
+    f.layout = infer_layout(planes, width, height) if layout is None else layout
     return f
+
+
+def search_planes(nplanes: int, layout: int) -> int:
+    """Planes a search covers: luma only at 4:0:0 and 4:2:2."""
+    return 3 if nplanes == 3 and layout != LAYOUT_422 else 1
 
 
 def line_number(d: int, i: int, j: int) -> int:
@@ -135,9 +159,9 @@ def filter_pixel(plane: np.ndarray, i: int, j: int, d: int, pri_s: int, pri_d: i
 
 def filter_frame(planes: Sequence[np.ndarray], width: int, height: int, bitdepth: int,
                  dir: np.ndarray, var: np.ndarray, skip: Optional[np.ndarray], damping: int,
-                 strengths: np.ndarray):
+                 strengths: np.ndarray, layout: Optional[int] = None):
     planes = [np.ascontiguousarray(p, dtype=np.uint16) for p in planes]
-    f = _frame(planes, width, height, bitdepth)
+    f = _frame(planes, width, height, bitdepth, layout)
     outs = [np.zeros_like(p) for p in planes]
     outp = (C.c_void_p * 3)(*([o.ctypes.data for o in outs] + [None] * (3 - len(outs))))
     outs_stride = (C.c_int64 * 3)(*([o.shape[1] for o in outs] + [0] * (3 - len(outs))))
@@ -152,7 +176,8 @@ def filter_frame(planes: Sequence[np.ndarray], width: int, height: int, bitdepth
 
 def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, height: int,
                bitdepth: int, dir: np.ndarray, var: np.ndarray, skip: Optional[np.ndarray],
-               damping: int, fbs, threads: int = 1, full: bool = False) -> np.ndarray:
+               damping: int, fbs, threads: int = 1, full: bool = False,
+               layout: Optional[int] = None) -> np.ndarray:
     """SSE tables [len(fbs)][nplanes][16][4] for the listed (fby, fbx) blocks,
     or [len(fbs)][nplanes][2][16][4] with full=True (skip condition bit 0, 1).
 
@@ -160,14 +185,15 @@ def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: in
     GIL during the call, so a thread pool runs filter blocks in parallel."""
     recon = [np.ascontiguousarray(p, dtype=np.uint16) for p in recon]
     src = [np.ascontiguousarray(p, dtype=np.uint16) for p in src]
-    fr = _frame(recon, width, height, bitdepth)
-    fs = _frame(src, width, height, bitdepth)
+    fr = _frame(recon, width, height, bitdepth, layout)
+    fs = _frame(src, width, height, bitdepth, fr.layout)
     dir = np.ascontiguousarray(dir, dtype=np.uint8)
     var = np.ascontiguousarray(var, dtype=np.int32)
     sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
     fbs = list(fbs)
     nskip = 2 if full else 1
-    out = np.zeros((len(fbs), len(recon), nskip, 16, 4), dtype=np.uint64)
+    out = np.zeros((len(fbs), search_planes(len(recon), fr.layout), nskip, 16, 4),
+                   dtype=np.uint64)
     L = lib()
 
     def one(k):
@@ -186,14 +212,16 @@ def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: in
 
 def search(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, height: int,
            bitdepth: int, skip: Optional[np.ndarray], damping: int, threads: int = 1,
-           full: bool = False):
+           full: bool = False, layout: Optional[int] = None):
     """Whole-frame search: (sse, dir, var); sse is [nplanes][fbr][fbc][16][4],
-    or [nplanes][fbr][fbc][2][16][4] with full=True."""
+    or [nplanes][fbr][fbc][2][16][4] with full=True (nplanes: the planes the
+    search covers)."""
     d, v = find_dir(recon[0], bitdepth)
     fbr, fbc = (height + 63) // 64, (width + 63) // 64
     fbs = [(by, bx) for by in range(fbr) for bx in range(fbc)]
-    t = search_fbs(recon, src, width, height, bitdepth, d, v, skip, damping, fbs, threads, full)
-    t = t.reshape((fbr, fbc, len(recon)) + t.shape[2:])
+    t = search_fbs(recon, src, width, height, bitdepth, d, v, skip, damping, fbs, threads, full,
+                   layout)
+    t = t.reshape((fbr, fbc, t.shape[1]) + t.shape[2:])
     sse = np.moveaxis(t, 2, 0)
     return np.ascontiguousarray(sse), d, v
 
@@ -201,17 +229,17 @@ def search(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, h
 def search_fbs_weighted(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int,
                         height: int, bitdepth: int, dir: np.ndarray, var: np.ndarray,
                         skip: Optional[np.ndarray], damping: int, fbs,
-                        threads: int = 1) -> np.ndarray:
+                        threads: int = 1, layout: Optional[int] = None) -> np.ndarray:
     """Eq. (14) distortion tables, float64 [len(fbs)][nplanes][16][4]."""
     recon = [np.ascontiguousarray(p, dtype=np.uint16) for p in recon]
     src = [np.ascontiguousarray(p, dtype=np.uint16) for p in src]
-    fr = _frame(recon, width, height, bitdepth)
-    fs = _frame(src, width, height, bitdepth)
+    fr = _frame(recon, width, height, bitdepth, layout)
+    fs = _frame(src, width, height, bitdepth, fr.layout)
     dir = np.ascontiguousarray(dir, dtype=np.uint8)
     var = np.ascontiguousarray(var, dtype=np.int32)
     sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
     fbs = list(fbs)
-    out = np.zeros((len(fbs), len(recon), 16, 4), dtype=np.float64)
+    out = np.zeros((len(fbs), search_planes(len(recon), fr.layout), 16, 4), dtype=np.float64)
     L = lib()
 
     def one(k):

@@ -36,6 +36,13 @@ SEED_BASE = 1602059750
 
 LAYOUT_400 = 0
 LAYOUT_420 = 1
+LAYOUT_422 = 2
+LAYOUT_444 = 3
+
+
+def chroma_shift(layout: int):
+    """(horizontal, vertical) chroma subsampling shifts."""
+    return {LAYOUT_420: (1, 1), LAYOUT_422: (1, 0), LAYOUT_444: (0, 0)}.get(layout, (0, 0))
 
 # Configurations of the synthetic workloads: (width, height) choices of the
 # mixed batch and serving requests.
@@ -62,12 +69,18 @@ class Frame:
 
     @property
     def nplanes(self) -> int:
-        return 3 if self.layout == LAYOUT_420 else 1
+        return 1 if self.layout == LAYOUT_400 else 3
+
+    @property
+    def search_planes(self) -> int:
+        """Planes the searches cover (4:2:2 chroma is never filtered)."""
+        return 3 if self.layout in (LAYOUT_420, LAYOUT_444) else 1
 
     def plane_dims(self, p: int):
         if p == 0:
             return self.width, self.height
-        return (self.width + 1) // 2, (self.height + 1) // 2
+        sx, sy = chroma_shift(self.layout)
+        return (self.width + sx) >> sx, (self.height + sy) >> sy
 
     @property
     def luma_pixels(self) -> int:
@@ -145,14 +158,15 @@ def make_frame(width: int, height: int, bitdepth: int, layout: int, seed: int,
     """Build one seeded frame (source, ringing reconstruction, skip map)."""
     if q is None:
         q = 24.0 if bitdepth == 8 else 64.0 * (1 << max(0, bitdepth - 10))
-    nplanes = 3 if layout == LAYOUT_420 else 1
+    nplanes = 1 if layout == LAYOUT_400 else 3
+    sx, sy = chroma_shift(layout)
     src, recon = [], []
     for p in range(nplanes):
         rng = np.random.Generator(np.random.PCG64([seed, p]))
         if p == 0:
             w, h, region = width, height, 64
         else:
-            w, h, region = (width + 1) // 2, (height + 1) // 2, 32
+            w, h, region = (width + sx) >> sx, (height + sy) >> sy, 64 >> max(sx, sy)
         s = _grating_plane(rng, w, h, region, bitdepth)
         r = _code_plane(s, q, bitdepth)
         src.append(np.ascontiguousarray(s.astype(np.uint16)))
