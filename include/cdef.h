@@ -54,10 +54,15 @@ typedef enum {
   CDEF_E_NOMEM = -4        /* a caller-provided workspace is too small */
 } cdef_status;
 
-enum { CDEF_LAYOUT_400 = 0, CDEF_LAYOUT_420 = 1 };
+/* Chroma layouts.  4:2:0 and 4:2:2 chroma planes are ceil(w/2) wide, 4:2:0
+ * ones ceil(h/2) high; 4:4:4 chroma has the luma size.  Section 4: at 4:2:2
+ * (subsampling differing horizontally and vertically) chroma is never
+ * filtered -- the filter copies it and the searches cover luma only; at
+ * 4:4:4 each 8x8 chroma block follows the co-located luma block. */
+enum { CDEF_LAYOUT_400 = 0, CDEF_LAYOUT_420 = 1, CDEF_LAYOUT_422 = 2, CDEF_LAYOUT_444 = 3 };
 
-/* One frame.  plane[1..2] may be NULL for CDEF_LAYOUT_400.  bitdepth is 8 or
- * 10 (12-bit content is valid CDEF but returns CDEF_E_UNSUPPORTED). */
+/* One frame.  plane[1..2] may be NULL for CDEF_LAYOUT_400.  bitdepth is 8, 10
+ * or 12 (Section 3.2: strengths scaled by 2^(b-8), damping raised by b-8). */
 typedef struct {
   const uint16_t *plane[3];
   int64_t stride[3];
@@ -96,7 +101,8 @@ typedef struct {
  *   Pixels above 8 bits are reduced to 8 bits (low bits dropped) first.
  *   Blocks cut by the frame edge use their in-frame pixels only.
  * Errors: CDEF_E_INVAL for a null frame/plane/output, size < 1, stride <
- * width, unknown layout; CDEF_E_UNSUPPORTED for bit depth other than 8/10. */
+ * width, unknown layout, bit depth other than 8/10/12; CDEF_E_UNSUPPORTED
+ * for a side above 65536. */
 cdef_status cdef_find_dir(const cdef_frame *f, uint8_t *dir, int32_t *var, void *stream);
 
 /* Filter a frame, Sections 3 and 4: Eq. (7)-(12) with the luma primary
@@ -128,6 +134,7 @@ cdef_status cdef_filter_frame(const cdef_frame *in, const cdef_frame_out *out,
  *   recon, src: same geometry; src is the uncoded frame.
  *   sse:        uint64 [nplanes][ceil(h/64)][ceil(w/64)][16][4]; the last
  *               index is S^(s) in the order 0, 1, 2, 4.  In-frame pixels only.
+ *               nplanes = 3 at 4:2:0 and 4:4:4, 1 at 4:0:0 and 4:2:2.
  *   dir, var:   optional outputs of the direction search (NULL to skip).
  * Errors: as cdef_filter_frame (damping, geometry), CDEF_E_INVAL for a null
  * sse or geometry mismatch between recon and src. */
@@ -198,8 +205,9 @@ typedef struct {
   int32_t njobs;
   int32_t nitems;     /* filter blocks over all jobs */
   int32_t variant;    /* launch variant 0..CDEF_BATCH_VARIANTS-1 (see below), 0 = default */
-  int32_t flags;      /* set by cdef_batch_prepare (bit 0: a job is a weighted search, whose
-                         kernels run at 2 waves per SIMD whatever the variant); keep */
+  int32_t flags;      /* set by cdef_batch_prepare (bit 0: a job needs the extended kernels
+                         -- weighted search, 12-bit or 4:4:4 -- which run at 2 waves per
+                         SIMD whatever the variant); keep */
 } cdef_batch_plan;
 
 /* Host-side checks of one job, exactly those cdef_batch_prepare applies to each

@@ -22,6 +22,8 @@ CDEF_E_HIP = -3
 CDEF_E_NOMEM = -4
 LAYOUT_400 = 0
 LAYOUT_420 = 1
+LAYOUT_422 = 2
+LAYOUT_444 = 3
 
 # Exported symbols of include/cdef.h (the tests check that each one exists).
 EXPORTS = (
@@ -172,7 +174,12 @@ class Frame:
 
     @property
     def nplanes(self) -> int:
-        return 3 if self.layout == LAYOUT_420 else 1
+        return 1 if self.layout == LAYOUT_400 else 3
+
+    @property
+    def search_planes(self) -> int:
+        """Planes the searches write (4:2:2 chroma is never filtered)."""
+        return 3 if self.layout in (LAYOUT_420, LAYOUT_444) else 1
 
     @property
     def block_shape(self):
@@ -282,7 +289,7 @@ def search_strengths(recon: Frame, src: Frame, skip, damping: int, want_dir=Fals
     import torch
     dev = recon.planes[0].device
     fbr, fbc = recon.fb_shape
-    shape = (recon.nplanes, fbr, fbc) + ((2, 16, 4) if full else (16, 4))
+    shape = (recon.search_planes, fbr, fbc) + ((2, 16, 4) if full else (16, 4))
     sse = torch.empty(shape, dtype=torch.float64 if weighted else torch.int64, device=dev)
     d = v = None
     if want_dir:

@@ -13,6 +13,9 @@
 static_assert(sizeof(cdef_preset_result) == sizeof(cdef::PresetResult), "preset result layout");
 static_assert(offsetof(cdef_preset_result, cost) == offsetof(cdef::PresetResult, cost),
               "preset result layout");
+static_assert(CDEF_LAYOUT_400 == cdef::kLayout400 && CDEF_LAYOUT_420 == cdef::kLayout420 &&
+                  CDEF_LAYOUT_422 == cdef::kLayout422 && CDEF_LAYOUT_444 == cdef::kLayout444,
+              "layouts");
 static_assert(CDEF_MODE_SEARCH == cdef::kModeSearch && CDEF_MODE_FILTER == cdef::kModeFilter &&
                   CDEF_MODE_SEARCH128 == cdef::kModeSearchFull &&
                   CDEF_MODE_SEARCH_WEIGHTED == cdef::kModeSearchWeighted,
@@ -27,11 +30,14 @@ bool ranges_overlap(const void *a, size_t an, const void *b, size_t bn) {
   return a0 < b0 + bn && b0 < a0 + an;
 }
 
-int nplanes_of(int32_t layout) { return layout == CDEF_LAYOUT_420 ? 3 : 1; }
+int nplanes_of(int32_t layout) { return layout == CDEF_LAYOUT_400 ? 1 : 3; }
 
+// Chroma halves the width at 4:2:0 and 4:2:2, the height at 4:2:0.
 void plane_dims(const cdef_frame *f, int p, int *w, int *h) {
-  *w = p == 0 ? f->width : (f->width + 1) / 2;
-  *h = p == 0 ? f->height : (f->height + 1) / 2;
+  const int sx = p > 0 && (f->layout == CDEF_LAYOUT_420 || f->layout == CDEF_LAYOUT_422);
+  const int sy = p > 0 && f->layout == CDEF_LAYOUT_420;
+  *w = (f->width + sx) >> sx;
+  *h = (f->height + sy) >> sy;
 }
 
 size_t plane_bytes(const cdef_frame *f, int p) {
@@ -43,11 +49,10 @@ size_t plane_bytes(const cdef_frame *f, int p) {
 // Checks shared by every entry point; fills `d` on success.
 cdef_status check_frame(const cdef_frame *f, FrameDesc *d) {
   if (!f) return CDEF_E_INVAL;
-  if (f->layout != CDEF_LAYOUT_400 && f->layout != CDEF_LAYOUT_420) return CDEF_E_INVAL;
+  if (f->layout < CDEF_LAYOUT_400 || f->layout > CDEF_LAYOUT_444) return CDEF_E_INVAL;
   if (f->width < 1 || f->height < 1) return CDEF_E_INVAL;
   if (f->width > (1 << 16) || f->height > (1 << 16)) return CDEF_E_UNSUPPORTED;
-  if (f->bitdepth == 12) return CDEF_E_UNSUPPORTED;
-  if (f->bitdepth != 8 && f->bitdepth != 10) return CDEF_E_INVAL;
+  if (f->bitdepth != 8 && f->bitdepth != 10 && f->bitdepth != 12) return CDEF_E_INVAL;
   const int np = nplanes_of(f->layout);
   for (int p = 0; p < np; ++p) {
     int w, h;
@@ -63,6 +68,7 @@ cdef_status check_frame(const cdef_frame *f, FrameDesc *d) {
   d->height = f->height;
   d->bitdepth = f->bitdepth;
   d->nplanes = np;
+  d->layout = f->layout;
   return CDEF_OK;
 }
 
@@ -129,6 +135,7 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
   o->bitdepth = r.bitdepth;
   o->damping = j->damping;
   o->nplanes = r.nplanes;
+  o->layout = r.layout;
   o->mode = j->mode;
   cdef::fill_job_geometry(*o);
   // 16-byte staging is possible when every plane read starts 16-byte aligned
@@ -247,8 +254,8 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
   int32_t flags = 0;
   cdef_status st = CDEF_OK;
   for (int32_t i = 0; i < njobs && st == CDEF_OK; ++i) {
-    if (jobs[i].mode == CDEF_MODE_SEARCH_WEIGHTED) flags |= 1;
     st = make_job(&jobs[i], &table[i]);
+    if (st == CDEF_OK && cdef::job_needs_extended(table[i])) flags |= 1;
     if (st == CDEF_OK) {
       table[i].item0 = (int32_t)items;
       items += (int64_t)table[i].fbc * table[i].fbr;

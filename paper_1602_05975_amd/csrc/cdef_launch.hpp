@@ -7,12 +7,16 @@
 
 namespace cdef {
 
+// Chroma layouts (the values of CDEF_LAYOUT_*).
+enum Layout : int32_t { kLayout400 = 0, kLayout420 = 1, kLayout422 = 2, kLayout444 = 3 };
+
 struct FrameDesc {
   const uint16_t *plane[3];
   int64_t stride[3];
   int width, height;  // luma
-  int bitdepth;       // 8 or 10
-  int nplanes;        // 1 (4:0:0) or 3 (4:2:0)
+  int bitdepth;       // 8, 10 or 12
+  int nplanes;        // 1 (4:0:0) or 3
+  int layout;
 };
 
 enum JobMode : int32_t {
@@ -41,6 +45,7 @@ struct JobDesc {
   int32_t fbc, fbr, bcols, brows;
   int32_t item0;  // first work item (filter block) of this job in the batch
   int32_t flags;  // bit 0: every plane's base and row pitch are 16-byte aligned
+  int32_t layout;
 };
 
 hipError_t launch_find_dir(const FrameDesc &f, uint8_t *dir, int32_t *var, hipStream_t s);
@@ -54,9 +59,10 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s);
 
 // Many frames: `jobs` is a device array of njobs descriptors (item0 set),
 // nitems the total number of filter blocks.
-// weighted: some job is a weighted search (kernels built for it).
+// extended: some job needs the extended kernels (12-bit, 4:4:4, weighted).
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              bool weighted, hipStream_t s);
+                              bool extended, hipStream_t s);
+bool job_needs_extended(const JobDesc &j);
 
 void fill_job_geometry(JobDesc &j);
 

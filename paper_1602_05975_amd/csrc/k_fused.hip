@@ -1,32 +1,39 @@
 // Fused CDEF kernel over 64x64 filter blocks (Section 4), one workgroup of
-// four waves per filter block, in one of two modes:
+// four waves per filter block, in one of four modes:
 //
 //  * search (Section 5): direction search (Section 2, Algorithm 1), the
 //    constrained filter (Section 3) under all 64 (S^(p), S^(s)) pairs and the
 //    per-filter-block distortion D_{b,p} = ||s - d||^2 for every plane, with
-//    filtered pixels never leaving registers; the full search adds the 64
-//    presets with the skip condition bit set (Section 4: skipped 8x8 blocks
-//    filtered too; strengths 0, 0 standing for 19, 7), 128 in all;
+//    filtered pixels never leaving registers;
+//  * full search: the 64 pairs with and without the skip condition bit
+//    (Section 4: skipped 8x8 blocks filtered too; strengths 0, 0 standing
+//    for 19, 7), 128 in all;
 //  * weighted search (Section 5, Eq. 14): the 64 pairs with the
 //    contrast-weighted distortion instead of the SSE;
 //  * filter: direction search and the filter (Eq. 7-13) at the block's own
-//    strengths, writing the filtered planes.
+//    preset, writing the filtered planes.
 //
 // A launch covers the filter blocks of one frame or of a batch of frames of
-// any size, bit depth (8/10) and damping; workgroup ids are remapped so that
-// each XCD (one L2 each) walks a contiguous range of filter blocks and
-// neighbouring blocks share their halo lines in L2.
+// any size, bit depth, chroma layout and damping; workgroup ids are remapped
+// so that each XCD (one L2 each) walks a contiguous range of filter blocks
+// and neighbouring blocks share their halo lines in L2.  Two sets of
+// kernels are built from this source: the base kernels (3 waves per SIMD;
+// 8/10-bit; 4:0:0, 4:2:0, 4:2:2) and the extended ones (2 waves per SIMD,
+// more registers and LDS), which add 12-bit samples, 4:4:4 and the weighted
+// search.
 //
 // Search decomposition per filter block:
 //  * recon tiles with a 2-pixel halo (the taps reach +-2) and source tiles are
-//    staged in LDS for luma and both 4:2:0 chroma planes;
+//    staged in LDS for luma and the chroma planes (4:2:2 chroma is never
+//    filtered, Section 4, and is not staged);
 //  * wave 0 runs Algorithm 1 for the 64 luma 8x8 blocks, one block per lane,
 //    while waves 1-3 sum (x - s)^2 over skipped blocks (identical for every
 //    pair);
 //  * non-skipped blocks are compacted; a luma task is two 8x8 blocks held in
 //    the two 16-bit halves of every lane (lane = pixel), so the per-block
-//    strengths are wave-uniform scalars; a chroma task is eight 4x4 blocks;
-//    waves 0-1 take the Cb tasks and waves 2-3 the Cr tasks;
+//    strengths are wave-uniform scalars; a 4:2:0 chroma task is eight 4x4
+//    blocks, Cb on waves 0-1 and Cr on waves 2-3; 4:4:4 chroma tasks are
+//    shaped like luma tasks, one plane after the other on all four waves;
 //  * per task and lane the candidate-independent work (12 tap magnitudes and
 //    signs, clamp bounds) is done once; secondary sums for S^(s) = 1, 2, 4,
 //    the primary sum once per S^(p), and per pair one packed
@@ -37,11 +44,15 @@
 //  * the full search runs the same tasks a second time over the skipped
 //    blocks, into separate sums, and evaluates (19, 7) in the slot of the
 //    pair (0, 0), whose unfiltered distortion is summed while wave 0 runs
-//    the direction search.  By
-//    8x8 block the distortion splits: with the bit, D = (blocks with residual
-//    at p) + (skipped blocks at p); without it, (blocks with residual at p) +
-//    (skipped blocks unfiltered); a filter block with every block skipped
-//    is never filtered.
+//    the direction search.  By 8x8 block the distortion splits: with the
+//    bit, D = (blocks with residual at p) + (skipped blocks at p); without
+//    it, (blocks with residual at p) + (skipped blocks unfiltered); a filter
+//    block with every block skipped is never filtered.
+//
+// 12-bit samples: the packed arithmetic stays in 16 bits (tap differences
+// and y - s below 2^12, strength sums below 2^13) but the source is no
+// longer folded into the rounding offset (16 (x - s) would not fit), and the
+// last two levels of the cross-lane sums run in 64 bits.
 #include "cdef_device.hpp"
 #include "cdef_launch.hpp"
 
@@ -51,7 +62,7 @@ namespace {
 
 constexpr int kLS = 80;  // luma recon tile row stride in samples (68 used)
 constexpr int kLC0 = 8;  // tile column that holds frame column x0 (16-byte aligned)
-constexpr int kCS = 48;  // chroma recon tile row stride (36 used)
+constexpr int kCS = 48;  // 4:2:0 chroma recon tile row stride (36 used)
 constexpr int kCC0 = 8;
 
 // LDS offsets of the six tap positions (inner, outer along d; along d+2;
@@ -68,7 +79,8 @@ __host__ __device__ constexpr TapTable make_tap_table(int stride) {
     }
   return t;
 }
-// Indexed with wave-uniform directions, so the reads are scalar loads.
+// Indexed with wave-uniform directions, so the reads are scalar loads.  Also
+// serves the 4:4:4 chroma tiles, which have the luma tile's stride.
 __constant__ TapTable kLumaTaps = make_tap_table(kLS);
 
 __device__ __forceinline__ s16x2 as_s(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
@@ -86,15 +98,16 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 
 // Per-lane, candidate-independent state of one task: two samples per lane.
 struct Taps {
-  u16x2 ad[12];  // |x_tap - x| (out-of-frame taps: >= 31745)
+  u16x2 ad[12];  // |x_tap - x| (out-of-frame taps: >= 28673)
   s16x2 sg[12];  // sign of x_tap - x as +-1
-  s16x2 X;       // 16 (x - s) + 8: the rounding offset with the source folded in
+  s16x2 X;       // 16 (x - s) + 8: the rounding offset with the source folded in (8/10-bit)
   s16x2 dxs;     // x - s
   s16x2 lo, hi;  // clamp range minus s
 };
 
 // Tap order: primary +inner, -inner, +outer, -outer; then for the two
 // secondary directions d+2 and d-2 the same four.
+template <bool B12>
 __device__ __forceinline__ void prepare(Taps &t, uint32_t xv, uint32_t sv, const uint32_t (&tp)[12]) {
   const s16x2 X = as_s(xv);
   s16x2 hi = X;
@@ -111,7 +124,7 @@ __device__ __forceinline__ void prepare(Taps &t, uint32_t xv, uint32_t sv, const
   }
   const s16x2 S = as_s(sv);
   t.dxs = X - S;
-  t.X = t.dxs * splat(16) + splat(8);
+  if (!B12) t.X = t.dxs * splat(16) + splat(8);
   t.lo = as_s(lo) - S;
   t.hi = hi - S;
 }
@@ -144,18 +157,25 @@ __device__ __forceinline__ s16x2 secondary(const Taps &t, uint32_t s, uint32_t s
   return q;
 }
 
+// round(v / 16), ties away from zero, as v + 8 - [v < 0] shifted right by 4.
+__device__ __forceinline__ s16x2 round16(s16x2 v) {
+  return (v + splat(8) + (v >> splat(15))) >> splat(4);
+}
+
 // One (S^(p), S^(s)) pair with both groups possibly active: round the sum
 // of P and Q ties-away-from-zero, add to x - s, clamp; returns y - s.
+template <bool B12>
 __device__ __forceinline__ s16x2 err_both(const Taps &t, s16x2 P, s16x2 Q) {
   const s16x2 sum = P + Q;
-  const s16x2 y = (t.X + sum + (sum >> splat(15))) >> splat(4);
+  const s16x2 y = B12 ? t.dxs + round16(sum) : (t.X + sum + (sum >> splat(15))) >> splat(4);
   return __builtin_elementwise_min(__builtin_elementwise_max(y, t.lo), t.hi);
 }
 
 // A pair with only one tap group: its weights sum to 12/16 < 1, so the
 // result cannot leave the clamp range and the clamp is skipped.
+template <bool B12>
 __device__ __forceinline__ s16x2 err_one(const Taps &t, s16x2 P) {
-  return (t.X + P + (P >> splat(15))) >> splat(4);
+  return B12 ? t.dxs + round16(P) : (t.X + P + (P >> splat(15))) >> splat(4);
 }
 
 // Secondary sums for S^(s) = 1, 2, 4 at damping `damp` (8-bit domain).
@@ -168,6 +188,7 @@ __device__ __forceinline__ void secondaries(const Taps &t, int c, int damp, s16x
 // The special preset (Section 4) on a luma task: S^(p) = 19 adjusted per
 // block by Eq. (13) (a19A, a19B), S^(s) = 7, each block's damping raised to
 // floor(log2 S) when lower.
+template <bool B12>
 __device__ __forceinline__ s16x2 luma_special(const Taps &t, int a19A, int a19B, int c, int D) {
   const int dA = luma_damping(D, a19A), dB = luma_damping(D, a19B);
   const uint32_t sp = ((uint32_t)a19A << c) | ((uint32_t)a19B << (16 + c));
@@ -180,11 +201,12 @@ __device__ __forceinline__ s16x2 luma_special(const Taps &t, int a19A, int a19B,
   for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
   const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
   const s16x2 Q = secondary(t, splat32(7u << c), (uint32_t)(dA - 2) | ((uint32_t)(dB - 2) << 16));
-  return err_both(t, P, Q);
+  return err_both<B12>(t, P, Q);
 }
 
 // The special preset on a chroma task: 19 (odd: weights 3, 3) and 7 at the
 // chroma damping max(D - 1, floor(log2 19) = 4).
+template <bool B12>
 __device__ __forceinline__ s16x2 chroma_special(const Taps &t, int c, int D) {
   const int Dc = max(D - 1, 4);
   u16x2 a[4];
@@ -192,26 +214,26 @@ __device__ __forceinline__ s16x2 chroma_special(const Taps &t, int c, int D) {
   for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32((uint32_t)(Dc - 4)));
   const s16x2 P = group_sum(t, a, 0, splat32(19u << c), splat32(3), splat32(3));
   const s16x2 Q = secondary(t, splat32(7u << c), splat32((uint32_t)(Dc - 2)));
-  return err_both(t, P, Q);
+  return err_both<B12>(t, P, Q);
 }
 
 // Luma task: 2 blocks (lo/hi half) with per-block adjusted primary
 // strengths (Eq. 13).  Per-strength parameters are wave-uniform 32-bit
 // scalars (low half: block A, high half: block B).  Each pair's y - s goes
 // to sink(pair, e), pair = S^(p) * 4 + index of S^(s).
-template <bool FULL, class Sink>
+template <bool FULL, bool B12, class Sink>
 __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_t adjB, int a19A,
                                            int a19B, int c, int D, Sink &&sink) {
   // pair (0, 0) filters nothing; in the full search its slot carries the
   // special preset instead (the unfiltered distortion is summed elsewhere)
   if (FULL)
-    sink(0, luma_special(t, a19A, a19B, c, D));
+    sink(0, luma_special<B12>(t, a19A, a19B, c, D));
   else
     sink(0, t.dxs);
   s16x2 Q[4];
   secondaries(t, c, D, Q);
 #pragma unroll
-  for (int si = 1; si < 4; ++si) sink(si, err_one(t, Q[si]));
+  for (int si = 1; si < 4; ++si) sink(si, err_one<B12>(t, Q[si]));
   uint32_t prev_sh = 0xFFFFFFFFu;
   u16x2 a[4];
 #pragma unroll
@@ -229,25 +251,25 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
       for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
     }
     const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
-    sink(4 * S, err_one(t, P));
+    sink(4 * S, err_one<B12>(t, P));
 #pragma unroll
-    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both(t, P, Q[si]));
+    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both<B12>(t, P, Q[si]));
   }
 }
 
 // Chroma task: strengths are not adjusted (uniform over the plane); the
 // chroma damping is max(D - 1, floor(log2 S^(p))) for both tap groups, which
 // differs from D - 1 only for D = 3 and S^(p) >= 8.
-template <bool FULL, class Sink>
+template <bool FULL, bool B12, class Sink>
 __device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, Sink &&sink) {
   if (FULL)
-    sink(0, chroma_special(t, c, D));
+    sink(0, chroma_special<B12>(t, c, D));
   else
     sink(0, t.dxs);
   s16x2 Q[4];
   secondaries(t, c, D - 1, Q);
 #pragma unroll
-  for (int si = 1; si < 4; ++si) sink(si, err_one(t, Q[si]));
+  for (int si = 1; si < 4; ++si) sink(si, err_one<B12>(t, Q[si]));
   u16x2 a[4];
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
@@ -260,9 +282,9 @@ __device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, Sink &
     }
     const uint32_t w1 = splat32((S & 1) ? 3u : 4u), w2 = splat32((S & 1) ? 3u : 2u);
     const s16x2 P = group_sum(t, a, 0, splat32((uint32_t)S << c), w1, w2);
-    sink(4 * S, err_one(t, P));
+    sink(4 * S, err_one<B12>(t, P));
 #pragma unroll
-    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both(t, P, Q[si]));
+    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both<B12>(t, P, Q[si]));
   }
 }
 
@@ -272,6 +294,12 @@ struct SquareSum {
   __device__ __forceinline__ void operator()(int k, s16x2 e) const {
     acc[k] = __builtin_amdgcn_sdot2(e, e, acc[k], false);
   }
+};
+
+// Keeps every pair's y - s of a task.
+struct StoreErr {
+  s16x2 (&e)[64];
+  __device__ __forceinline__ void operator()(int k, s16x2 v) const { e[k] = v; }
 };
 
 // One butterfly level at lane distance 8, 4, 2 or 1: the partner lane (DPP
@@ -288,19 +316,35 @@ __device__ __forceinline__ void dpp_level(uint32_t (&v)[64], bool up) {
   }
 }
 
-// Wave-wide sum of 64 per-lane accumulators; lane k returns the total of
-// accumulator k.  Each level halves the values kept per lane.
-__device__ __forceinline__ uint32_t reduce_transpose(const int (&acc)[64], int lane) {
-  uint32_t v[64];
+// The same level on 64-bit values (two 32-bit DPP moves per value).
+template <int HALF, int CTRL>
+__device__ __forceinline__ void dpp_level64(uint64_t (&v)[4], bool up) {
 #pragma unroll
-  for (int i = 0; i < 64; ++i) v[i] = (uint32_t)acc[i];
-  // distance 32: lanes 0-31 keep pair i, lanes 32-63 pair i + 32
+  for (int i = 0; i < HALF; ++i) {
+    const uint64_t a = v[i], b = v[i + HALF];
+    const uint64_t send = up ? a : b;
+    const uint64_t keep = up ? b : a;
+    const uint32_t lo =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)send, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(send >> 32),
+                                                              CTRL, 0xF, 0xF, false);
+    v[i] = keep + ((uint64_t)hi << 32 | lo);
+  }
+}
+
+// Wave-wide sums of 64 per-lane 32-bit values (consumed); lane k returns
+// the total of value k.  Each level halves the values kept per lane.  With
+// B12 the last two levels (sums over 32 and 64 lanes) run in 64 bits: after
+// 16 lanes a 12-bit sum is still below 2^32.
+template <bool B12>
+__device__ __forceinline__ uint64_t reduce_transpose_u(uint32_t (&v)[64], int lane) {
+  // distance 32: lanes 0-31 keep value i, lanes 32-63 value i + 32
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
     const auto r = __builtin_amdgcn_permlane32_swap(v[i], v[i + 32], false, false);
     v[i] = r[0] + r[1];
   }
-  // distance 16: odd rows of 16 keep pair i + 16
+  // distance 16: odd rows of 16 keep value i + 16
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const auto r = __builtin_amdgcn_permlane16_swap(v[i], v[i + 16], false, false);
@@ -308,28 +352,24 @@ __device__ __forceinline__ uint32_t reduce_transpose(const int (&acc)[64], int l
   }
   dpp_level<8, 0x140>(v, (lane & 8) != 0);  // row_mirror: 15 - l within a row
   dpp_level<4, 0x141>(v, (lane & 4) != 0);  // row_half_mirror: 7 - l within 8
-  dpp_level<2, 0x4E>(v, (lane & 2) != 0);   // quad_perm [2,3,0,1]
-  dpp_level<1, 0xB1>(v, (lane & 1) != 0);   // quad_perm [1,0,3,2]
-  return v[0];
+  if constexpr (B12) {
+    uint64_t w[4] = {v[0], v[1], v[2], v[3]};
+    dpp_level64<2, 0x4E>(w, (lane & 2) != 0);  // quad_perm [2,3,0,1]
+    dpp_level64<1, 0xB1>(w, (lane & 1) != 0);  // quad_perm [1,0,3,2]
+    return w[0];
+  } else {
+    dpp_level<2, 0x4E>(v, (lane & 2) != 0);
+    dpp_level<1, 0xB1>(v, (lane & 1) != 0);
+    return v[0];
+  }
 }
 
-// The same butterfly on values already in 32-bit registers (consumed).
-__device__ __forceinline__ uint32_t reduce_transpose_u(uint32_t (&v)[64], int lane) {
+template <bool B12>
+__device__ __forceinline__ uint64_t reduce_transpose(const int (&acc)[64], int lane) {
+  uint32_t v[64];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const auto r = __builtin_amdgcn_permlane32_swap(v[i], v[i + 32], false, false);
-    v[i] = r[0] + r[1];
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const auto r = __builtin_amdgcn_permlane16_swap(v[i], v[i + 16], false, false);
-    v[i] = r[0] + r[1];
-  }
-  dpp_level<8, 0x140>(v, (lane & 8) != 0);
-  dpp_level<4, 0x141>(v, (lane & 4) != 0);
-  dpp_level<2, 0x4E>(v, (lane & 2) != 0);
-  dpp_level<1, 0xB1>(v, (lane & 1) != 0);
-  return v[0];
+  for (int i = 0; i < 64; ++i) v[i] = (uint32_t)acc[i];
+  return reduce_transpose_u<B12>(v, lane);
 }
 
 // Sums within each row of 16 lanes: 64 values per lane in, and lane l of a
@@ -344,9 +384,15 @@ __device__ __forceinline__ void reduce_rows_transpose(uint32_t (&v)[64], int lan
   for (int j = 0; j < 4; ++j) out[j] = v[j];
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += (uint32_t)__shfl_xor((int)v, m, 64);
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
   return v;
 }
 
@@ -357,47 +403,65 @@ __device__ __forceinline__ int xcd_item(int wg, int n) {
   return x * q + min(x, r) + i;
 }
 
-struct Smem {
+// Planes a search covers: luma only at 4:0:0 and 4:2:2.
+__device__ __forceinline__ int search_planes(const JobDesc &J) {
+  return J.nplanes == 3 && J.layout != kLayout422 ? 3 : 1;
+}
+
+// LDS of one workgroup.  X (extended kernels): chroma tiles as large as
+// luma's for 4:4:4.
+template <bool X>
+struct SmemT {
+  static constexpr int kCT = X ? 68 * kLS : 36 * kCS;  // chroma recon tile
+  static constexpr int kCSrc = X ? 64 * 64 : 32 * 32;  // chroma source tile
   uint16_t ry[68 * kLS];
   uint16_t sy[64 * 64];
-  uint16_t rc[2][36 * kCS];
-  uint16_t sc[2][32 * 32];
+  uint16_t rc[2][kCT];
+  uint16_t sc[2][kCSrc];
   uint64_t adj[64];
   int32_t var[64];
-  uint32_t red[2][4][64];   // [luma, chroma][wave][pair]: blocks with residual
-  uint32_t red2[2][4][64];  // the same over skipped blocks (full search)
-  uint32_t skipsse[3];      // per plane: sum of (x - s)^2 over skipped blocks
-  uint32_t allsse[3];       // the same over every in-frame pixel (full search)
+  uint64_t red[3][4][64];  // [plane][wave][pair]: blocks with residual
+  union {
+    uint64_t red2[3][4][64];  // the same over skipped blocks (full search)
+    struct {
+      // weighted search, per plane and filtering unit (8x8 luma and 4:4:4
+      // chroma, 4x4 4:2:0 chroma): n, sum s, sum s^2, sum x, sum x^2, sum x s
+      // over in-frame pixels
+      uint32_t ustat[6][3][64];
+      double wred[3][4][64];  // per wave and pair: Eq. (14) over its tasks' units
+    } w;
+  };
+  uint64_t skipsse[3];  // per plane: sum of (x - s)^2 over skipped blocks
+  uint64_t allsse[3];   // the same over every in-frame pixel (full search)
+  double skipw[3];      // Eq. (14) over skipped units, per plane
   int16_t coff[8][6];
   uint8_t dir[64];
   uint8_t list[64];   // blocks with residual, then (full search) skipped blocks
   uint8_t adj19[64];  // Eq. (13) applied to 19 (full search)
   uint8_t flag[64];   // bit 0: in frame, bit 1: skipped
   int n, nsk;
-  // weighted search: per plane and filtering unit (8x8 luma, 4x4 chroma)
-  // n, sum s, sum s^2, sum x, sum x^2, sum x s over in-frame pixels
-  uint32_t ustat[6][3][64];
-  double skipw[3];          // Eq. (14) over skipped units, per plane
-  double wred[2][4][64];    // per wave and pair: Eq. (14) over its tasks' units
 };
 
-// Stage the recon tiles (all modes) and, for the search, the source tiles;
-// per-block flags for the 64 luma blocks.  Filter blocks whose tiles (with
-// the 16-byte-rounded halo) lie inside aligned planes take 16-byte loads;
-// the rest go sample by sample with the frame-edge sentinel.
-__device__ __forceinline__ void stage_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid,
-                                           bool search) {
+// Stage the recon tiles (all modes) and, for the searches, the source
+// tiles; per-block flags for the 64 luma blocks.  Filter blocks whose tiles
+// (with the 16-byte-rounded halo) lie inside aligned planes take 16-byte
+// loads; the rest go sample by sample with the frame-edge sentinel.
+template <bool X>
+__device__ __forceinline__ void stage_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
+                                           int tid, bool search) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
-  const bool chroma = J.nplanes == 3;
-  const bool fast = (J.flags & kAligned16) && y0 >= 2 && y0 + 66 <= H && x0 >= 8 &&
-                    x0 + 72 <= W &&
-                    (!chroma || (cy0 >= 2 && cy0 + 34 <= ch && cx0 >= 8 && cx0 + 40 <= cw));
+  const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
+  const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
+  const bool luma_fast = (J.flags & kAligned16) && y0 >= 2 && y0 + 66 <= H && x0 >= 8 &&
+                         x0 + 72 <= W;
+  const bool fast =
+      luma_fast && (!c420 || (cy0 >= 2 && cy0 + 34 <= ch && cx0 >= 8 && cx0 + 40 <= cw));
   if (fast) {
     // luma: 68 rows of columns x0-8 .. x0+71 (the tile's full 80-sample rows)
     stage_rows16<68, 10, kLS, 256>(sm.ry, J.rec[0], J.rstride[0], y0 - 2, x0 - kLC0, tid);
     if (search) stage_rows16<64, 8, 64, 256>(sm.sy, J.src[0], J.sstride[0], y0, x0, tid);
-    if (chroma) {
+    if (c420) {
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         stage_rows16<36, 6, kCS, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], cy0 - 2,
@@ -406,10 +470,21 @@ __device__ __forceinline__ void stage_item(Smem &sm, const JobDesc &J, int fby, 
           stage_rows16<32, 4, 32, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], cy0, cx0, tid);
       }
     }
+    if constexpr (X) {
+      if (c444) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          stage_rows16<68, 10, kLS, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], y0 - 2,
+                                         x0 - kLC0, tid);
+          if (search)
+            stage_rows16<64, 8, 64, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], y0, x0, tid);
+        }
+      }
+    }
   } else {
     stage_recon<64, 64, kLS, kLC0, 256>(sm.ry, J.rec[0], J.rstride[0], W, H, y0, x0, tid);
     if (search) stage_interior<64, 64, 256>(sm.sy, J.src[0], J.sstride[0], W, H, y0, x0, tid);
-    if (chroma) {
+    if (c420) {
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         stage_recon<32, 32, kCS, kCC0, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], cw, ch,
@@ -417,6 +492,18 @@ __device__ __forceinline__ void stage_item(Smem &sm, const JobDesc &J, int fby, 
         if (search)
           stage_interior<32, 32, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], cw, ch, cy0,
                                       cx0, tid);
+      }
+    }
+    if constexpr (X) {
+      if (c444) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          stage_recon<64, 64, kLS, kLC0, 256>(sm.rc[p], J.rec[p + 1], J.rstride[p + 1], W, H, y0,
+                                              x0, tid);
+          if (search)
+            stage_interior<64, 64, 256>(sm.sc[p], J.src[p + 1], J.sstride[p + 1], W, H, y0, x0,
+                                        tid);
+        }
       }
     }
   }
@@ -431,15 +518,17 @@ __device__ __forceinline__ void stage_item(Smem &sm, const JobDesc &J, int fby, 
     const bool sk = in && J.skip && J.skip[(int64_t)by * J.bcols + bx];
     sm.flag[tid] = (uint8_t)((in ? 1 : 0) | (sk ? 2 : 0));
   }
-  if (tid < 3) sm.skipsse[tid] = 0;
-  if (tid < 3) sm.allsse[tid] = 0;
+  if (tid < 3) {
+    sm.skipsse[tid] = 0;
+    sm.allsse[tid] = 0;
+  }
 }
 
 // Algorithm 1 for the 64 luma blocks of the filter block, one per lane of
 // wave 0; Eq. (13) adjusted strengths; compaction of the blocks to filter
 // (the full search lists the skipped in-frame blocks after them).
-template <bool FULL>
-__device__ __forceinline__ void direction_search(Smem &sm, const JobDesc &J, int fby, int fbx,
+template <bool FULL, bool X>
+__device__ __forceinline__ void direction_search(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
                                                  int lane) {
   const int b = lane;
   const int by = fby * 8 + (b >> 3), bx = fbx * 8 + (b & 7);
@@ -494,24 +583,41 @@ __device__ __forceinline__ void direction_search(Smem &sm, const JobDesc &J, int
   if (lane == 0) sm.n = __popcll(m);
 }
 
-// Sum of (x - s)^2 over pixels of skipped blocks, for each plane, and in
-// the full search also over every in-frame pixel; run by threads t0.. of
-// the workgroup (nt of them).
-template <bool FULL>
-__device__ __forceinline__ void skipped_sse(Smem &sm, const JobDesc &J, int fby, int fbx, int t,
-                                            int nt, int lane) {
+// Sum of (x - s)^2 over pixels of skipped blocks, for each searched plane,
+// and in the full search also over every in-frame pixel; run by threads
+// t0.. of the workgroup (nt of them).  Per-lane partial sums stay below
+// 2^32 (at most 22 pixels of 12 bits); the wave sums are 64-bit.
+template <bool FULL, bool X>
+__device__ __forceinline__ void skipped_sse(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
+                                            int t, int nt, int lane) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   uint32_t e[3] = {0, 0, 0}, a[3] = {0, 0, 0};
+  const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
   for (int i = t; i < 64 * 64; i += nt) {
     const int r = i >> 6, col = i & 63;
     if (y0 + r < H && x0 + col < W) {
-      const int dd = (int)sm.ry[(r + 2) * kLS + kLC0 + col] - (int)sm.sy[i];
+      const bool sk = sm.flag[(r >> 3) * 8 + (col >> 3)] & 2;
+      const int k = (r + 2) * kLS + kLC0 + col;
+      const int dd = (int)sm.ry[k] - (int)sm.sy[i];
       const uint32_t q = (uint32_t)(dd * dd);
-      if (sm.flag[(r >> 3) * 8 + (col >> 3)] & 2) e[0] += q;
+      if (sk) e[0] += q;
       a[0] += q;
+      if constexpr (X) {
+        if (c444) {
+          const int d1 = (int)sm.rc[0][k] - (int)sm.sc[0][i];
+          const int d2 = (int)sm.rc[1][k] - (int)sm.sc[1][i];
+          const uint32_t q1 = (uint32_t)(d1 * d1), q2 = (uint32_t)(d2 * d2);
+          if (sk) {
+            e[1] += q1;
+            e[2] += q2;
+          }
+          a[1] += q1;
+          a[2] += q2;
+        }
+      }
     }
   }
-  if (J.nplanes == 3) {
+  if (J.nplanes == 3 && J.layout == kLayout420) {
     const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
     for (int i = t; i < 32 * 32; i += nt) {
       const int r = i >> 5, col = i & 31;
@@ -531,25 +637,25 @@ __device__ __forceinline__ void skipped_sse(Smem &sm, const JobDesc &J, int fby,
   }
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
-    const uint32_t es = wave_sum(e[p]);
-    if (lane == 0) atomicAdd(&sm.skipsse[p], es);
+    const uint64_t es = wave_sum64(e[p]);
+    if (lane == 0) atomicAdd((unsigned long long *)&sm.skipsse[p], (unsigned long long)es);
     if (FULL) {
-      const uint32_t as = wave_sum(a[p]);
-      if (lane == 0) atomicAdd(&sm.allsse[p], as);
+      const uint64_t as = wave_sum64(a[p]);
+      if (lane == 0) atomicAdd((unsigned long long *)&sm.allsse[p], (unsigned long long)as);
     }
   }
 }
 
-// Luma tasks over list entries [first, first + count): two 8x8 blocks per
-// task, dealt round-robin to the four waves; per-wave pair totals go to
-// red[wave][pair].
-template <bool FULL>
-__device__ __forceinline__ void luma_tasks(Smem &sm, const JobDesc &J, int first, int count,
-                                           int y0, int x0, int wave, int lane, uint32_t *red) {
-  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
-  int acc[64];
-#pragma unroll
-  for (int i = 0; i < 64; ++i) acc[i] = 0;
+// Tasks over list entries [first, first + count) of one plane shaped like
+// luma (8x8 blocks, two per task, dealt round-robin to the four waves):
+// plane 0 is luma, planes 1-2 are 4:4:4 chroma.  For each task,
+// body(taps, A, B, hasB, packed source) consumes the pairs.
+template <bool X, bool B12, int CH, class Body>
+__device__ __forceinline__ void block_tasks(SmemT<X> &sm, const JobDesc &J, int first, int count,
+                                            int y0, int x0, int wave, int lane, Body &&body) {
+  const int W = J.width, H = J.height;
+  const uint16_t *rt = CH == 0 ? sm.ry : sm.rc[CH - 1];
+  const uint16_t *st = CH == 0 ? sm.sy : sm.sc[CH - 1];
   const int ntask = (count + 1) >> 1;
   const int r = lane >> 3, col = lane & 7;
   for (int tk = wave; tk < ntask; tk += 4) {
@@ -557,47 +663,71 @@ __device__ __forceinline__ void luma_tasks(Smem &sm, const JobDesc &J, int first
     const bool hasB = 2 * tk + 1 < count;
     const int B = hasB ? uniform(sm.list[first + 2 * tk + 1]) : A;
     const int dA = uniform(sm.dir[A]), dB = uniform(sm.dir[B]);
-    const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
     const int rA = 8 * (A >> 3) + r, cA = 8 * (A & 7) + col;
     const int rB = 8 * (B >> 3) + r, cB = 8 * (B & 7) + col;
     const bool vA = y0 + rA < H && x0 + cA < W;
     const bool vB = hasB && y0 + rB < H && x0 + cB < W;
     const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
     const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
-    const uint32_t xv = ((uint32_t)sm.ry[bA] | ((uint32_t)sm.ry[bB] << 16)) & vm;
-    const uint32_t sv =
-        ((uint32_t)sm.sy[rA * 64 + cA] | ((uint32_t)sm.sy[rB * 64 + cB] << 16)) & vm;
+    const uint32_t xv = ((uint32_t)rt[bA] | ((uint32_t)rt[bB] << 16)) & vm;
+    const uint32_t sv = ((uint32_t)st[rA * 64 + cA] | ((uint32_t)st[rB * 64 + cB] << 16)) & vm;
     uint32_t tp[12];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int oA = kLumaTaps.off[dA][k], oB = kLumaTaps.off[dB][k];
       const int slot = (k >> 1) * 4 + (k & 1) * 2;
-      tp[slot] = ((uint32_t)sm.ry[bA + oA] | ((uint32_t)sm.ry[bB + oB] << 16)) & vm;
-      tp[slot + 1] = ((uint32_t)sm.ry[bA - oA] | ((uint32_t)sm.ry[bB - oB] << 16)) & vm;
+      tp[slot] = ((uint32_t)rt[bA + oA] | ((uint32_t)rt[bB + oB] << 16)) & vm;
+      tp[slot + 1] = ((uint32_t)rt[bA - oA] | ((uint32_t)rt[bB - oB] << 16)) & vm;
     }
     Taps t;
-    prepare(t, xv, sv, tp);
-    const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
-    luma_pairs<FULL>(t, adjA, adjB, a19A, a19B, c, D, SquareSum{acc});
+    prepare<B12>(t, xv, sv, tp);
+    body(t, A, B, hasB, sv);
   }
-  red[wave * 64 + lane] = reduce_transpose(acc, lane);
 }
 
-// Chroma (4:2:0) tasks over list entries [first, first + count): eight 4x4
-// blocks per task (four per half); waves 0-1 take Cb, waves 2-3 Cr.
-template <bool FULL>
-__device__ __forceinline__ void chroma_tasks(Smem &sm, const JobDesc &J, int first, int count,
-                                             int y0, int x0, int wave, int lane, uint32_t *red) {
-  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
+// The pair generator of a luma-shaped task of plane CH.
+template <bool FULL, bool B12, int CH, bool X, class Sink>
+__device__ __forceinline__ void block_pairs(SmemT<X> &sm, const JobDesc &J, const Taps &t, int A,
+                                            int B, Sink &&sink) {
+  const int c = J.bitdepth - 8, D = J.damping;
+  if (CH == 0) {
+    const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
+    const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
+    luma_pairs<FULL, B12>(t, adjA, adjB, a19A, a19B, c, D, sink);
+  } else {
+    chroma_pairs<FULL, B12>(t, c, D, sink);
+  }
+}
+
+// SSE search over luma-shaped tasks; per-wave pair totals go to red[wave].
+template <bool FULL, bool B12, int CH, bool X>
+__device__ __forceinline__ void plane_tasks(SmemT<X> &sm, const JobDesc &J, int first, int count,
+                                            int y0, int x0, int wave, int lane, uint64_t *red) {
+  int acc[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) acc[i] = 0;
+  block_tasks<X, B12, CH>(sm, J, first, count, y0, x0, wave, lane,
+                          [&](const Taps &t, int A, int B, bool, uint32_t) {
+                            block_pairs<FULL, B12, CH>(sm, J, t, A, B, SquareSum{acc});
+                          });
+  red[wave * 64 + lane] = reduce_transpose<B12>(acc, lane);
+}
+
+// 4:2:0 chroma tasks over list entries [first, first + count): eight 4x4
+// blocks per task (four per half); waves 0-1 take Cb, waves 2-3 Cr.  For
+// each task, body(taps, L, Hb, hasL, hasH, packed source) consumes the
+// pairs.
+template <bool X, bool B12, class Body>
+__device__ __forceinline__ void chroma420_tasks(SmemT<X> &sm, const JobDesc &J, int first,
+                                                int count, int y0, int x0, int wave, int lane,
+                                                Body &&body) {
+  const int W = J.width, H = J.height;
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
   const int p = wave >> 1;
   const uint16_t *rt = sm.rc[p];
   const uint16_t *st = sm.sc[p];
   const int ntask = (count + 7) >> 3;
   const int sub = lane >> 4, r = (lane >> 2) & 3, col = lane & 3;
-  int acc[64];
-#pragma unroll
-  for (int i = 0; i < 64; ++i) acc[i] = 0;
   for (int tk = wave & 1; tk < ntask; tk += 2) {
     const int iL = 8 * tk + sub, iH = 8 * tk + 4 + sub;
     const bool hasL = iL < count, hasH = iH < count;
@@ -620,19 +750,42 @@ __device__ __forceinline__ void chroma_tasks(Smem &sm, const JobDesc &J, int fir
       tp[slot + 1] = ((uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16)) & vm;
     }
     Taps t;
-    prepare(t, xv, sv, tp);
-    chroma_pairs<FULL>(t, c, D, SquareSum{acc});
+    prepare<B12>(t, xv, sv, tp);
+    body(t, L, Hb, hasL, hasH, sv);
   }
-  red[wave * 64 + lane] = reduce_transpose(acc, lane);
 }
 
-template <bool FULL>
-__device__ __forceinline__ void search_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid) {
+// SSE search over 4:2:0 chroma tasks; plane 1 + p's totals go to
+// red[1 + p][wave & 1].
+template <bool FULL, bool B12, bool X>
+__device__ __forceinline__ void chroma420_sse(SmemT<X> &sm, const JobDesc &J, int first, int count,
+                                              int y0, int x0, int wave, int lane,
+                                              uint64_t (*red)[4][64]) {
+  const int c = J.bitdepth - 8, D = J.damping;
+  int acc[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) acc[i] = 0;
+  chroma420_tasks<X, B12>(sm, J, first, count, y0, x0, wave, lane,
+                          [&](const Taps &t, int, int, bool, bool, uint32_t) {
+                            chroma_pairs<FULL, B12>(t, c, D, SquareSum{acc});
+                          });
+  red[1 + (wave >> 1)][wave & 1][lane] = reduce_transpose<B12>(acc, lane);
+}
+
+// Waves whose per-wave sums make up plane P's totals.
+__device__ __forceinline__ int plane_waves(const JobDesc &J, int P) {
+  return P == 0 || J.layout == kLayout444 ? 4 : 2;
+}
+
+template <bool FULL, bool B12, bool X>
+__device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
+                                            int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   const int y0 = fby * 64, x0 = fbx * 64;
-  const bool chroma = J.nplanes == 3;
+  const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
+  const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
 
-  stage_item(sm, J, fby, fbx, tid, true);
+  stage_item<X>(sm, J, fby, fbx, tid, true);
   __syncthreads();
   if (wave == 0)
     direction_search<FULL>(sm, J, fby, fbx, lane);
@@ -641,39 +794,45 @@ __device__ __forceinline__ void search_item(Smem &sm, const JobDesc &J, int fby,
   __syncthreads();
   const int n = sm.n;
 
-  luma_tasks<FULL>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[0][0][0]);
-  if (chroma) chroma_tasks<FULL>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[1][0][0]);
+  plane_tasks<FULL, B12, 0>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[0][0][0]);
+  if (c420) chroma420_sse<FULL, B12>(sm, J, 0, n, y0, x0, wave, lane, sm.red);
+  if constexpr (X) {
+    if (c444) {
+      plane_tasks<FULL, B12, 1>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[1][0][0]);
+      plane_tasks<FULL, B12, 2>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[2][0][0]);
+    }
+  }
   // skipped blocks matter only where some block has residual
   if (FULL && n > 0) {
     const int nsk = sm.nsk;
-    luma_tasks<FULL>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[0][0][0]);
-    if (chroma) chroma_tasks<FULL>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[1][0][0]);
+    plane_tasks<FULL, B12, 0>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[0][0][0]);
+    if (c420) chroma420_sse<FULL, B12>(sm, J, n, nsk, y0, x0, wave, lane, sm.red2);
+    if constexpr (X) {
+      if (c444) {
+        plane_tasks<FULL, B12, 1>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[1][0][0]);
+        plane_tasks<FULL, B12, 2>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[2][0][0]);
+      }
+    }
   }
   __syncthreads();
 
+  const int P = tid >> 6, k = lane;
+  if (P >= search_planes(J)) return;
+  const int nw = plane_waves(J, P);
+  uint64_t A = 0, Bf = 0;
+  for (int w = 0; w < nw; ++w) {
+    A += sm.red[P][w][k];
+    if (FULL) Bf += sm.red2[P][w][k];
+  }
   const int64_t fbi = (int64_t)fby * J.fbc + fbx;
   const int64_t nfb = (int64_t)J.fbr * J.fbc;
-  int P = -1, k = tid & 63;
-  uint64_t A = 0, Bf = 0;
-  if (tid < 64) {
-    P = 0;
-    A = (uint64_t)sm.red[0][0][k] + sm.red[0][1][k] + sm.red[0][2][k] + sm.red[0][3][k];
-    if (FULL)
-      Bf = (uint64_t)sm.red2[0][0][k] + sm.red2[0][1][k] + sm.red2[0][2][k] + sm.red2[0][3][k];
-  } else if (chroma && tid < 192) {
-    const int p = (tid >> 6) - 1;
-    P = 1 + p;
-    A = (uint64_t)sm.red[1][2 * p][k] + sm.red[1][2 * p + 1][k];
-    if (FULL) Bf = (uint64_t)sm.red2[1][2 * p][k] + sm.red2[1][2 * p + 1][k];
-  }
-  if (P < 0) return;
   const uint64_t U = sm.skipsse[P];
   if (!FULL) {
     J.sse[(P * nfb + fbi) * 64 + k] = A + U;
   } else {
     // slot 0 holds the special preset; (0, 0) itself is the unfiltered sum
     uint64_t *o = J.sse + (P * nfb + fbi) * 128;
-    o[k] = k == 0 ? (uint64_t)sm.allsse[P] : A + U;
+    o[k] = k == 0 ? sm.allsse[P] : A + U;
     o[64 + k] = n > 0 ? A + Bf : U;  // every block skipped: nothing is filtered
   }
 }
@@ -695,11 +854,15 @@ __device__ __forceinline__ double eq14(int n, uint32_t ss, uint32_t ss2, uint32_
 // unit row (8 or 4 pixels) per step; run by threads t0.. (nt of them) while
 // wave 0 runs the direction search.  Unit rows are dealt so that
 // neighbouring threads add into different units.
-__device__ __forceinline__ void unit_stats(Smem &sm, const JobDesc &J, int fby, int fbx, int t,
-                                           int nt) {
+__device__ __forceinline__ void unit_stats(SmemT<true> &sm, const JobDesc &J, int fby, int fbx,
+                                           int t, int nt) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
-  const int nrows = J.nplanes == 3 ? 1024 : 512;
+  const int planes = search_planes(J);
+  const bool c444 = J.layout == kLayout444;
+  // unit rows: 512 luma, then per chroma plane 256 (4x4 units) or 512 (8x8)
+  const int crows = c444 ? 512 : 256;
+  const int nrows = 512 + (planes - 1) * crows;
   for (int k = t; k < nrows; k += nt) {
     int P, u, row;
     if (k < 512) {
@@ -707,17 +870,20 @@ __device__ __forceinline__ void unit_stats(Smem &sm, const JobDesc &J, int fby, 
       u = k & 63;
       row = k >> 6;
     } else {
-      P = 1 + ((k - 512) >> 8);
-      u = k & 63;
-      row = ((k - 512) >> 6) & 3;
+      const int kk = k - 512;
+      P = 1 + kk / crows;
+      u = kk & 63;
+      row = (kk % crows) >> 6;
     }
     uint32_t cnt = 0, a = 0, a2 = 0, b = 0, b2 = 0, ab = 0;
-    if (P == 0) {
+    if (P == 0 || c444) {
+      const uint16_t *rt = P == 0 ? sm.ry : sm.rc[P - 1];
+      const uint16_t *st = P == 0 ? sm.sy : sm.sc[P - 1];
       const int r = 8 * (u >> 3) + row, c0 = 8 * (u & 7);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (y0 + r < H && x0 + c0 + j < W) {
-          const uint32_t sv = sm.sy[r * 64 + c0 + j], xv = sm.ry[(r + 2) * kLS + kLC0 + c0 + j];
+          const uint32_t sv = st[r * 64 + c0 + j], xv = rt[(r + 2) * kLS + kLC0 + c0 + j];
           ++cnt;
           a += sv;
           a2 += sv * sv;
@@ -743,55 +909,61 @@ __device__ __forceinline__ void unit_stats(Smem &sm, const JobDesc &J, int fby, 
       }
     }
     if (cnt) {
-      atomicAdd(&sm.ustat[0][P][u], cnt);
-      atomicAdd(&sm.ustat[1][P][u], a);
-      atomicAdd(&sm.ustat[2][P][u], a2);
-      atomicAdd(&sm.ustat[3][P][u], b);
-      atomicAdd(&sm.ustat[4][P][u], b2);
-      atomicAdd(&sm.ustat[5][P][u], ab);
+      atomicAdd(&sm.w.ustat[0][P][u], cnt);
+      atomicAdd(&sm.w.ustat[1][P][u], a);
+      atomicAdd(&sm.w.ustat[2][P][u], a2);
+      atomicAdd(&sm.w.ustat[3][P][u], b);
+      atomicAdd(&sm.w.ustat[4][P][u], b2);
+      atomicAdd(&sm.w.ustat[5][P][u], ab);
     }
   }
 }
 
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
-
-// Keeps every pair's y - s of a task.
-struct StoreErr {
-  s16x2 (&e)[64];
-  __device__ __forceinline__ void operator()(int k, s16x2 v) const { e[k] = v; }
-};
-
-// The five per-pair moments of a task, summed over the lanes of each unit
-// (all 64 lanes for luma, each row of 16 for chroma): sum d packed (low
-// half: block of the low halves; each half stays below 2^16), sum d^2 and
-// sum (d - s)^2 for either half.
-template <bool ROWS>
+// The per-pair moments of a task, summed over the lanes of each unit (all
+// 64 lanes for 8x8 units, each row of 16 for 4x4 chroma units): sum d,
+// sum d^2 and sum (d - s)^2 for either half.  Sum d is packed two units per
+// register while a unit's sum stays below 2^16 (8x8 units up to 10 bits,
+// 4x4 units up to 12); otherwise each half is summed on its own.
+template <bool ROWS, bool B12>
 struct Moments {
   static constexpr int K = ROWS ? 4 : 1;
-  uint32_t sd[K], d2lo[K], d2hi[K], e2lo[K], e2hi[K];
+  uint32_t sdlo[K], sdhi[K], d2lo[K], d2hi[K], e2lo[K], e2hi[K];
 };
 
 template <bool ROWS>
-__device__ __forceinline__ void reduce_chunk(uint32_t (&v)[64], int lane, uint32_t (&o)[ROWS ? 4 : 1]) {
+__device__ __forceinline__ void reduce_chunk(uint32_t (&v)[64], int lane,
+                                             uint32_t (&o)[ROWS ? 4 : 1]) {
   if constexpr (ROWS)
     reduce_rows_transpose(v, lane, o);
   else
-    o[0] = reduce_transpose_u(v, lane);
+    o[0] = (uint32_t)reduce_transpose_u<false>(v, lane);  // unit sums stay below 2^32
 }
 
-template <bool ROWS>
+template <bool ROWS, bool B12>
 __device__ __forceinline__ void task_moments(const s16x2 (&ev)[64], uint32_t sv, int lane,
-                                             Moments<ROWS> &m) {
+                                             Moments<ROWS, B12> &m) {
+  constexpr int K = Moments<ROWS, B12>::K;
   const s16x2 s = as_s(sv);
   const u16x2 lo = u16x2{0xFFFF, 0}, hi = u16x2{0, 0xFFFF};
   uint32_t v[64];
+  if constexpr (ROWS || !B12) {
 #pragma unroll
-  for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s);
-  reduce_chunk<ROWS>(v, lane, m.sd);
+    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s);
+    uint32_t sd[K];
+    reduce_chunk<ROWS>(v, lane, sd);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      m.sdlo[j] = sd[j] & 0xFFFF;
+      m.sdhi[j] = sd[j] >> 16;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s) & 0xFFFF;
+    reduce_chunk<ROWS>(v, lane, m.sdlo);
+#pragma unroll
+    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s) >> 16;
+    reduce_chunk<ROWS>(v, lane, m.sdhi);
+  }
 #pragma unroll
   for (int i = 0; i < 64; ++i) {
     const u16x2 d = as_u(ev[i] + s);
@@ -814,105 +986,52 @@ __device__ __forceinline__ void task_moments(const s16x2 (&ev)[64], uint32_t sv,
   reduce_chunk<ROWS>(v, lane, m.e2hi);
 }
 
-// Luma tasks of the weighted search; lane k accumulates pair k.
-__device__ __forceinline__ void luma_tasks_w(Smem &sm, const JobDesc &J, int n, int y0, int x0,
-                                             int wave, int lane, double C1, double C2) {
-  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
+// Weighted search over luma-shaped tasks of plane CH; lane k accumulates
+// pair k, and the wave's sums go to wred[CH][wave].
+template <bool B12, int CH>
+__device__ __forceinline__ void plane_tasks_w(SmemT<true> &sm, const JobDesc &J, int n, int y0,
+                                              int x0, int wave, int lane, double C1, double C2) {
   double accw = 0.0;
-  const int ntask = (n + 1) >> 1;
-  const int r = lane >> 3, col = lane & 7;
-  for (int tk = wave; tk < ntask; tk += 4) {
-    const int A = uniform(sm.list[2 * tk]);
-    const bool hasB = 2 * tk + 1 < n;
-    const int B = hasB ? uniform(sm.list[2 * tk + 1]) : A;
-    const int dA = uniform(sm.dir[A]), dB = uniform(sm.dir[B]);
-    const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
-    const int rA = 8 * (A >> 3) + r, cA = 8 * (A & 7) + col;
-    const int rB = 8 * (B >> 3) + r, cB = 8 * (B & 7) + col;
-    const bool vA = y0 + rA < H && x0 + cA < W;
-    const bool vB = hasB && y0 + rB < H && x0 + cB < W;
-    const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
-    const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
-    const uint32_t xv = ((uint32_t)sm.ry[bA] | ((uint32_t)sm.ry[bB] << 16)) & vm;
-    const uint32_t sv =
-        ((uint32_t)sm.sy[rA * 64 + cA] | ((uint32_t)sm.sy[rB * 64 + cB] << 16)) & vm;
-    uint32_t tp[12];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int oA = kLumaTaps.off[dA][k], oB = kLumaTaps.off[dB][k];
-      const int slot = (k >> 1) * 4 + (k & 1) * 2;
-      tp[slot] = ((uint32_t)sm.ry[bA + oA] | ((uint32_t)sm.ry[bB + oB] << 16)) & vm;
-      tp[slot + 1] = ((uint32_t)sm.ry[bA - oA] | ((uint32_t)sm.ry[bB - oB] << 16)) & vm;
-    }
-    s16x2 ev[64];
-    {
-      Taps t;
-      prepare(t, xv, sv, tp);
-      luma_pairs<false>(t, adjA, adjB, 0, 0, c, D, StoreErr{ev});
-    }
-    Moments<false> m;
-    task_moments<false>(ev, sv, lane, m);
-    accw += eq14((int)sm.ustat[0][0][A], sm.ustat[1][0][A], sm.ustat[2][0][A], m.sd[0] & 0xFFFF,
-                 m.d2lo[0], m.e2lo[0], C1, C2);
-    if (hasB)
-      accw += eq14((int)sm.ustat[0][0][B], sm.ustat[1][0][B], sm.ustat[2][0][B], m.sd[0] >> 16,
-                   m.d2hi[0], m.e2hi[0], C1, C2);
-  }
-  sm.wred[0][wave][lane] = accw;
+  block_tasks<true, B12, CH>(
+      sm, J, 0, n, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t sv) {
+        s16x2 ev[64];
+        block_pairs<false, B12, CH>(sm, J, t, A, B, StoreErr{ev});
+        Moments<false, B12> m;
+        task_moments<false, B12>(ev, sv, lane, m);
+        accw += eq14((int)sm.w.ustat[0][CH][A], sm.w.ustat[1][CH][A], sm.w.ustat[2][CH][A],
+                     m.sdlo[0], m.d2lo[0], m.e2lo[0], C1, C2);
+        if (hasB)
+          accw += eq14((int)sm.w.ustat[0][CH][B], sm.w.ustat[1][CH][B], sm.w.ustat[2][CH][B],
+                       m.sdhi[0], m.d2hi[0], m.e2hi[0], C1, C2);
+      });
+  sm.w.wred[CH][wave][lane] = accw;
 }
 
-// Chroma tasks of the weighted search: each row of 16 lanes holds one 4x4
-// unit per half; lane l of a row accumulates pairs 4 (l mod 16) + j.
-__device__ __forceinline__ void chroma_tasks_w(Smem &sm, const JobDesc &J, int n, int y0, int x0,
-                                               int wave, int lane, double C1, double C2) {
-  const int W = J.width, H = J.height, c = J.bitdepth - 8, D = J.damping;
-  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
-  const int p = wave >> 1;
-  const uint16_t *rt = sm.rc[p];
-  const uint16_t *st = sm.sc[p];
-  const int ntask = (n + 7) >> 3;
-  const int sub = lane >> 4, r = (lane >> 2) & 3, col = lane & 3;
+// Weighted search over 4:2:0 chroma tasks: each row of 16 lanes holds one
+// 4x4 unit per half; lane l of a row accumulates pairs 4 (l mod 16) + j.
+template <bool B12>
+__device__ __forceinline__ void chroma420_w(SmemT<true> &sm, const JobDesc &J, int n, int y0,
+                                            int x0, int wave, int lane, double C1, double C2) {
+  const int c = J.bitdepth - 8, D = J.damping;
+  const int P = 1 + (wave >> 1);
   double accw[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int tk = wave & 1; tk < ntask; tk += 2) {
-    const int iL = 8 * tk + sub, iH = 8 * tk + 4 + sub;
-    const bool hasL = iL < n, hasH = iH < n;
-    const int L = hasL ? sm.list[iL] : 0, Hb = hasH ? sm.list[iH] : 0;
-    const int rL = 4 * (L >> 3) + r, cL = 4 * (L & 7) + col;
-    const int rH = 4 * (Hb >> 3) + r, cH = 4 * (Hb & 7) + col;
-    const bool vL = hasL && cy0 + rL < ch && cx0 + cL < cw;
-    const bool vH = hasH && cy0 + rH < ch && cx0 + cH < cw;
-    const uint32_t vm = (vL ? 0x0000FFFFu : 0u) | (vH ? 0xFFFF0000u : 0u);
-    const int bL = (rL + 2) * kCS + kCC0 + cL, bH = (rH + 2) * kCS + kCC0 + cH;
-    const int dL = sm.dir[L], dH = sm.dir[Hb];
-    const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
-    const uint32_t sv = ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm;
-    uint32_t tp[12];
+  chroma420_tasks<true, B12>(
+      sm, J, 0, n, y0, x0, wave, lane,
+      [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t sv) {
+        s16x2 ev[64];
+        chroma_pairs<false, B12>(t, c, D, StoreErr{ev});
+        Moments<true, B12> m;
+        task_moments<true, B12>(ev, sv, lane, m);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int oL = sm.coff[dL][k], oH = sm.coff[dH][k];
-      const int slot = (k >> 1) * 4 + (k & 1) * 2;
-      tp[slot] = ((uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16)) & vm;
-      tp[slot + 1] = ((uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16)) & vm;
-    }
-    s16x2 ev[64];
-    {
-      Taps t;
-      prepare(t, xv, sv, tp);
-      chroma_pairs<false>(t, c, D, StoreErr{ev});
-    }
-    Moments<true> m;
-    task_moments<true>(ev, sv, lane, m);
-    const int P = 1 + p;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (hasL)
-        accw[j] += eq14((int)sm.ustat[0][P][L], sm.ustat[1][P][L], sm.ustat[2][P][L],
-                        m.sd[j] & 0xFFFF, m.d2lo[j], m.e2lo[j], C1, C2);
-      if (hasH)
-        accw[j] += eq14((int)sm.ustat[0][P][Hb], sm.ustat[1][P][Hb], sm.ustat[2][P][Hb],
-                        m.sd[j] >> 16, m.d2hi[j], m.e2hi[j], C1, C2);
-    }
-  }
+        for (int j = 0; j < 4; ++j) {
+          if (hasL)
+            accw[j] += eq14((int)sm.w.ustat[0][P][L], sm.w.ustat[1][P][L], sm.w.ustat[2][P][L],
+                            m.sdlo[j], m.d2lo[j], m.e2lo[j], C1, C2);
+          if (hasH)
+            accw[j] += eq14((int)sm.w.ustat[0][P][Hb], sm.w.ustat[1][P][Hb], sm.w.ustat[2][P][Hb],
+                            m.sdhi[j], m.d2hi[j], m.e2hi[j], C1, C2);
+        }
+      });
   // the four rows hold the same pairs for different units
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -921,21 +1040,23 @@ __device__ __forceinline__ void chroma_tasks_w(Smem &sm, const JobDesc &J, int n
   }
   if (lane < 16)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) sm.wred[1][wave][4 * lane + j] = accw[j];
+    for (int j = 0; j < 4; ++j) sm.w.wred[P][wave & 1][4 * lane + j] = accw[j];
 }
 
-__device__ __forceinline__ void search_item_weighted(Smem &sm, const JobDesc &J, int fby, int fbx,
-                                                     int tid) {
+template <bool B12>
+__device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobDesc &J, int fby,
+                                                     int fbx, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   const int y0 = fby * 64, x0 = fbx * 64;
-  const bool chroma = J.nplanes == 3;
+  const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
+  const bool c444 = J.nplanes == 3 && J.layout == kLayout444;
   const int c = J.bitdepth - 8;
   // C1 = 6.25 and C2 = 312.5 at 8 bits, scaled like variances and their
   // products (exact powers of two)
   const double C1 = 6.25 * (double)(1 << (2 * c)), C2 = 312.5 * (double)(1 << (4 * c));
 
-  stage_item(sm, J, fby, fbx, tid, true);
-  for (int i = tid; i < 6 * 3 * 64; i += 256) (&sm.ustat[0][0][0])[i] = 0;
+  stage_item<true>(sm, J, fby, fbx, tid, true);
+  for (int i = tid; i < 6 * 3 * 64; i += 256) (&sm.w.ustat[0][0][0])[i] = 0;
   __syncthreads();
   if (wave == 0)
     direction_search<false>(sm, J, fby, fbx, lane);
@@ -943,47 +1064,51 @@ __device__ __forceinline__ void search_item_weighted(Smem &sm, const JobDesc &J,
     unit_stats(sm, J, fby, fbx, tid - 64, 192);
   __syncthreads();
   const int n = sm.n;
+  const int planes = search_planes(J);
 
   // skipped units are not filtered under any pair: wave P sums plane P's
   if (wave < 3) {
     const int P = wave, u = lane;
     double w = 0.0;
-    if ((P == 0 || chroma) && (sm.flag[u] & 2)) {
-      const uint32_t cnt = sm.ustat[0][P][u];
-      const uint32_t ss = sm.ustat[1][P][u], ss2 = sm.ustat[2][P][u];
-      const uint32_t sx = sm.ustat[3][P][u], sx2 = sm.ustat[4][P][u], sxs = sm.ustat[5][P][u];
+    if (P < planes && (sm.flag[u] & 2)) {
+      const uint32_t cnt = sm.w.ustat[0][P][u];
+      const uint32_t ss = sm.w.ustat[1][P][u], ss2 = sm.w.ustat[2][P][u];
+      const uint32_t sx = sm.w.ustat[3][P][u], sx2 = sm.w.ustat[4][P][u];
+      const uint32_t sxs = sm.w.ustat[5][P][u];
       if (cnt) w = eq14((int)cnt, ss, ss2, sx, sx2, sx2 + ss2 - 2 * sxs, C1, C2);
     }
     w = wave_sum_f64(w);
     if (lane == 0) sm.skipw[P] = w;
   }
 
-  luma_tasks_w(sm, J, n, y0, x0, wave, lane, C1, C2);
-  if (chroma) chroma_tasks_w(sm, J, n, y0, x0, wave, lane, C1, C2);
+  plane_tasks_w<B12, 0>(sm, J, n, y0, x0, wave, lane, C1, C2);
+  if (c420) chroma420_w<B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
+  if (c444) {
+    plane_tasks_w<B12, 1>(sm, J, n, y0, x0, wave, lane, C1, C2);
+    plane_tasks_w<B12, 2>(sm, J, n, y0, x0, wave, lane, C1, C2);
+  }
   __syncthreads();
 
+  const int P = tid >> 6, k = lane;
+  if (P >= planes) return;
+  const int nw = plane_waves(J, P);
+  double total = sm.skipw[P];
+  for (int w = 0; w < nw; ++w) total += sm.w.wred[P][w][k];
   const int64_t fbi = (int64_t)fby * J.fbc + fbx;
   const int64_t nfb = (int64_t)J.fbr * J.fbc;
-  double *out = reinterpret_cast<double *>(J.sse);
-  const int k = tid & 63;
-  if (tid < 64) {
-    out[fbi * 64 + k] = sm.wred[0][0][k] + sm.wred[0][1][k] + sm.wred[0][2][k] +
-                        sm.wred[0][3][k] + sm.skipw[0];
-  } else if (chroma && tid < 192) {
-    const int p = (tid >> 6) - 1;
-    out[((1 + p) * nfb + fbi) * 64 + k] =
-        sm.wred[1][2 * p][k] + sm.wred[1][2 * p + 1][k] + sm.skipw[1 + p];
-  }
+  reinterpret_cast<double *>(J.sse)[(P * nfb + fbi) * 64 + k] = total;
 }
 
 // Filter mode: the block's own preset (Section 3.2 ranges, Section 4 skip
 // rules; bad values are masked / clamped so the kernel stays defined), one
-// pixel per lane.
-__device__ __forceinline__ void filter_item(Smem &sm, const JobDesc &J, int fby, int fbx, int tid) {
+// pixel per lane.  4:2:2 chroma is copied.
+template <bool X>
+__device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
+                                            int tid) {
   const int wave = tid >> 6, lane = tid & 63;
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int c = J.bitdepth - 8, D = J.damping;
-  stage_item(sm, J, fby, fbx, tid, false);
+  stage_item<X>(sm, J, fby, fbx, tid, false);
   __syncthreads();
   if (wave == 0) direction_search<false>(sm, J, fby, fbx, lane);
   __syncthreads();
@@ -1007,10 +1132,37 @@ __device__ __forceinline__ void filter_item(Smem &sm, const JobDesc &J, int fby,
     J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] = (uint16_t)y;
   }
   if (J.nplanes != 3) return;
+  if (J.layout == kLayout422) {
+    // Section 4: chroma subsampled horizontally only is never filtered
+    const int cw = (W + 1) >> 1, cx0 = x0 >> 1;
+    for (int e = tid; e < 2 * 64 * 32; e += 256) {
+      const int p = e >> 11, r = (e >> 5) & 63, col = e & 31;
+      if (y0 + r >= H || cx0 + col >= cw) continue;
+      J.out[1 + p][(int64_t)(y0 + r) * J.ostride[1 + p] + cx0 + col] =
+          J.rec[1 + p][(int64_t)(y0 + r) * J.rstride[1 + p] + cx0 + col];
+    }
+    return;
+  }
   const int Dc = pc.pri ? max(D - 1, floor_log2(pc.pri)) : D - 1;
   const int ps = pc.pri << c, pshift = pc.pri ? Dc - floor_log2(pc.pri) : 0;
   const int w1 = (pc.pri & 1) ? 3 : 4, w2 = (pc.pri & 1) ? 3 : 2;
   const int ss = pc.sec << c, sshift = pc.sec ? Dc - floor_log2(pc.sec) : 0;
+  if constexpr (X) {
+    if (J.layout == kLayout444) {
+      for (int e = tid; e < 2 * 64 * 64; e += 256) {
+        const int p = e >> 12, r = (e >> 6) & 63, col = e & 63;
+        if (y0 + r >= H || x0 + col >= W) continue;
+        const int b = (r >> 3) * 8 + (col >> 3);
+        const int base = (r + 2) * kLS + kLC0 + col;
+        const bool filt = !fb_skipped && (!(sm.flag[b] & 2) || pc.skipcond);
+        const int y = filt ? filter_pixel(sm.rc[p], base, kLS, sm.dir[b], ps, pshift, w1, w2, ss,
+                                          sshift)
+                           : (int)sm.rc[p][base];
+        J.out[1 + p][(int64_t)(y0 + r) * J.ostride[1 + p] + x0 + col] = (uint16_t)y;
+      }
+      return;
+    }
+  }
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
   for (int e = tid; e < 2 * 32 * 32; e += 256) {
     const int p = e >> 10, r = (e >> 5) & 31, col = e & 31;
@@ -1025,42 +1177,56 @@ __device__ __forceinline__ void filter_item(Smem &sm, const JobDesc &J, int fby,
   }
 }
 
-// W: the kernel also carries the weighted search (it needs more registers,
-// so it is compiled into kernels of its own).
-template <bool W>
-__device__ __forceinline__ void run_item(Smem &sm, const JobDesc &J, int item, int tid) {
+// X: the extended kernels (12-bit samples, 4:4:4, the weighted search).
+template <bool X>
+__device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int item, int tid) {
   const int fby = item / J.fbc, fbx = item - fby * J.fbc;
+  if constexpr (X) {
+    if (J.bitdepth == 12) {
+      if (J.mode == kModeSearch)
+        search_item<false, true>(sm, J, fby, fbx, tid);
+      else if (J.mode == kModeSearchFull)
+        search_item<true, true>(sm, J, fby, fbx, tid);
+      else if (J.mode == kModeSearchWeighted)
+        search_item_weighted<true>(sm, J, fby, fbx, tid);
+      else
+        filter_item<X>(sm, J, fby, fbx, tid);
+      return;
+    }
+    if (J.mode == kModeSearchWeighted) {
+      search_item_weighted<false>(sm, J, fby, fbx, tid);
+      return;
+    }
+  }
   if (J.mode == kModeSearch)
-    search_item<false>(sm, J, fby, fbx, tid);
+    search_item<false, false>(sm, J, fby, fbx, tid);
   else if (J.mode == kModeSearchFull)
-    search_item<true>(sm, J, fby, fbx, tid);
-  else if (W && J.mode == kModeSearchWeighted)
-    search_item_weighted(sm, J, fby, fbx, tid);
+    search_item<true, false>(sm, J, fby, fbx, tid);
   else
-    filter_item(sm, J, fby, fbx, tid);
+    filter_item<X>(sm, J, fby, fbx, tid);
 }
 
 }  // namespace
 
 // One frame; the descriptor is a kernel argument.
 __global__ __launch_bounds__(256, 3) void k_fused_one(const JobDesc J) {
-  __shared__ __align__(16) Smem sm;
+  __shared__ __align__(16) SmemT<false> sm;
   run_item<false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
-// One frame of the weighted search (2 waves per SIMD: 256 VGPRs).
-__global__ __launch_bounds__(256, 2) void k_fused_one_w(const JobDesc J) {
-  __shared__ __align__(16) Smem sm;
+// One frame on the extended kernel (2 waves per SIMD: 256 VGPRs).
+__global__ __launch_bounds__(256, 2) void k_fused_one_x(const JobDesc J) {
+  __shared__ __align__(16) SmemT<true> sm;
   run_item<true>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 // A batch: descriptors in device memory, items numbered across jobs.
 // OCC bounds the waves per SIMD (and so the VGPR budget); XCD selects the
 // XCD-contiguous order of filter blocks.
-template <int OCC, bool XCD, bool W>
+template <int OCC, bool XCD, bool X>
 __global__ __launch_bounds__(256, OCC) void k_fused_batch(const JobDesc *__restrict__ jobs,
                                                           int njobs) {
-  __shared__ __align__(16) Smem sm;
+  __shared__ __align__(16) SmemT<X> sm;
   const int item = XCD ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   int lo = 0, hi = njobs - 1;  // last job with item0 <= item
   while (lo < hi) {
@@ -1071,7 +1237,7 @@ __global__ __launch_bounds__(256, OCC) void k_fused_batch(const JobDesc *__restr
       hi = mid - 1;
   }
   const JobDesc &J = jobs[lo];
-  run_item<W>(sm, J, item - J.item0, threadIdx.x);
+  run_item<X>(sm, J, item - J.item0, threadIdx.x);
 }
 
 void fill_job_geometry(JobDesc &j) {
@@ -1081,19 +1247,24 @@ void fill_job_geometry(JobDesc &j) {
   j.fbr = (j.height + 63) / 64;
 }
 
+bool job_needs_extended(const JobDesc &j) {
+  return j.mode == kModeSearchWeighted || j.bitdepth == 12 ||
+         (j.nplanes == 3 && j.layout == kLayout444);
+}
+
 hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
   const int grid = job.fbc * job.fbr;
-  if (job.mode == kModeSearchWeighted)
-    hipLaunchKernelGGL(k_fused_one_w, dim3(grid), dim3(256), 0, s, job);
+  if (job_needs_extended(job))
+    hipLaunchKernelGGL(k_fused_one_x, dim3(grid), dim3(256), 0, s, job);
   else
     hipLaunchKernelGGL(k_fused_one, dim3(grid), dim3(256), 0, s, job);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              bool weighted, hipStream_t s) {
+                              bool extended, hipStream_t s) {
   const dim3 g(nitems), b(256);
-  if (weighted) {  // 2 waves per SIMD; the variant picks the block order
+  if (extended) {  // 2 waves per SIMD; the variant picks the block order
     if (variant == 0 || variant == 1)
       hipLaunchKernelGGL((k_fused_batch<2, true, true>), g, b, 0, s, jobs, njobs);
     else

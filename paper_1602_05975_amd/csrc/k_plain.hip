@@ -46,7 +46,7 @@ struct FilterArgs {
   int64_t istride[3];
   uint16_t *out[3];
   int64_t ostride[3];
-  int width, height, nplanes;
+  int width, height, nplanes, layout;
   int bcols, fbc;
   int damping;
   const uint8_t *dir;
@@ -67,7 +67,7 @@ constexpr int kCC0 = 8;
 template <int BD>
 __global__ __launch_bounds__(256) void k_filter(const FilterArgs a) {
   __shared__ __align__(16) uint16_t ry[68 * kLS];
-  __shared__ __align__(16) uint16_t rc[36 * kCS];
+  __shared__ __align__(16) uint16_t rc[68 * kLS];  // one chroma plane (4:4:4 size)
   // per 8x8 block: dir, primary strength, primary shift, w1 | w2 << 8,
   // skipped, secondary shift (luma)
   __shared__ int s_par[64][6];
@@ -123,25 +123,44 @@ __global__ __launch_bounds__(256) void k_filter(const FilterArgs a) {
     }
   }
   if (a.nplanes == 1) return;
-  // Chroma (4:2:0): unadjusted strength, damping max(D - 1, floor(log2 S)).
+  if (a.layout == kLayout422) {
+    // Section 4: chroma subsampled horizontally only is never filtered
+    const int cw = (W + 1) >> 1, cx0 = x0 >> 1;
+    for (int p = 1; p < 3; ++p)
+      for (int e = tid; e < 64 * 32; e += 256) {
+        const int r = e >> 5, col = e & 31;
+        if (y0 + r >= H || cx0 + col >= cw) continue;
+        a.out[p][(int64_t)(y0 + r) * a.ostride[p] + cx0 + col] =
+            a.in[p][(int64_t)(y0 + r) * a.istride[p] + cx0 + col];
+      }
+    return;
+  }
+  // Chroma: unadjusted strength, damping max(D - 1, floor(log2 S)); 4:2:0
+  // 4x4 blocks in a 32x32 filter block, 4:4:4 8x8 blocks in 64x64.
   const int Dc = pc.pri ? max(D - 1, floor_log2(pc.pri)) : D - 1;
   const int ps = pc.pri << c, pshift = pc.pri ? Dc - floor_log2(pc.pri) : 0;
   const int w1 = (pc.pri & 1) ? 3 : 4, w2 = (pc.pri & 1) ? 3 : 2;
   const int ss = pc.sec << c, sshift = pc.sec ? Dc - floor_log2(pc.sec) : 0;
-  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  const bool c444 = a.layout == kLayout444;
+  const int sh = c444 ? 0 : 1;  // subsampling shift
+  const int cw = (W + sh) >> sh, ch = (H + sh) >> sh, cy0 = y0 >> sh, cx0 = x0 >> sh;
+  const int side = 64 >> sh, bsh = 3 - sh;  // filter block side, log2 block side
+  const int ts = c444 ? kLS : kCS, t0 = c444 ? kLC0 : kCC0;
   for (int p = 1; p < 3; ++p) {
     __syncthreads();
-    stage_recon<32, 32, kCS, kCC0, 256>(rc, a.in[p], a.istride[p], cw, ch, cy0, cx0, tid);
+    if (c444)
+      stage_recon<64, 64, kLS, kLC0, 256>(rc, a.in[p], a.istride[p], cw, ch, cy0, cx0, tid);
+    else
+      stage_recon<32, 32, kCS, kCC0, 256>(rc, a.in[p], a.istride[p], cw, ch, cy0, cx0, tid);
     __syncthreads();
-    for (int e = tid; e < 32 * 32; e += 256) {
-      const int r = e >> 5, col = e & 31;
+    for (int e = tid; e < side * side; e += 256) {
+      const int r = e / side, col = e - r * side;
       if (cy0 + r >= ch || cx0 + col >= cw) continue;
-      const int b = (r >> 2) * 8 + (col >> 2);
-      const int base = (r + 2) * kCS + kCC0 + col;
+      const int b = (r >> bsh) * 8 + (col >> bsh);
+      const int base = (r + 2) * ts + t0 + col;
       const int y = (fb_skipped || (s_par[b][4] && !pc.skipcond))
                         ? (int)rc[base]
-                        : filter_pixel(rc, base, kCS, s_par[b][0], ps, pshift, w1, w2, ss,
-                                       sshift);
+                        : filter_pixel(rc, base, ts, s_par[b][0], ps, pshift, w1, w2, ss, sshift);
       a.out[p][(int64_t)(cy0 + r) * a.ostride[p] + cx0 + col] = (uint16_t)y;
     }
   }
@@ -154,8 +173,11 @@ hipError_t launch_find_dir(const FrameDesc &f, uint8_t *dir, int32_t *var, hipSt
   if (f.bitdepth == 8)
     hipLaunchKernelGGL(k_find_dir<8>, dim3(grid), dim3(256), 0, s, f.plane[0], f.stride[0],
                        f.width, f.height, bcols, nb, dir, var);
-  else
+  else if (f.bitdepth == 10)
     hipLaunchKernelGGL(k_find_dir<10>, dim3(grid), dim3(256), 0, s, f.plane[0], f.stride[0],
+                       f.width, f.height, bcols, nb, dir, var);
+  else
+    hipLaunchKernelGGL(k_find_dir<12>, dim3(grid), dim3(256), 0, s, f.plane[0], f.stride[0],
                        f.width, f.height, bcols, nb, dir, var);
   return hipGetLastError();
 }
@@ -173,6 +195,7 @@ hipError_t launch_filter(const FrameDesc &in, uint16_t *const out[3], const int6
   a.width = in.width;
   a.height = in.height;
   a.nplanes = in.nplanes;
+  a.layout = in.layout;
   a.bcols = (in.width + 7) / 8;
   a.fbc = (in.width + 63) / 64;
   a.damping = damping;
@@ -183,8 +206,10 @@ hipError_t launch_filter(const FrameDesc &in, uint16_t *const out[3], const int6
   const int grid = a.fbc * ((in.height + 63) / 64);
   if (in.bitdepth == 8)
     hipLaunchKernelGGL(k_filter<8>, dim3(grid), dim3(256), 0, s, a);
-  else
+  else if (in.bitdepth == 10)
     hipLaunchKernelGGL(k_filter<10>, dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_filter<12>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

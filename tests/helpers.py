@@ -42,5 +42,5 @@ def oracle_search(oracle, fr, skip=True, damping=None, fbs=None, full=False):
     if fbs is None:
         fbs = [(by, bx) for by in range(fbr) for bx in range(fbc)]
     t = oracle.search_fbs(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, d, v, sk, D, fbs,
-                          threads=ORACLE_THREADS, full=full)
+                          threads=ORACLE_THREADS, full=full, layout=fr.layout)
     return t, d, v, fbs

@@ -41,11 +41,11 @@ def _frame(w=64, h=64, bd=10, layout=1, stride=None, ptr=0x10000):
     from paper_1602_05975_amd import cdef
     f = cdef.CdefFrame()
     f.width, f.height, f.bitdepth, f.layout = w, h, bd, layout
-    np_ = 3 if layout == 1 else 1
+    np_ = 1 if layout == 0 else 3
     for p in range(np_):
-        pw = w if p == 0 else (w + 1) // 2
+        pw = w if p == 0 or layout == 3 else (w + 1) // 2
         f.plane[p] = ptr + p * 0x100000
-        f.stride[p] = pw if stride is None else stride
+        f.stride[p] = pw if stride is None else stride if isinstance(stride, int) else stride[p]
     return f
 
 
@@ -55,9 +55,14 @@ def test_find_dir_argument_checks(lib):
     assert lib.cdef_find_dir(C.byref(_frame()), None, P, None) == -1
     assert lib.cdef_find_dir(C.byref(_frame(stride=3)), P, P, None) == -1
     assert lib.cdef_find_dir(C.byref(_frame(w=0)), P, P, None) == -1
-    assert lib.cdef_find_dir(C.byref(_frame(bd=12)), P, P, None) == -2
     assert lib.cdef_find_dir(C.byref(_frame(bd=9)), P, P, None) == -1
-    assert lib.cdef_find_dir(C.byref(_frame(layout=2)), P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(bd=16)), P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(layout=4)), P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(layout=-1)), P, P, None) == -1
+    assert lib.cdef_find_dir(C.byref(_frame(w=70000)), P, P, None) == -2
+    # 4:2:2 and 4:4:4 chroma planes: the stride must cover their width
+    f = _frame(w=64, layout=3, stride=(64, 32, 64))
+    assert lib.cdef_find_dir(C.byref(f), P, P, None) == -1
     f = _frame()
     f.plane[1] = None
     assert lib.cdef_find_dir(C.byref(f), P, P, None) == -1

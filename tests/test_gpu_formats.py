@@ -1,0 +1,146 @@
+"""12-bit samples, 4:2:2 and 4:4:4 on the GPU (Sections 3.2 and 4): the
+direction search, the filter (plain and fused), the 64- and 128-combination
+searches and the weighted search, against the oracle, and batches that mix
+formats against the per-frame entry points."""
+import numpy as np
+import pytest
+
+from helpers import ORACLE_THREADS, gpu_frame, gpu_search, oracle_search, to_np_u16
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05975_amd import cdef
+    cdef.load()
+
+
+def _synth():
+    from paper_1602_05975_amd import synth
+    return synth
+
+
+def _frame(w, h, bd, layout, seed, D=3, skip_prob=0.3):
+    s = _synth()
+    fr = s.make_frame(w, h, bd, layout, seed, skip_prob=skip_prob, damping=D)
+    if fr.fb_cols > 1:
+        fr.skip[0:8, 8:16] = 1
+    return fr
+
+
+CASES = [  # (w, h, bitdepth, layout, damping)
+    (200, 136, 12, 1, 3), (131, 67, 12, 0, 5), (136, 72, 12, 1, 6),
+    (200, 136, 10, 2, 4), (67, 33, 8, 2, 3), (136, 72, 12, 2, 5),
+    (200, 136, 10, 3, 3), (131, 67, 8, 3, 5), (136, 72, 12, 3, 6), (7, 5, 10, 3, 4)]
+IDS = [f"{w}x{h}-{bd}bit-L{lay}-D{D}" for (w, h, bd, lay, D) in CASES]
+
+
+@pytest.mark.parametrize("w,h,bd,layout,D", CASES, ids=IDS)
+def test_filter_formats(oracle, w, h, bd, layout, D):
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    fr = _frame(w, h, bd, layout, 81000 + w + bd + layout, D)
+    st = s.random_presets(fr, 82000 + h)
+    print(f"filter {w}x{h} {bd}-bit layout {layout} D={D}", flush=True)
+    f = gpu_frame(fr.recon, fr)
+    d, v = cdef.find_dir(f)
+    sk = torch.from_numpy(fr.skip).cuda()
+    stg = torch.from_numpy(st).cuda()
+    plain = cdef.filter_frame(f, d, v, sk, D, stg)
+    b = cdef.Batch()
+    fused = [torch.full_like(p, -1) for p in f.planes[:fr.nplanes]]
+    b.add_filter(f, fused, sk, D, stg)
+    b.prepare()
+    b.launch()
+    torch.cuda.synchronize()
+    od, ov = oracle.find_dir(fr.recon[0], bd)
+    assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
+    ref = oracle.filter_frame(fr.recon, w, h, bd, od, ov, fr.skip, D, st, layout=layout)
+    for p in range(fr.nplanes):
+        for name, got in (("plain", to_np_u16(plain[p])), ("fused", to_np_u16(fused[p]))):
+            bad = np.argwhere(got != ref[p])
+            assert bad.size == 0, (name, p, bad[:5])
+
+
+@pytest.mark.parametrize("w,h,bd,layout,D", CASES, ids=IDS)
+def test_searches_formats(oracle, w, h, bd, layout, D):
+    fr = _frame(w, h, bd, layout, 83000 + w + bd + layout, D)
+    print(f"search {w}x{h} {bd}-bit layout {layout} D={D}", flush=True)
+    for full in (False, True):
+        sse, d, v = gpu_search(fr, full=full)
+        ref, od, ov, fbs = oracle_search(oracle, fr, full=full)
+        assert (d == od).all() and (v == ov).all()
+        assert sse.shape[0] == fr.search_planes
+        for k, (by, bx) in enumerate(fbs):
+            assert (sse[:, by, bx] == ref[k]).all(), (full, by, bx)
+
+
+@pytest.mark.parametrize("w,h,bd,layout,D", CASES, ids=IDS)
+def test_weighted_formats(oracle, w, h, bd, layout, D):
+    import torch
+    from paper_1602_05975_amd import cdef
+    fr = _frame(w, h, bd, layout, 84000 + w + bd + layout, D)
+    print(f"weighted {w}x{h} {bd}-bit layout {layout} D={D}", flush=True)
+    rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+    sk = torch.from_numpy(fr.skip).cuda()
+    dist = cdef.search_strengths(rec, src, sk, D, weighted=True)
+    torch.cuda.synchronize()
+    dist = dist.cpu().numpy()
+    od, ov = oracle.find_dir(fr.recon[0], bd)
+    fbs = [(by, bx) for by in range(fr.fb_rows) for bx in range(fr.fb_cols)]
+    ref = oracle.search_fbs_weighted(fr.recon, fr.src, w, h, bd, od, ov, fr.skip, D, fbs,
+                                     threads=ORACLE_THREADS, layout=layout)
+    for k, (by, bx) in enumerate(fbs):
+        np.testing.assert_allclose(dist[:, by, bx], ref[k], rtol=1e-10, atol=1e-9)
+
+
+def test_mixed_format_batch_equals_per_frame():
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    specs = [(200, 136, 10, 1, "search"), (136, 72, 12, 1, "search"),
+             (131, 67, 8, 3, "full"), (200, 136, 10, 2, "search"),
+             (136, 72, 12, 3, "weighted"), (64, 64, 10, 3, "filter"), (67, 33, 12, 2, "filter")]
+    b = cdef.Batch()
+    jobs = []
+    for i, (w, h, bd, layout, mode) in enumerate(specs):
+        fr = _frame(w, h, bd, layout, 85000 + i, D=3 + i % 4)
+        rec = gpu_frame(fr.recon, fr)
+        skip = torch.from_numpy(fr.skip).cuda()
+        if mode == "filter":
+            st = torch.from_numpy(s.random_presets(fr, 86000 + i)).cuda()
+            o = [torch.full_like(p, -1) for p in rec.planes[:fr.nplanes]]
+            b.add_filter(rec, o, skip, fr.damping, st)
+            jobs.append((fr, mode, o, (rec, st, skip)))
+        else:
+            src = gpu_frame(fr.src, fr)
+            full, weighted = mode == "full", mode == "weighted"
+            shape = (fr.search_planes, fr.fb_rows, fr.fb_cols) + ((2, 16, 4) if full else (16, 4))
+            out = torch.full(shape, -1, dtype=torch.float64 if weighted else torch.int64,
+                             device="cuda")
+            b.add_search(rec, src, skip, fr.damping, out, full=full, weighted=weighted)
+            jobs.append((fr, mode, out, (rec, src, skip)))
+    b.prepare()
+    assert b.plan.flags & 1
+    print(f"mixed-format batch of {len(jobs)} jobs", flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for fr, mode, out, inp in jobs:
+        if mode == "filter":
+            rec, st, skip = inp
+            d, v = cdef.find_dir(rec)
+            want = cdef.filter_frame(rec, d, v, skip, fr.damping, st)
+            torch.cuda.synchronize()
+            for p in range(fr.nplanes):
+                assert torch.equal(out[p], want[p]), (mode, p)
+        else:
+            rec, src, skip = inp
+            want = cdef.search_strengths(rec, src, skip, fr.damping, full=mode == "full",
+                                         weighted=mode == "weighted")
+            torch.cuda.synchronize()
+            assert torch.equal(out, want), mode
