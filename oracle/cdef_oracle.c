@@ -75,6 +75,11 @@
  *  R21 4:4:4: each 8x8 chroma block takes the direction and skip flag of the
  *      co-located 8x8 luma block; chroma filter blocks are 64x64; strengths
  *      and damping follow the chroma rules of R13 as at 4:2:0.
+ *  R22 Subset search (Section 5): a subset of the presets is the product of
+ *      a set of S^(p) values, a set of S^(s) values and a set of skip
+ *      condition bits; the presets outside it are not evaluated (their table
+ *      entries hold the all-ones value) and the preset selection never
+ *      chooses them.
  */
 #include "cdef_oracle.h"
 
@@ -324,13 +329,21 @@ void cdef_oracle_filter_frame(const cdef_oracle_frame *in, uint16_t *const out[3
 
 static const int SEC_STRENGTHS[4] = {0, 1, 2, 4};
 
+/* R22: cand = S^(p) mask | S^(s) index mask << 16 | skip condition bit
+ * mask << 20, 0 for every preset. */
+static int candidate_in(uint32_t cand, int pri, int si, int k) {
+  if (cand == 0) return 1;
+  return ((cand >> pri) & 1) && ((cand >> (16 + si)) & 1) && ((cand >> (20 + k)) & 1);
+}
+
 /* Section 5: every candidate filters the whole filter block, as the filter
  * would with that preset (R18), and sums squared errors against the source.
  * Candidate (skip condition bit k, S^(p), S^(s) index) is at
  * sse[((p * nskip + k) * 16 + S^(p)) * 4 + index]. */
-void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+void cdef_oracle_search_fb3(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
                             const uint8_t *dir, const int32_t *var, const uint8_t *skip,
-                            int damping, int nskip, int fby, int fbx, uint64_t *sse) {
+                            int damping, int nskip, uint32_t cand, int fby, int fbx,
+                            uint64_t *sse) {
   int bcols = (recon->width + 7) / 8;
   int all_skipped = fb_skipped(recon, skip, fby, fbx);
   for (int p = 0; p < cdef_oracle_search_planes(recon); p++) {
@@ -342,6 +355,10 @@ void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_fr
     for (int k = 0; k < nskip; k++) {
       for (int pri_sig = 0; pri_sig < 16; pri_sig++) {
         for (int si = 0; si < 4; si++) {
+          if (!candidate_in(cand, pri_sig, si, k)) { /* R22 */
+            sse[((p * nskip + k) * 16 + pri_sig) * 4 + si] = UINT64_MAX;
+            continue;
+          }
           uint8_t st[4] = {(uint8_t)pri_sig, (uint8_t)(SEC_STRENGTHS[si] | (k << 7)),
                            (uint8_t)pri_sig, (uint8_t)(SEC_STRENGTHS[si] | (k << 7))};
           int pri, sec, skipcond;
@@ -441,6 +458,12 @@ void cdef_oracle_search_fb_weighted(const cdef_oracle_frame *recon,
   }
 }
 
+void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+                            const uint8_t *dir, const int32_t *var, const uint8_t *skip,
+                            int damping, int nskip, int fby, int fbx, uint64_t *sse) {
+  cdef_oracle_search_fb3(recon, src, dir, var, skip, damping, nskip, 0, fby, fbx, sse);
+}
+
 void cdef_oracle_search_fb(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
                            const uint8_t *dir, const int32_t *var, const uint8_t *skip,
                            int damping, int fby, int fbx, uint64_t *sse) {
@@ -498,6 +521,11 @@ static uint64_t set_distortion(const uint64_t *sse, int nplanes, int nfb, int nc
   return total;
 }
 
+/* R22: candidates outside cand_mask (NULL: none) are never chosen. */
+static int allowed(const uint64_t *cand_mask, int p) {
+  return !cand_mask || ((cand_mask[p >> 6] >> (p & 63)) & 1);
+}
+
 static int in_set(const int *set, int n, int p, int except) {
   for (int i = 0; i < n; i++)
     if (i != except && set[i] == p) return 1;
@@ -505,7 +533,7 @@ static int in_set(const int *set, int n, int p, int except) {
 }
 
 void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
-                                double lambda, int refine_passes, int32_t *n_chosen, int32_t *sets_l,
+                                const uint64_t *cand_mask, double lambda, int refine_passes, int32_t *n_chosen, int32_t *sets_l,
                                 int32_t *sets_c, uint64_t *dist, double *cost, uint8_t *fb_l,
                                 uint8_t *fb_c) {
   static const int NS[4] = {1, 2, 4, 8};
@@ -516,7 +544,7 @@ void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, int n
       int best = -1;
       uint64_t bestd = UINT64_MAX;
       for (int p = 0; p < ncand; p++) {
-        if (in_set(greedy, step, p, -1)) continue;
+        if (in_set(greedy, step, p, -1) || !allowed(cand_mask, p)) continue;
         greedy[step] = p;
         uint64_t d = set_distortion(sse, nplanes, nfb, ncand, g, greedy, step + 1, -1, -1);
         if (best < 0 || d < bestd) {
@@ -536,7 +564,7 @@ void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, int n
           int bestp = set[i];
           uint64_t bestd = curd;
           for (int p = 0; p < ncand; p++) {
-            if (in_set(set, n, p, i)) continue;
+            if (in_set(set, n, p, i) || !allowed(cand_mask, p)) continue;
             uint64_t d = set_distortion(sse, nplanes, nfb, ncand, g, set, n, i, p);
             if (d < bestd) {
               bestd = d;

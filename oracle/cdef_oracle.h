@@ -104,6 +104,14 @@ void cdef_oracle_search_fb2(const cdef_oracle_frame *recon, const cdef_oracle_fr
                             const uint8_t *dir, const int32_t *var, const uint8_t *skip,
                             int damping, int nskip, int fby, int fbx, uint64_t *sse);
 
+/* The same restricted to a subset of the presets (R22): cand = S^(p) mask
+ * (bits 0-15) | S^(s) index mask << 16 | skip condition bit mask << 20, or
+ * 0 for all; entries outside the subset are UINT64_MAX. */
+void cdef_oracle_search_fb3(const cdef_oracle_frame *recon, const cdef_oracle_frame *src,
+                            const uint8_t *dir, const int32_t *var, const uint8_t *skip,
+                            int damping, int nskip, uint32_t cand, int fby, int fbx,
+                            uint64_t *sse);
+
 /* Section 5, Eq. (14): the contrast-weighted distortion of filter block
  * (fby, fbx) for the 64 pairs (skip condition bit off), summed over the
  * block's filtering units (8x8 luma, 4x4 chroma at 4:2:0); C1 = 6.25 * 4^(b-8),
@@ -131,9 +139,11 @@ void cdef_oracle_search(const cdef_oracle_frame *recon, const cdef_oracle_frame 
  * J(N) = lambda * B * log2(N) + D^l(N) + D^c(N) with B = nfb; the smallest N
  * of minimal J is chosen.  Outputs: n_chosen; sets_l/sets_c [4][8] (slot
  * entries >= N are -1); dist [2][4] (luma, chroma; N = 1, 2, 4, 8); cost[4];
- * per-block preset slots fb_l / fb_c (lowest slot on ties) for N*. */
+ * per-block preset slots fb_l / fb_c (lowest slot on ties) for N*.
+ * cand_mask: two words, bit p = candidate p may be chosen (NULL: all); at
+ * least 8 candidates must be allowed. */
 void cdef_oracle_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
-                                double lambda, int refine_passes, int32_t *n_chosen, int32_t *sets_l,
+                                const uint64_t *cand_mask, double lambda, int refine_passes, int32_t *n_chosen, int32_t *sets_l,
                                 int32_t *sets_c, uint64_t *dist, double *cost, uint8_t *fb_l,
                                 uint8_t *fb_c);
 

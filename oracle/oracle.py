@@ -69,12 +69,16 @@ def lib():
         L.cdef_oracle_search_fb2.argtypes = [C.POINTER(OracleFrame), C.POINTER(OracleFrame), P,
                                              P, P, C.c_int, C.c_int, C.c_int, C.c_int, P]
         L.cdef_oracle_search_fb2.restype = None
+        L.cdef_oracle_search_fb3.argtypes = [C.POINTER(OracleFrame), C.POINTER(OracleFrame), P,
+                                             P, P, C.c_int, C.c_int, C.c_uint32, C.c_int,
+                                             C.c_int, P]
+        L.cdef_oracle_search_fb3.restype = None
         L.cdef_oracle_search_fb_weighted.argtypes = [C.POINTER(OracleFrame),
                                                      C.POINTER(OracleFrame), P, P, P, C.c_int,
                                                      C.c_int, C.c_int, P]
         L.cdef_oracle_search_fb_weighted.restype = None
-        L.cdef_oracle_select_presets.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
-                                                 P, P, P, P, P, P, P]
+        L.cdef_oracle_select_presets.argtypes = [P, C.c_int, C.c_int, C.c_int, P, C.c_double,
+                                                 C.c_int, P, P, P, P, P, P, P]
         L.cdef_oracle_select_presets.restype = None
         _lib = L
     return _lib
@@ -177,9 +181,11 @@ def filter_frame(planes: Sequence[np.ndarray], width: int, height: int, bitdepth
 def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, height: int,
                bitdepth: int, dir: np.ndarray, var: np.ndarray, skip: Optional[np.ndarray],
                damping: int, fbs, threads: int = 1, full: bool = False,
-               layout: Optional[int] = None) -> np.ndarray:
+               layout: Optional[int] = None, cand: int = 0) -> np.ndarray:
     """SSE tables [len(fbs)][nplanes][16][4] for the listed (fby, fbx) blocks,
     or [len(fbs)][nplanes][2][16][4] with full=True (skip condition bit 0, 1).
+    cand: preset subset (S^(p) mask | S^(s) index mask << 16 | skip bit mask
+    << 20, 0 = all); entries outside it are 2^64 - 1.
 
     dir/var must come from find_dir (the oracle's own).  ctypes releases the
     GIL during the call, so a thread pool runs filter blocks in parallel."""
@@ -198,8 +204,8 @@ def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: in
 
     def one(k):
         by, bx = fbs[k]
-        L.cdef_oracle_search_fb2(C.byref(fr), C.byref(fs), dir.ctypes.data, var.ctypes.data,
-                                 _ptr(sk), damping, nskip, by, bx, out[k].ctypes.data)
+        L.cdef_oracle_search_fb3(C.byref(fr), C.byref(fs), dir.ctypes.data, var.ctypes.data,
+                                 _ptr(sk), damping, nskip, cand, by, bx, out[k].ctypes.data)
 
     if threads <= 1:
         for k in range(len(fbs)):
@@ -212,7 +218,7 @@ def search_fbs(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: in
 
 def search(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, height: int,
            bitdepth: int, skip: Optional[np.ndarray], damping: int, threads: int = 1,
-           full: bool = False, layout: Optional[int] = None):
+           full: bool = False, layout: Optional[int] = None, cand: int = 0):
     """Whole-frame search: (sse, dir, var); sse is [nplanes][fbr][fbc][16][4],
     or [nplanes][fbr][fbc][2][16][4] with full=True (nplanes: the planes the
     search covers)."""
@@ -220,7 +226,7 @@ def search(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], width: int, h
     fbr, fbc = (height + 63) // 64, (width + 63) // 64
     fbs = [(by, bx) for by in range(fbr) for bx in range(fbc)]
     t = search_fbs(recon, src, width, height, bitdepth, d, v, skip, damping, fbs, threads, full,
-                   layout)
+                   layout, cand)
     t = t.reshape((fbr, fbc, t.shape[1]) + t.shape[2:])
     sse = np.moveaxis(t, 2, 0)
     return np.ascontiguousarray(sse), d, v
@@ -257,9 +263,11 @@ def search_fbs_weighted(recon: Sequence[np.ndarray], src: Sequence[np.ndarray], 
     return out
 
 
-def select_presets(sse: np.ndarray, lam: float, refine_passes: int = 0) -> dict:
+def select_presets(sse: np.ndarray, lam: float, refine_passes: int = 0,
+                   cand_mask: Optional[Sequence[int]] = None) -> dict:
     """Eq. (15) preset selection on an SSE table [nplanes][fbr][fbc][16][4]
-    (64 candidates) or [nplanes][fbr][fbc][2][16][4] (128 candidates)."""
+    (64 candidates) or [nplanes][fbr][fbc][2][16][4] (128 candidates);
+    cand_mask: two 64-bit words of allowed candidates (None: all)."""
     sse = np.ascontiguousarray(sse, dtype=np.uint64)
     nplanes = sse.shape[0]
     nfb = int(np.prod(sse.shape[1:3]))
@@ -272,7 +280,8 @@ def select_presets(sse: np.ndarray, lam: float, refine_passes: int = 0) -> dict:
     cost = np.zeros(4, np.float64)
     fl = np.zeros(nfb, np.uint8)
     fc = np.zeros(nfb, np.uint8)
-    lib().cdef_oracle_select_presets(sse.ctypes.data, nplanes, nfb, ncand, float(lam),
+    cm = None if cand_mask is None else np.array(cand_mask, dtype=np.uint64)
+    lib().cdef_oracle_select_presets(sse.ctypes.data, nplanes, nfb, ncand, _ptr(cm), float(lam),
                                      refine_passes, n.ctypes.data, sl.ctypes.data, sc.ctypes.data,
                                      dist.ctypes.data, cost.ctypes.data, fl.ctypes.data,
                                      fc.ctypes.data)
