@@ -152,6 +152,29 @@ cdef_status cdef_search_strengths128(const cdef_frame *recon, const cdef_frame *
                                      const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
                                      uint8_t *dir, int32_t *var, void *stream);
 
+/* The low-complexity search of Section 5: only a subset of the presets,
+ * the product of a set of S^(p) values, a set of S^(s) values and a set of
+ * skip condition bits, encoded as
+ *   candidates = S^(p) mask (bit S, 16 bits)
+ *              | S^(s) index mask << 16 (bit i for S^(s) = 0, 1, 2, 4: 4 bits)
+ *              | skip condition bit mask << 20 (bit k for the bit k: 2 bits).
+ * The work shrinks with the subset (strengths outside it are not filtered).
+ *   sse: the 64-combination table of cdef_search_strengths when the skip
+ *        mask is 1, else the 128-combination table of
+ *        cdef_search_strengths128; entries of presets outside the subset hold
+ *        UINT64_MAX.  Pass the same subset (cdef_candidate_mask) to
+ *        cdef_select_presets.
+ * Errors: as cdef_search_strengths, plus CDEF_E_INVAL for an empty mask or
+ * bits above 21. */
+cdef_status cdef_search_subset(const cdef_frame *recon, const cdef_frame *src,
+                               const uint8_t *skip8x8, int32_t damping, uint32_t candidates,
+                               uint64_t *sse, uint8_t *dir, int32_t *var, void *stream);
+
+/* The candidate indices of a subset (bit p of mask[p / 64] for candidate p =
+ * 64 * skip bit + 4 * S^(p) + index of S^(s)), as cdef_select_presets takes
+ * them; 0 = every preset. */
+void cdef_candidate_mask(uint32_t candidates, uint64_t mask[2]);
+
 /* The strength search with the contrast-weighted distortion of Section 5,
  * Eq. (14), instead of the SSE: for every filter block, plane and pair,
  *   sum over filtering units of
@@ -196,6 +219,9 @@ typedef struct {
   int32_t damping;           /* luma D, 3..6 */
   int32_t mode;              /* CDEF_MODE_SEARCH, CDEF_MODE_SEARCH128, CDEF_MODE_SEARCH_WEIGHTED
                                 or CDEF_MODE_FILTER */
+  uint32_t candidates;       /* CDEF_MODE_SEARCH / SEARCH128: preset subset as for
+                                cdef_search_subset, 0 = every preset; otherwise 0 */
+  int32_t reserved;          /* 0 */
 } cdef_job;
 
 /* What cdef_batch_prepare leaves for cdef_batch_launch (host memory, owned by
@@ -280,6 +306,8 @@ size_t cdef_select_presets_workspace_bytes(void);
 /* sse:       device, uint64 [nplanes][fb_rows][fb_cols][ncand] as written by
  *            cdef_search_strengths (ncand = 64) or cdef_search_strengths128
  *            (ncand = 128).
+ * cand_mask: host, two words, bit p = candidate p may be chosen (NULL: all);
+ *            at least 8 of the ncand candidates must be allowed.
  * lambda:    rate multiplier, finite and >= 0.  refine_passes: 0..16.
  * result:    device pointer, written by the kernels.  result->n == 0 reports
  *            that the selection could not complete (its workgroups could not
@@ -290,13 +318,13 @@ size_t cdef_select_presets_workspace_bytes(void);
  *            256-byte aligned, owned by the caller; it must not be shared by
  *            calls that may run at the same time.
  * Errors: CDEF_E_INVAL for null pointers, a short or misaligned workspace,
- * nplanes not 1 or 3, ncand not 64 or 128, sizes < 1, a bad lambda or
- * refine_passes;
+ * nplanes not 1 or 3, ncand not 64 or 128, fewer than 8 allowed candidates,
+ * sizes < 1, a bad lambda or refine_passes;
  * CDEF_E_UNSUPPORTED for more than 2^24 filter blocks.  Three kernel launches
  * on `stream`, no allocation, no host synchronization. */
 cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
-                                int32_t fb_cols, int32_t ncand, double lambda,
-                                int32_t refine_passes,
+                                int32_t fb_cols, int32_t ncand, const uint64_t *cand_mask,
+                                double lambda, int32_t refine_passes,
                                 cdef_preset_result *result, uint8_t *fb_luma,
                                 uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
                                 void *stream);

@@ -31,6 +31,8 @@ EXPORTS = (
     "cdef_filter_frame",
     "cdef_search_strengths",
     "cdef_search_strengths128",
+    "cdef_search_subset",
+    "cdef_candidate_mask",
     "cdef_search_weighted",
     "cdef_batch_workspace_bytes",
     "cdef_batch_prepare",
@@ -75,6 +77,8 @@ class CdefJob(C.Structure):
         ("var", C.c_void_p),
         ("damping", C.c_int32),
         ("mode", C.c_int32),
+        ("candidates", C.c_uint32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -131,6 +135,11 @@ def load(path: str = LIB_PATH):
     L.cdef_search_strengths128.restype = C.c_int
     L.cdef_search_weighted.argtypes = L.cdef_search_strengths.argtypes
     L.cdef_search_weighted.restype = C.c_int
+    L.cdef_search_subset.argtypes = [C.POINTER(CdefFrame), C.POINTER(CdefFrame), P, C.c_int32,
+                                     C.c_uint32, P, P, P, P]
+    L.cdef_search_subset.restype = C.c_int
+    L.cdef_candidate_mask.argtypes = [C.c_uint32, C.POINTER(C.c_uint64 * 2)]
+    L.cdef_candidate_mask.restype = None
     L.cdef_batch_workspace_bytes.argtypes = [C.c_int32]
     L.cdef_batch_workspace_bytes.restype = C.c_size_t
     L.cdef_batch_prepare.argtypes = [C.POINTER(CdefJob), C.c_int32, P, P, C.c_size_t,
@@ -140,8 +149,8 @@ def load(path: str = LIB_PATH):
     L.cdef_batch_launch.restype = C.c_int
     L.cdef_job_validate.argtypes = [C.POINTER(CdefJob)]
     L.cdef_job_validate.restype = C.c_int
-    L.cdef_select_presets.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
-                                      C.c_int32, P, P, P, P, C.c_size_t, P]
+    L.cdef_select_presets.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P,
+                                      C.c_double, C.c_int32, P, P, P, P, C.c_size_t, P]
     L.cdef_select_presets_workspace_bytes.argtypes = []
     L.cdef_select_presets_workspace_bytes.restype = C.c_size_t
     L.cdef_select_presets.restype = C.c_int
@@ -255,6 +264,46 @@ def cdef_search_strengths128(recon: Frame, src: Frame, skip, damping: int, sse, 
     _check(st, "cdef_search_strengths128")
 
 
+def subset(pri=range(16), sec_index=range(4), skip_bits=(0,)) -> int:
+    """Preset subset word: the S^(p) values, S^(s) indices (0..3 for 0, 1,
+    2, 4) and skip condition bits to evaluate."""
+    w = 0
+    for p in pri:
+        w |= 1 << p
+    for i in sec_index:
+        w |= 1 << (16 + i)
+    for k in skip_bits:
+        w |= 1 << (20 + k)
+    return w
+
+
+def candidate_mask(candidates: int):
+    """The two 64-bit candidate words of a subset (cdef_candidate_mask)."""
+    m = (C.c_uint64 * 2)()
+    load().cdef_candidate_mask(candidates, C.byref(m))
+    return [int(m[0]), int(m[1])]
+
+
+def cdef_search_subset(recon: Frame, src: Frame, skip, damping: int, candidates: int, sse,
+                       dir=None, var=None, stream=None) -> None:
+    st = load().cdef_search_subset(C.byref(recon.c_struct()), C.byref(src.c_struct()),
+                                   _ptr(skip), damping, candidates, _ptr(sse), _ptr(dir),
+                                   _ptr(var), _stream_handle(stream))
+    _check(st, "cdef_search_subset")
+
+
+def search_subset(recon: Frame, src: Frame, skip, damping: int, candidates: int, stream=None):
+    """The subset search's table (128-combination layout when the subset has
+    the skip condition bit set, else 64); presets outside: 2^64 - 1."""
+    import torch
+    fbr, fbc = recon.fb_shape
+    full = bool((candidates >> 21) & 1)
+    shape = (recon.search_planes, fbr, fbc) + ((2, 16, 4) if full else (16, 4))
+    sse = torch.empty(shape, dtype=torch.int64, device=recon.planes[0].device)
+    cdef_search_subset(recon, src, skip, damping, candidates, sse, stream=stream)
+    return sse
+
+
 def cdef_search_weighted(recon: Frame, src: Frame, skip, damping: int, dist, dir=None, var=None,
                          stream=None) -> None:
     st = load().cdef_search_weighted(C.byref(recon.c_struct()), C.byref(src.c_struct()),
@@ -314,13 +363,14 @@ def _out_struct(out_planes) -> CdefFrameOut:
 
 
 def make_search_job(recon: Frame, src: Frame, skip, damping: int, sse, dir=None,
-                    var=None, full=False, weighted=False) -> CdefJob:
+                    var=None, full=False, weighted=False, candidates=0) -> CdefJob:
     j = CdefJob()
     j.recon, j.src = recon.c_struct(), src.c_struct()
     j.skip8x8, j.sse = _ptr(skip), _ptr(sse)
     j.dir, j.var = _ptr(dir), _ptr(var)
     j.damping = damping
     j.mode = MODE_SEARCH_WEIGHTED if weighted else MODE_SEARCH128 if full else MODE_SEARCH
+    j.candidates = candidates
     return j
 
 
@@ -353,9 +403,9 @@ class Batch:
         self.staging = None
 
     def add_search(self, recon: Frame, src: Frame, skip, damping: int, sse, dir=None, var=None,
-                   full=False, weighted=False):
+                   full=False, weighted=False, candidates=0):
         return self.add_job(make_search_job(recon, src, skip, damping, sse, dir, var, full,
-                                            weighted),
+                                            weighted, candidates),
                             (recon, src, skip, sse, dir, var))
 
     def add_filter(self, recon: Frame, out_planes, skip, damping: int, fb, dir=None, var=None):
@@ -399,13 +449,16 @@ class Batch:
 # ---- preset selection (Section 5, Eq. 15) -------------------------------------
 
 def cdef_select_presets(sse, lam: float, refine_passes: int, result, fb_luma, fb_chroma,
-                        workspace, stream=None) -> None:
-    """sse: [nplanes][fbr][fbc][16][4] (64 candidates) or [..][2][16][4] (128)."""
+                        workspace, stream=None, cand_mask=None) -> None:
+    """sse: [nplanes][fbr][fbc][16][4] (64 candidates) or [..][2][16][4] (128);
+    cand_mask: two 64-bit words of allowed candidates (None: all)."""
     nplanes, fbr, fbc = sse.shape[0], sse.shape[1], sse.shape[2]
     ncand = 1
     for n in sse.shape[3:]:
         ncand *= n
-    st = load().cdef_select_presets(_ptr(sse), nplanes, fbr, fbc, ncand, float(lam),
+    cm = None if cand_mask is None else (C.c_uint64 * 2)(*cand_mask)
+    st = load().cdef_select_presets(_ptr(sse), nplanes, fbr, fbc, ncand,
+                                    None if cm is None else C.addressof(cm), float(lam),
                                     refine_passes,
                                     _ptr(result), _ptr(fb_luma), _ptr(fb_chroma),
                                     _ptr(workspace), workspace.numel() * workspace.element_size(),
@@ -419,7 +472,8 @@ def preset_workspace(device="cuda"):
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 
-def select_presets(sse, lam: float, refine_passes: int = 0, stream=None, workspace=None) -> dict:
+def select_presets(sse, lam: float, refine_passes: int = 0, stream=None, workspace=None,
+                   cand_mask=None) -> dict:
     """Run the preset selection on a device SSE table and return the result
     (this reads the result back, so it synchronizes the stream)."""
     import numpy as np
@@ -430,7 +484,7 @@ def select_presets(sse, lam: float, refine_passes: int = 0, stream=None, workspa
     fl = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
     fc = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
     ws = preset_workspace(dev) if workspace is None else workspace
-    cdef_select_presets(sse, lam, refine_passes, res, fl, fc, ws, stream)
+    cdef_select_presets(sse, lam, refine_passes, res, fl, fc, ws, stream, cand_mask)
     r = CdefPresetResult.from_buffer_copy(res.cpu().numpy().tobytes())
     if r.n == 0:
         raise CdefError("cdef_select_presets: the selection did not complete")

@@ -81,12 +81,22 @@ bool same_geometry(const cdef_frame *a, const cdef_frame *b) {
 
 bool stride32(int64_t s) { return s >= 0 && s <= INT32_MAX; }
 
+// A preset subset: non-empty S^(p), S^(s) and skip-bit masks, no other
+// bits; the skip condition bit only in the 128-combination search.
+bool candidates_valid(uint32_t cand, int32_t mode) {
+  if (cand >> 22) return false;
+  if (!(cand & 0xFFFF) || !((cand >> 16) & 15) || !((cand >> 20) & 3)) return false;
+  if (mode == CDEF_MODE_SEARCH) return ((cand >> 20) & 3) == 1;
+  return mode == CDEF_MODE_SEARCH128;
+}
+
 // Host-side checks of one job plus its descriptor for the fused kernel.
 cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
   FrameDesc r;
   cdef_status st = check_frame(&j->recon, &r);
   if (st != CDEF_OK) return st;
   if (j->damping < 3 || j->damping > 6) return CDEF_E_INVAL;
+  if (j->candidates && !candidates_valid(j->candidates, j->mode)) return CDEF_E_INVAL;
   if ((j->dir == nullptr) != (j->var == nullptr)) return CDEF_E_INVAL;
   memset(o, 0, sizeof(*o));
   for (int p = 0; p < r.nplanes; ++p) {
@@ -137,6 +147,7 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
   o->nplanes = r.nplanes;
   o->layout = r.layout;
   o->mode = j->mode;
+  o->cand = j->candidates;
   cdef::fill_job_geometry(*o);
   // 16-byte staging is possible when every plane read starts 16-byte aligned
   // and every row pitch keeps it so
@@ -192,7 +203,7 @@ namespace {
 
 cdef_status search_one(const cdef_frame *recon, const cdef_frame *src, const uint8_t *skip8x8,
                        int32_t damping, uint64_t *sse, uint8_t *dir, int32_t *var, int32_t mode,
-                       void *stream) {
+                       void *stream, uint32_t candidates = 0) {
   if (!recon || !src) return CDEF_E_INVAL;
   cdef_job j;
   memset(&j, 0, sizeof(j));
@@ -204,6 +215,7 @@ cdef_status search_one(const cdef_frame *recon, const cdef_frame *src, const uin
   j.var = var;
   j.damping = damping;
   j.mode = mode;
+  j.candidates = candidates;
   cdef::JobDesc d;
   const cdef_status st = make_job(&j, &d);
   if (st != CDEF_OK) return st;
@@ -222,6 +234,25 @@ cdef_status cdef_search_strengths128(const cdef_frame *recon, const cdef_frame *
                                      const uint8_t *skip8x8, int32_t damping, uint64_t *sse,
                                      uint8_t *dir, int32_t *var, void *stream) {
   return search_one(recon, src, skip8x8, damping, sse, dir, var, CDEF_MODE_SEARCH128, stream);
+}
+
+cdef_status cdef_search_subset(const cdef_frame *recon, const cdef_frame *src,
+                               const uint8_t *skip8x8, int32_t damping, uint32_t candidates,
+                               uint64_t *sse, uint8_t *dir, int32_t *var, void *stream) {
+  const int32_t mode = ((candidates >> 20) & 2) ? CDEF_MODE_SEARCH128 : CDEF_MODE_SEARCH;
+  if (!candidates_valid(candidates, mode)) return CDEF_E_INVAL;
+  return search_one(recon, src, skip8x8, damping, sse, dir, var, mode, stream, candidates);
+}
+
+void cdef_candidate_mask(uint32_t candidates, uint64_t mask[2]) {
+  mask[0] = mask[1] = 0;
+  for (int k = 0; k < 2; ++k)
+    for (int p = 0; p < 64; ++p) {
+      const bool in = candidates == 0 || (((candidates >> (p >> 2)) & 1) &&
+                                          ((candidates >> (16 + (p & 3))) & 1) &&
+                                          ((candidates >> (20 + k)) & 1));
+      if (in) mask[k] |= 1ull << p;
+    }
 }
 
 cdef_status cdef_search_weighted(const cdef_frame *recon, const cdef_frame *src,
@@ -290,8 +321,8 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
 size_t cdef_select_presets_workspace_bytes(void) { return cdef::preset_workspace_bytes(); }
 
 cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
-                                int32_t fb_cols, int32_t ncand, double lambda,
-                                int32_t refine_passes,
+                                int32_t fb_cols, int32_t ncand, const uint64_t *cand_mask,
+                                double lambda, int32_t refine_passes,
                                 cdef_preset_result *result, uint8_t *fb_luma,
                                 uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
                                 void *stream) {
@@ -300,12 +331,18 @@ cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb
     return CDEF_E_INVAL;
   if (nplanes != 1 && nplanes != 3) return CDEF_E_INVAL;
   if (ncand != 64 && ncand != 128) return CDEF_E_INVAL;
+  uint64_t mask[2] = {~0ull, ncand == 128 ? ~0ull : 0ull};
+  if (cand_mask) {
+    mask[0] = cand_mask[0];
+    mask[1] = ncand == 128 ? cand_mask[1] : 0ull;
+  }
+  if (__builtin_popcountll(mask[0]) + __builtin_popcountll(mask[1]) < 8) return CDEF_E_INVAL;
   if (fb_rows < 1 || fb_cols < 1) return CDEF_E_INVAL;
   if (!(lambda >= 0.0) || !isfinite(lambda)) return CDEF_E_INVAL;
   if (refine_passes < 0 || refine_passes > 16) return CDEF_E_INVAL;
   const int64_t nfb = (int64_t)fb_rows * fb_cols;
   if (nfb > (1 << 24)) return CDEF_E_UNSUPPORTED;
-  return from_hip(cdef::launch_select_presets(sse, nplanes, (int)nfb, ncand, lambda,
+  return from_hip(cdef::launch_select_presets(sse, nplanes, (int)nfb, ncand, mask, lambda,
                                               refine_passes,
                                               reinterpret_cast<cdef::PresetResult *>(result),
                                               fb_luma, fb_chroma, workspace,

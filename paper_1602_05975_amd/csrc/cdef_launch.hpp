@@ -46,6 +46,7 @@ struct JobDesc {
   int32_t item0;  // first work item (filter block) of this job in the batch
   int32_t flags;  // bit 0: every plane's base and row pitch are 16-byte aligned
   int32_t layout;
+  uint32_t cand;  // searches: preset subset (S^(p) | S^(s) << 16 | skip bit << 20), 0 = all
 };
 
 hipError_t launch_find_dir(const FrameDesc &f, uint8_t *dir, int32_t *var, hipStream_t s);
@@ -76,7 +77,8 @@ struct PresetResult {
 
 size_t preset_workspace_bytes();
 hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
-                                 double lambda, int refine, PresetResult *out, uint8_t *fb_luma,
-                                 uint8_t *fb_chroma, void *workspace, hipStream_t s);
+                                 const uint64_t mask[2], double lambda, int refine,
+                                 PresetResult *out, uint8_t *fb_luma, uint8_t *fb_chroma,
+                                 void *workspace, hipStream_t s);
 
 }  // namespace cdef

@@ -221,23 +221,30 @@ __device__ __forceinline__ s16x2 chroma_special(const Taps &t, int c, int D) {
 // strengths (Eq. 13).  Per-strength parameters are wave-uniform 32-bit
 // scalars (low half: block A, high half: block B).  Each pair's y - s goes
 // to sink(pair, e), pair = S^(p) * 4 + index of S^(s).
-template <bool FULL, bool B12, class Sink>
+//
+// SUB: only the strengths of a subset (pm: S^(p) mask, qm: S^(s) index mask,
+// sp19: the special preset) are evaluated; the sink sees no other pair.
+template <bool FULL, bool B12, bool SUB, class Sink>
 __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_t adjB, int a19A,
-                                           int a19B, int c, int D, Sink &&sink) {
+                                           int a19B, int c, int D, uint32_t pm, uint32_t qm,
+                                           bool sp19, Sink &&sink) {
   // pair (0, 0) filters nothing; in the full search its slot carries the
   // special preset instead (the unfiltered distortion is summed elsewhere)
-  if (FULL)
-    sink(0, luma_special<B12>(t, a19A, a19B, c, D));
-  else
+  if (FULL) {
+    if (!SUB || sp19) sink(0, luma_special<B12>(t, a19A, a19B, c, D));
+  } else if (!SUB || (pm & qm & 1)) {
     sink(0, t.dxs);
+  }
   s16x2 Q[4];
   secondaries(t, c, D, Q);
 #pragma unroll
-  for (int si = 1; si < 4; ++si) sink(si, err_one<B12>(t, Q[si]));
+  for (int si = 1; si < 4; ++si)
+    if (!SUB || ((pm & 1) && ((qm >> si) & 1))) sink(si, err_one<B12>(t, Q[si]));
   uint32_t prev_sh = 0xFFFFFFFFu;
   u16x2 a[4];
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
+    if (SUB && !((pm >> S) & 1)) continue;
     const uint32_t sa = (uint32_t)(adjA >> (4 * S)) & 15u, sb = (uint32_t)(adjB >> (4 * S)) & 15u;
     const uint32_t sp = (sa << c) | (sb << (16 + c));
     const uint32_t sha = sa ? (uint32_t)(D - floor_log2((int)sa)) : 0u;
@@ -251,42 +258,69 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
       for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
     }
     const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
-    sink(4 * S, err_one<B12>(t, P));
+    if (!SUB || (qm & 1)) sink(4 * S, err_one<B12>(t, P));
 #pragma unroll
-    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both<B12>(t, P, Q[si]));
+    for (int si = 1; si < 4; ++si)
+      if (!SUB || ((qm >> si) & 1)) sink(4 * S + si, err_both<B12>(t, P, Q[si]));
   }
 }
 
 // Chroma task: strengths are not adjusted (uniform over the plane); the
 // chroma damping is max(D - 1, floor(log2 S^(p))) for both tap groups, which
 // differs from D - 1 only for D = 3 and S^(p) >= 8.
-template <bool FULL, bool B12, class Sink>
-__device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, Sink &&sink) {
-  if (FULL)
-    sink(0, chroma_special<B12>(t, c, D));
-  else
+template <bool FULL, bool B12, bool SUB, class Sink>
+__device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, uint32_t pm, uint32_t qm,
+                                             bool sp19, Sink &&sink) {
+  if (FULL) {
+    if (!SUB || sp19) sink(0, chroma_special<B12>(t, c, D));
+  } else if (!SUB || (pm & qm & 1)) {
     sink(0, t.dxs);
+  }
   s16x2 Q[4];
   secondaries(t, c, D - 1, Q);
 #pragma unroll
-  for (int si = 1; si < 4; ++si) sink(si, err_one<B12>(t, Q[si]));
+  for (int si = 1; si < 4; ++si)
+    if (!SUB || ((pm & 1) && ((qm >> si) & 1))) sink(si, err_one<B12>(t, Q[si]));
   u16x2 a[4];
+  uint32_t prev_sh = 0xFFFFFFFFu;
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
     const int lg = S >= 8 ? 3 : S >= 4 ? 2 : S >= 2 ? 1 : 0;
     if (S == 8 && D == 3) secondaries(t, c, 3, Q);  // chroma damping becomes 3
     const int Dc = max(D - 1, lg);
-    if (S == 1 || S == 2 || S == 4 || S == 8 || (S == 8 && D == 3)) {
+    if (SUB) {
+      // strengths may be skipped, so the shifted magnitudes follow the shift
+      if (!((pm >> S) & 1)) continue;
+      const uint32_t sh = (uint32_t)(Dc - lg);
+      if (sh != prev_sh) {
+        prev_sh = sh;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32(sh));
+      }
+    } else if (S == 1 || S == 2 || S == 4 || S == 8 || (S == 8 && D == 3)) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32((uint32_t)(Dc - lg)));
     }
     const uint32_t w1 = splat32((S & 1) ? 3u : 4u), w2 = splat32((S & 1) ? 3u : 2u);
     const s16x2 P = group_sum(t, a, 0, splat32((uint32_t)S << c), w1, w2);
-    sink(4 * S, err_one<B12>(t, P));
+    if (!SUB || (qm & 1)) sink(4 * S, err_one<B12>(t, P));
 #pragma unroll
-    for (int si = 1; si < 4; ++si) sink(4 * S + si, err_both<B12>(t, P, Q[si]));
+    for (int si = 1; si < 4; ++si)
+      if (!SUB || ((qm >> si) & 1)) sink(4 * S + si, err_both<B12>(t, P, Q[si]));
   }
 }
+
+// The subset of a job: S^(p) mask, S^(s) index mask, skip-bit mask (all
+// presets when the job carries none).
+struct Subset {
+  uint32_t pm, qm, km;
+  __device__ __forceinline__ explicit Subset(uint32_t cand)
+      : pm(cand ? cand & 0xFFFF : 0xFFFF), qm(cand ? (cand >> 16) & 15 : 15),
+        km(cand ? (cand >> 20) & 3 : 3) {}
+  __device__ __forceinline__ bool has(int k, int pair) const {
+    return ((pm >> (pair >> 2)) & (qm >> (pair & 3)) & (km >> k) & 1) != 0;
+  }
+};
 
 // Square-accumulate sink of the SSE searches.
 struct SquareSum {
@@ -686,21 +720,23 @@ __device__ __forceinline__ void block_tasks(SmemT<X> &sm, const JobDesc &J, int 
 }
 
 // The pair generator of a luma-shaped task of plane CH.
-template <bool FULL, bool B12, int CH, bool X, class Sink>
+template <bool FULL, bool B12, int CH, bool SUB = false, bool X, class Sink>
 __device__ __forceinline__ void block_pairs(SmemT<X> &sm, const JobDesc &J, const Taps &t, int A,
                                             int B, Sink &&sink) {
   const int c = J.bitdepth - 8, D = J.damping;
+  const Subset sub(SUB ? J.cand : 0u);
+  const bool sp19 = sub.has(1, 0);
   if (CH == 0) {
     const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
     const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
-    luma_pairs<FULL, B12>(t, adjA, adjB, a19A, a19B, c, D, sink);
+    luma_pairs<FULL, B12, SUB>(t, adjA, adjB, a19A, a19B, c, D, sub.pm, sub.qm, sp19, sink);
   } else {
-    chroma_pairs<FULL, B12>(t, c, D, sink);
+    chroma_pairs<FULL, B12, SUB>(t, c, D, sub.pm, sub.qm, sp19, sink);
   }
 }
 
 // SSE search over luma-shaped tasks; per-wave pair totals go to red[wave].
-template <bool FULL, bool B12, int CH, bool X>
+template <bool FULL, bool B12, bool SUB, int CH, bool X>
 __device__ __forceinline__ void plane_tasks(SmemT<X> &sm, const JobDesc &J, int first, int count,
                                             int y0, int x0, int wave, int lane, uint64_t *red) {
   int acc[64];
@@ -708,7 +744,7 @@ __device__ __forceinline__ void plane_tasks(SmemT<X> &sm, const JobDesc &J, int 
   for (int i = 0; i < 64; ++i) acc[i] = 0;
   block_tasks<X, B12, CH>(sm, J, first, count, y0, x0, wave, lane,
                           [&](const Taps &t, int A, int B, bool, uint32_t) {
-                            block_pairs<FULL, B12, CH>(sm, J, t, A, B, SquareSum{acc});
+                            block_pairs<FULL, B12, CH, SUB>(sm, J, t, A, B, SquareSum{acc});
                           });
   red[wave * 64 + lane] = reduce_transpose<B12>(acc, lane);
 }
@@ -757,17 +793,20 @@ __device__ __forceinline__ void chroma420_tasks(SmemT<X> &sm, const JobDesc &J, 
 
 // SSE search over 4:2:0 chroma tasks; plane 1 + p's totals go to
 // red[1 + p][wave & 1].
-template <bool FULL, bool B12, bool X>
+template <bool FULL, bool B12, bool SUB, bool X>
 __device__ __forceinline__ void chroma420_sse(SmemT<X> &sm, const JobDesc &J, int first, int count,
                                               int y0, int x0, int wave, int lane,
                                               uint64_t (*red)[4][64]) {
   const int c = J.bitdepth - 8, D = J.damping;
+  const Subset sub(SUB ? J.cand : 0u);
+  const bool sp19 = sub.has(1, 0);
   int acc[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) acc[i] = 0;
   chroma420_tasks<X, B12>(sm, J, first, count, y0, x0, wave, lane,
                           [&](const Taps &t, int, int, bool, bool, uint32_t) {
-                            chroma_pairs<FULL, B12>(t, c, D, SquareSum{acc});
+                            chroma_pairs<FULL, B12, SUB>(t, c, D, sub.pm, sub.qm, sp19,
+                                                         SquareSum{acc});
                           });
   red[1 + (wave >> 1)][wave & 1][lane] = reduce_transpose<B12>(acc, lane);
 }
@@ -777,7 +816,7 @@ __device__ __forceinline__ int plane_waves(const JobDesc &J, int P) {
   return P == 0 || J.layout == kLayout444 ? 4 : 2;
 }
 
-template <bool FULL, bool B12, bool X>
+template <bool FULL, bool B12, bool SUB, bool X>
 __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
                                             int tid) {
   const int lane = tid & 63, wave = tid >> 6;
@@ -794,23 +833,25 @@ __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int 
   __syncthreads();
   const int n = sm.n;
 
-  plane_tasks<FULL, B12, 0>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[0][0][0]);
-  if (c420) chroma420_sse<FULL, B12>(sm, J, 0, n, y0, x0, wave, lane, sm.red);
+  const Subset sub(SUB ? J.cand : 0u);
+  plane_tasks<FULL, B12, SUB, 0>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[0][0][0]);
+  if (c420) chroma420_sse<FULL, B12, SUB>(sm, J, 0, n, y0, x0, wave, lane, sm.red);
   if constexpr (X) {
     if (c444) {
-      plane_tasks<FULL, B12, 1>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[1][0][0]);
-      plane_tasks<FULL, B12, 2>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[2][0][0]);
+      plane_tasks<FULL, B12, SUB, 1>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[1][0][0]);
+      plane_tasks<FULL, B12, SUB, 2>(sm, J, 0, n, y0, x0, wave, lane, &sm.red[2][0][0]);
     }
   }
-  // skipped blocks matter only where some block has residual
-  if (FULL && n > 0) {
+  // skipped blocks matter only where some block has residual, and only for
+  // the presets with the skip condition bit
+  if (FULL && n > 0 && (!SUB || (sub.km & 2))) {
     const int nsk = sm.nsk;
-    plane_tasks<FULL, B12, 0>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[0][0][0]);
-    if (c420) chroma420_sse<FULL, B12>(sm, J, n, nsk, y0, x0, wave, lane, sm.red2);
+    plane_tasks<FULL, B12, SUB, 0>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[0][0][0]);
+    if (c420) chroma420_sse<FULL, B12, SUB>(sm, J, n, nsk, y0, x0, wave, lane, sm.red2);
     if constexpr (X) {
       if (c444) {
-        plane_tasks<FULL, B12, 1>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[1][0][0]);
-        plane_tasks<FULL, B12, 2>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[2][0][0]);
+        plane_tasks<FULL, B12, SUB, 1>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[1][0][0]);
+        plane_tasks<FULL, B12, SUB, 2>(sm, J, n, nsk, y0, x0, wave, lane, &sm.red2[2][0][0]);
       }
     }
   }
@@ -827,13 +868,17 @@ __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int 
   const int64_t fbi = (int64_t)fby * J.fbc + fbx;
   const int64_t nfb = (int64_t)J.fbr * J.fbc;
   const uint64_t U = sm.skipsse[P];
+  // presets outside a subset read 2^64 - 1 (12-bit jobs evaluate them all
+  // and mark them here)
+  const Subset out(J.cand);
   if (!FULL) {
-    J.sse[(P * nfb + fbi) * 64 + k] = A + U;
+    J.sse[(P * nfb + fbi) * 64 + k] = out.has(0, k) ? A + U : UINT64_MAX;
   } else {
     // slot 0 holds the special preset; (0, 0) itself is the unfiltered sum
     uint64_t *o = J.sse + (P * nfb + fbi) * 128;
-    o[k] = k == 0 ? sm.allsse[P] : A + U;
-    o[64 + k] = n > 0 ? A + Bf : U;  // every block skipped: nothing is filtered
+    o[k] = out.has(0, k) ? (k == 0 ? sm.allsse[P] : A + U) : UINT64_MAX;
+    // every block skipped: nothing is filtered
+    o[64 + k] = out.has(1, k) ? (n > 0 ? A + Bf : U) : UINT64_MAX;
   }
 }
 
@@ -1019,7 +1064,7 @@ __device__ __forceinline__ void chroma420_w(SmemT<true> &sm, const JobDesc &J, i
       sm, J, 0, n, y0, x0, wave, lane,
       [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t sv) {
         s16x2 ev[64];
-        chroma_pairs<false, B12>(t, c, D, StoreErr{ev});
+        chroma_pairs<false, B12, false>(t, c, D, 0xFFFFu, 15u, false, StoreErr{ev});
         Moments<true, B12> m;
         task_moments<true, B12>(ev, sv, lane, m);
 #pragma unroll
@@ -1184,9 +1229,9 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
   if constexpr (X) {
     if (J.bitdepth == 12) {
       if (J.mode == kModeSearch)
-        search_item<false, true>(sm, J, fby, fbx, tid);
+        search_item<false, true, false>(sm, J, fby, fbx, tid);
       else if (J.mode == kModeSearchFull)
-        search_item<true, true>(sm, J, fby, fbx, tid);
+        search_item<true, true, false>(sm, J, fby, fbx, tid);
       else if (J.mode == kModeSearchWeighted)
         search_item_weighted<true>(sm, J, fby, fbx, tid);
       else
@@ -1198,12 +1243,19 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
       return;
     }
   }
-  if (J.mode == kModeSearch)
-    search_item<false, false>(sm, J, fby, fbx, tid);
-  else if (J.mode == kModeSearchFull)
-    search_item<true, false>(sm, J, fby, fbx, tid);
-  else
+  if (J.mode == kModeSearch) {
+    if (J.cand)
+      search_item<false, false, true>(sm, J, fby, fbx, tid);
+    else
+      search_item<false, false, false>(sm, J, fby, fbx, tid);
+  } else if (J.mode == kModeSearchFull) {
+    if (J.cand)
+      search_item<true, false, true>(sm, J, fby, fbx, tid);
+    else
+      search_item<true, false, false>(sm, J, fby, fbx, tid);
+  } else {
     filter_item<X>(sm, J, fby, fbx, tid);
+  }
 }
 
 }  // namespace

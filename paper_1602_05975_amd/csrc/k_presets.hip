@@ -2,7 +2,9 @@
 //
 // D^luma_{b,p} is the luma SSE of filter block b under candidate p (p =
 // skip condition bit * 64 + S^(p) * 4 + index of S^(s); 64 candidates
-// without the bit, 128 with it); D^chroma_{b,p} is the Cb + Cr SSE.  For each group a
+// without the bit, 128 with it); D^chroma_{b,p} is the Cb + Cr SSE.  A
+// candidate mask restricts the choice to a subset (the low-complexity
+// search leaves the others unevaluated).  For each group a
 // greedy sequence of 8 presets is built, each step adding the candidate not
 // yet chosen that most lowers sum_b min over the set (lowest index on ties);
 // for N = 1, 2, 4, 8 the greedy prefix is re-optimized one preset at a time
@@ -64,6 +66,12 @@ __device__ __forceinline__ uint64_t group_dist(const uint64_t *sse, int nfb, int
 struct Query {
   int set[8];
   int n, excl;
+};
+
+// Candidates outside the caller's subset are never chosen.
+struct CandMask {
+  uint64_t w[2];
+  __device__ __forceinline__ bool allowed(int p) const { return (w[p >> 6] >> (p & 63)) & 1; }
 };
 
 template <int NC>
@@ -180,7 +188,8 @@ __device__ bool round_totals(CoopSmem<NC> &sm, PresetWork *work, int g, int G, i
 template <int NC, bool LDS>
 __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict__ sse,
                                                      int nplanes, int nfb, int G, int refine,
-                                                     PresetWork *work, PresetResult *out) {
+                                                     CandMask cm, PresetWork *work,
+                                                     PresetResult *out) {
   using Smem = CoopSmem<NC>;
   constexpr int R = Smem::kRows;
   __shared__ Smem sm;
@@ -292,7 +301,7 @@ __global__ __launch_bounds__(kNT) void k_preset_coop(const uint64_t *__restrict_
 #pragma unroll
       for (int h = 0; h < NC / 64; ++h) {
         const int cand = lane + 64 * h;
-        if (!excluded(q, cand)) argmin2(c, p, sm.cost[wave][cand], cand);
+        if (!excluded(q, cand) && cm.allowed(cand)) argmin2(c, p, sm.cost[wave][cand], cand);
       }
       wave_argmin(c, p);
       if (lane == 0) {
@@ -417,9 +426,9 @@ size_t preset_workspace_bytes() { return sizeof(PresetWork); }
 namespace {
 
 template <int NC>
-hipError_t select_presets_nc(const uint64_t *sse, int nplanes, int nfb, double lambda, int refine,
-                             PresetResult *out, uint8_t *fb_luma, uint8_t *fb_chroma,
-                             PresetWork *work, hipStream_t s) {
+hipError_t select_presets_nc(const uint64_t *sse, int nplanes, int nfb, CandMask cm,
+                             double lambda, int refine, PresetResult *out, uint8_t *fb_luma,
+                             uint8_t *fb_chroma, PresetWork *work, hipStream_t s) {
   constexpr int kSlice = slice_blocks<NC>();
   const int G = min(kMaxG, (nfb + kSlice - 1) / kSlice);
   const int per = (nfb + G - 1) / G;
@@ -430,10 +439,10 @@ hipError_t select_presets_nc(const uint64_t *sse, int nplanes, int nfb, double l
   // once, so every wait for the last arrival of a round ends.
   if (per <= kSlice)
     hipLaunchKernelGGL((k_preset_coop<NC, true>), dim3(2 * G), dim3(kNT), 0, s, sse, nplanes, nfb,
-                       G, refine, work, out);
+                       G, refine, cm, work, out);
   else
     hipLaunchKernelGGL((k_preset_coop<NC, false>), dim3(2 * G), dim3(kNT), 0, s, sse, nplanes,
-                       nfb, G, refine, work, out);
+                       nfb, G, refine, cm, work, out);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_preset_finish<NC>, dim3((nfb + kNT - 1) / kNT), dim3(kNT), 0, s, sse,
@@ -444,14 +453,16 @@ hipError_t select_presets_nc(const uint64_t *sse, int nplanes, int nfb, double l
 }  // namespace
 
 hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, int ncand,
-                                 double lambda, int refine, PresetResult *out, uint8_t *fb_luma,
-                                 uint8_t *fb_chroma, void *workspace, hipStream_t s) {
+                                 const uint64_t mask[2], double lambda, int refine,
+                                 PresetResult *out, uint8_t *fb_luma, uint8_t *fb_chroma,
+                                 void *workspace, hipStream_t s) {
   PresetWork *work = static_cast<PresetWork *>(workspace);
+  const CandMask cm{{mask[0], mask[1]}};
   if (ncand == 128)
-    return select_presets_nc<128>(sse, nplanes, nfb, lambda, refine, out, fb_luma, fb_chroma,
+    return select_presets_nc<128>(sse, nplanes, nfb, cm, lambda, refine, out, fb_luma, fb_chroma,
                                   work, s);
-  return select_presets_nc<64>(sse, nplanes, nfb, lambda, refine, out, fb_luma, fb_chroma, work,
-                               s);
+  return select_presets_nc<64>(sse, nplanes, nfb, cm, lambda, refine, out, fb_luma, fb_chroma,
+                               work, s);
 }
 
 }  // namespace cdef

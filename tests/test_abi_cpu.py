@@ -139,8 +139,9 @@ def test_select_presets_argument_checks(lib):
     assert 0 < n < (1 << 20)
     f = lib.cdef_select_presets
 
-    def call(sse=P, npl=3, fbr=2, fbc=2, nc=64, lam=1.0, ref=0, res=P, fl=P, fc=P, ws=W, wsb=n):
-        return f(sse, npl, fbr, fbc, nc, lam, ref, res, fl, fc, ws, wsb, None)
+    def call(sse=P, npl=3, fbr=2, fbc=2, nc=64, lam=1.0, ref=0, res=P, fl=P, fc=P, ws=W, wsb=n,
+             mask=None):
+        return f(sse, npl, fbr, fbc, nc, mask, lam, ref, res, fl, fc, ws, wsb, None)
 
     assert call(sse=None) == -1
     assert call(res=None) == -1
@@ -160,3 +161,31 @@ def test_select_presets_argument_checks(lib):
     assert call(ref=17) == -1
     assert call(npl=1, fbr=4097, fbc=4097) == -2
     assert call(npl=1, fbr=4097, fbc=4097, nc=128) == -2
+    # fewer than 8 allowed candidates (the second word does not count at 64)
+    seven = (C.c_uint64 * 2)(0x7F, 0)
+    assert call(mask=C.addressof(seven)) == -1
+    hi = (C.c_uint64 * 2)(0, 0xFF)
+    assert call(mask=C.addressof(hi)) == -1
+    assert call(nc=128, mask=C.addressof(hi), npl=1, fbr=4097, fbc=4097) == -2
+
+
+def test_subset_masks(lib):
+    from paper_1602_05975_amd import cdef
+    w = cdef.subset(pri=(0, 3, 15), sec_index=(1, 2), skip_bits=(0, 1))
+    m = cdef.candidate_mask(w)
+    want = [0, 0]
+    for k in (0, 1):
+        for p in (0, 3, 15):
+            for i in (1, 2):
+                want[k] |= 1 << (4 * p + i)
+    assert m == want
+    assert cdef.candidate_mask(0) == [2**64 - 1, 2**64 - 1]
+    P = 0x20000
+    r, s = _frame(), _frame(ptr=0x900000)
+    f = lib.cdef_search_subset
+    assert f(C.byref(r), C.byref(s), None, 3, 0, P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 3, 1 << 22, P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 3, 0xFFFF | (1 << 20), P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 3, 0xF0000 | (1 << 20), P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 3, 0xFFFF | 0xF0000, P, None, None, None) == -1
+    assert f(C.byref(r), C.byref(s), None, 7, w, P, None, None, None) == -1
