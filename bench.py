@@ -48,6 +48,12 @@ OPS_PER_SAMPLE_MOMENTS = 6
 # packed 16-bit instructions do two element operations per lane.
 PEAK_PACKED_I16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
+# The subset workload's default: S^(p) in {0, 1, 2, 3, 4, 6, 8, 11}, every
+# S^(s), skip condition bit 0 -- 32 of the 64 pairs.
+DEFAULT_SUBSET = (0b0000100101011111 | (0b1111 << 16) | (0b01 << 20))
+# bit depth and layout of the format workloads (luma 3840x2160, 8 frames)
+FORMATS = {"search4k": (10, 1), "search128": (10, 1), "weighted": (10, 1), "subset": (10, 1),
+           "search12": (12, 1), "search444": (10, 3), "search422": (10, 2)}
 KERNEL_SOURCES = ["k_fused.hip", "cdef_device.hpp"]
 
 
@@ -63,20 +69,38 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def frame_work(fr, full=False, weighted=False):
+def subset_counts(cand):
+    """(non-zero S^(p) values, non-zero S^(s) values, (S^(p), S^(s)) pairs,
+    skip condition bits) of a preset subset word (0: all presets)."""
+    if not cand:
+        return 15, 3, 64, 2
+    pri = [p for p in range(16) if (cand >> p) & 1]
+    sec = [i for i in range(4) if (cand >> (16 + i)) & 1]
+    skb = [k for k in range(2) if (cand >> (20 + k)) & 1]
+    return (len([p for p in pri if p]), len([i for i in sec if i]), len(pri) * len(sec), len(skb))
+
+
+def ops_per_filtered_sample(cand=0):
+    """OPS_PER_FILTERED_SAMPLE restricted to a subset's strengths and pairs."""
+    npri, nsec, npairs, _ = subset_counts(cand)
+    return 48 + 24 * npri + 48 * nsec + 8 * npairs
+
+
+def frame_work(fr, full=False, weighted=False, cand=0):
     """(algorithmic ops, algorithmic HBM bytes) of one fused search launch
     (full: the 128-combination search, where the skipped blocks of filter
-    blocks with residual are filtered under every preset too)."""
+    blocks with residual are filtered under every preset too; cand: a preset
+    subset, whose absent strengths and pairs cost nothing)."""
     filtered = skipped = 0
     sk = fr.skip.astype(bool)
     fb_all = np.zeros((fr.fb_rows, fr.fb_cols), bool)
     for by in range(fr.fb_rows):
         for bx in range(fr.fb_cols):
             fb_all[by, bx] = sk[8 * by:8 * by + 8, 8 * bx:8 * bx + 8].all()
-    for p in range(fr.nplanes):
+    for p in range(fr.search_planes):
         w, h = fr.plane_dims(p)
-        bs = 8 if p == 0 else 4
-        fs = 64 if p == 0 else 32
+        sx, sy = (0, 0) if p == 0 else synth_shift(fr.layout)
+        bs, fs = 8 >> sx, 64 >> sx
         if full:  # every sample of a filter block with residual is filtered
             allsk = np.repeat(np.repeat(fb_all, fs, axis=0), fs, axis=1)[:h, :w]
             n_sk = int(allsk.sum())
@@ -85,7 +109,9 @@ def frame_work(fr, full=False, weighted=False):
             n_sk = int(px_sk.sum())
         skipped += n_sk
         filtered += w * h - n_sk
-    per_filtered = OPS_PER_FILTERED_SAMPLE + (OPS_PER_SPECIAL_SAMPLE if full else 0)
+    per_filtered = ops_per_filtered_sample(cand)
+    if full and (not cand or (cand >> 21) & 1):
+        per_filtered += OPS_PER_SPECIAL_SAMPLE
     if weighted:
         per_filtered = OPS_PER_FILTERED_SAMPLE_W
     ops = (per_filtered * filtered + OPS_PER_SKIPPED_SAMPLE * skipped
@@ -98,8 +124,13 @@ def frame_work(fr, full=False, weighted=False):
     nfb = fr.fb_rows * fr.fb_cols
     nblk = fr.blk_rows * fr.blk_cols
     ncand = 128 if full else 64
-    bytes_ = 2 * 2 * samples + nblk + nfb * ncand * 8 * fr.nplanes + 5 * nblk
+    bytes_ = 2 * 2 * samples + nblk + nfb * ncand * 8 * fr.search_planes + 5 * nblk
     return ops, bytes_
+
+
+def synth_shift(layout):
+    from paper_1602_05975_amd import synth
+    return synth.chroma_shift(layout)
 
 
 def cpu_baseline(fr, fb_rows: int = 6):
@@ -330,16 +361,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-frame", action="store_true",
                     help="one cdef_search_strengths launch per frame instead of one batch")
-    ap.add_argument("--workload", choices=["search4k", "search128", "weighted", "presets", "batch",
-                                           "serve"],
+    ap.add_argument("--workload", choices=["search4k", "search128", "weighted", "search12",
+                                           "search444", "search422", "subset", "presets",
+                                           "batch", "serve"],
                     default="search4k",
                     help="search4k: the headline line (default); search128: the same frames "
                          "under the 128-combination search; weighted: the same frames with the "
-                         "Eq. (14) distortion; presets: Eq. (15) preset "
+                         "Eq. (14) distortion; search12 / search444 / search422: 12-bit 4:2:0, "
+                         "10-bit 4:4:4, 10-bit 4:2:2 frames of the same size; subset: the "
+                         "headline frames under a preset subset (--subset); presets: Eq. (15) "
+                         "preset "
                          "selection on their tables; batch: 64 mixed frames, "
                          "per-frame launches vs one tuned, graph-replayed batch; serve: "
                          "Poisson request stream, continuous batching vs one request per "
                          "launch")
+    ap.add_argument("--subset", type=lambda x: int(x, 0), default=DEFAULT_SUBSET,
+                    help="preset subset word of the subset workload: S^(p) mask | S^(s) index "
+                         "mask << 16 | skip condition bit mask << 20")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling HBM counters)")
@@ -372,11 +410,20 @@ def main():
         return run_presets(args)
     full = args.workload == "search128"
     weighted = args.workload == "weighted"
+    cand = args.subset if args.workload == "subset" else 0
+    if cand and (cand >> 21) & 1:
+        full = True
+    bd, layout = FORMATS[args.workload]
+    lname = {0: "4:0:0", 1: "4:2:0", 2: "4:2:2", 3: "4:4:4"}[layout]
 
-    log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
-    frames = synth.config2(args.frames)
-    ops = sum(frame_work(f, full, weighted)[0] for f in frames)
-    algo_bytes = sum(frame_work(f, full, weighted)[1] for f in frames)
+    log(f"generating {args.frames} synthetic 3840x2160 {bd}-bit {lname} frames")
+    if (bd, layout) == (10, 1):
+        frames = synth.config2(args.frames)
+    else:
+        frames = [synth.make_frame(3840, 2160, bd, layout, synth.config_seed(2, f),
+                                   skip_prob=0.3, damping=3) for f in range(args.frames)]
+    ops = sum(frame_work(f, full, weighted, cand)[0] for f in frames)
+    algo_bytes = sum(frame_work(f, full, weighted, cand)[1] for f in frames)
 
     dev = torch.device("cuda:0")
     jobs = []
@@ -384,7 +431,7 @@ def main():
         rec = cdef.Frame.from_numpy(fr.recon, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
         src = cdef.Frame.from_numpy(fr.src, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
         skip = torch.from_numpy(fr.skip).to(dev)
-        shape = (fr.nplanes, fr.fb_rows, fr.fb_cols) + ((2, 16, 4) if full else (16, 4))
+        shape = (fr.search_planes, fr.fb_rows, fr.fb_cols) + ((2, 16, 4) if full else (16, 4))
         sse = torch.empty(shape, dtype=torch.float64 if weighted else torch.int64, device=dev)
         d = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.uint8, device=dev)
         v = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.int32, device=dev)
@@ -394,11 +441,15 @@ def main():
     stream = torch.cuda.current_stream()
     search_one = (cdef.cdef_search_weighted if weighted else
                   cdef.cdef_search_strengths128 if full else cdef.cdef_search_strengths)
+    if cand:
+        def search_one(rec, src, skip, D, sse, d, v, stream):
+            cdef.cdef_search_subset(rec, src, skip, D, cand, sse, d, v, stream)
     batch = None
     if not args.per_frame:
         batch = cdef.Batch()
         for (rec, src, skip, D, sse, d, v) in jobs:
-            batch.add_search(rec, src, skip, D, sse, d, v, full=full, weighted=weighted)
+            batch.add_search(rec, src, skip, D, sse, d, v, full=full, weighted=weighted,
+                             candidates=cand)
         batch.prepare(stream)
         torch.cuda.synchronize()
 
@@ -444,16 +495,24 @@ def main():
     achieved = ops_per_launch / avg_launch_s / 1e12
     frame_ms = launch_ms if batch is None else launch_ms  # a batch's frames finish together
     kname = "k_fused_batch" if batch is not None else "k_fused_one"
-    traffic = load_traffic(kname + ("_full" if full else "_weighted" if weighted else ""))
-    what = ("all 128 (primary, secondary, skip condition) presets" if full else
-            "all 64 (primary, secondary) strength pairs")
+    suffix = {"search4k": "", "search128": "_full", "weighted": "_weighted"}.get(args.workload,
+                                                                           "_" + args.workload)
+    traffic = load_traffic(kname + suffix)
+    npri, nsec, npairs, nskb = subset_counts(cand)
+    what = ("all 128 (primary, secondary, skip condition) presets" if full and not cand else
+            "all 64 (primary, secondary) strength pairs" if not cand else
+            f"a subset of {npairs * nskb} presets (word {cand:#x})")
     if weighted:
         what += " with the Eq. (14) contrast-weighted distortion (float64 table)"
+    fmt = f"{bd}-bit {lname}"
     result = {
-        "metric": ("Mpixel/s for dir+filter+128-combination SSE search, 4K 10-bit" if full else
-                   "Mpixel/s for dir+filter+all-strength Eq. (14) weighted search, 4K 10-bit"
+        "metric": ("Mpixel/s for dir+filter+128-combination SSE search, 4K 10-bit" if full and not cand
+                   else "Mpixel/s for dir+filter+all-strength Eq. (14) weighted search, 4K 10-bit"
                    if weighted else
-                   "Mpixel/s for dir+filter+all-strength SSE search, 4K 10-bit; p99 frame latency"),
+                   f"Mpixel/s for dir+filter+subset SSE search, 4K 10-bit" if cand else
+                   "Mpixel/s for dir+filter+all-strength SSE search, 4K 10-bit; p99 frame latency"
+                   if (bd, layout) == (10, 1) else
+                   f"Mpixel/s for dir+filter+all-strength SSE search, 4K {fmt}"),
         "value": round(value, 1),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -466,7 +525,7 @@ def main():
         "dtype": "int16",
         "data": "synthetic",
         "config": {
-            "workload": f"{len(frames)}x3840x2160 10-bit 4:2:0 frames, 30% of 8x8 blocks "
+            "workload": f"{len(frames)}x3840x2160 {fmt} frames, 30% of 8x8 blocks "
                         f"skipped, damping 3: fused direction search + filter under {what} "
                         "+ per-64x64 SSE, "
                         + ("one launch per frame" if batch is None else
@@ -493,7 +552,7 @@ def main():
             "hbm_peak_gbs": PEAK_HBM_GBS,
         },
     }
-    if not args.no_cpu_baseline and not full and not weighted:
+    if not args.no_cpu_baseline and args.workload == "search4k":
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(frames[0])
     print(json.dumps(result), flush=True)
