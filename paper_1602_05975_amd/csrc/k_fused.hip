@@ -1227,21 +1227,22 @@ template <bool X>
 __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int item, int tid) {
   const int fby = item / J.fbc, fbx = item - fby * J.fbc;
   if constexpr (X) {
-    if (J.bitdepth == 12) {
-      if (J.mode == kModeSearch)
-        search_item<false, true, false>(sm, J, fby, fbx, tid);
-      else if (J.mode == kModeSearchFull)
-        search_item<true, true, false>(sm, J, fby, fbx, tid);
-      else if (J.mode == kModeSearchWeighted)
+    if (J.mode == kModeSearchWeighted) {
+      if (J.bitdepth == 12)
         search_item_weighted<true>(sm, J, fby, fbx, tid);
       else
-        filter_item<X>(sm, J, fby, fbx, tid);
+        search_item_weighted<false>(sm, J, fby, fbx, tid);
       return;
     }
-    if (J.mode == kModeSearchWeighted) {
-      search_item_weighted<false>(sm, J, fby, fbx, tid);
-      return;
-    }
+  }
+  if (J.bitdepth == 12) {
+    if (J.mode == kModeSearch)
+      search_item<false, true, false>(sm, J, fby, fbx, tid);
+    else if (J.mode == kModeSearchFull)
+      search_item<true, true, false>(sm, J, fby, fbx, tid);
+    else
+      filter_item<X>(sm, J, fby, fbx, tid);
+    return;
   }
   if (J.mode == kModeSearch) {
     if (J.cand)
@@ -1266,10 +1267,16 @@ __global__ __launch_bounds__(256, 3) void k_fused_one(const JobDesc J) {
   run_item<false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
-// One frame on the extended kernel (2 waves per SIMD: 256 VGPRs).
+// One frame on the extended kernel (2 waves per SIMD: 256 VGPRs).  The
+// descriptor is read through a global-memory view of the argument segment:
+// as with the batch kernel's table, its fields are then reloaded where used
+// instead of being held in registers for the whole kernel.
 __global__ __launch_bounds__(256, 2) void k_fused_one_x(const JobDesc J) {
   __shared__ __align__(16) SmemT<true> sm;
-  run_item<true>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+  (void)J;
+  const uintptr_t args = reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr());
+  const JobDesc *__restrict__ jp = reinterpret_cast<const JobDesc *>(args);
+  run_item<true>(sm, *jp, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 // A batch: descriptors in device memory, items numbered across jobs.
@@ -1300,8 +1307,7 @@ void fill_job_geometry(JobDesc &j) {
 }
 
 bool job_needs_extended(const JobDesc &j) {
-  return j.mode == kModeSearchWeighted || j.bitdepth == 12 ||
-         (j.nplanes == 3 && j.layout == kLayout444);
+  return j.mode == kModeSearchWeighted || (j.nplanes == 3 && j.layout == kLayout444);
 }
 
 hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {

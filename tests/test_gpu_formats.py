@@ -144,3 +144,43 @@ def test_mixed_format_batch_equals_per_frame():
                                          weighted=mode == "weighted")
             torch.cuda.synchronize()
             assert torch.equal(out, want), mode
+
+
+def test_12bit_base_kernel_batch(oracle):
+    # 12-bit 4:0:0 / 4:2:0 / 4:2:2 searches and filters need no extended
+    # kernel; the batch stays on the 3-wave one and matches the oracle
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    specs = [(200, 136, 1, False), (131, 67, 0, True), (136, 72, 2, False), (200, 136, 1, True)]
+    b = cdef.Batch()
+    jobs = []
+    for i, (w, h, layout, full) in enumerate(specs):
+        fr = _frame(w, h, 12, layout, 87000 + i, D=3 + i)
+        rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+        skip = torch.from_numpy(fr.skip).cuda()
+        shape = (fr.search_planes, fr.fb_rows, fr.fb_cols) + ((2, 16, 4) if full else (16, 4))
+        out = torch.full(shape, -1, dtype=torch.int64, device="cuda")
+        b.add_search(rec, src, skip, fr.damping, out, full=full)
+        jobs.append((fr, full, out))
+    ff = _frame(136, 72, 12, 1, 87100, D=4)
+    rec = gpu_frame(ff.recon, ff)
+    skip = torch.from_numpy(ff.skip).cuda()
+    st = s.random_presets(ff, 87101)
+    fo = [torch.full_like(p, -1) for p in rec.planes[:ff.nplanes]]
+    b.add_filter(rec, fo, skip, ff.damping, torch.from_numpy(st).cuda())
+    b.prepare()
+    assert not (b.plan.flags & 1)
+    print(f"12-bit batch of {len(jobs) + 1} jobs on the base kernel", flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for fr, full, out in jobs:
+        ref, _, _, fbs = oracle_search(oracle, fr, full=full)
+        got = out.cpu().numpy().view(np.uint64)
+        for k, (by, bx) in enumerate(fbs):
+            assert (got[:, by, bx] == ref[k]).all(), (fr.width, full, by, bx)
+    od, ov = oracle.find_dir(ff.recon[0], 12)
+    want = oracle.filter_frame(ff.recon, ff.width, ff.height, 12, od, ov, ff.skip, ff.damping, st,
+                               layout=ff.layout)
+    for p in range(ff.nplanes):
+        assert (to_np_u16(fo[p]) == want[p]).all(), p
