@@ -359,6 +359,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="launch variant of the batched launch (cdef_batch_plan.variant: "
+                         "0 / 1: at most 3 / 2 waves per SIMD, XCD-contiguous filter-block "
+                         "order; 2 / 3: the same in plain order)")
     ap.add_argument("--per-frame", action="store_true",
                     help="one cdef_search_strengths launch per frame instead of one batch")
     ap.add_argument("--workload", choices=["search4k", "search128", "weighted", "search12",
@@ -451,6 +455,7 @@ def main():
             batch.add_search(rec, src, skip, D, sse, d, v, full=full, weighted=weighted,
                              candidates=cand)
         batch.prepare(stream)
+        batch.plan.variant = args.variant
         torch.cuda.synchronize()
 
     # launches of one step, each bracketed by HIP events on the launch stream

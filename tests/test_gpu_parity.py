@@ -152,3 +152,80 @@ def test_search_config2_sampled(oracle):
         fbs |= {(int(rng.integers(0, fbr)), int(rng.integers(0, fbc))) for _ in range(40)}
         print(f"search config2 seed {fr.seed}", flush=True)
         _compare_search(oracle, fr, fbs=sorted(fbs))
+
+
+def test_search_config2_batched_as_benchmarked(oracle):
+    # The benchmarked launch: the eight 3840x2160 frames in one batch with the
+    # default plan.  Every entry equals the one-frame launches; filter blocks
+    # of every frame (its edges and a seeded random set) equal the oracle.
+    import torch
+    from helpers import ORACLE_THREADS
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    frames = s.config2(8)
+    b = cdef.Batch()
+    outs = []
+    for fr in frames:
+        rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+        sk = torch.from_numpy(fr.skip).cuda()
+        t = torch.empty((3, fr.fb_rows, fr.fb_cols, 16, 4), dtype=torch.int64, device="cuda")
+        d = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.uint8, device="cuda")
+        v = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.int32, device="cuda")
+        b.add_search(rec, src, sk, fr.damping, t, d, v)
+        outs.append((rec, src, sk, t, d, v))
+    b.prepare()
+    assert b.plan.variant == 0 and not (b.plan.flags & 1)
+    print("search config2: 8 frames in one batched launch", flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(22)
+    for fr, (rec, src, sk, t, d, v) in zip(frames, outs):
+        one, d1, v1 = cdef.search_strengths(rec, src, sk, fr.damping, want_dir=True)
+        torch.cuda.synchronize()
+        assert torch.equal(one, t) and torch.equal(d1, d) and torch.equal(v1, v)
+        od, ov = oracle.find_dir(fr.recon[0], fr.bitdepth)
+        assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
+        fbr, fbc = fr.fb_rows, fr.fb_cols
+        fbs = {(0, 0), (fbr - 1, fbc - 1), (fbr - 1, 0), (0, fbc - 1)}
+        fbs |= {(int(rng.integers(0, fbr)), int(rng.integers(0, fbc))) for _ in range(6)}
+        fbs = sorted(fbs)
+        ref = oracle.search_fbs(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, od, ov,
+                                fr.skip, fr.damping, fbs, threads=ORACLE_THREADS)
+        got = t.cpu().numpy().view(np.uint64)
+        for k, (by, bx) in enumerate(fbs):
+            assert (got[:, by, bx] == ref[k]).all(), (fr.seed, by, bx)
+
+
+@pytest.mark.parametrize("w,h", [(65536, 72), (24, 65536)])
+def test_maximum_frame_sizes(oracle, w, h):
+    # The largest width and height the library takes (2^16): the search on
+    # sampled filter blocks (every one along the long edge's ends and a seeded
+    # set) and the whole filtered frame, against the oracle.
+    import torch
+    from helpers import ORACLE_THREADS
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    fr = s.make_frame(w, h, 10, s.LAYOUT_420, 23000 + w, skip_prob=0.3, damping=4)
+    print(f"maximum size {w}x{h}", flush=True)
+    rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+    sk = torch.from_numpy(fr.skip).cuda()
+    sse, d, v = cdef.search_strengths(rec, src, sk, fr.damping, want_dir=True)
+    st = s.random_presets(fr, 23100 + w)
+    outs = cdef.filter_frame(rec, d, v, sk, fr.damping, torch.from_numpy(st).cuda())
+    torch.cuda.synchronize()
+    od, ov = oracle.find_dir(fr.recon[0], 10)
+    assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
+    fbr, fbc = fr.fb_rows, fr.fb_cols
+    rng = np.random.default_rng(23)
+    fbs = {(by, bx) for by in range(fbr) for bx in range(fbc)
+           if min(by, fbr - 1 - by) < 2 and min(bx, fbc - 1 - bx) < 2}
+    fbs |= {(int(rng.integers(0, fbr)), int(rng.integers(0, fbc))) for _ in range(12)}
+    fbs = sorted(fbs)
+    ref = oracle.search_fbs(fr.recon, fr.src, w, h, 10, od, ov, fr.skip, fr.damping, fbs,
+                            threads=ORACLE_THREADS)
+    got = sse.cpu().numpy().view(np.uint64)
+    for k, (by, bx) in enumerate(fbs):
+        assert (got[:, by, bx] == ref[k]).all(), (by, bx)
+    want = oracle.filter_frame(fr.recon, w, h, 10, od, ov, fr.skip, fr.damping, st)
+    for p in range(3):
+        assert (to_np_u16(outs[p]) == want[p]).all(), p
