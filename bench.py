@@ -44,6 +44,12 @@ OPS_PER_SAMPLE_UNFILTERED = 3
 # per sample; the per-unit double-precision weights are not counted.
 OPS_PER_FILTERED_SAMPLE_W = OPS_PER_FILTERED_SAMPLE + 64 * (13 - 8)
 OPS_PER_SAMPLE_MOMENTS = 6
+# The decoder path (direction search + the filter at one signaled preset
+# per filter block) in 32-bit lanes: per filtered sample 12 tap differences
+# and magnitudes, 8 clamp bounds, 4 primary and 8 secondary taps x 6, the
+# sum, 3-op round, add and clamp, about 126 element operations.
+OPS_PER_SAMPLE_FILTER = 126
+PEAK_I32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T int32 lane-ops/s;
 # packed 16-bit instructions do two element operations per lane.
 PEAK_PACKED_I16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -284,6 +290,84 @@ def run_batching(args):
     print(json.dumps(res), flush=True)
 
 
+def run_filter(args):
+    """The decoder path on the eight 4K frames with random per-filter-block
+    strengths: per frame cdef_find_dir + cdef_filter_frame (two launches),
+    and the same work as one batched launch of filter jobs (direction search
+    fused in).  Outputs of both are compared before timing."""
+    import torch
+    from paper_1602_05975_amd import cdef, synth
+    log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
+    frames = synth.config2(args.frames)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    jobs = []
+    for i, fr in enumerate(frames):
+        rec = cdef.Frame.from_numpy(fr.recon, fr.width, fr.height, fr.bitdepth, fr.layout, dev)
+        skip = torch.from_numpy(fr.skip).to(dev)
+        st = torch.from_numpy(synth.random_strengths(fr, 600 + i)).to(dev)
+        d = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.uint8, device=dev)
+        v = torch.empty((fr.blk_rows, fr.blk_cols), dtype=torch.int32, device=dev)
+        plain = [torch.empty_like(p) for p in rec.planes[:fr.nplanes]]
+        fused = [torch.empty_like(p) for p in rec.planes[:fr.nplanes]]
+        jobs.append((fr, rec, skip, st, d, v, plain, fused))
+
+    def step_plain():
+        for fr, rec, skip, st, d, v, plain, _ in jobs:
+            cdef.cdef_find_dir(rec, d, v, stream)
+            cdef.cdef_filter_frame(rec, plain, d, v, skip, fr.damping, st, stream)
+
+    batch = cdef.Batch()
+    for fr, rec, skip, st, d, v, _, fused in jobs:
+        batch.add_filter(rec, fused, skip, fr.damping, st)
+    batch.prepare(stream)
+    step_plain()
+    batch.launch(stream)
+    torch.cuda.synchronize()
+    exact = all(torch.equal(a, b) for j in jobs for a, b in zip(j[6], j[7]))
+    log(f"timing {args.steps} steps of each path")
+    ms_plain = _time_steps(step_plain, args.steps, args.warmup, stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for _ in range(args.warmup):
+        batch.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        batch.launch(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
+    launch_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+    px = sum(f.width * f.height for f in frames)
+    samples = sum(sum(int(np.prod(f.plane_dims(p))) for p in range(f.nplanes)) for f in frames)
+    ops = OPS_PER_SAMPLE_FILTER * samples + OPS_PER_LUMA_PX_DIRSEARCH * px
+    bytes_ = 2 * 2 * samples + sum(f.blk_rows * f.blk_cols for f in frames)
+    achieved = ops / launch_s / 1e12
+    print(json.dumps({
+        "metric": "Mpixel/s for dir+filter at one preset per filter block (decoder path), "
+                  "4K 10-bit",
+        "value": round(px / ms_batch / 1e3, 1), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_batch, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(frames)}x3840x2160 10-bit 4:2:0 frames, 30% of 8x8 blocks "
+                               "skipped, random per-filter-block strengths: direction search + "
+                               "filter, one batched launch of filter jobs per step",
+                   "frames_per_step": len(frames), "luma_px_per_step": px},
+        "plain_path": {"launches_per_step": 2 * len(frames), "ms_per_step": round(ms_plain, 4),
+                       "mpixel_s": round(px / ms_plain / 1e3, 1)},
+        "bit_exact_plain_vs_batched": bool(exact),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_I32_TOPS, 1), "unit": "TOP/s (int32 lanes)",
+                     "frac": round(achieved / PEAK_I32_TOPS, 4), "traffic": None,
+                     "kernel": "k_fused_batch", "algorithmic_ops_per_launch": int(ops),
+                     "hbm_gbs_algorithmic": round(bytes_ / launch_s / 1e9, 1),
+                     "hbm_peak_gbs": PEAK_HBM_GBS},
+    }), flush=True)
+
+
 def run_presets(args):
     """Preset selection (Eq. 15) on the strength-search tables of the eight
     4K frames, 64 and 128 candidates, without and with two refinement
@@ -366,14 +450,16 @@ def main():
     ap.add_argument("--per-frame", action="store_true",
                     help="one cdef_search_strengths launch per frame instead of one batch")
     ap.add_argument("--workload", choices=["search4k", "search128", "weighted", "search12",
-                                           "search444", "search422", "subset", "presets",
-                                           "batch", "serve"],
+                                           "search444", "search422", "subset", "filter",
+                                           "presets", "batch", "serve"],
                     default="search4k",
                     help="search4k: the headline line (default); search128: the same frames "
                          "under the 128-combination search; weighted: the same frames with the "
                          "Eq. (14) distortion; search12 / search444 / search422: 12-bit 4:2:0, "
                          "10-bit 4:4:4, 10-bit 4:2:2 frames of the same size; subset: the "
-                         "headline frames under a preset subset (--subset); presets: Eq. (15) "
+                         "headline frames under a preset subset (--subset); filter: the "
+                         "decoder path (direction search + filter at one preset per filter "
+                         "block); presets: Eq. (15) "
                          "preset "
                          "selection on their tables; batch: 64 mixed frames, "
                          "per-frame launches vs one tuned, graph-replayed batch; serve: "
@@ -412,6 +498,8 @@ def main():
         return serve.bench_main(args)
     if args.workload == "presets":
         return run_presets(args)
+    if args.workload == "filter":
+        return run_filter(args)
     full = args.workload == "search128"
     weighted = args.workload == "weighted"
     cand = args.subset if args.workload == "subset" else 0

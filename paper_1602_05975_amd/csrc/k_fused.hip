@@ -824,6 +824,11 @@ __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int 
   const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
   const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
 
+  // Staging and the direction search run at raised wave priority: the
+  // other workgroups on the CU are in their task loops, and issuing this
+  // one's loads and wave-0 work first brings its four waves to the task
+  // loops sooner (measured: +5 % on 8 x 4K frames).
+  __builtin_amdgcn_s_setprio(2);
   stage_item<X>(sm, J, fby, fbx, tid, true);
   __syncthreads();
   if (wave == 0)
@@ -831,6 +836,7 @@ __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int 
   else
     skipped_sse<FULL>(sm, J, fby, fbx, tid - 64, 192, lane);
   __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
   const int n = sm.n;
 
   const Subset sub(SUB ? J.cand : 0u);
@@ -1100,6 +1106,7 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
   // products (exact powers of two)
   const double C1 = 6.25 * (double)(1 << (2 * c)), C2 = 312.5 * (double)(1 << (4 * c));
 
+  __builtin_amdgcn_s_setprio(2);  // as in the SSE search
   stage_item<true>(sm, J, fby, fbx, tid, true);
   for (int i = tid; i < 6 * 3 * 64; i += 256) (&sm.w.ustat[0][0][0])[i] = 0;
   __syncthreads();
@@ -1108,6 +1115,7 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
   else
     unit_stats(sm, J, fby, fbx, tid - 64, 192);
   __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
   const int n = sm.n;
   const int planes = search_planes(J);
 
@@ -1153,10 +1161,12 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
   const int wave = tid >> 6, lane = tid & 63;
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int c = J.bitdepth - 8, D = J.damping;
+  __builtin_amdgcn_s_setprio(2);  // as in the searches
   stage_item<X>(sm, J, fby, fbx, tid, false);
   __syncthreads();
   if (wave == 0) direction_search<false>(sm, J, fby, fbx, lane);
   __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
   const uint8_t *st = J.strengths + 4 * ((int64_t)fby * J.fbc + fbx);
   const Preset py = decode_preset(st[0], st[1]);
   const Preset pc = decode_preset(st[2], st[3]);
