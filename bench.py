@@ -361,7 +361,8 @@ def run_filter(args):
         "bit_exact_plain_vs_batched": bool(exact),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_I32_TOPS, 1), "unit": "TOP/s (int32 lanes)",
-                     "frac": round(achieved / PEAK_I32_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_I32_TOPS, 4),
+                     "traffic": load_traffic("k_fused_batch_filter"),
                      "kernel": "k_fused_batch", "algorithmic_ops_per_launch": int(ops),
                      "hbm_gbs_algorithmic": round(bytes_ / launch_s / 1e9, 1),
                      "hbm_peak_gbs": PEAK_HBM_GBS},
