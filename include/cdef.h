@@ -158,7 +158,9 @@ cdef_status cdef_search_strengths128(const cdef_frame *recon, const cdef_frame *
  *   candidates = S^(p) mask (bit S, 16 bits)
  *              | S^(s) index mask << 16 (bit i for S^(s) = 0, 1, 2, 4: 4 bits)
  *              | skip condition bit mask << 20 (bit k for the bit k: 2 bits).
- * The work shrinks with the subset (strengths outside it are not filtered).
+ * The work shrinks with the subset: at 8 and 10 bits, strengths outside it
+ * are not filtered (at 12 bits every preset is evaluated and the others are
+ * only marked).
  *   sse: the 64-combination table of cdef_search_strengths when the skip
  *        mask is 1, else the 128-combination table of
  *        cdef_search_strengths128; entries of presets outside the subset hold
@@ -179,8 +181,8 @@ void cdef_candidate_mask(uint32_t candidates, uint64_t mask[2]);
  * Eq. (14), instead of the SSE: for every filter block, plane and pair,
  *   sum over filtering units of
  *   (sigma_s^2 + sigma_d^2 + C1) / (2 sqrt(sigma_s^2 sigma_d^2 + C2)) ||s - d||^2,
- * where a filtering unit is an 8x8 luma block or its co-located 4x4 chroma
- * block (4:2:0), sigma^2 are population variances over the unit's in-frame
+ * where a filtering unit is an 8x8 luma block or its co-located chroma block
+ * (4x4 at 4:2:0, 8x8 at 4:4:4), sigma^2 are population variances over the unit's in-frame
  * pixels, and C1 = 6.25 * 4^(b-8), C2 = 312.5 * 16^(b-8).  The moments are
  * summed exactly in integers and the weight is evaluated in double
  * precision (relative difference to a direct double evaluation ~1e-15).
@@ -192,7 +194,7 @@ cdef_status cdef_search_weighted(const cdef_frame *recon, const cdef_frame *src,
                                  uint8_t *dir, int32_t *var, void *stream);
 
 /* ---- Batches ----------------------------------------------------------------
- * Many frames -- of any size, bit depth 8 or 10 and damping -- in one launch
+ * Many frames -- of any size, bit depth (8, 10, 12), layout and damping -- in one launch
  * over all their 64x64 filter blocks.  Each job is the strength search of
  * cdef_search_strengths, the full search of cdef_search_strengths128, the
  * weighted search of cdef_search_weighted, or the direction search + filter
@@ -232,8 +234,8 @@ typedef struct {
   int32_t nitems;     /* filter blocks over all jobs */
   int32_t variant;    /* launch variant 0..CDEF_BATCH_VARIANTS-1 (see below), 0 = default */
   int32_t flags;      /* set by cdef_batch_prepare (bit 0: a job needs the extended kernels
-                         -- weighted search, 12-bit or 4:4:4 -- which run at 2 waves per
-                         SIMD whatever the variant); keep */
+                         -- weighted search or 4:4:4 -- which run at 2 waves per SIMD
+                         whatever the variant); keep */
 } cdef_batch_plan;
 
 /* Host-side checks of one job, exactly those cdef_batch_prepare applies to each
