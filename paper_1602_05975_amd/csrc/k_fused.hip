@@ -53,6 +53,8 @@
 // and y - s below 2^12, strength sums below 2^13) but the source is no
 // longer folded into the rounding offset (16 (x - s) would not fit), and the
 // last two levels of the cross-lane sums run in 64 bits.
+#include <type_traits>
+
 #include "cdef_device.hpp"
 #include "cdef_launch.hpp"
 
@@ -684,7 +686,7 @@ __device__ __forceinline__ void skipped_sse(SmemT<X> &sm, const JobDesc &J, int 
 // luma (8x8 blocks, two per task, dealt round-robin to the four waves):
 // plane 0 is luma, planes 1-2 are 4:4:4 chroma.  For each task,
 // body(taps, A, B, hasB, packed source) consumes the pairs.
-template <bool X, bool B12, int CH, class Body>
+template <bool X, bool B12, int CH, bool SRC = true, class Body>
 __device__ __forceinline__ void block_tasks(SmemT<X> &sm, const JobDesc &J, int first, int count,
                                             int y0, int x0, int wave, int lane, Body &&body) {
   const int W = J.width, H = J.height;
@@ -704,7 +706,9 @@ __device__ __forceinline__ void block_tasks(SmemT<X> &sm, const JobDesc &J, int 
     const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
     const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
     const uint32_t xv = ((uint32_t)rt[bA] | ((uint32_t)rt[bB] << 16)) & vm;
-    const uint32_t sv = ((uint32_t)st[rA * 64 + cA] | ((uint32_t)st[rB * 64 + cB] << 16)) & vm;
+    // without a source (filter mode) y - s is y itself
+    const uint32_t sv =
+        SRC ? ((uint32_t)st[rA * 64 + cA] | ((uint32_t)st[rB * 64 + cB] << 16)) & vm : 0u;
     uint32_t tp[12];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -753,7 +757,7 @@ __device__ __forceinline__ void plane_tasks(SmemT<X> &sm, const JobDesc &J, int 
 // blocks per task (four per half); waves 0-1 take Cb, waves 2-3 Cr.  For
 // each task, body(taps, L, Hb, hasL, hasH, packed source) consumes the
 // pairs.
-template <bool X, bool B12, class Body>
+template <bool X, bool B12, bool SRC = true, class Body>
 __device__ __forceinline__ void chroma420_tasks(SmemT<X> &sm, const JobDesc &J, int first,
                                                 int count, int y0, int x0, int wave, int lane,
                                                 Body &&body) {
@@ -776,7 +780,8 @@ __device__ __forceinline__ void chroma420_tasks(SmemT<X> &sm, const JobDesc &J, 
     const int bL = (rL + 2) * kCS + kCC0 + cL, bH = (rH + 2) * kCS + kCC0 + cH;
     const int dL = sm.dir[L], dH = sm.dir[Hb];
     const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
-    const uint32_t sv = ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm;
+    const uint32_t sv =
+        SRC ? ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm : 0u;
     uint32_t tp[12];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -1153,9 +1158,14 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
 }
 
 // Filter mode: the block's own preset (Section 3.2 ranges, Section 4 skip
-// rules; bad values are masked / clamped so the kernel stays defined), one
-// pixel per lane.  4:2:2 chroma is copied.
-template <bool X>
+// rules; bad values are masked / clamped so the kernel stays defined).  The
+// filtered blocks (with residual, and under the skip condition bit the
+// skipped ones too; none when every in-frame block is skipped) go through
+// the searches' task loops, two samples per lane, with the source taken as 0
+// so that a pair's "y - s" is y; results land in the idle source tiles, and
+// every in-frame pixel is then copied out, filtered or not.  4:2:2 chroma is
+// copied.
+template <bool X, bool B12>
 __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
                                             int tid) {
   const int wave = tid >> 6, lane = tid & 63;
@@ -1164,27 +1174,101 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
   __builtin_amdgcn_s_setprio(2);  // as in the searches
   stage_item<X>(sm, J, fby, fbx, tid, false);
   __syncthreads();
-  if (wave == 0) direction_search<false>(sm, J, fby, fbx, lane);
+  if (wave == 0) direction_search<true>(sm, J, fby, fbx, lane);
   __syncthreads();
   __builtin_amdgcn_s_setprio(0);
   const uint8_t *st = J.strengths + 4 * ((int64_t)fby * J.fbc + fbx);
   const Preset py = decode_preset(st[0], st[1]);
   const Preset pc = decode_preset(st[2], st[3]);
-  const bool fb_skipped = sm.n == 0;  // no block with residual: not filtered
+  const int n = sm.n, nsk = sm.nsk;
+  const int ny = n == 0 ? 0 : n + (py.skipcond ? nsk : 0);
+  const int nc = n == 0 ? 0 : n + (pc.skipcond ? nsk : 0);
+  const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
+  const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
+  const int r8 = lane >> 3, col8 = lane & 7;
+
+  // luma: per-block adjusted primary strength (Eq. 13), its parity weights
+  // and damping (raised for 16..19), per 16-bit half
+  block_tasks<X, B12, 0, false>(
+      sm, J, 0, ny, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
+        const int aA = py.pri == 19 ? uniform(sm.adj19[A])
+                                    : (int)(uniform64(sm.adj[A]) >> (4 * py.pri)) & 15;
+        const int aB = py.pri == 19 ? uniform(sm.adj19[B])
+                                    : (int)(uniform64(sm.adj[B]) >> (4 * py.pri)) & 15;
+        const int DA = luma_damping(D, aA), DB = luma_damping(D, aB);
+        const uint32_t sp = ((uint32_t)aA << c) | ((uint32_t)aB << (16 + c));
+        const uint32_t sh = (uint32_t)(aA ? DA - floor_log2(aA) : 0) |
+                            ((uint32_t)(aB ? DB - floor_log2(aB) : 0) << 16);
+        const uint32_t w1 = ((aA & 1) ? 3u : 4u) | (((aB & 1) ? 3u : 4u) << 16);
+        const uint32_t w2 = ((aA & 1) ? 3u : 2u) | (((aB & 1) ? 3u : 2u) << 16);
+        u16x2 a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
+        const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
+        const int lq = py.sec ? floor_log2(py.sec) : 0;
+        const uint32_t qsh = (uint32_t)(py.sec ? DA - lq : 0) |
+                             ((uint32_t)(py.sec ? DB - lq : 0) << 16);
+        const s16x2 Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
+        const uint32_t y = __builtin_bit_cast(uint32_t, err_both<B12>(t, P, Q));
+        sm.sy[(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
+        if (hasB) sm.sy[(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] = (uint16_t)(y >> 16);
+      });
+
+  // chroma: one preset for both planes; damping max(D - 1, floor(log2 S^(p)))
+  const int Dc = pc.pri ? max(D - 1, floor_log2(pc.pri)) : D - 1;
+  const uint32_t csp = splat32((uint32_t)pc.pri << c);
+  const uint32_t csh = splat32((uint32_t)(pc.pri ? Dc - floor_log2(pc.pri) : 0));
+  const uint32_t cw1 = splat32((pc.pri & 1) ? 3u : 4u), cw2 = splat32((pc.pri & 1) ? 3u : 2u);
+  const uint32_t css = splat32((uint32_t)pc.sec << c);
+  const uint32_t cqsh = splat32((uint32_t)(pc.sec ? Dc - floor_log2(pc.sec) : 0));
+  auto chroma_y = [&](const Taps &t) {
+    u16x2 a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(csh);
+    const s16x2 P = group_sum(t, a, 0, csp, cw1, cw2);
+    const s16x2 Q = secondary(t, css, cqsh);
+    return __builtin_bit_cast(uint32_t, err_both<B12>(t, P, Q));
+  };
+  if (c420) {
+    const int p = wave >> 1, sub = lane >> 4, r4 = (lane >> 2) & 3, col4 = lane & 3;
+    (void)sub;
+    chroma420_tasks<X, B12, false>(
+        sm, J, 0, nc, y0, x0, wave, lane,
+        [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t) {
+          const uint32_t y = chroma_y(t);
+          if (hasL) sm.sc[p][(4 * (L >> 3) + r4) * 32 + 4 * (L & 7) + col4] = (uint16_t)y;
+          if (hasH)
+            sm.sc[p][(4 * (Hb >> 3) + r4) * 32 + 4 * (Hb & 7) + col4] = (uint16_t)(y >> 16);
+        });
+  }
+  if constexpr (X) {
+    if (c444) {
+      auto plane444 = [&](auto ch) {
+        constexpr int CH = decltype(ch)::value;
+        block_tasks<X, B12, CH, false>(
+            sm, J, 0, nc, y0, x0, wave, lane,
+            [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
+              const uint32_t y = chroma_y(t);
+              sm.sc[CH - 1][(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
+              if (hasB)
+                sm.sc[CH - 1][(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] =
+                    (uint16_t)(y >> 16);
+            });
+      };
+      plane444(std::integral_constant<int, 1>{});
+      plane444(std::integral_constant<int, 2>{});
+    }
+  }
+  __syncthreads();
+
+  // copy-out: filtered pixels from the result tiles, the rest unchanged
   for (int e = tid; e < 64 * 64; e += 256) {
     const int r = e >> 6, col = e & 63;
     if (y0 + r >= H || x0 + col >= W) continue;
     const int b = (r >> 3) * 8 + (col >> 3);
-    const int base = (r + 2) * kLS + kLC0 + col;
-    int y = sm.ry[base];
-    if (!fb_skipped && (!(sm.flag[b] & 2) || py.skipcond)) {
-      const int adj = adjust_strength(py.pri, sm.var[b]);  // Eq. (13)
-      const int Dl = luma_damping(D, adj);
-      y = filter_pixel(sm.ry, base, kLS, sm.dir[b], adj << c, adj ? Dl - floor_log2(adj) : 0,
-                       (adj & 1) ? 3 : 4, (adj & 1) ? 3 : 2, py.sec << c,
-                       py.sec ? Dl - floor_log2(py.sec) : 0);
-    }
-    J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] = (uint16_t)y;
+    const bool filt = n > 0 && (!(sm.flag[b] & 2) || py.skipcond);
+    J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] =
+        filt ? sm.sy[e] : sm.ry[(r + 2) * kLS + kLC0 + col];
   }
   if (J.nplanes != 3) return;
   if (J.layout == kLayout422) {
@@ -1198,22 +1282,15 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
     }
     return;
   }
-  const int Dc = pc.pri ? max(D - 1, floor_log2(pc.pri)) : D - 1;
-  const int ps = pc.pri << c, pshift = pc.pri ? Dc - floor_log2(pc.pri) : 0;
-  const int w1 = (pc.pri & 1) ? 3 : 4, w2 = (pc.pri & 1) ? 3 : 2;
-  const int ss = pc.sec << c, sshift = pc.sec ? Dc - floor_log2(pc.sec) : 0;
   if constexpr (X) {
-    if (J.layout == kLayout444) {
+    if (c444) {
       for (int e = tid; e < 2 * 64 * 64; e += 256) {
         const int p = e >> 12, r = (e >> 6) & 63, col = e & 63;
         if (y0 + r >= H || x0 + col >= W) continue;
         const int b = (r >> 3) * 8 + (col >> 3);
-        const int base = (r + 2) * kLS + kLC0 + col;
-        const bool filt = !fb_skipped && (!(sm.flag[b] & 2) || pc.skipcond);
-        const int y = filt ? filter_pixel(sm.rc[p], base, kLS, sm.dir[b], ps, pshift, w1, w2, ss,
-                                          sshift)
-                           : (int)sm.rc[p][base];
-        J.out[1 + p][(int64_t)(y0 + r) * J.ostride[1 + p] + x0 + col] = (uint16_t)y;
+        const bool filt = n > 0 && (!(sm.flag[b] & 2) || pc.skipcond);
+        J.out[1 + p][(int64_t)(y0 + r) * J.ostride[1 + p] + x0 + col] =
+            filt ? sm.sc[p][r * 64 + col] : sm.rc[p][(r + 2) * kLS + kLC0 + col];
       }
       return;
     }
@@ -1223,12 +1300,9 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
     const int p = e >> 10, r = (e >> 5) & 31, col = e & 31;
     if (cy0 + r >= ch || cx0 + col >= cw) continue;
     const int b = (r >> 2) * 8 + (col >> 2);
-    const int base = (r + 2) * kCS + kCC0 + col;
-    const bool filt = !fb_skipped && (!(sm.flag[b] & 2) || pc.skipcond);
-    const int y = filt ? filter_pixel(sm.rc[p], base, kCS, sm.dir[b], ps, pshift, w1, w2, ss,
-                                      sshift)
-                       : (int)sm.rc[p][base];
-    J.out[1 + p][(int64_t)(cy0 + r) * J.ostride[1 + p] + cx0 + col] = (uint16_t)y;
+    const bool filt = n > 0 && (!(sm.flag[b] & 2) || pc.skipcond);
+    J.out[1 + p][(int64_t)(cy0 + r) * J.ostride[1 + p] + cx0 + col] =
+        filt ? sm.sc[p][r * 32 + col] : sm.rc[p][(r + 2) * kCS + kCC0 + col];
   }
 }
 
@@ -1251,7 +1325,7 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
     else if (J.mode == kModeSearchFull)
       search_item<true, true, false>(sm, J, fby, fbx, tid);
     else
-      filter_item<X>(sm, J, fby, fbx, tid);
+      filter_item<X, true>(sm, J, fby, fbx, tid);
     return;
   }
   if (J.mode == kModeSearch) {
@@ -1265,7 +1339,7 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
     else
       search_item<true, false, false>(sm, J, fby, fbx, tid);
   } else {
-    filter_item<X>(sm, J, fby, fbx, tid);
+    filter_item<X, false>(sm, J, fby, fbx, tid);
   }
 }
 
