@@ -175,28 +175,23 @@ cdef_status cdef_find_dir(const cdef_frame *f, uint8_t *dir, int32_t *var, void 
 cdef_status cdef_filter_frame(const cdef_frame *in, const cdef_frame_out *out, const uint8_t *dir,
                               const int32_t *var, const uint8_t *skip8x8, int32_t damping,
                               const cdef_strength *fb, void *stream) {
-  FrameDesc d;
-  const cdef_status st = check_frame(in, &d);
+  if (!in || !out || !dir || !var || !fb) return CDEF_E_INVAL;
+  // the fused kernel's filter mode, with the caller's directions
+  cdef_job j;
+  memset(&j, 0, sizeof(j));
+  j.recon = *in;
+  j.out = *out;
+  j.skip8x8 = skip8x8;
+  j.fb = fb;
+  j.dir = const_cast<uint8_t *>(dir);
+  j.var = const_cast<int32_t *>(var);
+  j.damping = damping;
+  j.mode = CDEF_MODE_FILTER;
+  cdef::JobDesc d;
+  const cdef_status st = make_job(&j, &d);
   if (st != CDEF_OK) return st;
-  if (!out || !dir || !var || !fb) return CDEF_E_INVAL;
-  if (damping < 3 || damping > 6) return CDEF_E_INVAL;
-  uint16_t *outp[3] = {nullptr, nullptr, nullptr};
-  int64_t outs[3] = {0, 0, 0};
-  for (int p = 0; p < d.nplanes; ++p) {
-    int w, h;
-    plane_dims(in, p, &w, &h);
-    if (!out->plane[p] || out->stride[p] < w) return CDEF_E_INVAL;
-    cdef_frame o = *in;
-    o.stride[p] = out->stride[p];
-    for (int q = 0; q < d.nplanes; ++q)
-      if (ranges_overlap(out->plane[p], plane_bytes(&o, p), in->plane[q], plane_bytes(in, q)))
-        return CDEF_E_INVAL;
-    outp[p] = out->plane[p];
-    outs[p] = out->stride[p];
-  }
-  return from_hip(cdef::launch_filter(d, outp, outs, dir, var, skip8x8, damping,
-                                      reinterpret_cast<const uint8_t *>(fb),
-                                      (hipStream_t)stream));
+  d.flags |= cdef::kDirIn;
+  return from_hip(cdef::launch_fused_one(d, (hipStream_t)stream));
 }
 
 namespace {

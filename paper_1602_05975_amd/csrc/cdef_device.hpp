@@ -277,61 +277,4 @@ __device__ __forceinline__ void stage_rows16(uint16_t *lds, const uint16_t *plan
   }
 }
 
-// ---- One pixel of the filter, 32-bit lanes (plain path) -------------------
-// Eq. (7): f(diff, S, D) with k = D - floor(log2 S) given as `shift`; the
-// function is anti-symmetric, and S = 0 passes nothing.
-__device__ __forceinline__ int constrain(int diff, int s, int shift) {
-  const int a = abs(diff);
-  const int m = min(a, max(0, s - (a >> shift)));
-  return diff < 0 ? -m : m;
-}
-
-// Eq. (8)-(12) for the pixel at LDS index `base` of a tile with row stride
-// `ts`.  Strengths are scaled to the bit depth; shifts are D - floor(log2 S)
-// (ignored when the strength is 0).  Out-of-frame taps (kOutside) are
-// ignored and excluded from the clamp range.
-__device__ __forceinline__ int filter_pixel(const uint16_t *t, int base, int ts, int d, int ps,
-                                            int pshift, int w1, int w2, int ss, int sshift) {
-  const int x = t[base];
-  int sum = 0, lo = x, hi = x;
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int w = k == 0 ? w1 : w2;
-    const int o = tap_dr(d, k) * ts + tap_dc(d, k);
-    const int v0 = t[base + o], v1 = t[base - o];
-    if (v0 != kOutside) {
-      sum += w * constrain(v0 - x, ps, pshift);
-      lo = min(lo, v0);
-      hi = max(hi, v0);
-    }
-    if (v1 != kOutside) {
-      sum += w * constrain(v1 - x, ps, pshift);
-      lo = min(lo, v1);
-      hi = max(hi, v1);
-    }
-  }
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int d2 = h == 0 ? (d + 2) & 7 : (d + 6) & 7;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int w = k == 0 ? 2 : 1;
-      const int o = tap_dr(d2, k) * ts + tap_dc(d2, k);
-      const int v0 = t[base + o], v1 = t[base - o];
-      if (v0 != kOutside) {
-        sum += w * constrain(v0 - x, ss, sshift);
-        lo = min(lo, v0);
-        hi = max(hi, v0);
-      }
-      if (v1 != kOutside) {
-        sum += w * constrain(v1 - x, ss, sshift);
-        lo = min(lo, v1);
-        hi = max(hi, v1);
-      }
-    }
-  }
-  const int y = x + ((sum + 8 - (sum < 0 ? 1 : 0)) >> 4);
-  return min(hi, max(lo, y));
-}
-
 }  // namespace cdef

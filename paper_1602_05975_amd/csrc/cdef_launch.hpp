@@ -25,7 +25,9 @@ enum JobMode : int32_t {
   kModeSearchFull = 2,
   kModeSearchWeighted = 3
 };
-enum JobFlags : int32_t { kAligned16 = 1 };
+// kDirIn: filter mode takes dir / var as inputs (cdef_filter_frame) instead
+// of running the direction search and optionally writing them.
+enum JobFlags : int32_t { kAligned16 = 1, kDirIn = 2 };
 
 // One frame of work as the fused kernel reads it (kernel argument for a
 // single frame, or an element of a device-resident table for a batch).
@@ -38,22 +40,18 @@ struct JobDesc {
   const uint8_t *strengths;  // filter mode: [fbr][fbc][4]
   uint64_t *sse;           // search modes: [nplanes][fbr][fbc][64] (full: [..][2][64];
                            // weighted: double [..][64])
-  uint8_t *dir;            // optional
-  int32_t *var;            // optional
+  uint8_t *dir;            // optional outputs (inputs with kDirIn)
+  int32_t *var;
   int32_t rstride[3], sstride[3], ostride[3];
   int32_t width, height, bitdepth, damping, nplanes, mode;
   int32_t fbc, fbr, bcols, brows;
   int32_t item0;  // first work item (filter block) of this job in the batch
-  int32_t flags;  // bit 0: every plane's base and row pitch are 16-byte aligned
+  int32_t flags;  // JobFlags
   int32_t layout;
   uint32_t cand;  // searches: preset subset (S^(p) | S^(s) << 16 | skip bit << 20), 0 = all
 };
 
 hipError_t launch_find_dir(const FrameDesc &f, uint8_t *dir, int32_t *var, hipStream_t s);
-
-hipError_t launch_filter(const FrameDesc &in, uint16_t *const out[3], const int64_t out_stride[3],
-                         const uint8_t *dir, const int32_t *var, const uint8_t *skip, int damping,
-                         const uint8_t *strengths, hipStream_t s);
 
 // One frame, job descriptor passed by value.
 hipError_t launch_fused_one(const JobDesc &job, hipStream_t s);

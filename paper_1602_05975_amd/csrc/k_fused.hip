@@ -571,7 +571,11 @@ __device__ __forceinline__ void direction_search(SmemT<X> &sm, const JobDesc &J,
   const int c = J.bitdepth - 8;
   const bool in = sm.flag[b] & 1, sk = sm.flag[b] & 2;
   int d = 0, v = 0;
-  if (in) {
+  if (in && (J.flags & kDirIn)) {
+    // the caller's directions (masked to 0..7) and contrasts
+    d = J.dir[(int64_t)by * J.bcols + bx] & 7;
+    v = J.var[(int64_t)by * J.bcols + bx];
+  } else if (in) {
     const int bw = min(8, J.width - 8 * bx), bh = min(8, J.height - 8 * by);
     int x[64];
     const uint16_t *row0 = sm.ry + (2 + 8 * (b >> 3)) * kLS + kLC0 + 8 * (b & 7);

@@ -229,3 +229,31 @@ def test_maximum_frame_sizes(oracle, w, h):
     want = oracle.filter_frame(fr.recon, w, h, 10, od, ov, fr.skip, fr.damping, st)
     for p in range(3):
         assert (to_np_u16(outs[p]) == want[p]).all(), p
+
+
+@pytest.mark.parametrize("w,h,bd,layout", [(200, 136, 10, 1), (131, 67, 8, 0), (136, 72, 12, 3),
+                                           (67, 33, 10, 2), (426, 240, 12, 1)])
+def test_filter_frame_uses_caller_directions(oracle, w, h, bd, layout):
+    # cdef_filter_frame filters with the directions and contrasts it is given
+    # (a direction is taken modulo 8), not with ones it finds itself
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    fr = s.make_frame(w, h, bd, layout, 24000 + w + bd, skip_prob=0.3, damping=4)
+    rng = np.random.default_rng(24 + w)
+    d = rng.integers(0, 16, size=(fr.blk_rows, fr.blk_cols)).astype(np.uint8)
+    v = rng.integers(-5, 1 << 27, size=(fr.blk_rows, fr.blk_cols)).astype(np.int32)
+    v[rng.random(v.shape) < 0.2] = 0
+    st = s.random_presets(fr, 24100 + h)
+    print(f"filter with caller directions {w}x{h} {bd}-bit layout {layout}", flush=True)
+    f = gpu_frame(fr.recon, fr)
+    outs = cdef.filter_frame(f, torch.from_numpy(d).cuda(), torch.from_numpy(v).cuda(),
+                             torch.from_numpy(fr.skip).cuda(), fr.damping,
+                             torch.from_numpy(st).cuda())
+    torch.cuda.synchronize()
+    want = oracle.filter_frame(fr.recon, w, h, bd, d & 7, v, fr.skip, fr.damping, st,
+                               layout=layout)
+    for p in range(fr.nplanes):
+        got = to_np_u16(outs[p])
+        bad = np.argwhere(got != want[p])
+        assert bad.size == 0, (p, bad[:5])
