@@ -157,6 +157,12 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
     if (search) al = al && ((uintptr_t)o->src[p] & 15) == 0 && (o->sstride[p] & 7) == 0;
   }
   o->flags = al ? cdef::kAligned16 : 0;
+  if (j->mode == CDEF_MODE_FILTER) {
+    bool ao = true;
+    for (int p = 0; p < r.nplanes; ++p)
+      ao = ao && ((uintptr_t)o->out[p] & 15) == 0 && (o->ostride[p] & 7) == 0;
+    if (ao) o->flags |= cdef::kOut16;
+  }
   return CDEF_OK;
 }
 

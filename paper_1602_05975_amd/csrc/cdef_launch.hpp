@@ -27,7 +27,9 @@ enum JobMode : int32_t {
 };
 // kDirIn: filter mode takes dir / var as inputs (cdef_filter_frame) instead
 // of running the direction search and optionally writing them.
-enum JobFlags : int32_t { kAligned16 = 1, kDirIn = 2 };
+// kOut16: filter mode's output planes have 16-byte aligned bases and row
+// pitches.
+enum JobFlags : int32_t { kAligned16 = 1, kDirIn = 2, kOut16 = 4 };
 
 // One frame of work as the fused kernel reads it (kernel argument for a
 // single frame, or an element of a device-resident table for a batch).

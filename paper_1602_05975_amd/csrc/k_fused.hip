@@ -1265,14 +1265,28 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
   }
   __syncthreads();
 
-  // copy-out: filtered pixels from the result tiles, the rest unchanged
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int r = e >> 6, col = e & 63;
-    if (y0 + r >= H || x0 + col >= W) continue;
-    const int b = (r >> 3) * 8 + (col >> 3);
-    const bool filt = n > 0 && (!(sm.flag[b] & 2) || py.skipcond);
-    J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] =
-        filt ? sm.sy[e] : sm.ry[(r + 2) * kLS + kLC0 + col];
+  // copy-out: filtered pixels from the result tiles, the rest unchanged.
+  // Aligned outputs move a block row at a time (16 bytes; 8 for 4:2:0
+  // chroma): every sample of it shares the block's decision.
+  const bool out16 = J.flags & kOut16;
+  if (out16 && x0 + 64 <= W) {
+    for (int e = tid; e < 64 * 8; e += 256) {
+      const int r = e >> 3, q = e & 7;
+      if (y0 + r >= H) continue;
+      const bool filt = n > 0 && (!(sm.flag[(r >> 3) * 8 + q] & 2) || py.skipcond);
+      const uint4 v = filt ? *reinterpret_cast<const uint4 *>(&sm.sy[r * 64 + 8 * q])
+                           : *reinterpret_cast<const uint4 *>(&sm.ry[(r + 2) * kLS + kLC0 + 8 * q]);
+      *reinterpret_cast<uint4 *>(&J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + 8 * q]) = v;
+    }
+  } else {
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e >> 6, col = e & 63;
+      if (y0 + r >= H || x0 + col >= W) continue;
+      const int b = (r >> 3) * 8 + (col >> 3);
+      const bool filt = n > 0 && (!(sm.flag[b] & 2) || py.skipcond);
+      J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + col] =
+          filt ? sm.sy[e] : sm.ry[(r + 2) * kLS + kLC0 + col];
+    }
   }
   if (J.nplanes != 3) return;
   if (J.layout == kLayout422) {
@@ -1288,6 +1302,19 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
   }
   if constexpr (X) {
     if (c444) {
+      if (out16 && x0 + 64 <= W) {
+        for (int e = tid; e < 2 * 64 * 8; e += 256) {
+          const int p = e >> 9, r = (e >> 3) & 63, q = e & 7;
+          if (y0 + r >= H) continue;
+          const bool filt = n > 0 && (!(sm.flag[(r >> 3) * 8 + q] & 2) || pc.skipcond);
+          const uint4 v =
+              filt ? *reinterpret_cast<const uint4 *>(&sm.sc[p][r * 64 + 8 * q])
+                   : *reinterpret_cast<const uint4 *>(&sm.rc[p][(r + 2) * kLS + kLC0 + 8 * q]);
+          *reinterpret_cast<uint4 *>(
+              &J.out[1 + p][(int64_t)(y0 + r) * J.ostride[1 + p] + x0 + 8 * q]) = v;
+        }
+        return;
+      }
       for (int e = tid; e < 2 * 64 * 64; e += 256) {
         const int p = e >> 12, r = (e >> 6) & 63, col = e & 63;
         if (y0 + r >= H || x0 + col >= W) continue;
@@ -1300,6 +1327,18 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
     }
   }
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  if (out16 && cx0 + 32 <= cw) {
+    for (int e = tid; e < 2 * 32 * 8; e += 256) {
+      const int p = e >> 8, r = (e >> 3) & 31, q = e & 7;
+      if (cy0 + r >= ch) continue;
+      const bool filt = n > 0 && (!(sm.flag[(r >> 2) * 8 + q] & 2) || pc.skipcond);
+      const uint2 v = filt ? *reinterpret_cast<const uint2 *>(&sm.sc[p][r * 32 + 4 * q])
+                           : *reinterpret_cast<const uint2 *>(&sm.rc[p][(r + 2) * kCS + kCC0 + 4 * q]);
+      *reinterpret_cast<uint2 *>(
+          &J.out[1 + p][(int64_t)(cy0 + r) * J.ostride[1 + p] + cx0 + 4 * q]) = v;
+    }
+    return;
+  }
   for (int e = tid; e < 2 * 32 * 32; e += 256) {
     const int p = e >> 10, r = (e >> 5) & 31, col = e & 31;
     if (cy0 + r >= ch || cx0 + col >= cw) continue;

@@ -257,3 +257,35 @@ def test_filter_frame_uses_caller_directions(oracle, w, h, bd, layout):
         got = to_np_u16(outs[p])
         bad = np.argwhere(got != want[p])
         assert bad.size == 0, (p, bad[:5])
+
+
+@pytest.mark.parametrize("w,h,bd,layout", [(336, 200, 10, 1), (336, 200, 12, 3), (320, 136, 8, 0),
+                                           (384, 72, 10, 2)])
+def test_filter_aligned_outputs(oracle, w, h, bd, layout):
+    # Output rows 16-byte aligned (every plane's pitch a multiple of 8
+    # samples): the filter copies block rows out whole, except in the
+    # right-hand partial filter blocks; plain and batched against the oracle.
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    fr = s.make_frame(w, h, bd, layout, 25000 + w + bd, skip_prob=0.3, damping=5)
+    st = s.random_presets(fr, 25100 + h)
+    print(f"filter aligned {w}x{h} {bd}-bit layout {layout}", flush=True)
+    f = gpu_frame(fr.recon, fr)
+    assert all(p.stride(0) % 8 == 0 for p in f.planes[:fr.nplanes])
+    sk = torch.from_numpy(fr.skip).cuda()
+    stg = torch.from_numpy(st).cuda()
+    d, v = cdef.find_dir(f)
+    plain = cdef.filter_frame(f, d, v, sk, fr.damping, stg)
+    b = cdef.Batch()
+    fused = [torch.full_like(p, -1) for p in f.planes[:fr.nplanes]]
+    b.add_filter(f, fused, sk, fr.damping, stg)
+    b.prepare()
+    b.launch()
+    torch.cuda.synchronize()
+    od, ov = oracle.find_dir(fr.recon[0], bd)
+    want = oracle.filter_frame(fr.recon, w, h, bd, od, ov, fr.skip, fr.damping, st, layout=layout)
+    for p in range(fr.nplanes):
+        for name, got in (("plain", to_np_u16(plain[p])), ("batched", to_np_u16(fused[p]))):
+            bad = np.argwhere(got != want[p])
+            assert bad.size == 0, (name, p, bad[:5])
