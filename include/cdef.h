@@ -235,7 +235,9 @@ typedef struct {
   int32_t variant;    /* launch variant 0..CDEF_BATCH_VARIANTS-1 (see below), 0 = default */
   int32_t flags;      /* set by cdef_batch_prepare (bit 0: a job needs the extended kernels
                          -- weighted search or 4:4:4 -- which run at 2 waves per SIMD
-                         whatever the variant); keep */
+                         whatever the variant; bit 1: every job is a filter job, run by
+                         the filter-only kernels, to which the variant does not apply);
+                         keep */
 } cdef_batch_plan;
 
 /* Host-side checks of one job, exactly those cdef_batch_prepare applies to each

@@ -283,11 +283,12 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
                                       : (cdef::JobDesc *)malloc(need);
   if (!table) return CDEF_E_NOMEM;
   int64_t items = 0;
-  int32_t flags = 0;
+  int32_t flags = 2;
   cdef_status st = CDEF_OK;
   for (int32_t i = 0; i < njobs && st == CDEF_OK; ++i) {
     st = make_job(&jobs[i], &table[i]);
     if (st == CDEF_OK && cdef::job_needs_extended(table[i])) flags |= 1;
+    if (st == CDEF_OK && table[i].mode != CDEF_MODE_FILTER) flags &= ~2;
     if (st == CDEF_OK) {
       table[i].item0 = (int32_t)items;
       items += (int64_t)table[i].fbc * table[i].fbr;
@@ -316,7 +317,7 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
   if (plan->variant < 0 || plan->variant >= CDEF_BATCH_VARIANTS) return CDEF_E_INVAL;
   return from_hip(cdef::launch_fused_batch((const cdef::JobDesc *)plan->table, plan->njobs,
                                            plan->nitems, plan->variant, (plan->flags & 1) != 0,
-                                           (hipStream_t)stream));
+                                           (plan->flags & 2) != 0, (hipStream_t)stream));
 }
 
 size_t cdef_select_presets_workspace_bytes(void) { return cdef::preset_workspace_bytes(); }

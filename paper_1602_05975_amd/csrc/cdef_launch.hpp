@@ -60,9 +60,10 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s);
 
 // Many frames: `jobs` is a device array of njobs descriptors (item0 set),
 // nitems the total number of filter blocks.
-// extended: some job needs the extended kernels (12-bit, 4:4:4, weighted).
+// extended: some job needs the extended kernels (4:4:4, weighted);
+// filter_only: every job is a filter job (the filter-only kernels run it).
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              bool extended, hipStream_t s);
+                              bool extended, bool filter_only, hipStream_t s);
 bool job_needs_extended(const JobDesc &j);
 
 void fill_job_geometry(JobDesc &j);

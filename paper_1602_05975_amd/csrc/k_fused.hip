@@ -445,17 +445,29 @@ __device__ __forceinline__ int search_planes(const JobDesc &J) {
 }
 
 // LDS of one workgroup.  X (extended kernels): chroma tiles as large as
-// luma's for 4:4:4.
+// luma's for 4:4:4.  SmemCore: the tiles and per-block state every mode
+// uses (the filter-only kernels hold just this); SmemT adds the searches'
+// reduction buffers.
 template <bool X>
-struct SmemT {
+struct SmemCore {
   static constexpr int kCT = X ? 68 * kLS : 36 * kCS;  // chroma recon tile
   static constexpr int kCSrc = X ? 64 * 64 : 32 * 32;  // chroma source tile
   uint16_t ry[68 * kLS];
-  uint16_t sy[64 * 64];
+  uint16_t sy[64 * 64];  // searches: source; filter: filtered luma
   uint16_t rc[2][kCT];
-  uint16_t sc[2][kCSrc];
+  uint16_t sc[2][kCSrc];  // searches: source; filter: filtered chroma
   uint64_t adj[64];
   int32_t var[64];
+  int16_t coff[8][6];
+  uint8_t dir[64];
+  uint8_t list[64];   // blocks with residual, then (full search, filter) skipped blocks
+  uint8_t adj19[64];  // Eq. (13) applied to 19 (full search, filter)
+  uint8_t flag[64];   // bit 0: in frame, bit 1: skipped
+  int n, nsk;
+};
+
+template <bool X>
+struct SmemT : SmemCore<X> {
   uint64_t red[3][4][64];  // [plane][wave][pair]: blocks with residual
   union {
     uint64_t red2[3][4][64];  // the same over skipped blocks (full search)
@@ -470,12 +482,6 @@ struct SmemT {
   uint64_t skipsse[3];  // per plane: sum of (x - s)^2 over skipped blocks
   uint64_t allsse[3];   // the same over every in-frame pixel (full search)
   double skipw[3];      // Eq. (14) over skipped units, per plane
-  int16_t coff[8][6];
-  uint8_t dir[64];
-  uint8_t list[64];   // blocks with residual, then (full search) skipped blocks
-  uint8_t adj19[64];  // Eq. (13) applied to 19 (full search)
-  uint8_t flag[64];   // bit 0: in frame, bit 1: skipped
-  int n, nsk;
 };
 
 // Stage the recon tiles (all modes) and, for the searches, the source
@@ -483,7 +489,7 @@ struct SmemT {
 // (with the 16-byte-rounded halo) lie inside aligned planes take 16-byte
 // loads; the rest go sample by sample with the frame-edge sentinel.
 template <bool X>
-__device__ __forceinline__ void stage_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
+__device__ __forceinline__ void stage_item(SmemCore<X> &sm, const JobDesc &J, int fby, int fbx,
                                            int tid, bool search) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
@@ -554,17 +560,13 @@ __device__ __forceinline__ void stage_item(SmemT<X> &sm, const JobDesc &J, int f
     const bool sk = in && J.skip && J.skip[(int64_t)by * J.bcols + bx];
     sm.flag[tid] = (uint8_t)((in ? 1 : 0) | (sk ? 2 : 0));
   }
-  if (tid < 3) {
-    sm.skipsse[tid] = 0;
-    sm.allsse[tid] = 0;
-  }
 }
 
 // Algorithm 1 for the 64 luma blocks of the filter block, one per lane of
 // wave 0; Eq. (13) adjusted strengths; compaction of the blocks to filter
 // (the full search lists the skipped in-frame blocks after them).
 template <bool FULL, bool X>
-__device__ __forceinline__ void direction_search(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
+__device__ __forceinline__ void direction_search(SmemCore<X> &sm, const JobDesc &J, int fby, int fbx,
                                                  int lane) {
   const int b = lane;
   const int by = fby * 8 + (b >> 3), bx = fbx * 8 + (b & 7);
@@ -691,7 +693,7 @@ __device__ __forceinline__ void skipped_sse(SmemT<X> &sm, const JobDesc &J, int 
 // plane 0 is luma, planes 1-2 are 4:4:4 chroma.  For each task,
 // body(taps, A, B, hasB, packed source) consumes the pairs.
 template <bool X, bool B12, int CH, bool SRC = true, class Body>
-__device__ __forceinline__ void block_tasks(SmemT<X> &sm, const JobDesc &J, int first, int count,
+__device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, int first, int count,
                                             int y0, int x0, int wave, int lane, Body &&body) {
   const int W = J.width, H = J.height;
   const uint16_t *rt = CH == 0 ? sm.ry : sm.rc[CH - 1];
@@ -762,7 +764,7 @@ __device__ __forceinline__ void plane_tasks(SmemT<X> &sm, const JobDesc &J, int 
 // each task, body(taps, L, Hb, hasL, hasH, packed source) consumes the
 // pairs.
 template <bool X, bool B12, bool SRC = true, class Body>
-__device__ __forceinline__ void chroma420_tasks(SmemT<X> &sm, const JobDesc &J, int first,
+__device__ __forceinline__ void chroma420_tasks(SmemCore<X> &sm, const JobDesc &J, int first,
                                                 int count, int y0, int x0, int wave, int lane,
                                                 Body &&body) {
   const int W = J.width, H = J.height;
@@ -839,6 +841,10 @@ __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int 
   // loops sooner (measured: +5 % on 8 x 4K frames).
   __builtin_amdgcn_s_setprio(2);
   stage_item<X>(sm, J, fby, fbx, tid, true);
+  if (tid < 3) {
+    sm.skipsse[tid] = 0;
+    sm.allsse[tid] = 0;
+  }
   __syncthreads();
   if (wave == 0)
     direction_search<FULL>(sm, J, fby, fbx, lane);
@@ -1170,7 +1176,7 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
 // every in-frame pixel is then copied out, filtered or not.  4:2:2 chroma is
 // copied.
 template <bool X, bool B12>
-__device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
+__device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, int fby, int fbx,
                                             int tid) {
   const int wave = tid >> 6, lane = tid & 63;
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
@@ -1349,8 +1355,10 @@ __device__ __forceinline__ void filter_item(SmemT<X> &sm, const JobDesc &J, int 
   }
 }
 
-// X: the extended kernels (12-bit samples, 4:4:4, the weighted search).
-template <bool X>
+// X: the extended kernels (4:4:4, the weighted search).  FILTER: the kernel
+// also runs filter jobs (batches that mix them with searches; single filter
+// jobs and filter-only batches have kernels of their own).
+template <bool X, bool FILTER = true>
 __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int item, int tid) {
   const int fby = item / J.fbc, fbx = item - fby * J.fbc;
   if constexpr (X) {
@@ -1367,7 +1375,7 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
       search_item<false, true, false>(sm, J, fby, fbx, tid);
     else if (J.mode == kModeSearchFull)
       search_item<true, true, false>(sm, J, fby, fbx, tid);
-    else
+    else if constexpr (FILTER)
       filter_item<X, true>(sm, J, fby, fbx, tid);
     return;
   }
@@ -1381,17 +1389,17 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
       search_item<true, false, true>(sm, J, fby, fbx, tid);
     else
       search_item<true, false, false>(sm, J, fby, fbx, tid);
-  } else {
+  } else if constexpr (FILTER) {
     filter_item<X, false>(sm, J, fby, fbx, tid);
   }
 }
 
 }  // namespace
 
-// One frame; the descriptor is a kernel argument.
+// One search job; the descriptor is a kernel argument.
 __global__ __launch_bounds__(256, 3) void k_fused_one(const JobDesc J) {
   __shared__ __align__(16) SmemT<false> sm;
-  run_item<false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+  run_item<false, false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 // One frame on the extended kernel (2 waves per SIMD: 256 VGPRs).  The
@@ -1403,7 +1411,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_one_x(const JobDesc J) {
   (void)J;
   const uintptr_t args = reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr());
   const JobDesc *__restrict__ jp = reinterpret_cast<const JobDesc *>(args);
-  run_item<true>(sm, *jp, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+  run_item<true, false>(sm, *jp, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 // A batch: descriptors in device memory, items numbered across jobs.
@@ -1426,6 +1434,46 @@ __global__ __launch_bounds__(256, OCC) void k_fused_batch(const JobDesc *__restr
   run_item<X>(sm, J, item - J.item0, threadIdx.x);
 }
 
+// Filter-only kernels: the LDS holds just the tiles and per-block state
+// (31 KB without the 4:4:4 chroma tiles) and the code just the filter mode.
+// The direction search's registers keep them at 3 waves per SIMD.
+template <bool X>
+__device__ __forceinline__ void filter_run(SmemCore<X> &sm, const JobDesc &J, int item,
+                                           int tid) {
+  const int fby = item / J.fbc, fbx = item - fby * J.fbc;
+  if (J.bitdepth == 12)
+    filter_item<X, true>(sm, J, fby, fbx, tid);
+  else
+    filter_item<X, false>(sm, J, fby, fbx, tid);
+}
+
+__global__ __launch_bounds__(256, 3) void k_filter_one(const JobDesc J) {
+  __shared__ __align__(16) SmemCore<false> sm;
+  filter_run<false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+}
+
+__global__ __launch_bounds__(256, 2) void k_filter_one_x(const JobDesc J) {
+  __shared__ __align__(16) SmemCore<true> sm;
+  filter_run<true>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+}
+
+template <bool X>
+__global__ __launch_bounds__(256, X ? 2 : 3) void k_filter_batch(const JobDesc *__restrict__ jobs,
+                                                                 int njobs) {
+  __shared__ __align__(16) SmemCore<X> sm;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  int lo = 0, hi = njobs - 1;  // last job with item0 <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item0 <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const JobDesc &J = jobs[lo];
+  filter_run<X>(sm, J, item - J.item0, threadIdx.x);
+}
+
 void fill_job_geometry(JobDesc &j) {
   j.bcols = (j.width + 7) / 8;
   j.brows = (j.height + 7) / 8;
@@ -1439,6 +1487,13 @@ bool job_needs_extended(const JobDesc &j) {
 
 hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
   const int grid = job.fbc * job.fbr;
+  if (job.mode == kModeFilter) {
+    if (job_needs_extended(job))
+      hipLaunchKernelGGL(k_filter_one_x, dim3(grid), dim3(256), 0, s, job);
+    else
+      hipLaunchKernelGGL(k_filter_one, dim3(grid), dim3(256), 0, s, job);
+    return hipGetLastError();
+  }
   if (job_needs_extended(job))
     hipLaunchKernelGGL(k_fused_one_x, dim3(grid), dim3(256), 0, s, job);
   else
@@ -1447,8 +1502,15 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
 }
 
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              bool extended, hipStream_t s) {
+                              bool extended, bool filter_only, hipStream_t s) {
   const dim3 g(nitems), b(256);
+  if (filter_only) {  // the variant does not apply
+    if (extended)
+      hipLaunchKernelGGL((k_filter_batch<true>), g, b, 0, s, jobs, njobs);
+    else
+      hipLaunchKernelGGL((k_filter_batch<false>), g, b, 0, s, jobs, njobs);
+    return hipGetLastError();
+  }
   if (extended) {  // 2 waves per SIMD; the variant picks the block order
     if (variant == 0 || variant == 1)
       hipLaunchKernelGGL((k_fused_batch<2, true, true>), g, b, 0, s, jobs, njobs);
