@@ -1,0 +1,46 @@
+"""Register budget of the gfx950 kernels, from the compiler's resource
+remarks that the build records: the hot kernels keep their occupancy and
+spill at most a few VGPRs (on cold paths such as edge-block direction
+searches).  A spill in a task loop costs far more than it looks: one such
+regression once cut the per-frame search by a fifth."""
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RES = os.path.join(ROOT, "paper_1602_05975_amd", "_build", "kernel_resources.json")
+
+# mangled-name fragment -> (waves per SIMD, max spilled VGPRs)
+BUDGET = {
+    "k_fused_batchILi3ELb1ELb0E": (3, 8),   # the headline kernel
+    "k_fused_batchILi3ELb0ELb0E": (3, 8),
+    "k_fused_batchILi2ELb1ELb1E": (2, 8),   # weighted search, 4:4:4
+    "k_fused_batchILi2ELb0ELb1E": (2, 8),
+    "k_fused_oneE": (3, 8),
+    "k_fused_one_xE": (2, 8),
+    "k_filter_oneE": (3, 8),
+    "k_filter_one_xE": (2, 8),
+    "k_filter_batchILb0E": (3, 8),
+    "k_filter_batchILb1E": (2, 8),
+    "k_preset_coop": (None, 0),
+}
+
+
+@pytest.fixture(scope="module")
+def resources():
+    if not os.path.exists(RES):
+        pytest.skip("library not built here (run __graft_entry__.build())")
+    with open(RES) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("frag", sorted(BUDGET))
+def test_kernel_register_budget(resources, frag):
+    occ, max_spill = BUDGET[frag]
+    hits = {k: v for k, v in resources.items() if frag in k}
+    assert hits, f"no kernel matching {frag}"
+    for name, r in hits.items():
+        assert r["VGPRs Spill"] <= max_spill, (name, r)
+        if occ is not None:
+            assert r["Occupancy"] >= occ, (name, r)
