@@ -363,8 +363,8 @@ def run_filter(args):
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_PACKED_I16_TOPS, 1), "unit": "TOP/s",
                      "frac": round(achieved / PEAK_PACKED_I16_TOPS, 4),
-                     "traffic": load_traffic("k_fused_batch_filter"),
-                     "kernel": "k_fused_batch", "algorithmic_ops_per_launch": int(ops),
+                     "traffic": load_traffic("k_filter_batch"),
+                     "kernel": "k_filter_batch", "algorithmic_ops_per_launch": int(ops),
                      "hbm_gbs_algorithmic": round(bytes_ / launch_s / 1e9, 1),
                      "hbm_peak_gbs": PEAK_HBM_GBS},
     }), flush=True)
