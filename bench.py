@@ -225,7 +225,7 @@ def run_batching(args):
     import torch
     from paper_1602_05975_amd import cdef, synth, tune
     log("generating the 64-frame mixed batch")
-    frames = synth.config3(64)
+    frames = synth.mixed_frames(64)
     dev = torch.device("cuda:0")
     jobs = _device_search_jobs(frames, dev)
     stream = torch.cuda.current_stream()
@@ -299,7 +299,7 @@ def run_filter(args):
     import torch
     from paper_1602_05975_amd import cdef, synth
     log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
-    frames = synth.config2(args.frames)
+    frames = synth.uhd4k_frames(args.frames)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     jobs = []
@@ -379,7 +379,7 @@ def run_presets(args):
     from paper_1602_05975_amd import cdef, synth
     from oracle import oracle
     log(f"generating {args.frames} synthetic 3840x2160 10-bit 4:2:0 frames")
-    frames = synth.config2(args.frames)
+    frames = synth.uhd4k_frames(args.frames)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     tables = {64: [], 128: []}
@@ -476,7 +476,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(frames shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(frames are independent: a batch shards across GPUs by frame with no exchange)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -512,9 +513,9 @@ def main():
 
     log(f"generating {args.frames} synthetic 3840x2160 {bd}-bit {lname} frames")
     if (bd, layout) == (10, 1):
-        frames = synth.config2(args.frames)
+        frames = synth.uhd4k_frames(args.frames)
     else:
-        frames = [synth.make_frame(3840, 2160, bd, layout, synth.config_seed(2, f),
+        frames = [synth.make_frame(3840, 2160, bd, layout, synth.workload_seed(WL_4K, f),
                                    skip_prob=0.3, damping=3) for f in range(args.frames)]
     ops = sum(frame_work(f, full, weighted, cand)[0] for f in frames)
     algo_bytes = sum(frame_work(f, full, weighted, cand)[1] for f in frames)

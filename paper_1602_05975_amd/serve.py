@@ -340,7 +340,7 @@ def make_request_pool(n_frames: int = 20, seed: int = 4):
     pool = []
     params = synth.mixed_frame_params(n_frames, 4)
     for i, (w, h, bd, D) in enumerate(params):
-        fr = synth.make_frame(w, h, bd, synth.LAYOUT_420, synth.config_seed(4, i), damping=D)
+        fr = synth.make_frame(w, h, bd, synth.LAYOUT_420, synth.workload_seed(synth.WL_SERVE, i), damping=D)
         rec = cdef.Frame.from_numpy(fr.recon, w, h, bd, fr.layout)
         src = cdef.Frame.from_numpy(fr.src, w, h, bd, fr.layout)
         st = torch.from_numpy(synth.random_strengths(fr, 70 + i)).cuda()

@@ -49,8 +49,12 @@ def chroma_shift(layout: int):
 MIXED_RESOLUTIONS = [(426, 240), (640, 360), (1280, 720), (1920, 1080), (3840, 2160)]
 
 
-def config_seed(config: int, frame: int) -> int:
-    return SEED_BASE + 1000 * config + frame
+# Seed streams of the synthetic workloads.
+WL_CIF, WL_1080P, WL_4K, WL_MIXED, WL_SERVE = 0, 1, 2, 3, 4
+
+
+def workload_seed(workload: int, frame: int) -> int:
+    return SEED_BASE + 1000 * workload + frame
 
 
 @dataclasses.dataclass
@@ -210,25 +214,25 @@ def random_presets(frame: Frame, seed: int, p_skipcond: float = 0.5,
     return out
 
 
-def config0() -> Frame:
+def cif_luma() -> Frame:
     """352x288 8-bit luma, filtered with (pri 4, sec 2) and damping 5."""
-    return make_frame(352, 288, 8, LAYOUT_400, config_seed(0, 0), damping=5)
+    return make_frame(352, 288, 8, LAYOUT_400, workload_seed(WL_CIF, 0), damping=5)
 
 
-def config1() -> Frame:
+def hd1080_frame() -> Frame:
     """One 1920x1080 10-bit 4:2:0 frame for the full strength search (damping 3)."""
-    return make_frame(1920, 1080, 10, LAYOUT_420, config_seed(1, 0), damping=3)
+    return make_frame(1920, 1080, 10, LAYOUT_420, workload_seed(WL_1080P, 0), damping=3)
 
 
-def config2(nframes: int = 8) -> List[Frame]:
+def uhd4k_frames(nframes: int = 8) -> List[Frame]:
     """Eight 3840x2160 10-bit 4:2:0 frames with 30% of 8x8 blocks skipped."""
-    return [make_frame(3840, 2160, 10, LAYOUT_420, config_seed(2, f), skip_prob=0.3, damping=3)
+    return [make_frame(3840, 2160, 10, LAYOUT_420, workload_seed(WL_4K, f), skip_prob=0.3, damping=3)
             for f in range(nframes)]
 
 
-def mixed_frame_params(n: int, config: int = 3):
+def mixed_frame_params(n: int, workload: int = WL_MIXED):
     """Resolution, bit depth and damping of each frame of an uneven batch."""
-    rng = np.random.Generator(np.random.PCG64([config_seed(config, 0), 99]))
+    rng = np.random.Generator(np.random.PCG64([workload_seed(workload, 0), 99]))
     out = []
     for _ in range(n):
         w, h = MIXED_RESOLUTIONS[int(rng.integers(0, len(MIXED_RESOLUTIONS)))]
@@ -238,7 +242,7 @@ def mixed_frame_params(n: int, config: int = 3):
     return out
 
 
-def config3(nframes: int = 64) -> List[Frame]:
+def mixed_frames(nframes: int = 64) -> List[Frame]:
     """An uneven batch of mixed resolution and bit depth frames."""
-    return [make_frame(w, h, bd, LAYOUT_420, config_seed(3, i), damping=d)
-            for i, (w, h, bd, d) in enumerate(mixed_frame_params(nframes, 3))]
+    return [make_frame(w, h, bd, LAYOUT_420, workload_seed(WL_MIXED, i), damping=d)
+            for i, (w, h, bd, d) in enumerate(mixed_frame_params(nframes, WL_MIXED))]

@@ -98,13 +98,13 @@ def test_mixed_batch_matches_per_frame_and_oracle(oracle):
         assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
 
 
-def test_config3_batch_matches_per_frame_launches(oracle):
+def test_mixed_batch_matches_per_frame_launches(oracle):
     # 64 frames, resolutions from 426x240 to 3840x2160, 8- and 10-bit, damping
     # 3..6, full search: one launch vs 64 cdef_search_strengths launches.
     import torch
     from paper_1602_05975_amd import cdef
     s = _synth()
-    frames = s.config3(64)
+    frames = s.mixed_frames(64)
     b = cdef.Batch()
     res, ins = [], []
     for fr in frames:
@@ -114,7 +114,7 @@ def test_config3_batch_matches_per_frame_launches(oracle):
         res.append((sse, d, v))
         ins.append((rec, src))
     b.prepare()
-    print(f"config-3 batch: {b.nitems} filter blocks", flush=True)
+    print(f"mixed 64-frame batch: {b.nitems} filter blocks", flush=True)
     b.launch()
     torch.cuda.synchronize()
     rng = np.random.default_rng(3)

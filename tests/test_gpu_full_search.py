@@ -122,19 +122,19 @@ def test_search128_all_skipped(oracle):
             assert (sse[p, 0, bx] == sse[p, 0, bx, 0, 0, 0]).all()
 
 
-def test_search128_config1_sampled(oracle):
+def test_search128_1080p_sampled(oracle):
     # 1920x1080 10-bit 4:2:0 with 30% skipped blocks: 40 of the 510 filter
     # blocks (edges, corners and a spread of interior ones) checked entry by
     # entry, the rest through the half that equals the 64-combination search.
     s = _synth()
-    base = s.config1()
+    base = s.hd1080_frame()
     fr = s.make_frame(base.width, base.height, 10, s.LAYOUT_420, base.seed, skip_prob=0.3,
                       damping=3)
     rng = np.random.default_rng(46000)
     fbs = {(0, 0), (0, 29), (16, 0), (16, 29), (8, 15)}
     while len(fbs) < 40:
         fbs.add((int(rng.integers(0, 17)), int(rng.integers(0, 30))))
-    print("search128 config1 sampled", flush=True)
+    print("search128 1920x1080 sampled", flush=True)
     sse = _compare_full(oracle, fr, fbs=sorted(fbs))
     half, _, _ = gpu_search(fr)
     assert (sse[:, :, :, 0] == half).all()

@@ -62,13 +62,13 @@ def _filter_case(oracle, fr, strengths, skip):
         assert bad.size == 0, (p, bad[:5], got[tuple(bad[0])], ref[p][tuple(bad[0])])
 
 
-def test_filter_config0(oracle):
+def test_filter_cif_luma(oracle):
     # 352x288 8-bit luma, every filter block at (pri 4, sec 2), damping 5.
     s = _synth()
-    fr = s.config0()
+    fr = s.cif_luma()
     st = np.zeros(fr.skip.shape[:0] + (fr.fb_rows, fr.fb_cols, 4), np.uint8)
     st[..., 0], st[..., 1] = 4, 2
-    print("filter config0", flush=True)
+    print("filter 352x288 luma", flush=True)
     _filter_case(oracle, fr, st, None)
 
 
@@ -131,30 +131,30 @@ def test_search_all_skipped(oracle):
     _compare_search(oracle, fr)
 
 
-def test_search_config1_full(oracle):
+def test_search_1080p_full(oracle):
     # 1920x1080 10-bit 4:2:0, damping 3, no skip: all 97,920 SSEs.
     s = _synth()
-    fr = s.config1()
-    print("search config1", flush=True)
+    fr = s.hd1080_frame()
+    print("search 1920x1080", flush=True)
     _compare_search(oracle, fr, skip=False)
 
 
-def test_search_config2_sampled(oracle):
+def test_search_4k_sampled(oracle):
     # 3840x2160 10-bit 4:2:0 with 30 % skipped blocks, one frame per launch as
     # the benchmark runs it; filter blocks sampled (every edge block plus a
     # seeded random set), directions compared everywhere.
     s = _synth()
-    frames = s.config2(2)
+    frames = s.uhd4k_frames(2)
     rng = np.random.default_rng(2)
     for fr in frames:
         fbr, fbc = fr.fb_rows, fr.fb_cols
         fbs = {(fbr - 1, bx) for bx in range(0, fbc, 7)} | {(by, fbc - 1) for by in range(fbr)}
         fbs |= {(int(rng.integers(0, fbr)), int(rng.integers(0, fbc))) for _ in range(40)}
-        print(f"search config2 seed {fr.seed}", flush=True)
+        print(f"search 3840x2160 seed {fr.seed}", flush=True)
         _compare_search(oracle, fr, fbs=sorted(fbs))
 
 
-def test_search_config2_batched_as_benchmarked(oracle):
+def test_search_4k_batched_as_benchmarked(oracle):
     # The benchmarked launch: the eight 3840x2160 frames in one batch with the
     # default plan.  Every entry equals the one-frame launches; filter blocks
     # of every frame (its edges and a seeded random set) equal the oracle.
@@ -162,7 +162,7 @@ def test_search_config2_batched_as_benchmarked(oracle):
     from helpers import ORACLE_THREADS
     from paper_1602_05975_amd import cdef
     s = _synth()
-    frames = s.config2(8)
+    frames = s.uhd4k_frames(8)
     b = cdef.Batch()
     outs = []
     for fr in frames:
@@ -175,7 +175,7 @@ def test_search_config2_batched_as_benchmarked(oracle):
         outs.append((rec, src, sk, t, d, v))
     b.prepare()
     assert b.plan.variant == 0 and not (b.plan.flags & 1)
-    print("search config2: 8 frames in one batched launch", flush=True)
+    print("search 8 x 3840x2160 in one batched launch", flush=True)
     b.launch()
     torch.cuda.synchronize()
     rng = np.random.default_rng(22)

@@ -64,7 +64,7 @@ def test_on_searched_frame(oracle):
     # the table the strength search produces for a 1080p 10-bit 4:2:0 frame
     from helpers import gpu_search
     from paper_1602_05975_amd import synth
-    sse, _, _ = gpu_search(synth.config1())
+    sse, _, _ = gpu_search(synth.hd1080_frame())
     for lam in (0.0, 2e3, 2e4, 2e5):
         for refine in (0, 4):
             _compare(sse, lam, refine, oracle)

@@ -95,16 +95,16 @@ def test_weighted_all_skipped(oracle):
         assert (dist[p] == dist[p, :, :, :1, :1]).all()
 
 
-def test_weighted_config1_sampled(oracle):
+def test_weighted_1080p_sampled(oracle):
     s = _synth()
-    base = s.config1()
+    base = s.hd1080_frame()
     fr = s.make_frame(base.width, base.height, 10, s.LAYOUT_420, base.seed, skip_prob=0.3,
                       damping=3)
     rng = np.random.default_rng(64000)
     fbs = {(0, 0), (0, 29), (16, 0), (16, 29), (8, 15)}
     while len(fbs) < 40:
         fbs.add((int(rng.integers(0, 17)), int(rng.integers(0, 30))))
-    print("weighted config1 sampled", flush=True)
+    print("weighted 1920x1080 sampled", flush=True)
     _compare(oracle, fr, fbs=sorted(fbs))
 
 
