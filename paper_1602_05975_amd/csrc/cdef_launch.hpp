@@ -66,6 +66,21 @@ hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int va
                               bool extended, bool filter_only, hipStream_t s);
 bool job_needs_extended(const JobDesc &j);
 
+// The kernels behind launch_fused_one / launch_fused_batch, built in sets of
+// one translation unit each.  Batch kernels: base3 / base2 = base LDS layout
+// at 3 / 2 waves per SIMD, ext = extended layout; _xcd = XCD-contiguous
+// filter-block order, _seq = plain order.
+hipError_t launch_one_ext(const JobDesc &job, hipStream_t s);
+hipError_t launch_filter_one(const JobDesc &job, bool extended, hipStream_t s);
+hipError_t launch_filter_batch(bool extended, const JobDesc *jobs, int njobs, int nitems,
+                               hipStream_t s);
+hipError_t launch_batch_base3_xcd(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
+hipError_t launch_batch_base3_seq(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
+hipError_t launch_batch_base2_xcd(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
+hipError_t launch_batch_base2_seq(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
+hipError_t launch_batch_ext_xcd(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
+hipError_t launch_batch_ext_seq(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
+
 void fill_job_geometry(JobDesc &j);
 
 // Result of the preset selection; same layout as cdef_preset_result.

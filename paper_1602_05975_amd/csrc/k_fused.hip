@@ -58,6 +58,14 @@
 #include "cdef_device.hpp"
 #include "cdef_launch.hpp"
 
+// The kernels are built in sets, one translation unit of this source per
+// set (CDEF_KSET = 0..6) so that they compile in parallel; without
+// CDEF_KSET every set is built into one object.
+#ifndef CDEF_KSET
+#define CDEF_KSET -1
+#endif
+#define CDEF_IN_KSET(n) (CDEF_KSET < 0 || CDEF_KSET == (n))
+
 namespace cdef {
 
 namespace {
@@ -1397,21 +1405,45 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
 }  // namespace
 
 // One search job; the descriptor is a kernel argument.
+#if CDEF_IN_KSET(0)
 __global__ __launch_bounds__(256, 3) void k_fused_one(const JobDesc J) {
   __shared__ __align__(16) SmemT<false> sm;
   run_item<false, false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
+#endif
 
 // One frame on the extended kernel (2 waves per SIMD: 256 VGPRs).  The
 // descriptor is read through a global-memory view of the argument segment:
 // as with the batch kernel's table, its fields are then reloaded where used
 // instead of being held in registers for the whole kernel.
+#if CDEF_IN_KSET(1)
 __global__ __launch_bounds__(256, 2) void k_fused_one_x(const JobDesc J) {
   __shared__ __align__(16) SmemT<true> sm;
   (void)J;
   const uintptr_t args = reinterpret_cast<uintptr_t>(__builtin_amdgcn_kernarg_segment_ptr());
   const JobDesc *__restrict__ jp = reinterpret_cast<const JobDesc *>(args);
   run_item<true, false>(sm, *jp, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
+}
+
+hipError_t launch_one_ext(const JobDesc &job, hipStream_t s) {
+  hipLaunchKernelGGL(k_fused_one_x, dim3(job.fbc * job.fbr), dim3(256), 0, s, job);
+  return hipGetLastError();
+}
+#endif
+
+// Index of the job that holds batch item `item`: the last job with
+// item0 <= item.
+__device__ __forceinline__ int job_of_item(const JobDesc *__restrict__ jobs, int njobs,
+                                           int item) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item0 <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 // A batch: descriptors in device memory, items numbered across jobs.
@@ -1422,18 +1454,35 @@ __global__ __launch_bounds__(256, OCC) void k_fused_batch(const JobDesc *__restr
                                                           int njobs) {
   __shared__ __align__(16) SmemT<X> sm;
   const int item = XCD ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  int lo = 0, hi = njobs - 1;  // last job with item0 <= item
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].item0 <= item)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const JobDesc &J = jobs[lo];
+  const JobDesc &J = jobs[job_of_item(jobs, njobs, item)];
   run_item<X>(sm, J, item - J.item0, threadIdx.x);
 }
 
+// One launcher per instantiation; the two orders of a set may sit in
+// different translation units.
+#define CDEF_BATCH_LAUNCHER(NAME, OCC, XCD, X)                                          \
+  hipError_t NAME(const JobDesc *jobs, int njobs, int nitems, hipStream_t s) {      \
+    hipLaunchKernelGGL((k_fused_batch<OCC, XCD, X>), dim3(nitems), dim3(256), 0, s, \
+                       jobs, njobs);                                               \
+    return hipGetLastError();                                                      \
+  }
+#if CDEF_IN_KSET(2)
+CDEF_BATCH_LAUNCHER(launch_batch_base3_xcd, 3, true, false)
+CDEF_BATCH_LAUNCHER(launch_batch_base3_seq, 3, false, false)
+#endif
+#if CDEF_IN_KSET(3)
+CDEF_BATCH_LAUNCHER(launch_batch_base2_xcd, 2, true, false)
+CDEF_BATCH_LAUNCHER(launch_batch_base2_seq, 2, false, false)
+#endif
+#if CDEF_IN_KSET(4)
+CDEF_BATCH_LAUNCHER(launch_batch_ext_xcd, 2, true, true)
+#endif
+#if CDEF_IN_KSET(6)
+CDEF_BATCH_LAUNCHER(launch_batch_ext_seq, 2, false, true)
+#endif
+#undef CDEF_BATCH_LAUNCHER
+
+#if CDEF_IN_KSET(5)
 // Filter-only kernels: the LDS holds just the tiles and per-block state
 // (31 KB without the 4:4:4 chroma tiles) and the code just the filter mode.
 // The direction search's registers keep them at 3 waves per SIMD.
@@ -1462,18 +1511,31 @@ __global__ __launch_bounds__(256, X ? 2 : 3) void k_filter_batch(const JobDesc *
                                                                  int njobs) {
   __shared__ __align__(16) SmemCore<X> sm;
   const int item = xcd_item(blockIdx.x, gridDim.x);
-  int lo = 0, hi = njobs - 1;  // last job with item0 <= item
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].item0 <= item)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const JobDesc &J = jobs[lo];
+  const JobDesc &J = jobs[job_of_item(jobs, njobs, item)];
   filter_run<X>(sm, J, item - J.item0, threadIdx.x);
 }
 
+hipError_t launch_filter_one(const JobDesc &job, bool extended, hipStream_t s) {
+  const dim3 g(job.fbc * job.fbr), b(256);
+  if (extended)
+    hipLaunchKernelGGL(k_filter_one_x, g, b, 0, s, job);
+  else
+    hipLaunchKernelGGL(k_filter_one, g, b, 0, s, job);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_batch(bool extended, const JobDesc *jobs, int njobs, int nitems,
+                               hipStream_t s) {
+  const dim3 g(nitems), b(256);
+  if (extended)
+    hipLaunchKernelGGL((k_filter_batch<true>), g, b, 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL((k_filter_batch<false>), g, b, 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+#endif
+
+#if CDEF_IN_KSET(0)
 void fill_job_geometry(JobDesc &j) {
   j.bcols = (j.width + 7) / 8;
   j.brows = (j.height + 7) / 8;
@@ -1486,45 +1548,28 @@ bool job_needs_extended(const JobDesc &j) {
 }
 
 hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
-  const int grid = job.fbc * job.fbr;
-  if (job.mode == kModeFilter) {
-    if (job_needs_extended(job))
-      hipLaunchKernelGGL(k_filter_one_x, dim3(grid), dim3(256), 0, s, job);
-    else
-      hipLaunchKernelGGL(k_filter_one, dim3(grid), dim3(256), 0, s, job);
-    return hipGetLastError();
-  }
-  if (job_needs_extended(job))
-    hipLaunchKernelGGL(k_fused_one_x, dim3(grid), dim3(256), 0, s, job);
-  else
-    hipLaunchKernelGGL(k_fused_one, dim3(grid), dim3(256), 0, s, job);
+  if (job.mode == kModeFilter) return launch_filter_one(job, job_needs_extended(job), s);
+  if (job_needs_extended(job)) return launch_one_ext(job, s);
+  hipLaunchKernelGGL(k_fused_one, dim3(job.fbc * job.fbr), dim3(256), 0, s, job);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
                               bool extended, bool filter_only, hipStream_t s) {
-  const dim3 g(nitems), b(256);
-  if (filter_only) {  // the variant does not apply
-    if (extended)
-      hipLaunchKernelGGL((k_filter_batch<true>), g, b, 0, s, jobs, njobs);
-    else
-      hipLaunchKernelGGL((k_filter_batch<false>), g, b, 0, s, jobs, njobs);
-    return hipGetLastError();
-  }
-  if (extended) {  // 2 waves per SIMD; the variant picks the block order
-    if (variant == 0 || variant == 1)
-      hipLaunchKernelGGL((k_fused_batch<2, true, true>), g, b, 0, s, jobs, njobs);
-    else
-      hipLaunchKernelGGL((k_fused_batch<2, false, true>), g, b, 0, s, jobs, njobs);
-    return hipGetLastError();
-  }
-  switch (variant) {
-    case 1: hipLaunchKernelGGL((k_fused_batch<2, true, false>), g, b, 0, s, jobs, njobs); break;
-    case 2: hipLaunchKernelGGL((k_fused_batch<3, false, false>), g, b, 0, s, jobs, njobs); break;
-    case 3: hipLaunchKernelGGL((k_fused_batch<2, false, false>), g, b, 0, s, jobs, njobs); break;
-    default: hipLaunchKernelGGL((k_fused_batch<3, true, false>), g, b, 0, s, jobs, njobs); break;
-  }
-  return hipGetLastError();
+  // the variant picks the occupancy bound (3 or 2 waves per SIMD; the
+  // extended kernels always run at 2) and the filter-block order; it does
+  // not apply to filter-only batches
+  if (filter_only) return launch_filter_batch(extended, jobs, njobs, nitems, s);
+  const bool xcd = variant == 0 || variant == 1;
+  if (extended)
+    return xcd ? launch_batch_ext_xcd(jobs, njobs, nitems, s)
+               : launch_batch_ext_seq(jobs, njobs, nitems, s);
+  if (variant == 1 || variant == 3)
+    return xcd ? launch_batch_base2_xcd(jobs, njobs, nitems, s)
+               : launch_batch_base2_seq(jobs, njobs, nitems, s);
+  return xcd ? launch_batch_base3_xcd(jobs, njobs, nitems, s)
+             : launch_batch_base3_seq(jobs, njobs, nitems, s);
 }
+#endif
 
 }  // namespace cdef
