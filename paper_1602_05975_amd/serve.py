@@ -76,29 +76,105 @@ def output_bytes(req: Request) -> int:
     return 2 * px + dv
 
 
+class DeviceClock:
+    """Maps completion-event times to the host clock.
+
+    The offset is calibrated once per process and shared by every executor,
+    so latencies of different executors are comparable.  Each calibration
+    event k is recorded right after host time a_k; it is stamped on the
+    device lat_k >= 0 later, so the host time of event 0 is at least
+    a_k - elapsed(0, k) for every k, and the largest such bound is the
+    tightest (it is reached for the smallest submission delay)."""
+
+    _shared = None
+
+    def __init__(self, rounds: int = 64):
+        import torch
+        s = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        self.ref = torch.cuda.Event(enable_timing=True)
+        self.ref.record(s)
+        torch.cuda.synchronize()
+        best = -1e30
+        for _ in range(rounds):
+            ev = torch.cuda.Event(enable_timing=True)
+            a = time.perf_counter()
+            ev.record(s)
+            ev.synchronize()
+            best = max(best, a - self.ref.elapsed_time(ev) / 1e3)
+        self.t0_host = best
+
+    @classmethod
+    def shared(cls) -> "DeviceClock":
+        if cls._shared is None:
+            cls._shared = cls()
+        return cls._shared
+
+    def host_time(self, ev) -> float:
+        return self.t0_host + self.ref.elapsed_time(ev) / 1e3
+
+
+def request_items(req: Request) -> int:
+    """Filter blocks (workgroups) of a request."""
+    fbr, fbc = req.recon.fb_shape
+    return fbr * fbc
+
+
+def choose_stream(inflight: List[List[int]], items: int, depth: int, heavy_items: int,
+                  fifo_heavy: bool) -> int:
+    """Stream for a new batch of `items` filter blocks, given the filter-block
+    counts of the batches in flight on each stream (oldest first); -1 when
+    every stream holds `depth` batches.  A heavy batch goes behind a heavy
+    one in flight (fifo_heavy), else to an idle stream, else to the stream
+    with the least work in flight."""
+    room = [i for i, q in enumerate(inflight) if len(q) < depth]
+    if not room:
+        return -1
+    if fifo_heavy and items > heavy_items:
+        behind = [i for i in room if any(n > heavy_items for n in inflight[i])]
+        if behind:
+            return min(behind, key=lambda i: len(inflight[i]))
+    idle = [i for i in room if not inflight[i]]
+    if idle:
+        return idle[0]
+    return min(room, key=lambda i: sum(inflight[i]))
+
+
 class GpuBatchExecutor:
     """Batches of requests through cdef_batch_prepare / cdef_batch_launch on a
-    pool of streams (default priority)."""
+    pool of streams (default priority).  Each stream runs one batch and may
+    hold `depth - 1` more queued behind it, so a batch formed while every
+    stream is busy is already on the device when the running one ends.
 
-    def __init__(self, n_streams: int = 2, variant: Optional[int] = None, max_batch: int = 256):
+    Stream choice: a light batch (at most `heavy_items` filter blocks, by
+    default one round of workgroups over the chip) runs beside whatever is
+    running, on an idle stream if there is one, and fills the CUs that a
+    running batch's last workgroups leave idle.  A heavy batch is queued
+    behind a heavy batch already in flight when `fifo_heavy` is set: two
+    heavy batches sharing the chip would both finish late, while in order
+    the first finishes as early as it would alone."""
+
+    def __init__(self, n_streams: int = 4, variant: Optional[int] = None, max_batch: int = 256,
+                 depth: int = 2, heavy_items: int = 768, fifo_heavy: bool = True):
         import torch
         self.torch = torch
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
-        self.slots = [cdef.Batch() for _ in range(n_streams)]
-        for b in self.slots:
-            b.reserve(max_batch)
-        self.busy = [None] * n_streams  # event of the batch running in each slot
+        self.depth = depth
+        self.heavy_items = heavy_items
+        self.fifo_heavy = fifo_heavy
+        # per stream: the slots (Batch objects) of its in-flight batches
+        self.slots = [[cdef.Batch() for _ in range(depth)] for _ in range(n_streams)]
+        for row in self.slots:
+            for b in row:
+                b.reserve(max_batch)
+        self.inflight: List[collections.deque] = [collections.deque() for _ in range(n_streams)]
+        self.handles: Dict[int, tuple] = {}  # handle -> (stream index, event)
+        self.next = 0
         self.variant = variant
-        self.t0_event = None
+        self.clock = None
 
     def set_epoch(self):
-        """Align device event times with the host clock."""
-        torch = self.torch
-        torch.cuda.synchronize()
-        self.t0_event = torch.cuda.Event(enable_timing=True)
-        self.t0_event.record(torch.cuda.current_stream())
-        torch.cuda.synchronize()
-        self.t0_host = time.perf_counter()
+        self.clock = DeviceClock.shared()
 
     def allocate(self, req: Request):
         torch = self.torch
@@ -120,15 +196,20 @@ class GpuBatchExecutor:
         return cdef.validate_job(req.job)
 
     def free_slot(self) -> int:
-        for i, e in enumerate(self.busy):
-            if e is None:
-                return i
-        return -1
+        """A stream with room for another batch (an idle one first), else -1."""
+        best, load = -1, self.depth
+        for i, q in enumerate(self.inflight):
+            if len(q) < load:
+                best, load = i, len(q)
+        return best
 
     def launch(self, reqs: List[Request]):
-        i = self.free_slot()
+        items = sum(request_items(r) for r in reqs)
+        i = choose_stream([[n for _, _, n in q] for q in self.inflight], items, self.depth,
+                          self.heavy_items, self.fifo_heavy)
         assert i >= 0
-        b = self.slots[i]
+        used = {id(b) for b, _, _ in self.inflight[i]}
+        b = next(x for x in self.slots[i] if id(x) not in used)
         b.jobs, b._keep = [], []
         for r in reqs:
             b.add_job(r.job, (r.recon, r.src, r.skip, r.strengths, r.outputs))
@@ -139,20 +220,29 @@ class GpuBatchExecutor:
         b.launch(s)
         ev = self.torch.cuda.Event(enable_timing=True)
         ev.record(s)
-        self.busy[i] = ev
-        return i
+        self.inflight[i].append((b, ev, items))
+        h = self.next
+        self.next += 1
+        self.handles[h] = (i, ev)
+        return h
 
     def poll(self, handle) -> Optional[float]:
         """Completion time (host clock) of a finished launch, else None."""
-        ev = self.busy[handle]
-        if ev is None or not ev.query():
+        i, ev = self.handles[handle]
+        if not ev.query():
             return None
-        self.busy[handle] = None
-        return self.t0_host + self.t0_event.elapsed_time(ev) / 1e3
+        del self.handles[handle]
+        q = self.inflight[i]
+        for k, (_, e, _) in enumerate(q):
+            if e is ev:  # it and the batches before it on its stream are done
+                for _ in range(k + 1):
+                    q.popleft()
+                break
+        return self.clock.host_time(ev)
 
     @property
     def capacity(self) -> int:
-        return len(self.slots)
+        return len(self.streams) * self.depth
 
 
 class GpuPlainExecutor:
@@ -167,7 +257,7 @@ class GpuPlainExecutor:
         self.stream = torch.cuda.Stream()
         self.pending: Dict[int, object] = {}
         self.next = 0
-        self.t0_event = None
+        self.clock = None
 
     set_epoch = GpuBatchExecutor.set_epoch
     allocate = GpuBatchExecutor.allocate
@@ -196,7 +286,7 @@ class GpuPlainExecutor:
         if ev is None or not ev.query():
             return None
         del self.pending[handle]
-        return self.t0_host + self.t0_event.elapsed_time(ev) / 1e3
+        return self.clock.host_time(ev)
 
     @property
     def capacity(self) -> int:
@@ -209,8 +299,12 @@ class Scheduler:
     capacity."""
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 256,
-                 batching: bool = True, clock: Callable[[], float] = time.perf_counter):
+                 batching: bool = True, clock: Callable[[], float] = time.perf_counter,
+                 release_outputs: bool = False):
         self.ex = executor
+        # drop each finished request's output tensors (a consumer that only
+        # needs timings), so the caching allocator reuses their memory
+        self.release_outputs = release_outputs
         self.budget = budget_bytes
         self.in_use = 0
         self.max_batch = max_batch if batching else 1
@@ -269,6 +363,8 @@ class Scheduler:
             for r in self.running.pop(h):
                 r.done = t
                 self.in_use -= r.out_bytes
+                if self.release_outputs:
+                    r.outputs, r.job = (), None
                 done.append(r)
         self.finished.extend(done)
         return done
@@ -379,7 +475,7 @@ def _stats(reqs: List[Request], wall: float) -> dict:
 
 def bench_main(args) -> None:
     import torch
-    n_req = 2000
+    n_req = 4000
     warm = 200
     _log("building the request pool")
     pool = make_request_pool()
@@ -389,11 +485,11 @@ def bench_main(args) -> None:
     reqs = make_requests(pool, warm, 1)
     ex = GpuPlainExecutor()
     ex.set_epoch()
-    sch = Scheduler(ex, budget, batching=False)
+    sch = Scheduler(ex, budget, batching=False, release_outputs=True)
     run_trace(sch, reqs, np.zeros(len(reqs)))
     reqs = make_requests(pool, n_req, 2)
     ex.set_epoch()
-    sch = Scheduler(ex, budget, batching=False)
+    sch = Scheduler(ex, budget, batching=False, release_outputs=True)
     wall = run_trace(sch, reqs, np.zeros(len(reqs)))
     plain_rate = n_req / wall
     _log(f"plain path back-to-back: {plain_rate:.0f} requests/s")
@@ -401,7 +497,7 @@ def bench_main(args) -> None:
     # sustainable rate of the batched path
     ex = GpuBatchExecutor()
     ex.set_epoch()
-    sch = Scheduler(ex, budget)
+    sch = Scheduler(ex, budget, release_outputs=True)
     reqs = make_requests(pool, n_req, 2)
     wall = run_trace(sch, reqs, np.zeros(len(reqs)))
     batched_rate = n_req / wall
@@ -421,7 +517,7 @@ def bench_main(args) -> None:
                                    ("batched", GpuBatchExecutor, True)):
             ex = mk()
             ex.set_epoch()
-            sch = Scheduler(ex, budget, batching=batching)
+            sch = Scheduler(ex, budget, batching=batching, release_outputs=True)
             reqs = make_requests(pool, n_req + warm, 3)
             wall = run_trace(sch, reqs, offs)
             kept = sorted(sch.finished, key=lambda r: r.rid)[warm:]

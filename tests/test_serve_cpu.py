@@ -134,3 +134,29 @@ def test_plain_mode_is_one_request_per_launch():
     sched = serve.Scheduler(ex, budget_bytes=1 << 30, batching=False, clock=clock)
     _run(sched, clock, [_req(i) for i in range(6)], [0.0] * 6)
     assert all(len(b) == 1 for b in ex.launches) and len(ex.launches) == 6
+
+
+def test_release_outputs_drops_finished_results():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sched = serve.Scheduler(ex, budget_bytes=1 << 30, clock=clock, release_outputs=True)
+    _run(sched, clock, [_req(i) for i in range(5)], [0.0] * 5)
+    assert len(sched.finished) == 5
+    assert all(r.outputs == () and r.job is None and r.done >= r.arrival for r in sched.finished)
+
+
+def test_stream_choice():
+    H = 768
+    # idle stream first; no room anywhere -> -1
+    assert serve.choose_stream([[], []], 10, 2, H, True) == 0
+    assert serve.choose_stream([[5], []], 10, 2, H, True) == 1
+    assert serve.choose_stream([[5, 5], [9, 9]], 10, 2, H, True) == -1
+    # light batch with every stream busy: least work in flight
+    assert serve.choose_stream([[2000], [30]], 10, 2, H, True) == 1
+    # heavy batch behind a heavy one in flight, even when a stream is idle
+    assert serve.choose_stream([[30], [2040], []], 2040, 2, H, True) == 1
+    assert serve.choose_stream([[30], [2040], []], 2040, 2, H, False) == 2
+    # the heavy stream is full: an idle stream takes it
+    assert serve.choose_stream([[2040, 2040], []], 2040, 2, H, True) == 1
+    # depth 1 never queues behind
+    assert serve.choose_stream([[2040], []], 2040, 1, H, True) == 1
