@@ -1,7 +1,7 @@
 // C ABI of the gfx950 CDEF library: argument checks on the host, then one
 // kernel launch per call.  See include/cdef.h for the contract of each entry
 // point.
-#include "../../include/cdef.h"
+#include "cdef.h"
 #include "cdef_launch.hpp"
 
 #include <math.h>

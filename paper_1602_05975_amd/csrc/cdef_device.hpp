@@ -58,6 +58,15 @@ __device__ __forceinline__ int inv840(int n) {
   return n <= 5 ? (int)((lo >> (10 * n)) & 1023) : (int)((hi >> (10 * (n - 6))) & 1023);
 }
 
+// ---- Algorithm 1 in 32-bit lanes ---------------------------------------------
+// The 64 centred values of a block in 64 registers, one 32-bit line sum per
+// line.  Its adds and 24-bit multiplies issue as 2-cycle VOP2 instructions,
+// so it is the cheaper form in issue cycles; the packed form below needs
+// half the registers.  The search kernels, which are VALU-bound and whose
+// task loops set their register budget anyway, use this one; the filter
+// kernels and the stand-alone search, whose occupancy the direction search
+// limits, use the packed one.  Both compute the same integers.
+
 // Number of pixels on every line of every direction of a full 8x8 block,
 // evaluated by the compiler.
 struct LineCounts {
@@ -137,6 +146,174 @@ __device__ __forceinline__ void dir_costs_partial(const int (&x)[64], int bw, in
   cost[5] = dir_cost_partial<5>(x, bw, bh);
   cost[6] = dir_cost_partial<6>(x, bw, bh);
   cost[7] = dir_cost_partial<7>(x, bw, bh);
+}
+
+
+// ---- Algorithm 1 on packed 16-bit halves ------------------------------------
+// Row i of an 8x8 block is held as four 32-bit words; word m packs the
+// centred 8-bit values of columns 2m (low half) and 2m + 1 (high half).  For
+// direction D the halves of word (i, m) lie on lines line_key(D, i, 2m) and
+// line_key(D, i, 2m + 1).  Words whose halves lie on the same pair of lines
+// add into one packed accumulator (a line sum is at most 8 * 128 in
+// magnitude, so 16 bits hold it), which makes the 64 pixel additions 32
+// packed ones.  Each line then has at most one low-half and one high-half
+// source (asserted below); v_dot2 with (1, 1) adds the two.
+
+struct PackedLines {
+  int nacc;            // packed accumulators
+  int acc[8][4];       // accumulator of word (i, m)
+  int nl;              // lines
+  int lo[15], hi[15];  // per line: accumulator of its low / high half, -1 if none
+  int nlo[15], nhi[15];
+  int n[15];           // pixels on the line in a full block
+};
+
+__host__ __device__ constexpr PackedLines make_packed_lines(int d) {
+  PackedLines t{};
+  int kl[32] = {}, kh[32] = {};
+  for (int l = 0; l < 15; ++l) t.lo[l] = t.hi[l] = -1;
+  for (int i = 0; i < 8; ++i)
+    for (int m = 0; m < 4; ++m) {
+      const int a = line_key(d, i, 2 * m), b = line_key(d, i, 2 * m + 1);
+      int id = -1;
+      for (int k = 0; k < t.nacc; ++k)
+        if (kl[k] == a && kh[k] == b) id = k;
+      if (id < 0) {
+        id = t.nacc++;
+        kl[id] = a;
+        kh[id] = b;
+      }
+      t.acc[i][m] = id;
+      t.n[a] += 1;
+      t.n[b] += 1;
+      t.nl = a + 1 > t.nl ? a + 1 : t.nl;
+      t.nl = b + 1 > t.nl ? b + 1 : t.nl;
+    }
+  for (int k = 0; k < t.nacc; ++k) {
+    t.lo[kl[k]] = k;
+    t.nlo[kl[k]] += 1;
+    t.hi[kh[k]] = k;
+    t.nhi[kh[k]] += 1;
+  }
+  return t;
+}
+
+constexpr bool packed_lines_ok() {
+  for (int d = 0; d < 8; ++d) {
+    const PackedLines t = make_packed_lines(d);
+    if (t.nacc > 15) return false;
+    for (int l = 0; l < t.nl; ++l)
+      if (t.nlo[l] > 1 || t.nhi[l] > 1 || t.n[l] == 0) return false;
+  }
+  return true;
+}
+static_assert(packed_lines_ok(), "a line with two sources of one half, or an empty line");
+
+// Line lengths of every direction for a block cut by the frame edge to its
+// top-left bw x bh pixels: 4 bits per line (at most 8), lines 0..14 in one
+// 64-bit word, indexed [d][bh - 1][bw - 1].  Evaluated by the compiler.
+struct CutLineCounts {
+  uint64_t w[8][8][8];
+};
+__host__ __device__ constexpr CutLineCounts make_cut_line_counts() {
+  CutLineCounts t{};
+  for (int d = 0; d < 8; ++d)
+    for (int bh = 1; bh <= 8; ++bh)
+      for (int bw = 1; bw <= 8; ++bw)
+        for (int i = 0; i < bh; ++i)
+          for (int j = 0; j < bw; ++j) t.w[d][bh - 1][bw - 1] += 1ull << (4 * line_key(d, i, j));
+  return t;
+}
+static __constant__ CutLineCounts kCutLineCounts = make_cut_line_counts();
+
+// Square of line l's value from its packed sources: with B = (low-half
+// source, high-half source) and v = b0 + b1, v^2 = dot2(B, (v, v)), where
+// (v, v) = B + B with its halves swapped.  Full-rate 16-bit work only; no
+// 32-bit multiply.
+template <int D>
+__device__ __forceinline__ int line_square(const uint32_t (&A)[15], int l) {
+  constexpr PackedLines T = make_packed_lines(D);
+  const int p = T.lo[l], q = T.hi[l];
+  uint32_t w;
+  if (p >= 0 && q >= 0)
+    w = p == q ? A[p] : (A[p] & 0xFFFFu) | (A[q] & 0xFFFF0000u);
+  else if (p >= 0)
+    w = A[p] & 0xFFFFu;
+  else
+    w = A[q] & 0xFFFF0000u;
+  const s16x2 b = __builtin_bit_cast(s16x2, w);
+  return __builtin_amdgcn_sdot2(b, b + b.yx, 0, false);
+}
+
+// The 840-scaled s_D of Eq. (5) for one direction.  x: the 32 packed words of
+// centred values (zero outside the frame); PARTIAL: the block is cut by the
+// frame edge to its top-left bw x bh pixels (1..8 each), so line lengths are
+// those of the cut block (840 / N stays exact).  D is a template parameter so that every
+// accumulator index and every full-block 840 / N is a compile-time constant.
+template <int D, bool PARTIAL>
+__device__ __forceinline__ int dir_cost_packed(const uint32_t (&x)[32], int bw, int bh) {
+  constexpr PackedLines T = make_packed_lines(D);
+  uint32_t A[15];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) A[k] = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int a = T.acc[i][m];
+      A[a] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, A[a]) +
+                                              __builtin_bit_cast(s16x2, x[4 * i + m]));
+    }
+  if constexpr (D == 6 && !PARTIAL) {
+    // one half per line, every line 8 pixels: 105 * sum of squared halves
+    int sq = 0;
+#pragma unroll
+    for (int k = 0; k < T.nacc; ++k)
+      sq = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, A[k]),
+                                  __builtin_bit_cast(s16x2, A[k]), sq, false);
+    return __mul24(sq, 105);
+  } else {
+    // v^2 <= 1024^2 and 840 / N <= 840: both factors fit 24 bits
+    const uint64_t cnt = PARTIAL ? kCutLineCounts.w[D][bh - 1][bw - 1] : 0;
+    int c = 0;
+#pragma unroll
+    for (int l = 0; l < T.nl; ++l) {
+      const int sq = line_square<D>(A, l);
+      if (PARTIAL)
+        c += __mul24(sq, inv840((int)(cnt >> (4 * l)) & 15));
+      else
+        c += __mul24(sq, 840 / T.n[l]);
+    }
+    return c;
+  }
+}
+
+template <bool PARTIAL>
+__device__ __forceinline__ void dir_costs_packed(const uint32_t (&x)[32], int bw, int bh,
+                                                 int (&cost)[8]) {
+  cost[0] = dir_cost_packed<0, PARTIAL>(x, bw, bh);
+  cost[1] = dir_cost_packed<1, PARTIAL>(x, bw, bh);
+  cost[2] = dir_cost_packed<2, PARTIAL>(x, bw, bh);
+  cost[3] = dir_cost_packed<3, PARTIAL>(x, bw, bh);
+  cost[4] = dir_cost_packed<4, PARTIAL>(x, bw, bh);
+  cost[5] = dir_cost_packed<5, PARTIAL>(x, bw, bh);
+  cost[6] = dir_cost_packed<6, PARTIAL>(x, bw, bh);
+  cost[7] = dir_cost_packed<7, PARTIAL>(x, bw, bh);
+}
+
+// Centres a word of two raw samples for the search: (x >> c) - 128 per half
+// (the downscale to 8 bits of Section 2 for c = bit depth - 8 > 0).
+__device__ __forceinline__ uint32_t centre_word(uint32_t raw, int c) {
+  const u16x2 v = __builtin_bit_cast(u16x2, raw) >> (u16x2){(unsigned short)c, (unsigned short)c};
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, v) - (s16x2){128, 128});
+}
+
+// Keeps the halves of word (i, m) that lie inside the top-left bw x bh
+// pixels of the block; zeroes the others.
+__device__ __forceinline__ uint32_t mask_word(uint32_t w, int i, int m, int bw, int bh) {
+  const uint32_t lo = (i < bh && 2 * m < bw) ? 0xFFFFu : 0u;
+  const uint32_t hi = (i < bh && 2 * m + 1 < bw) ? 0xFFFF0000u : 0u;
+  return w & (lo | hi);
 }
 
 // Argmax with a strict '>' from d = 0, and the directional contrast

@@ -573,7 +573,9 @@ __device__ __forceinline__ void stage_item(SmemCore<X> &sm, const JobDesc &J, in
 // Algorithm 1 for the 64 luma blocks of the filter block, one per lane of
 // wave 0; Eq. (13) adjusted strengths; compaction of the blocks to filter
 // (the full search lists the skipped in-frame blocks after them).
-template <bool FULL, bool X>
+// PACKED: Algorithm 1 on packed 16-bit halves (half the registers; the
+// filter kernels), else in 32-bit lanes (fewer issue cycles; the searches).
+template <bool FULL, bool X, bool PACKED = false>
 __device__ __forceinline__ void direction_search(SmemCore<X> &sm, const JobDesc &J, int fby, int fbx,
                                                  int lane) {
   const int b = lane;
@@ -587,28 +589,49 @@ __device__ __forceinline__ void direction_search(SmemCore<X> &sm, const JobDesc 
     v = J.var[(int64_t)by * J.bcols + bx];
   } else if (in) {
     const int bw = min(8, J.width - 8 * bx), bh = min(8, J.height - 8 * by);
-    int x[64];
     const uint16_t *row0 = sm.ry + (2 + 8 * (b >> 3)) * kLS + kLC0 + 8 * (b & 7);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const uint4 q = *reinterpret_cast<const uint4 *>(row0 + i * kLS);
-      const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int px = (int)((w4[j >> 1] >> (16 * (j & 1))) & 0xFFFF);
-        x[i * 8 + j] = (px >> c) - 128;
-      }
-    }
     int cost[8];
-    if (bw == 8 && bh == 8) {
-      dir_costs_full(x, cost);
+    if constexpr (PACKED) {
+      uint32_t x[32];  // row i, word m: columns 2m and 2m + 1, centred
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(row0 + i * kLS);
+        x[4 * i + 0] = centre_word(q.x, c);
+        x[4 * i + 1] = centre_word(q.y, c);
+        x[4 * i + 2] = centre_word(q.z, c);
+        x[4 * i + 3] = centre_word(q.w, c);
+      }
+      if (bw == 8 && bh == 8) {
+        dir_costs_packed<false>(x, 8, 8, cost);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) x[4 * i + m] = mask_word(x[4 * i + m], i, m, bw, bh);
+        dir_costs_packed<true>(x, bw, bh, cost);
+      }
     } else {
+      int x[64];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < 8; ++i) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(row0 + i * kLS);
+        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (i >= bh || j >= bw) x[i * 8 + j] = 0;
-      dir_costs_partial(x, bw, bh, cost);
+        for (int j = 0; j < 8; ++j) {
+          const int px = (int)((w4[j >> 1] >> (16 * (j & 1))) & 0xFFFF);
+          x[i * 8 + j] = (px >> c) - 128;
+        }
+      }
+      if (bw == 8 && bh == 8) {
+        dir_costs_full(x, cost);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (i >= bh || j >= bw) x[i * 8 + j] = 0;
+        dir_costs_partial(x, bw, bh, cost);
+      }
     }
     pick_direction(cost, d, v);
     if (J.dir) {
@@ -1183,7 +1206,9 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
 // so that a pair's "y - s" is y; results land in the idle source tiles, and
 // every in-frame pixel is then copied out, filtered or not.  4:2:2 chroma is
 // copied.
-template <bool X, bool B12>
+// PACKED: the packed direction search (the filter-only kernels, whose
+// occupancy it sets); the search kernels' filter mode keeps the 32-bit one.
+template <bool X, bool B12, bool PACKED>
 __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, int fby, int fbx,
                                             int tid) {
   const int wave = tid >> 6, lane = tid & 63;
@@ -1192,7 +1217,7 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   __builtin_amdgcn_s_setprio(2);  // as in the searches
   stage_item<X>(sm, J, fby, fbx, tid, false);
   __syncthreads();
-  if (wave == 0) direction_search<true>(sm, J, fby, fbx, lane);
+  if (wave == 0) direction_search<true, X, PACKED>(sm, J, fby, fbx, lane);
   __syncthreads();
   __builtin_amdgcn_s_setprio(0);
   const uint8_t *st = J.strengths + 4 * ((int64_t)fby * J.fbc + fbx);
@@ -1384,7 +1409,7 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
     else if (J.mode == kModeSearchFull)
       search_item<true, true, false>(sm, J, fby, fbx, tid);
     else if constexpr (FILTER)
-      filter_item<X, true>(sm, J, fby, fbx, tid);
+      filter_item<X, true, false>(sm, J, fby, fbx, tid);
     return;
   }
   if (J.mode == kModeSearch) {
@@ -1398,7 +1423,7 @@ __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int ite
     else
       search_item<true, false, false>(sm, J, fby, fbx, tid);
   } else if constexpr (FILTER) {
-    filter_item<X, false>(sm, J, fby, fbx, tid);
+    filter_item<X, false, false>(sm, J, fby, fbx, tid);
   }
 }
 
@@ -1491,12 +1516,12 @@ __device__ __forceinline__ void filter_run(SmemCore<X> &sm, const JobDesc &J, in
                                            int tid) {
   const int fby = item / J.fbc, fbx = item - fby * J.fbc;
   if (J.bitdepth == 12)
-    filter_item<X, true>(sm, J, fby, fbx, tid);
+    filter_item<X, true, true>(sm, J, fby, fbx, tid);
   else
-    filter_item<X, false>(sm, J, fby, fbx, tid);
+    filter_item<X, false, true>(sm, J, fby, fbx, tid);
 }
 
-__global__ __launch_bounds__(256, 3) void k_filter_one(const JobDesc J) {
+__global__ __launch_bounds__(256, 5) void k_filter_one(const JobDesc J) {
   __shared__ __align__(16) SmemCore<false> sm;
   filter_run<false>(sm, J, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
@@ -1507,7 +1532,7 @@ __global__ __launch_bounds__(256, 2) void k_filter_one_x(const JobDesc J) {
 }
 
 template <bool X>
-__global__ __launch_bounds__(256, X ? 2 : 3) void k_filter_batch(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(256, X ? 2 : 5) void k_filter_batch(const JobDesc *__restrict__ jobs,
                                                                  int njobs) {
   __shared__ __align__(16) SmemCore<X> sm;
   const int item = xcd_item(blockIdx.x, gridDim.x);

@@ -19,11 +19,12 @@ BUDGET = {
     "k_fused_batchILi2ELb0ELb1E": (2, 8),
     "k_fused_oneE": (3, 8),
     "k_fused_one_xE": (2, 8),
-    "k_filter_oneE": (3, 8),
+    "k_filter_oneE": (5, 0),                # the decoder path: 84 VGPRs, 31 KB LDS
     "k_filter_one_xE": (2, 8),
-    "k_filter_batchILb0E": (3, 8),
+    "k_filter_batchILb0E": (5, 0),
     "k_filter_batchILb1E": (2, 8),
     "k_preset_coop": (None, 0),
+    "k_find_dir": (4, 0),
 }
 
 
