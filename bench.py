@@ -515,7 +515,7 @@ def main():
     if (bd, layout) == (10, 1):
         frames = synth.uhd4k_frames(args.frames)
     else:
-        frames = [synth.make_frame(3840, 2160, bd, layout, synth.workload_seed(WL_4K, f),
+        frames = [synth.make_frame(3840, 2160, bd, layout, synth.workload_seed(synth.WL_4K, f),
                                    skip_prob=0.3, damping=3) for f in range(args.frames)]
     ops = sum(frame_work(f, full, weighted, cand)[0] for f in frames)
     algo_bytes = sum(frame_work(f, full, weighted, cand)[1] for f in frames)
