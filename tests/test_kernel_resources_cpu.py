@@ -24,7 +24,6 @@ BUDGET = {
     "k_filter_batchILb0E": (5, 0),
     "k_filter_batchILb1E": (2, 8),
     "k_preset_coop": (None, 0),
-    "k_find_dir": (4, 0),
 }
 
 
