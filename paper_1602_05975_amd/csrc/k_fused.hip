@@ -1037,15 +1037,31 @@ __device__ __forceinline__ void reduce_chunk(uint32_t (&v)[64], int lane,
 }
 
 template <bool ROWS, bool B12>
-__device__ __forceinline__ void task_moments(const s16x2 (&ev)[64], uint32_t sv, int lane,
+__device__ __forceinline__ void task_moments(s16x2 (&ev)[64], uint32_t sv, int lane,
                                              Moments<ROWS, B12> &m) {
   constexpr int K = Moments<ROWS, B12>::K;
-  const s16x2 s = as_s(sv);
-  const u16x2 lo = u16x2{0xFFFF, 0}, hi = u16x2{0, 0xFFFF};
   uint32_t v[64];
+  // squares of the 16-bit halves as single 24-bit multiplies of the
+  // selected halves (|e| and d stay below 2^12, so every square is exact)
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const int e = (int)(int16_t)(__builtin_bit_cast(uint32_t, ev[i]) & 0xFFFFu);
+    v[i] = (uint32_t)__mul24(e, e);
+  }
+  reduce_chunk<ROWS>(v, lane, m.e2lo);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const int e = (int)__builtin_bit_cast(uint32_t, ev[i]) >> 16;
+    v[i] = (uint32_t)__mul24(e, e);
+  }
+  reduce_chunk<ROWS>(v, lane, m.e2hi);
+  // d = e + s, in place
+  const s16x2 s = as_s(sv);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) ev[i] = ev[i] + s;
   if constexpr (ROWS || !B12) {
 #pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s);
+    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i]);
     uint32_t sd[K];
     reduce_chunk<ROWS>(v, lane, sd);
 #pragma unroll
@@ -1055,32 +1071,24 @@ __device__ __forceinline__ void task_moments(const s16x2 (&ev)[64], uint32_t sv,
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s) & 0xFFFF;
+    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i]) & 0xFFFF;
     reduce_chunk<ROWS>(v, lane, m.sdlo);
 #pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i] + s) >> 16;
+    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i]) >> 16;
     reduce_chunk<ROWS>(v, lane, m.sdhi);
   }
 #pragma unroll
   for (int i = 0; i < 64; ++i) {
-    const u16x2 d = as_u(ev[i] + s);
-    v[i] = __builtin_amdgcn_udot2(d, d & lo, 0u, false);
+    const uint32_t d = __builtin_bit_cast(uint32_t, ev[i]) & 0xFFFFu;
+    v[i] = __umul24(d, d);
   }
   reduce_chunk<ROWS>(v, lane, m.d2lo);
 #pragma unroll
   for (int i = 0; i < 64; ++i) {
-    const u16x2 d = as_u(ev[i] + s);
-    v[i] = __builtin_amdgcn_udot2(d, d & hi, 0u, false);
+    const uint32_t d = __builtin_bit_cast(uint32_t, ev[i]) >> 16;
+    v[i] = __umul24(d, d);
   }
   reduce_chunk<ROWS>(v, lane, m.d2hi);
-#pragma unroll
-  for (int i = 0; i < 64; ++i)
-    v[i] = (uint32_t)__builtin_amdgcn_sdot2(ev[i], ev[i] & as_s(lo), 0, false);
-  reduce_chunk<ROWS>(v, lane, m.e2lo);
-#pragma unroll
-  for (int i = 0; i < 64; ++i)
-    v[i] = (uint32_t)__builtin_amdgcn_sdot2(ev[i], ev[i] & as_s(hi), 0, false);
-  reduce_chunk<ROWS>(v, lane, m.e2hi);
 }
 
 // Weighted search over luma-shaped tasks of plane CH; lane k accumulates
