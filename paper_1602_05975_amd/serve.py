@@ -114,24 +114,31 @@ class DeviceClock:
         return self.t0_host + self.ref.elapsed_time(ev) / 1e3
 
 
-def request_items(req: Request) -> int:
-    """Filter blocks (workgroups) of a request."""
+# Device work of one filter block in units of a filter-mode filter block: a
+# strength-search filter block costs about four (0.159 against 0.043 ms per
+# 4K 10-bit frame in a batch).
+SEARCH_WORK = 4
+
+
+def request_work(req: Request, search_work: int = SEARCH_WORK) -> int:
+    """Device work of a request: its filter blocks (workgroups), each weighted
+    by its mode's cost."""
     fbr, fbc = req.recon.fb_shape
-    return fbr * fbc
+    return fbr * fbc * (search_work if req.mode == SEARCH else 1)
 
 
-def choose_stream(inflight: List[List[int]], items: int, depth: int, heavy_items: int,
+def choose_stream(inflight: List[List[int]], work: int, depth: int, heavy_work: int,
                   fifo_heavy: bool) -> int:
-    """Stream for a new batch of `items` filter blocks, given the filter-block
-    counts of the batches in flight on each stream (oldest first); -1 when
-    every stream holds `depth` batches.  A heavy batch goes behind a heavy
-    one in flight (fifo_heavy), else to an idle stream, else to the stream
-    with the least work in flight."""
+    """Stream for a new batch of `work` units, given the work of the batches
+    in flight on each stream (oldest first); -1 when every stream holds
+    `depth` batches.  A heavy batch goes behind a heavy one in flight
+    (fifo_heavy), else to an idle stream, else to the stream with the least
+    work in flight."""
     room = [i for i, q in enumerate(inflight) if len(q) < depth]
     if not room:
         return -1
-    if fifo_heavy and items > heavy_items:
-        behind = [i for i in room if any(n > heavy_items for n in inflight[i])]
+    if fifo_heavy and work > heavy_work:
+        behind = [i for i in room if any(n > heavy_work for n in inflight[i])]
         if behind:
             return min(behind, key=lambda i: len(inflight[i]))
     idle = [i for i in room if not inflight[i]]
@@ -146,22 +153,25 @@ class GpuBatchExecutor:
     hold `depth - 1` more queued behind it, so a batch formed while every
     stream is busy is already on the device when the running one ends.
 
-    Stream choice: a light batch (at most `heavy_items` filter blocks, by
-    default one round of workgroups over the chip) runs beside whatever is
-    running, on an idle stream if there is one, and fills the CUs that a
-    running batch's last workgroups leave idle.  A heavy batch is queued
-    behind a heavy batch already in flight when `fifo_heavy` is set: two
-    heavy batches sharing the chip would both finish late, while in order
-    the first finishes as early as it would alone."""
+    Stream choice: a light batch (at most `heavy_work` units of
+    request_work, by default one round of search workgroups over the chip,
+    768 x SEARCH_WORK) runs beside whatever is running, on an idle stream if
+    there is one, and fills the CUs that a running batch's last workgroups
+    leave idle.  A heavy batch is queued behind a heavy batch already in
+    flight when `fifo_heavy` is set: two heavy batches sharing the chip
+    would both finish late, while in order the first finishes as early as
+    it would alone.  search_work = 1 counts filter blocks alone."""
 
     def __init__(self, n_streams: int = 4, variant: Optional[int] = None, max_batch: int = 256,
-                 depth: int = 2, heavy_items: int = 768, fifo_heavy: bool = True):
+                 depth: int = 2, heavy_work: int = 768 * SEARCH_WORK, fifo_heavy: bool = True,
+                 search_work: int = SEARCH_WORK):
         import torch
         self.torch = torch
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.depth = depth
-        self.heavy_items = heavy_items
+        self.heavy_work = heavy_work
         self.fifo_heavy = fifo_heavy
+        self.search_work = search_work
         # per stream: the slots (Batch objects) of its in-flight batches
         self.slots = [[cdef.Batch() for _ in range(depth)] for _ in range(n_streams)]
         for row in self.slots:
@@ -204,9 +214,9 @@ class GpuBatchExecutor:
         return best
 
     def launch(self, reqs: List[Request]):
-        items = sum(request_items(r) for r in reqs)
-        i = choose_stream([[n for _, _, n in q] for q in self.inflight], items, self.depth,
-                          self.heavy_items, self.fifo_heavy)
+        work = sum(request_work(r, self.search_work) for r in reqs)
+        i = choose_stream([[n for _, _, n in q] for q in self.inflight], work, self.depth,
+                          self.heavy_work, self.fifo_heavy)
         assert i >= 0
         used = {id(b) for b, _, _ in self.inflight[i]}
         b = next(x for x in self.slots[i] if id(x) not in used)
@@ -220,7 +230,7 @@ class GpuBatchExecutor:
         b.launch(s)
         ev = self.torch.cuda.Event(enable_timing=True)
         ev.record(s)
-        self.inflight[i].append((b, ev, items))
+        self.inflight[i].append((b, ev, work))
         h = self.next
         self.next += 1
         self.handles[h] = (i, ev)

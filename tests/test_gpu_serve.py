@@ -53,10 +53,11 @@ def _alone(req):
     return cdef.filter_frame(req.recon, d, v, req.skip, req.damping, req.strengths)
 
 
-# heavy_items 16: frames above 640x256 count as heavy, so the small test
-# frames exercise the policy that queues heavy batches behind each other
+# heavy_work 64: searches above 16 filter blocks (and filters above 64)
+# count as heavy, so the small test frames exercise the policy that queues
+# heavy batches behind each other
 @pytest.mark.parametrize("batching,streams,depth,heavy", [
-    (True, 2, 1, 768), (True, 1, 2, 768), (True, 2, 2, 768), (True, 2, 2, 16), (True, 3, 2, 16),
+    (True, 2, 1, 3072), (True, 1, 2, 3072), (True, 2, 2, 3072), (True, 2, 2, 64), (True, 3, 2, 64),
     (False, 1, 1, 0)])
 def test_served_results_equal_alone(batching, streams, depth, heavy):
     import torch
@@ -64,14 +65,14 @@ def test_served_results_equal_alone(batching, streams, depth, heavy):
     pool = _pool()
     reqs = _requests(pool, 120, 5)
     if batching:
-        ex = serve.GpuBatchExecutor(n_streams=streams, depth=depth, heavy_items=heavy)
+        ex = serve.GpuBatchExecutor(n_streams=streams, depth=depth, heavy_work=heavy)
     else:
         ex = serve.GpuPlainExecutor()
     ex.set_epoch()
     sched = serve.Scheduler(ex, budget_bytes=64 << 20, batching=batching)
     offs = np.cumsum(np.random.default_rng(6).exponential(1.0 / 4000.0, len(reqs)))
     print(f"serving {len(reqs)} requests, batching={batching}, {streams} streams, "
-          f"depth {depth}, heavy above {heavy} filter blocks", flush=True)
+          f"depth {depth}, heavy above {heavy} work units", flush=True)
     serve.run_trace(sched, reqs, offs)
     torch.cuda.synchronize()
     assert len(sched.finished) == len(reqs) and not sched.rejected

@@ -145,6 +145,15 @@ def test_release_outputs_drops_finished_results():
     assert all(r.outputs == () and r.job is None and r.done >= r.arrival for r in sched.finished)
 
 
+def test_request_work():
+    f = cdef.Frame([None, None, None], 3840, 2160, 10, cdef.LAYOUT_420)
+    search = serve.Request(rid=0, mode=serve.SEARCH, recon=f)
+    filt = serve.Request(rid=1, mode=serve.FILTER, recon=f)
+    assert serve.request_work(filt) == 60 * 34
+    assert serve.request_work(search) == 60 * 34 * serve.SEARCH_WORK
+    assert serve.request_work(search, 1) == 60 * 34
+
+
 def test_stream_choice():
     H = 768
     # idle stream first; no room anywhere -> -1
