@@ -740,7 +740,9 @@ __device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, i
     const int rB = 8 * (B >> 3) + r, cB = 8 * (B & 7) + col;
     const bool vA = y0 + rA < H && x0 + cA < W;
     const bool vB = hasB && y0 + rB < H && x0 + cB < W;
-    const uint32_t vm = (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
+    // searches: lanes outside the frame see zeros and add nothing to a sum;
+    // filter mode discards them (only in-frame pixels are copied out)
+    const uint32_t vm = !SRC ? ~0u : (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
     const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
     const uint32_t xv = ((uint32_t)rt[bA] | ((uint32_t)rt[bB] << 16)) & vm;
     // without a source (filter mode) y - s is y itself
@@ -813,7 +815,7 @@ __device__ __forceinline__ void chroma420_tasks(SmemCore<X> &sm, const JobDesc &
     const int rH = 4 * (Hb >> 3) + r, cH = 4 * (Hb & 7) + col;
     const bool vL = hasL && cy0 + rL < ch && cx0 + cL < cw;
     const bool vH = hasH && cy0 + rH < ch && cx0 + cH < cw;
-    const uint32_t vm = (vL ? 0x0000FFFFu : 0u) | (vH ? 0xFFFF0000u : 0u);
+    const uint32_t vm = !SRC ? ~0u : (vL ? 0x0000FFFFu : 0u) | (vH ? 0xFFFF0000u : 0u);
     const int bL = (rL + 2) * kCS + kCC0 + cL, bH = (rH + 2) * kCS + kCC0 + cH;
     const int dL = sm.dir[L], dH = sm.dir[Hb];
     const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
