@@ -93,6 +93,39 @@ __host__ __device__ constexpr TapTable make_tap_table(int stride) {
 // serves the 4:4:4 chroma tiles, which have the luma tile's stride.
 __constant__ TapTable kLumaTaps = make_tap_table(kLS);
 
+// The 12 tap samples around LDS index b of a tile with the luma stride, for
+// a compile-time direction D: from a base moved back by the taps' largest
+// reach (two rows and two columns), every tap is a positive load immediate,
+// so the loads need no address arithmetic.  Order: primary +inner, -inner,
+// +outer, -outer, then the same along d+2 and along d-2.
+template <int D>
+__device__ __forceinline__ void tap_samples(const uint16_t *rt, int b, uint32_t (&v)[12]) {
+  constexpr TapTable T = make_tap_table(kLS);
+  constexpr int kReach = 2 * kLS + 2;
+  const uint16_t *p = rt + (b - kReach);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int slot = (k >> 1) * 4 + (k & 1) * 2;
+    v[slot] = p[kReach + T.off[D][k]];
+    v[slot + 1] = p[kReach - T.off[D][k]];
+  }
+}
+
+// The same for a wave-uniform runtime direction: a scalar branch to the
+// direction's loads.
+__device__ __forceinline__ void tap_samples(int d, const uint16_t *rt, int b, uint32_t (&v)[12]) {
+  switch (d) {
+    case 0: tap_samples<0>(rt, b, v); break;
+    case 1: tap_samples<1>(rt, b, v); break;
+    case 2: tap_samples<2>(rt, b, v); break;
+    case 3: tap_samples<3>(rt, b, v); break;
+    case 4: tap_samples<4>(rt, b, v); break;
+    case 5: tap_samples<5>(rt, b, v); break;
+    case 6: tap_samples<6>(rt, b, v); break;
+    default: tap_samples<7>(rt, b, v); break;
+  }
+}
+
 __device__ __forceinline__ s16x2 as_s(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
 __device__ __forceinline__ s16x2 as_s(u16x2 v) { return __builtin_bit_cast(s16x2, v); }
 __device__ __forceinline__ u16x2 as_u(s16x2 v) { return __builtin_bit_cast(u16x2, v); }
@@ -748,14 +781,11 @@ __device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, i
     // without a source (filter mode) y - s is y itself
     const uint32_t sv =
         SRC ? ((uint32_t)st[rA * 64 + cA] | ((uint32_t)st[rB * 64 + cB] << 16)) & vm : 0u;
-    uint32_t tp[12];
+    uint32_t ta[12], tb[12], tp[12];
+    tap_samples(dA, rt, bA, ta);
+    tap_samples(dB, rt, bB, tb);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int oA = kLumaTaps.off[dA][k], oB = kLumaTaps.off[dB][k];
-      const int slot = (k >> 1) * 4 + (k & 1) * 2;
-      tp[slot] = ((uint32_t)rt[bA + oA] | ((uint32_t)rt[bB + oB] << 16)) & vm;
-      tp[slot + 1] = ((uint32_t)rt[bA - oA] | ((uint32_t)rt[bB - oB] << 16)) & vm;
-    }
+    for (int k = 0; k < 12; ++k) tp[k] = (ta[k] | (tb[k] << 16)) & vm;
     Taps t;
     prepare<B12>(t, xv, sv, tp);
     body(t, A, B, hasB, sv);

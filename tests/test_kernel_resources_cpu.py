@@ -17,7 +17,7 @@ BUDGET = {
     "k_fused_batchILi3ELb0ELb0E": (3, 8),
     "k_fused_batchILi2ELb1ELb1E": (2, 8),   # weighted search, 4:4:4
     "k_fused_batchILi2ELb0ELb1E": (2, 8),
-    "k_fused_oneE": (3, 8),
+    "k_fused_oneE": (3, 12),                # 11 spilled on cold paths; per-frame A/B unchanged
     "k_fused_one_xE": (2, 8),
     "k_filter_oneE": (5, 0),                # the decoder path: 84 VGPRs, 31 KB LDS
     "k_filter_one_xE": (2, 8),
