@@ -188,9 +188,13 @@ def test_filter_only_batch_kernels_and_graph_replay(oracle):
             rec = gpu_frame(fr.recon, fr)
             st = s.random_presets(fr, 32100 + i)
             outs = [torch.full_like(p, -1) for p in rec.planes[:fr.nplanes]]
+            # directions and contrasts too: the filter-only kernels compute
+            # them with the packed form of Algorithm 1
+            d = torch.full((fr.blk_rows, fr.blk_cols), 255, dtype=torch.uint8, device="cuda")
+            v = torch.full((fr.blk_rows, fr.blk_cols), -1, dtype=torch.int32, device="cuda")
             b.add_filter(rec, outs, torch.from_numpy(fr.skip).cuda(), fr.damping,
-                         torch.from_numpy(st).cuda())
-            jobs.append((fr, st, outs))
+                         torch.from_numpy(st).cuda(), d, v)
+            jobs.append((fr, st, outs, d, v))
         b.prepare()
         assert b.plan.flags & 2 and bool(b.plan.flags & 1) == with444
         print(f"filter-only batch, 4:4:4 job: {with444}", flush=True)
@@ -199,8 +203,9 @@ def test_filter_only_batch_kernels_and_graph_replay(oracle):
             b.launch(stream)
         stream.synchronize()
         want = []
-        for fr, st, outs in jobs:
+        for fr, st, outs, d, v in jobs:
             od, ov = oracle.find_dir(fr.recon[0], fr.bitdepth)
+            assert np.array_equal(d.cpu().numpy(), od) and np.array_equal(v.cpu().numpy(), ov)
             ref = oracle.filter_frame(fr.recon, fr.width, fr.height, fr.bitdepth, od, ov, fr.skip,
                                       fr.damping, st, layout=fr.layout)
             for p in range(fr.nplanes):
@@ -210,12 +215,49 @@ def test_filter_only_batch_kernels_and_graph_replay(oracle):
         with torch.cuda.graph(g, stream=stream):
             b.launch(stream)
         for rep in range(3):
-            for _, _, outs in jobs:
+            for _, _, outs, _, _ in jobs:
                 for o in outs:
                     o.fill_(rep)
             torch.cuda.synchronize()
             g.replay()
             torch.cuda.synchronize()
-            for (fr, _, outs), ref in zip(jobs, want):
+            for (fr, _, outs, _, _), ref in zip(jobs, want):
                 for p in range(fr.nplanes):
                     assert (to_np_u16(outs[p]) == ref[p]).all(), (rep, fr.width, p)
+
+
+def test_filter_only_batch_every_cut_block_size(oracle):
+    # Frames of (16 + a) x (16 + b) samples put a block cut to a x b pixels in
+    # the bottom-right corner (and a x 8, 8 x b along the edges), for every
+    # a, b in 1..8; the filter-only kernels take the line lengths of cut
+    # blocks from a table indexed by the cut size.
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    b = cdef.Batch()
+    jobs = []
+    for a in range(1, 9):
+        for c in range(1, 9):
+            w, h = 16 + a, 16 + c
+            fr = s.make_frame(w, h, 10 if (a + c) % 2 else 8, s.LAYOUT_400, 33000 + 8 * a + c,
+                              skip_prob=0.2, damping=3 + (a % 4))
+            rec = gpu_frame(fr.recon, fr)
+            st = s.random_presets(fr, 33500 + 8 * a + c)
+            outs = [torch.full_like(rec.planes[0], -1)]
+            d = torch.full((fr.blk_rows, fr.blk_cols), 255, dtype=torch.uint8, device="cuda")
+            v = torch.full((fr.blk_rows, fr.blk_cols), -1, dtype=torch.int32, device="cuda")
+            b.add_filter(rec, outs, torch.from_numpy(fr.skip).cuda(), fr.damping,
+                         torch.from_numpy(st).cuda(), d, v)
+            jobs.append((fr, st, outs, d, v))
+    b.prepare()
+    assert b.plan.flags & 2
+    print(f"filter-only batch of {len(jobs)} frames, every cut block size", flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for fr, st, outs, d, v in jobs:
+        od, ov = oracle.find_dir(fr.recon[0], fr.bitdepth)
+        assert np.array_equal(d.cpu().numpy(), od), (fr.width, fr.height)
+        assert np.array_equal(v.cpu().numpy(), ov), (fr.width, fr.height)
+        ref = oracle.filter_frame(fr.recon, fr.width, fr.height, fr.bitdepth, od, ov, fr.skip,
+                                  fr.damping, st, layout=fr.layout)
+        assert (to_np_u16(outs[0]) == ref[0]).all(), (fr.width, fr.height)
