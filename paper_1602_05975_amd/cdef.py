@@ -199,6 +199,15 @@ class Frame:
         return ((self.height + 63) // 64, (self.width + 63) // 64)
 
     def c_struct(self) -> CdefFrame:
+        """The cdef_frame of this frame.  Built once and reused while the
+        planes' addresses and row strides and the geometry stay the same (the
+        struct holds nothing else; a serving loop calls this per request);
+        the callers copy it by value or only read it."""
+        key = (tuple(None if t is None else (t.data_ptr(), t.stride(0)) for t in self.planes[:3]),
+               self.width, self.height, self.bitdepth, self.layout)
+        cached = self.__dict__.get("_cstruct")
+        if cached is not None and cached[0] == key:
+            return cached[1]
         f = CdefFrame()
         for p, t in enumerate(self.planes[:3]):
             if t is None:
@@ -207,6 +216,7 @@ class Frame:
             f.plane[p] = t.data_ptr()
             f.stride[p] = t.stride(0)
         f.width, f.height, f.bitdepth, f.layout = self.width, self.height, self.bitdepth, self.layout
+        self.__dict__["_cstruct"] = (key, f)
         return f
 
     @staticmethod

@@ -310,8 +310,12 @@ class Scheduler:
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 256,
                  batching: bool = True, clock: Callable[[], float] = time.perf_counter,
-                 release_outputs: bool = False):
+                 release_outputs: bool = False, split_modes: bool = True):
         self.ex = executor
+        # one mode per batch: a batch of filter jobs only runs on the leaner
+        # filter-only kernels, a mixed one runs its filter jobs inside the
+        # search kernel
+        self.split_modes = split_modes
         # drop each finished request's output tensors (a consumer that only
         # needs timings), so the caching allocator reuses their memory
         self.release_outputs = release_outputs
@@ -386,7 +390,15 @@ class Scheduler:
         while self.ready and len(self.running) < self.ex.capacity:
             if getattr(self.ex, "free_slot", None) and self.ex.free_slot() < 0:
                 break
-            take, self.ready = self.ready[:self.max_batch], self.ready[self.max_batch:]
+            if self.split_modes and self.max_batch > 1:
+                # the oldest ready request's mode, its requests in arrival order
+                mode = self.ready[0].mode
+                take, rest = [], []
+                for r in self.ready:
+                    (take if r.mode == mode and len(take) < self.max_batch else rest).append(r)
+                self.ready = rest
+            else:
+                take, self.ready = self.ready[:self.max_batch], self.ready[self.max_batch:]
             h = self.ex.launch(take)
             for r in take:
                 r.batch_id = self.nbatches

@@ -169,3 +169,23 @@ def test_stream_choice():
     assert serve.choose_stream([[2040, 2040], []], 2040, 2, H, True) == 1
     # depth 1 never queues behind
     assert serve.choose_stream([[2040], []], 2040, 1, H, True) == 1
+
+
+def test_batches_hold_one_mode_in_arrival_order():
+    clock = Clock()
+    ex = FakeExecutor(clock, cost_per_px=1e-7)
+    sched = serve.Scheduler(ex, budget_bytes=1 << 30, clock=clock)
+    modes = [serve.SEARCH, serve.FILTER, serve.SEARCH, serve.FILTER, serve.FILTER, serve.SEARCH]
+    reqs = [_req(i, mode=m) for i, m in enumerate(modes)]
+    _run(sched, clock, reqs, [0.0] * len(reqs), dt=5e-6)
+    mode_of = {r.rid: r.mode for r in reqs}
+    assert sorted(rid for b in ex.launches for rid in b) == list(range(len(reqs)))
+    for b in ex.launches:
+        assert len({mode_of[rid] for rid in b}) == 1 and b == sorted(b)
+    # the first batch takes the oldest request's mode; the other mode follows
+    assert ex.launches[0] == [0, 2, 5] and ex.launches[1] == [1, 3, 4]
+    # without splitting, one batch takes everything that is ready
+    ex2 = FakeExecutor(Clock(), cost_per_px=1e-7)
+    sched2 = serve.Scheduler(ex2, budget_bytes=1 << 30, clock=ex2.clock, split_modes=False)
+    _run(sched2, ex2.clock, [_req(i, mode=m) for i, m in enumerate(modes)], [0.0] * 6, dt=5e-6)
+    assert ex2.launches[0] == list(range(6))
