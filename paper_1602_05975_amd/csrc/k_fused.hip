@@ -295,7 +295,10 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
     const uint32_t sh = sha | (shb << 16);
     const uint32_t w1 = ((sa & 1) ? 3u : 4u) | (((sb & 1) ? 3u : 4u) << 16);
     const uint32_t w2 = ((sa & 1) ? 3u : 2u) | (((sb & 1) ? 3u : 2u) << 16);
-    if (sh != prev_sh) {  // the shift pair changes only a few times over S = 1..15
+    // the shift pair changes only a few times over S = 1..15; a subset
+    // re-shifts at every strength it visits (cheaper than the per-lane
+    // selects the compiler makes of the test there)
+    if (SUB || sh != prev_sh) {
       prev_sh = sh;
 #pragma unroll
       for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
@@ -325,25 +328,18 @@ __device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, uint32
   for (int si = 1; si < 4; ++si)
     if (!SUB || ((pm & 1) && ((qm >> si) & 1))) sink(si, err_one<B12>(t, Q[si]));
   u16x2 a[4];
-  uint32_t prev_sh = 0xFFFFFFFFu;
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
     const int lg = S >= 8 ? 3 : S >= 4 ? 2 : S >= 2 ? 1 : 0;
     if (S == 8 && D == 3) secondaries(t, c, 3, Q);  // chroma damping becomes 3
     const int Dc = max(D - 1, lg);
-    if (SUB) {
-      // strengths may be skipped, so the shifted magnitudes follow the shift
-      if (!((pm >> S) & 1)) continue;
-      const uint32_t sh = (uint32_t)(Dc - lg);
-      if (sh != prev_sh) {
-        prev_sh = sh;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32(sh));
-      }
-    } else if (S == 1 || S == 2 || S == 4 || S == 8 || (S == 8 && D == 3)) {
+    // the shift changes only where floor(log2 S) does (compile-time), so the
+    // magnitudes are re-shifted there, also when a subset skips that S
+    if (S == 1 || S == 2 || S == 4 || S == 8) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(splat32((uint32_t)(Dc - lg)));
     }
+    if (SUB && !((pm >> S) & 1)) continue;
     const uint32_t w1 = splat32((S & 1) ? 3u : 4u), w2 = splat32((S & 1) ? 3u : 2u);
     const s16x2 P = group_sum(t, a, 0, splat32((uint32_t)S << c), w1, w2);
     if (!SUB || (qm & 1)) sink(4 * S, err_one<B12>(t, P));
