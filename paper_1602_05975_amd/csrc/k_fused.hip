@@ -89,15 +89,13 @@ __host__ __device__ constexpr TapTable make_tap_table(int stride) {
     }
   return t;
 }
-// Indexed with wave-uniform directions, so the reads are scalar loads.  Also
-// serves the 4:4:4 chroma tiles, which have the luma tile's stride.
-__constant__ TapTable kLumaTaps = make_tap_table(kLS);
 
-// The 12 tap samples around LDS index b of a tile with the luma stride, for
-// a compile-time direction D: from a base moved back by the taps' largest
-// reach (two rows and two columns), every tap is a positive load immediate,
-// so the loads need no address arithmetic.  Order: primary +inner, -inner,
-// +outer, -outer, then the same along d+2 and along d-2.
+// The 12 tap samples around LDS index b of a tile with the luma stride (also
+// the 4:4:4 chroma tiles' stride), for a compile-time direction D: from a
+// base moved back by the taps' largest reach (two rows and two columns),
+// every tap is a positive load immediate, so the loads need no address
+// arithmetic.  Order: primary +inner, -inner, +outer, -outer, then the same
+// along d+2 and along d-2.
 template <int D>
 __device__ __forceinline__ void tap_samples(const uint16_t *rt, int b, uint32_t (&v)[12]) {
   constexpr TapTable T = make_tap_table(kLS);
