@@ -51,7 +51,9 @@ typedef enum {
   CDEF_E_INVAL = -1,       /* bad argument (null pointer, size, range, aliasing) */
   CDEF_E_UNSUPPORTED = -2, /* valid CDEF input that this library does not handle */
   CDEF_E_HIP = -3,         /* the HIP runtime reported an error */
-  CDEF_E_NOMEM = -4        /* a caller-provided workspace is too small */
+  CDEF_E_NOMEM = -4,       /* a caller-provided workspace is too small */
+  CDEF_E_TIMEOUT = -5      /* never returned by a call: names the outcome of a device-side
+                              bounded wait that gave up (cdef_select_presets' result n == 0) */
 } cdef_status;
 
 /* Chroma layouts.  4:2:0 and 4:2:2 chroma planes are ceil(w/2) wide, 4:2:0

@@ -13,7 +13,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcdef_oracle.so")
+# CDEF_ORACLE_LIB selects another build of the same source (the sanitizer
+# run of the CPU tests loads an instrumented copy this way).
+LIB_PATH = os.environ.get("CDEF_ORACLE_LIB") or os.path.join(HERE, "libcdef_oracle.so")
 
 
 class OracleFrame(C.Structure):

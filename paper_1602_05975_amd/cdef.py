@@ -20,6 +20,7 @@ CDEF_E_INVAL = -1
 CDEF_E_UNSUPPORTED = -2
 CDEF_E_HIP = -3
 CDEF_E_NOMEM = -4
+CDEF_E_TIMEOUT = -5
 LAYOUT_400 = 0
 LAYOUT_420 = 1
 LAYOUT_422 = 2
@@ -497,7 +498,9 @@ def select_presets(sse, lam: float, refine_passes: int = 0, stream=None, workspa
     cdef_select_presets(sse, lam, refine_passes, res, fl, fc, ws, stream, cand_mask)
     r = CdefPresetResult.from_buffer_copy(res.cpu().numpy().tobytes())
     if r.n == 0:
-        raise CdefError("cdef_select_presets: the selection did not complete")
+        # the cooperative selection kernel gave up waiting for its workgroups
+        # (all of them must be resident at once; see cdef_select_presets)
+        raise CdefError(CDEF_E_TIMEOUT, "cdef_select_presets: the selection did not complete")
     return {"n": r.n, "luma": np.array(r.luma, dtype=np.int32),
             "chroma": np.array(r.chroma, dtype=np.int32),
             "dist": np.array([list(r.dist_luma), list(r.dist_chroma)], dtype=np.uint64),

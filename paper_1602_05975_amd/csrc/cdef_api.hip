@@ -358,6 +358,7 @@ const char *cdef_status_str(cdef_status s) {
     case CDEF_E_UNSUPPORTED: return "unsupported input";
     case CDEF_E_HIP: return "HIP runtime error";
     case CDEF_E_NOMEM: return "workspace too small";
+    case CDEF_E_TIMEOUT: return "a bounded device-side wait gave up";
   }
   return "unknown status";
 }

@@ -33,8 +33,28 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_status_strings(lib):
     from paper_1602_05975_amd import cdef
-    for s in (0, -1, -2, -3, -4, 7):
+    for s in (0, -1, -2, -3, -4, -5, 7):
         assert isinstance(cdef.status_str(s), str) and cdef.status_str(s)
+    assert len({cdef.status_str(s) for s in (0, -1, -2, -3, -4, -5, 7)}) == 7
+
+
+def test_select_presets_incomplete_result_raises(lib, monkeypatch):
+    # A result with n == 0 (the cooperative selection gave up waiting for its
+    # workgroups) must surface as a CdefError carrying CDEF_E_TIMEOUT.  The
+    # device call is replaced by a no-op, so the zero-filled result buffer
+    # reaches the result handling unchanged; host tensors stand in for device
+    # ones.
+    import torch
+    from paper_1602_05975_amd import cdef
+    calls = []
+    monkeypatch.setattr(cdef, "cdef_select_presets", lambda *a, **k: calls.append(a))
+    monkeypatch.setattr(cdef, "preset_workspace", lambda device="cuda": torch.empty(16, dtype=torch.uint8))
+    sse = torch.zeros((3, 2, 2, 16, 4), dtype=torch.int64)
+    with pytest.raises(cdef.CdefError) as e:
+        cdef.select_presets(sse, 1.0, 0)
+    assert e.value.status == cdef.CDEF_E_TIMEOUT
+    assert "did not complete" in str(e.value)
+    assert len(calls) == 1
 
 
 def _frame(w=64, h=64, bd=10, layout=1, stride=None, ptr=0x10000):

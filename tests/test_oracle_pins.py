@@ -308,6 +308,31 @@ def test_filter_pixel_hand_cases(oracle):
         assert got == int(expected), r
 
 
+def test_filter_frame_high_bitdepth_hand_cases(oracle):
+    # Section 3.2 above 8 bits, through the frame filter with signaled
+    # (8-bit-domain) strengths: Eq. (13) on the signaled luma strength,
+    # weights by its parity, then strengths << (b-8) and damping + (b-8),
+    # including the 12-bit damping range 7..10 and the chroma damping rule.
+    rows = _golden_rows("filter_hbd_cases.txt")
+    assert len(rows) >= 10
+    for r in rows:
+        head, changes, expected = [p.strip() for p in r.split("|")]
+        (bd, layout, plane, D, py, sy, puv, suv, d, var, base, ci, cj) = map(int, head.split())
+        w = h = 16
+        cw = w // 2 if layout == 1 else w
+        planes = [np.full((h, w), base, np.uint16)]
+        if layout == 1:
+            planes += [np.full((h // 2, cw), base, np.uint16) for _ in range(2)]
+        for ch in changes.split(";"):
+            dr, dc, v = map(int, ch.split())
+            planes[plane][ci + dr, cj + dc] = v
+        dirs = np.full((2, 2), d, np.uint8)
+        vars_ = np.full((2, 2), var, np.int32)
+        st = np.array([[[py, sy, puv, suv]]], np.uint8)
+        out = oracle.filter_frame(planes, w, h, bd, dirs, vars_, None, D, st, layout=layout)
+        assert int(out[plane][ci, cj]) == int(expected), r
+
+
 def _uniform_strengths(w, h, pri_y, sec_y, pri_uv, sec_uv):
     st = np.zeros(((h + 63) // 64, (w + 63) // 64, 4), np.uint8)
     st[...] = (pri_y, sec_y, pri_uv, sec_uv)
