@@ -214,6 +214,76 @@ def random_presets(frame: Frame, seed: int, p_skipcond: float = 0.5,
     return out
 
 
+# Inputs that reach the method's degenerate cases and the arithmetic limits
+# of a fixed-width implementation: flat planes, the largest possible
+# |recon - source| in both signs, two-level stripes and checkerboards (equal
+# line costs for several directions), and full-range noise.
+EDGE_KINDS = ("constant", "extreme_hi", "extreme_lo", "stripes", "checker", "noise", "binary")
+
+
+def _edge_plane(kind: str, rng: np.random.Generator, w: int, h: int, maxv: int):
+    """(recon, source) of one plane for an edge-case kind."""
+    def noise():
+        return rng.integers(0, maxv + 1, size=(h, w))
+
+    if kind == "constant":
+        a, b = (int(x) for x in rng.integers(0, maxv + 1, 2))
+        return np.full((h, w), a), np.full((h, w), b)
+    if kind == "extreme_hi":
+        return np.full((h, w), maxv), np.zeros((h, w), np.int64)
+    if kind == "extreme_lo":
+        return np.zeros((h, w), np.int64), np.full((h, w), maxv)
+    if kind == "noise":
+        return noise(), noise()
+    if kind == "binary":
+        return maxv * rng.integers(0, 2, size=(h, w)), noise()
+    # two-level patterns per 8x8 region of the plane
+    yy, xx = np.mgrid[0:h, 0:w]
+    rec = np.zeros((h, w), np.int64)
+    for ry in range(0, h, 8):
+        for rx in range(0, w, 8):
+            y = yy[ry:ry + 8, rx:rx + 8]
+            x = xx[ry:ry + 8, rx:rx + 8]
+            lo, hi = (int(v) for v in rng.integers(0, maxv + 1, 2))
+            if kind == "stripes":
+                period = int(rng.integers(1, 5))
+                orient = int(rng.integers(0, 4))
+                coord = (y, x, x + y, x - y + 64)[orient]
+                on = (coord // period) % 2
+            else:  # checker
+                cell = int((1, 2, 4)[rng.integers(0, 3)])
+                on = (y // cell + x // cell) % 2
+            rec[ry:ry + 8, rx:rx + 8] = np.where(on == 1, hi, lo)
+    src = noise() if kind == "stripes" else np.full((h, w), (maxv + 1) // 2)
+    return rec, src
+
+
+def edge_frame(kind: str, width: int, height: int, bitdepth: int, layout: int, seed: int,
+               damping: int = 3, skip_prob: float = 0.3) -> Frame:
+    """A seeded frame of one of EDGE_KINDS.  The skip map is Bernoulli
+    (skip_prob) per 8x8 block, with every block of filter block (0, 1)
+    skipped and none of filter block (1, 0), where those exist."""
+    assert kind in EDGE_KINDS, kind
+    nplanes = 1 if layout == LAYOUT_400 else 3
+    sx, sy = chroma_shift(layout)
+    maxv = (1 << bitdepth) - 1
+    src, recon = [], []
+    for p in range(nplanes):
+        rng = np.random.Generator(np.random.PCG64([seed, p, 17]))
+        w, h = (width, height) if p == 0 else ((width + sx) >> sx, (height + sy) >> sy)
+        r, s = _edge_plane(kind, rng, w, h, maxv)
+        recon.append(np.ascontiguousarray(r.astype(np.uint16)))
+        src.append(np.ascontiguousarray(s.astype(np.uint16)))
+    brows, bcols = (height + 7) // 8, (width + 7) // 8
+    rng = np.random.Generator(np.random.PCG64([seed, 7, 17]))
+    skip = (rng.random((brows, bcols)) < skip_prob).astype(np.uint8)
+    if bcols > 8:
+        skip[0:8, 8:16] = 1
+    if brows > 8:
+        skip[8:16, 0:8] = 0
+    return Frame(width, height, bitdepth, layout, src, recon, skip, damping, seed)
+
+
 def cif_luma() -> Frame:
     """352x288 8-bit luma, filtered with (pri 4, sec 2) and damping 5."""
     return make_frame(352, 288, 8, LAYOUT_400, workload_seed(WL_CIF, 0), damping=5)

@@ -98,9 +98,11 @@ def test_mixed_batch_matches_per_frame_and_oracle(oracle):
         assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
 
 
-def test_mixed_batch_matches_per_frame_launches(oracle):
-    # 64 frames, resolutions from 426x240 to 3840x2160, 8- and 10-bit, damping
-    # 3..6, full search: one launch vs 64 cdef_search_strengths launches.
+@pytest.fixture(scope="module")
+def mixed64():
+    """The 64-frame uneven batch (resolutions 426x240 .. 3840x2160, 8 and 10
+    bits, damping 3..6, 4:2:0, no skip map, 64-pair search) in one launch;
+    every entry also equals the frame's own cdef_search_strengths launch."""
     import torch
     from paper_1602_05975_amd import cdef
     s = _synth()
@@ -117,19 +119,33 @@ def test_mixed_batch_matches_per_frame_launches(oracle):
     print(f"mixed 64-frame batch: {b.nitems} filter blocks", flush=True)
     b.launch()
     torch.cuda.synchronize()
-    rng = np.random.default_rng(3)
+    out = []
     for k, (fr, (sse, d, v), (rec, src)) in enumerate(zip(frames, res, ins)):
-        ref = cdef.search_strengths(rec, src, None, fr.damping)
+        ref, d1, v1 = cdef.search_strengths(rec, src, None, fr.damping, want_dir=True)
         torch.cuda.synchronize()
-        assert torch.equal(sse, ref), k
-        if k % 8 == 0:  # oracle on two sampled filter blocks of every eighth frame
-            fbs = [(int(rng.integers(0, fr.fb_rows)), int(rng.integers(0, fr.fb_cols))),
-                   (fr.fb_rows - 1, fr.fb_cols - 1)]
-            t, od, ov, _ = oracle_search(oracle, fr, skip=False, fbs=fbs)
-            got = sse.cpu().numpy().view(np.uint64)
-            for i, (by, bx) in enumerate(fbs):
-                assert (got[:, by, bx] == t[i]).all()
-            assert (d.cpu().numpy() == od).all()
+        assert torch.equal(sse, ref) and torch.equal(d, d1) and torch.equal(v, v1), k
+        out.append((sse.cpu().numpy().view(np.uint64), d.cpu().numpy(), v.cpu().numpy()))
+    return frames, out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("part", range(4))
+def test_mixed_batch_every_block_matches_oracle(oracle, mixed64, part):
+    # every direction, contrast and SSE of every fourth frame of the batch
+    # (starting at `part`) against the oracle on all host threads
+    from helpers import ORACLE_THREADS
+    frames, out = mixed64
+    for k in range(part, len(frames), 4):
+        fr = frames[k]
+        got, d, v = out[k]
+        print(f"oracle on frame {k}: {fr.width}x{fr.height} {fr.bitdepth}-bit D={fr.damping}",
+              flush=True)
+        ref, od, ov = oracle.search(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, None,
+                                    fr.damping, threads=ORACLE_THREADS)
+        assert (d == od).all() and (v == ov).all(), k
+        if not np.array_equal(got, ref):
+            bad = np.argwhere(got != ref)
+            raise AssertionError(f"frame {k}: {len(bad)} SSEs differ, first {tuple(bad[0])}")
 
 
 def test_batch_graph_capture_replays():

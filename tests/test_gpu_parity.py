@@ -139,27 +139,12 @@ def test_search_1080p_full(oracle):
     _compare_search(oracle, fr, skip=False)
 
 
-def test_search_4k_sampled(oracle):
-    # 3840x2160 10-bit 4:2:0 with 30 % skipped blocks, one frame per launch as
-    # the benchmark runs it; filter blocks sampled (every edge block plus a
-    # seeded random set), directions compared everywhere.
-    s = _synth()
-    frames = s.uhd4k_frames(2)
-    rng = np.random.default_rng(2)
-    for fr in frames:
-        fbr, fbc = fr.fb_rows, fr.fb_cols
-        fbs = {(fbr - 1, bx) for bx in range(0, fbc, 7)} | {(by, fbc - 1) for by in range(fbr)}
-        fbs |= {(int(rng.integers(0, fbr)), int(rng.integers(0, fbc))) for _ in range(40)}
-        print(f"search 3840x2160 seed {fr.seed}", flush=True)
-        _compare_search(oracle, fr, fbs=sorted(fbs))
-
-
-def test_search_4k_batched_as_benchmarked(oracle):
-    # The benchmarked launch: the eight 3840x2160 frames in one batch with the
-    # default plan.  Every entry equals the one-frame launches; filter blocks
-    # of every frame (its edges and a seeded random set) equal the oracle.
+@pytest.fixture(scope="module")
+def uhd_batch():
+    """The benchmarked launch: the eight 3840x2160 10-bit 4:2:0 frames (30 %
+    of blocks skipped, damping 3) in one batch with the default plan; every
+    entry also equals the frame's own cdef_search_strengths launch."""
     import torch
-    from helpers import ORACLE_THREADS
     from paper_1602_05975_amd import cdef
     s = _synth()
     frames = s.uhd4k_frames(8)
@@ -178,22 +163,33 @@ def test_search_4k_batched_as_benchmarked(oracle):
     print("search 8 x 3840x2160 in one batched launch", flush=True)
     b.launch()
     torch.cuda.synchronize()
-    rng = np.random.default_rng(22)
+    res = []
     for fr, (rec, src, sk, t, d, v) in zip(frames, outs):
         one, d1, v1 = cdef.search_strengths(rec, src, sk, fr.damping, want_dir=True)
         torch.cuda.synchronize()
         assert torch.equal(one, t) and torch.equal(d1, d) and torch.equal(v1, v)
-        od, ov = oracle.find_dir(fr.recon[0], fr.bitdepth)
-        assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
-        fbr, fbc = fr.fb_rows, fr.fb_cols
-        fbs = {(0, 0), (fbr - 1, fbc - 1), (fbr - 1, 0), (0, fbc - 1)}
-        fbs |= {(int(rng.integers(0, fbr)), int(rng.integers(0, fbc))) for _ in range(6)}
-        fbs = sorted(fbs)
-        ref = oracle.search_fbs(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, od, ov,
-                                fr.skip, fr.damping, fbs, threads=ORACLE_THREADS)
-        got = t.cpu().numpy().view(np.uint64)
-        for k, (by, bx) in enumerate(fbs):
-            assert (got[:, by, bx] == ref[k]).all(), (fr.seed, by, bx)
+        res.append((t.cpu().numpy().view(np.uint64), d.cpu().numpy(), v.cpu().numpy()))
+    return frames, res
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("k", range(8))
+def test_search_4k_batched_every_block(oracle, uhd_batch, k):
+    # every direction, contrast and SSE of frame k of the benchmarked batch
+    # (2,040 filter blocks x 3 planes x 64 pairs) against the oracle, which
+    # runs on all host threads
+    from helpers import ORACLE_THREADS
+    frames, res = uhd_batch
+    fr = frames[k]
+    got, d, v = res[k]
+    print(f"oracle on every filter block of 3840x2160 frame {k} (seed {fr.seed})", flush=True)
+    ref, od, ov = oracle.search(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, fr.skip,
+                                fr.damping, threads=ORACLE_THREADS)
+    assert (d == od).all() and (v == ov).all()
+    if not np.array_equal(got, ref):
+        bad = np.argwhere(got != ref)
+        raise AssertionError(f"{len(bad)} SSEs differ, first {tuple(bad[0])}: "
+                             f"gpu {got[tuple(bad[0])]} oracle {ref[tuple(bad[0])]}")
 
 
 @pytest.mark.parametrize("w,h", [(65536, 72), (24, 65536)])
