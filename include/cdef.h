@@ -335,6 +335,29 @@ cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb
                                 uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
                                 void *stream);
 
+/* For callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid allocation):
+ * cdef_select_presets without the workspace argument.  Results are those of
+ * cdef_select_presets with the same other arguments.
+ *   The workspace is a library-owned device array of
+ *   CDEF_PRESET_SCRATCH_BYTES bytes, one per device, held from the first
+ *   call on that device until the process ends.  It has the same size for
+ *   every table (the selection's limit of 2^24 filter blocks still applies:
+ *   CDEF_E_UNSUPPORTED beyond it).  Every call on one device uses the same
+ *   array and starts by clearing what must start at zero, so calls that may
+ *   overlap on one device -- on different streams, or from threads without
+ *   ordering -- race and must be serialized by the caller (e.g. one stream).
+ *   The array lives on the device of `stream` (the current device for NULL).
+ * Allocates nothing: no hipMalloc/hipFree, no host synchronization.
+ * Errors: as cdef_select_presets (without the workspace checks), and
+ * CDEF_E_HIP if the array's device address cannot be obtained. */
+#define CDEF_PRESET_SCRATCH_BYTES 20480
+cdef_status cdef_select_presets_noalloc(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
+                                        int32_t fb_cols, int32_t ncand,
+                                        const uint64_t *cand_mask, double lambda,
+                                        int32_t refine_passes, cdef_preset_result *result,
+                                        uint8_t *fb_luma, uint8_t *fb_chroma, void *stream);
+
 /* Human-readable name of a status code (static storage, never NULL). */
 const char *cdef_status_str(cdef_status s);
 

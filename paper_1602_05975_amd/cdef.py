@@ -41,6 +41,7 @@ EXPORTS = (
     "cdef_job_validate",
     "cdef_select_presets",
     "cdef_select_presets_workspace_bytes",
+    "cdef_select_presets_noalloc",
     "cdef_status_str",
     "cdef_abi_version",
 )
@@ -155,6 +156,9 @@ def load(path: str = LIB_PATH):
     L.cdef_select_presets_workspace_bytes.argtypes = []
     L.cdef_select_presets_workspace_bytes.restype = C.c_size_t
     L.cdef_select_presets.restype = C.c_int
+    L.cdef_select_presets_noalloc.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P,
+                                              C.c_double, C.c_int32, P, P, P, P]
+    L.cdef_select_presets_noalloc.restype = C.c_int
     L.cdef_status_str.argtypes = [C.c_int]
     L.cdef_status_str.restype = C.c_char_p
     L.cdef_abi_version.argtypes = []
@@ -475,6 +479,22 @@ def cdef_select_presets(sse, lam: float, refine_passes: int, result, fb_luma, fb
                                     _ptr(workspace), workspace.numel() * workspace.element_size(),
                                     _stream_handle(stream))
     _check(st, "cdef_select_presets")
+
+
+def cdef_select_presets_noalloc(sse, lam: float, refine_passes: int, result, fb_luma, fb_chroma,
+                                stream=None, cand_mask=None) -> None:
+    """cdef_select_presets on the library's own per-device workspace (no
+    allocation anywhere; calls that may overlap on one device race)."""
+    nplanes, fbr, fbc = sse.shape[0], sse.shape[1], sse.shape[2]
+    ncand = 1
+    for n in sse.shape[3:]:
+        ncand *= n
+    cm = None if cand_mask is None else (C.c_uint64 * 2)(*cand_mask)
+    st = load().cdef_select_presets_noalloc(_ptr(sse), nplanes, fbr, fbc, ncand,
+                                            None if cm is None else C.addressof(cm), float(lam),
+                                            refine_passes, _ptr(result), _ptr(fb_luma),
+                                            _ptr(fb_chroma), _stream_handle(stream))
+    _check(st, "cdef_select_presets_noalloc")
 
 
 def preset_workspace(device="cuda"):

@@ -13,6 +13,7 @@
 static_assert(sizeof(cdef_preset_result) == sizeof(cdef::PresetResult), "preset result layout");
 static_assert(offsetof(cdef_preset_result, cost) == offsetof(cdef::PresetResult, cost),
               "preset result layout");
+static_assert(CDEF_PRESET_SCRATCH_BYTES == cdef::kPresetScratchBytes, "preset scratch size");
 static_assert(CDEF_LAYOUT_400 == cdef::kLayout400 && CDEF_LAYOUT_420 == cdef::kLayout420 &&
                   CDEF_LAYOUT_422 == cdef::kLayout422 && CDEF_LAYOUT_444 == cdef::kLayout444,
               "layouts");
@@ -322,18 +323,22 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
 
 size_t cdef_select_presets_workspace_bytes(void) { return cdef::preset_workspace_bytes(); }
 
-cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
-                                int32_t fb_cols, int32_t ncand, const uint64_t *cand_mask,
-                                double lambda, int32_t refine_passes,
-                                cdef_preset_result *result, uint8_t *fb_luma,
-                                uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
-                                void *stream) {
-  if (!sse || !result || !fb_luma || !fb_chroma || !workspace) return CDEF_E_INVAL;
-  if (workspace_bytes < cdef::preset_workspace_bytes() || ((uintptr_t)workspace & 255))
-    return CDEF_E_INVAL;
+}  // extern "C"
+
+namespace {
+
+// Host-side checks of a selection's arguments other than the workspace;
+// fills the candidate mask and the number of filter blocks.
+cdef_status check_selection(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
+                            int32_t fb_cols, int32_t ncand, const uint64_t *cand_mask,
+                            double lambda, int32_t refine_passes, cdef_preset_result *result,
+                            uint8_t *fb_luma, uint8_t *fb_chroma, uint64_t mask[2],
+                            int *nfb) {
+  if (!sse || !result || !fb_luma || !fb_chroma) return CDEF_E_INVAL;
   if (nplanes != 1 && nplanes != 3) return CDEF_E_INVAL;
   if (ncand != 64 && ncand != 128) return CDEF_E_INVAL;
-  uint64_t mask[2] = {~0ull, ncand == 128 ? ~0ull : 0ull};
+  mask[0] = ~0ull;
+  mask[1] = ncand == 128 ? ~0ull : 0ull;
   if (cand_mask) {
     mask[0] = cand_mask[0];
     mask[1] = ncand == 128 ? cand_mask[1] : 0ull;
@@ -342,13 +347,56 @@ cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb
   if (fb_rows < 1 || fb_cols < 1) return CDEF_E_INVAL;
   if (!(lambda >= 0.0) || !isfinite(lambda)) return CDEF_E_INVAL;
   if (refine_passes < 0 || refine_passes > 16) return CDEF_E_INVAL;
-  const int64_t nfb = (int64_t)fb_rows * fb_cols;
-  if (nfb > (1 << 24)) return CDEF_E_UNSUPPORTED;
-  return from_hip(cdef::launch_select_presets(sse, nplanes, (int)nfb, ncand, mask, lambda,
-                                              refine_passes,
-                                              reinterpret_cast<cdef::PresetResult *>(result),
-                                              fb_luma, fb_chroma, workspace,
-                                              (hipStream_t)stream));
+  const int64_t n = (int64_t)fb_rows * fb_cols;
+  if (n > (1 << 24)) return CDEF_E_UNSUPPORTED;
+  *nfb = (int)n;
+  return CDEF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cdef_status cdef_select_presets(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
+                                int32_t fb_cols, int32_t ncand, const uint64_t *cand_mask,
+                                double lambda, int32_t refine_passes,
+                                cdef_preset_result *result, uint8_t *fb_luma,
+                                uint8_t *fb_chroma, void *workspace, size_t workspace_bytes,
+                                void *stream) {
+  if (!workspace) return CDEF_E_INVAL;
+  if (workspace_bytes < cdef::preset_workspace_bytes() || ((uintptr_t)workspace & 255))
+    return CDEF_E_INVAL;
+  uint64_t mask[2];
+  int nfb = 0;
+  const cdef_status st = check_selection(sse, nplanes, fb_rows, fb_cols, ncand, cand_mask,
+                                         lambda, refine_passes, result, fb_luma, fb_chroma,
+                                         mask, &nfb);
+  if (st != CDEF_OK) return st;
+  return from_hip(cdef::launch_select_presets(
+      sse, nplanes, nfb, ncand, mask, lambda, refine_passes,
+      reinterpret_cast<cdef::PresetResult *>(result), fb_luma, fb_chroma, workspace,
+      (hipStream_t)stream));
+}
+
+cdef_status cdef_select_presets_noalloc(const uint64_t *sse, int32_t nplanes, int32_t fb_rows,
+                                        int32_t fb_cols, int32_t ncand,
+                                        const uint64_t *cand_mask, double lambda,
+                                        int32_t refine_passes, cdef_preset_result *result,
+                                        uint8_t *fb_luma, uint8_t *fb_chroma, void *stream) {
+  uint64_t mask[2];
+  int nfb = 0;
+  const cdef_status st = check_selection(sse, nplanes, fb_rows, fb_cols, ncand, cand_mask,
+                                         lambda, refine_passes, result, fb_luma, fb_chroma,
+                                         mask, &nfb);
+  if (st != CDEF_OK) return st;
+  // the workspace has one size for every table, which the fixed scratch holds
+  if (cdef::preset_workspace_bytes() > cdef::kPresetScratchBytes) return CDEF_E_NOMEM;
+  void *scratch = nullptr;
+  if (cdef::preset_scratch((hipStream_t)stream, &scratch) != hipSuccess) return CDEF_E_HIP;
+  return from_hip(cdef::launch_select_presets(
+      sse, nplanes, nfb, ncand, mask, lambda, refine_passes,
+      reinterpret_cast<cdef::PresetResult *>(result), fb_luma, fb_chroma, scratch,
+      (hipStream_t)stream));
 }
 
 const char *cdef_status_str(cdef_status s) {

@@ -97,4 +97,10 @@ hipError_t launch_select_presets(const uint64_t *sse, int nplanes, int nfb, int 
                                  PresetResult *out, uint8_t *fb_luma, uint8_t *fb_chroma,
                                  void *workspace, hipStream_t s);
 
+// The library-owned workspace of the allocation-free selection: bytes of
+// device memory it holds per device, and its address on the device of
+// stream `s` (looked up on the first call for that device).
+constexpr size_t kPresetScratchBytes = 20480;
+hipError_t preset_scratch(hipStream_t s, void **ptr);
+
 }  // namespace cdef

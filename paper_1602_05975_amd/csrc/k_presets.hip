@@ -36,6 +36,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 namespace cdef {
 
 namespace {
@@ -422,6 +424,46 @@ __global__ __launch_bounds__(kNT) void k_preset_finish(const uint64_t *__restric
 }  // namespace
 
 size_t preset_workspace_bytes() { return sizeof(PresetWork); }
+
+// Workspace of the allocation-free selection (cdef_select_presets_noalloc):
+// a file-scope device array instead of caller memory.  Every device holds
+// its own copy, at its own address, until the process ends.  On the host
+// the array's name is only a stand-in for the symbol: kernels get the
+// address hipGetSymbolAddress returns for the device, never the name.
+static_assert(sizeof(PresetWork) <= kPresetScratchBytes, "selection workspace exceeds scratch");
+static __device__ __align__(256) unsigned char scratch[kPresetScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t preset_scratch(hipStream_t s, void **ptr) {
+  int dev = 0;
+  hipError_t e = s ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    // the symbol's address on `dev`, looked up with `dev` current
+    int cur = 0;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (((uintptr_t)p & 255) != 0) return hipErrorInvalidValue;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 namespace {
 

@@ -209,3 +209,25 @@ def test_subset_masks(lib):
     assert f(C.byref(r), C.byref(s), None, 3, 0xF0000 | (1 << 20), P, None, None, None) == -1
     assert f(C.byref(r), C.byref(s), None, 3, 0xFFFF | 0xF0000, P, None, None, None) == -1
     assert f(C.byref(r), C.byref(s), None, 7, w, P, None, None, None) == -1
+
+
+def test_select_presets_noalloc_argument_checks(lib):
+    # every host-side check runs before the library looks up its scratch, so
+    # a bad argument never reaches the device
+    P = C.c_void_p(0x10000)
+    f = lib.cdef_select_presets_noalloc
+
+    def call(sse=P, npl=3, fbr=2, fbc=2, nc=64, lam=1.0, ref=0, res=P, fl=P, fc=P, mask=None):
+        return f(sse, npl, fbr, fbc, nc, mask, lam, ref, res, fl, fc, None)
+
+    assert call(sse=None) == -1 and call(res=None) == -1
+    assert call(fl=None) == -1 and call(fc=None) == -1
+    assert call(npl=2) == -1 and call(nc=65) == -1
+    assert call(fbr=0) == -1 and call(fbc=-1) == -1
+    assert call(lam=-1.0) == -1 and call(lam=float("nan")) == -1
+    assert call(ref=17) == -1
+    assert call(npl=1, fbr=4097, fbc=4097) == -2
+    seven = (C.c_uint64 * 2)(0x7F, 0)
+    assert call(mask=C.addressof(seven)) == -1
+    assert lib.cdef_select_presets_workspace_bytes() <= 20480
+
