@@ -138,41 +138,91 @@ def synth_shift(layout):
     return synth.chroma_shift(layout)
 
 
-def cpu_baseline(fr, fb_rows: int = 0):
-    """The oracle, as it stands, on the first `fb_rows` filter-block rows of
-    one frame (0: all of them; direction search of those rows + the search of
-    their filter blocks), on all host cores the box gives this process (max
-    16).  One whole 4K frame is about 35 s of CPU time."""
-    from oracle import oracle
+def _host_facts():
+    """CPU model, logical CPUs, threads this process may use, the oracle's
+    compiler and flags."""
+    model = "unknown"
     try:
-        cores = len(os.sched_getaffinity(0))
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(16, cores))
+        usable = os.cpu_count() or 1
+    from oracle import build as oracle_build
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_threads": usable,
+            "oracle_build": "gcc " + " ".join(oracle_build.CFLAGS)}
+
+
+def cpu_baseline(fr, fb_rows: int = 0, single_rows: int = 3, other_configs: bool = True):
+    """The oracle, as it stands: on all host threads the box gives this
+    process (max 16) over the first `fb_rows` filter-block rows of one frame
+    (0: all; direction search of those rows + the search of their filter
+    blocks), single-threaded over its first `single_rows` rows, and on all
+    threads over the 1920x1080 10-bit search and the 352x288 8-bit filter.
+    One whole 4K frame is about 35 s of CPU time."""
+    from oracle import oracle
+    from paper_1602_05975_amd import synth
+    facts = _host_facts()
+    cores = max(1, min(16, facts["usable_threads"]))
+
+    def search_rows(f, rows_fb, threads):
+        rows = min(f.height, 64 * rows_fb)
+        t0 = time.perf_counter()
+        d, v = oracle.find_dir(np.ascontiguousarray(f.recon[0][:rows]), f.bitdepth)
+        dfull = np.zeros((f.blk_rows, f.blk_cols), np.uint8)
+        vfull = np.zeros((f.blk_rows, f.blk_cols), np.int32)
+        dfull[:d.shape[0]] = d
+        vfull[:v.shape[0]] = v
+        fbs = [(by, bx) for by in range(rows_fb) for bx in range(f.fb_cols)]
+        oracle.search_fbs(f.recon, f.src, f.width, f.height, f.bitdepth, dfull, vfull,
+                          f.skip, f.damping, fbs, threads=threads)
+        return rows * f.width, time.perf_counter() - t0, len(fbs)
+
     fb_rows = fb_rows or fr.fb_rows
-    rows = min(fr.height, 64 * fb_rows)
-    t0 = time.perf_counter()
-    d, v = oracle.find_dir(np.ascontiguousarray(fr.recon[0][:rows]), fr.bitdepth)
-    t_dir = time.perf_counter() - t0
-    dfull = np.zeros((fr.blk_rows, fr.blk_cols), np.uint8)
-    vfull = np.zeros((fr.blk_rows, fr.blk_cols), np.int32)
-    dfull[:d.shape[0]] = d
-    vfull[:v.shape[0]] = v
-    fbs = [(by, bx) for by in range(fb_rows) for bx in range(fr.fb_cols)]
-    t0 = time.perf_counter()
-    oracle.search_fbs(fr.recon, fr.src, fr.width, fr.height, fr.bitdepth, dfull, vfull,
-                      fr.skip, fr.damping, fbs, threads=cores)
-    t_search = time.perf_counter() - t0
-    px = rows * fr.width
-    return {
-        "value": px / (t_dir + t_search) / 1e6,
+    px, t_all, nfb = search_rows(fr, fb_rows, cores)
+    px1, t_one, nfb1 = search_rows(fr, single_rows, 1)
+    out = {
+        "value": px / t_all / 1e6,
         "unit": "Mpixel/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"{len(fbs)} filter blocks ({fb_rows} rows of 64) of one 3840x2160 10-bit "
+        "sample": f"{nfb} filter blocks ({fb_rows} rows of 64) of one 3840x2160 10-bit "
                   f"4:2:0 frame, 30% skip: direction search + all-pair search, "
-                  f"{t_dir + t_search:.1f} s wall on {cores} threads",
+                  f"{t_all:.1f} s wall on {cores} threads",
+        "single_thread": {"value": px1 / t_one / 1e6, "unit": "Mpixel/s", "cores": 1,
+                          "sample": f"{nfb1} filter blocks ({single_rows} rows of 64) of the "
+                                    f"same frame, {t_one:.1f} s"},
+        **facts,
     }
+    if other_configs:
+        hd = synth.hd1080_frame()
+        t0 = time.perf_counter()
+        oracle.search(hd.recon, hd.src, hd.width, hd.height, hd.bitdepth, None, hd.damping,
+                      threads=cores)
+        t_hd = time.perf_counter() - t0
+        out["search_1920x1080_10bit"] = {
+            "value": hd.width * hd.height / t_hd / 1e6, "unit": "Mpixel/s", "cores": cores,
+            "sample": f"the whole frame (510 filter blocks, no skip, damping 3), {t_hd:.2f} s"}
+        cif = synth.cif_luma()
+        st = np.zeros((cif.fb_rows, cif.fb_cols, 4), np.uint8)
+        st[..., 0], st[..., 1] = 4, 2
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            d, v = oracle.find_dir(cif.recon[0], 8)
+            oracle.filter_frame(cif.recon, cif.width, cif.height, 8, d, v, None, cif.damping, st)
+        t_cif = (time.perf_counter() - t0) / reps
+        out["filter_352x288_8bit"] = {
+            "value": cif.width * cif.height / t_cif / 1e6, "unit": "Mpixel/s", "cores": 1,
+            "sample": f"direction search + filter at (4, 2), damping 5, {t_cif * 1e3:.1f} ms "
+                      "per frame (single-threaded)"}
+    return out
 
 
 def load_traffic(kernel):
@@ -217,15 +267,15 @@ def _time_steps(fn, steps, warmup, stream):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def run_batching(args):
-    """The 64-frame uneven batch (resolutions 426x240 .. 3840x2160, 8/10 bit,
-    damping 3..6, full search): 64 per-frame launches vs one batched launch,
+def measure_batching(nframes: int = 64, steps: int = 10):
+    """The uneven batch (resolutions 426x240 .. 3840x2160, 8/10 bit,
+    damping 3..6, 64-pair search): per-frame launches vs one batched launch,
     tuned, eager and replayed from a captured HIP graph.  Results of all
     paths are compared bit for bit before timing."""
     import torch
     from paper_1602_05975_amd import cdef, synth, tune
-    log("generating the 64-frame mixed batch")
-    frames = synth.mixed_frames(64)
+    log(f"generating the {nframes}-frame mixed batch")
+    frames = synth.mixed_frames(nframes)
     dev = torch.device("cuda:0")
     jobs = _device_search_jobs(frames, dev)
     stream = torch.cuda.current_stream()
@@ -267,13 +317,12 @@ def run_batching(args):
     torch.cuda.synchronize()
     exact = exact and all(torch.equal(j[4], r) for j, r in zip(jobs, ref))
 
-    steps, warm = max(3, args.steps // 3), 2
-    log(f"timing {steps} steps of each path")
-    t_plain = _time_steps(plain, steps, warm, stream)
-    t_batch = _time_steps(lambda: batch.launch(stream), steps, warm, stream)
-    t_graph = _time_steps(graph.replay, steps, warm, stream)
-    res = {
-        "workload": "64 frames, resolutions uniform over 426x240..3840x2160, 8/10-bit, "
+    log(f"timing {steps} steps of each batching path")
+    t_plain = _time_steps(plain, steps, 2, stream)
+    t_batch = _time_steps(lambda: batch.launch(stream), steps, 2, stream)
+    t_graph = _time_steps(graph.replay, steps, 2, stream)
+    return {
+        "workload": f"{nframes} frames, resolutions uniform over 426x240..3840x2160, 8/10-bit, "
                     "damping 3..6, 4:2:0, full 64-pair search",
         "luma_px_per_step": px,
         "filter_blocks": batch.nitems,
@@ -288,7 +337,10 @@ def run_batching(args):
         "tuned_variant": best,
         "variant_ms": {tune.VARIANT_NAMES[k]: round(v, 4) for k, v in per_variant.items()},
     }
-    print(json.dumps(res), flush=True)
+
+
+def run_batching(args):
+    print(json.dumps(measure_batching(64, max(3, args.steps // 3))), flush=True)
 
 
 def run_filter(args):
@@ -445,6 +497,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-frames", type=int, default=64,
+                    help="frames of the uneven batch measured in the headline line (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="timed requests of the serving trace whose p50/p99 the headline "
+                         "line reports (0: skip; report the batch launch time instead)")
     ap.add_argument("--variant", type=int, default=0,
                     help="launch variant of the batched launch (cdef_batch_plan.variant: "
                          "0 / 1: at most 3 / 2 waves per SIMD, XCD-contiguous filter-block "
@@ -629,12 +686,6 @@ def main():
             "frames_per_step": len(frames),
             "luma_px_per_step": px_per_step,
         },
-        "frame_latency_ms": {
-            "p50": round(float(np.percentile(frame_ms, 50)), 4),
-            "p99": round(float(np.percentile(frame_ms, 99)), 4),
-            "note": "per-frame launch time" if batch is None else
-                    "batch launch time (all frames of a step complete together)",
-        },
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),
@@ -648,6 +699,27 @@ def main():
             "hbm_peak_gbs": PEAK_HBM_GBS,
         },
     }
+    result["batch_launch_ms"] = {
+        "p50": round(float(np.percentile(launch_ms, 50)), 4),
+        "p99": round(float(np.percentile(launch_ms, 99)), 4),
+        "note": "per-frame launch time" if batch is None else
+                "launch time of the whole step (all frames of a step complete together)"}
+    headline = args.workload == "search4k" and not args.per_frame
+    if headline and args.serve_requests > 0:
+        from paper_1602_05975_amd import serve
+        tr = serve.latency_summary(n_req=args.serve_requests, warm=max(20, args.serve_requests // 10))
+        result["frame_latency_ms"] = {
+            "p50": tr["batched"]["p50_ms"], "p99": tr["batched"]["p99_ms"],
+            "plain_p50": tr["plain"]["p50_ms"], "plain_p99": tr["plain"]["p99_ms"],
+            "p99_gain_vs_plain": tr["p99_gain"], "p50_gain_vs_plain": tr["p50_gain"],
+            "note": "serving trace: arrival to completion of each request, continuous batching "
+                    "vs one request per launch on the same Poisson arrivals at "
+                    f"{tr['rate_fraction_of_plain']} x the plain path's capacity"}
+        result["serving"] = tr
+    else:
+        result["frame_latency_ms"] = dict(result["batch_launch_ms"])
+    if headline and args.batch_frames > 0:
+        result["batching"] = measure_batching(args.batch_frames, 10)
     if not args.no_cpu_baseline and args.workload == "search4k":
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(frames[0])

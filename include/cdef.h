@@ -251,8 +251,16 @@ cdef_status cdef_job_validate(const cdef_job *job);
  *   0: at most 3 waves per SIMD (168 VGPRs), XCD-contiguous filter-block order
  *   1: at most 2 waves per SIMD (256 VGPRs), XCD-contiguous order
  *   2: 3 waves per SIMD, plain order
- *   3: 2 waves per SIMD, plain order */
-#define CDEF_BATCH_VARIANTS 4
+ *   3: 2 waves per SIMD, plain order
+ *   4: persistent workgroups at 3 waves per SIMD: as many as fit on the
+ *      device at once, each taking filter blocks from work queues (one
+ *      contiguous range of filter blocks per XCD; a workgroup whose range is
+ *      used up takes from the others) until none is left
+ *   5: the same at 2 waves per SIMD
+ * Variants 4 and 5 keep their queue counters in the batch workspace and
+ * reset them as the launch ends: launches of one prepared batch in these
+ * variants must not overlap (issue them on one stream, or order them). */
+#define CDEF_BATCH_VARIANTS 6
 
 /* Bytes of device workspace (and of pinned host staging, if used) for a
  * batch of njobs; 0 for njobs < 1. */
@@ -263,7 +271,8 @@ size_t cdef_batch_workspace_bytes(int32_t njobs);
  * host_staging: pinned host memory of the same size, owned by the caller;
  * the upload is then an asynchronous copy on `stream` and the caller must
  * leave the staging untouched until the stream has passed it.  With
- * host_staging NULL the upload is synchronous.  Errors: CDEF_E_INVAL for a
+ * host_staging NULL the call waits until the upload is done.  Either way the
+ * upload is ordered on `stream` after the work already there.  Errors: CDEF_E_INVAL for a
  * bad job (its index is not reported), CDEF_E_NOMEM if the workspace is too
  * small; nothing is enqueued on error. */
 cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_staging,
@@ -275,6 +284,39 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
  * copies, no allocation), so it can be captured in a HIP graph and replayed
  * while the workspace and all job buffers stay valid. */
 cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream);
+
+/* Launch parameters of a batch, as a tuner chooses them.
+ *   tile_w, tile_h: the work unit; the 64x64 filter block of Section 4 is
+ *                   the only one (0 = default; anything else is
+ *                   CDEF_E_UNSUPPORTED).
+ *   wg_per_cu:      workgroups (of 4 waves) resident per CU, i.e. waves per
+ *                   SIMD: 3 (168 VGPRs) or 2 (256 VGPRs); 0 = 3.  The
+ *                   extended kernels (weighted search, 4:4:4) always run 2.
+ *   cand_group:     strength pairs evaluated per pass over a filter block;
+ *                   all 64 at once is the only grouping (0 = default).
+ *   order:          0 = XCD-contiguous filter blocks, 1 = plain order.
+ *   persistent:     1 = persistent workgroups on work queues (order 0 only). */
+typedef struct {
+  int32_t tile_w, tile_h, wg_per_cu, cand_group, order, persistent;
+} cdef_tuning;
+
+/* The launch variant (above) of a tuning.  Errors: CDEF_E_INVAL for a null
+ * argument or an order/persistent value other than 0/1, CDEF_E_UNSUPPORTED
+ * for a tile, grouping or occupancy the kernels do not have. */
+cdef_status cdef_tuning_variant(const cdef_tuning *t, int32_t *variant);
+
+/* cdef_batch_prepare + cdef_batch_launch in one call: validate the n jobs,
+ * upload their table to `workspace` (device, at least
+ * cdef_batch_workspace_bytes(n) bytes) in order on `stream`, wait for that
+ * upload, and launch in the variant of `t` (NULL: variant 0; the Python
+ * binding's tuner supplies a cached tuning).  The library allocates no
+ * device memory; the caller owns the workspace, which must outlive the
+ * launch.  Errors: those of cdef_tuning_variant and cdef_batch_prepare
+ * (nothing is enqueued on error), CDEF_E_HIP from the copy or the launch.
+ * The prepare/launch pair remains the form to use under HIP graph capture
+ * (the copy and the wait cannot be captured). */
+cdef_status cdef_search_batch(const cdef_job *jobs, int32_t n, const cdef_tuning *t,
+                              void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---- Preset selection -------------------------------------------------------
  * Section 5, Eq. (15): choose the frame's presets from a strength-search SSE

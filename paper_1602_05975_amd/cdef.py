@@ -38,6 +38,8 @@ EXPORTS = (
     "cdef_batch_workspace_bytes",
     "cdef_batch_prepare",
     "cdef_batch_launch",
+    "cdef_tuning_variant",
+    "cdef_search_batch",
     "cdef_job_validate",
     "cdef_select_presets",
     "cdef_select_presets_workspace_bytes",
@@ -92,6 +94,14 @@ class CdefBatchPlan(C.Structure):
         ("variant", C.c_int32),
         ("flags", C.c_int32),
     ]
+
+
+class CdefTuning(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("cand_group", C.c_int32), ("order", C.c_int32), ("persistent", C.c_int32)]
+
+
+BATCH_VARIANTS = 6
 
 
 class CdefPresetResult(C.Structure):
@@ -149,6 +159,11 @@ def load(path: str = LIB_PATH):
     L.cdef_batch_prepare.restype = C.c_int
     L.cdef_batch_launch.argtypes = [C.POINTER(CdefBatchPlan), P]
     L.cdef_batch_launch.restype = C.c_int
+    L.cdef_tuning_variant.argtypes = [C.POINTER(CdefTuning), C.POINTER(C.c_int32)]
+    L.cdef_tuning_variant.restype = C.c_int
+    L.cdef_search_batch.argtypes = [C.POINTER(CdefJob), C.c_int32, C.POINTER(CdefTuning), P,
+                                    C.c_size_t, P]
+    L.cdef_search_batch.restype = C.c_int
     L.cdef_job_validate.argtypes = [C.POINTER(CdefJob)]
     L.cdef_job_validate.restype = C.c_int
     L.cdef_select_presets.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P,
@@ -459,6 +474,36 @@ class Batch:
     @property
     def nitems(self) -> int:
         return self.plan.nitems
+
+
+def tuning(wg_per_cu=0, order=0, persistent=0) -> CdefTuning:
+    t = CdefTuning()
+    t.wg_per_cu, t.order, t.persistent = wg_per_cu, order, persistent
+    return t
+
+
+def tuning_variant(t: CdefTuning) -> int:
+    v = C.c_int32()
+    _check(load().cdef_tuning_variant(C.byref(t), C.byref(v)), "cdef_tuning_variant")
+    return v.value
+
+
+def cdef_search_batch(jobs: Sequence[CdefJob], t: Optional[CdefTuning], workspace,
+                      stream=None) -> None:
+    """Validate, upload and launch a batch in one call (the caller keeps the
+    jobs' tensors and the workspace alive until the stream has passed it)."""
+    n = len(jobs)
+    arr = (CdefJob * n)(*jobs)
+    st = load().cdef_search_batch(arr, n, None if t is None else C.byref(t), _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(),
+                                  _stream_handle(stream))
+    _check(st, "cdef_search_batch")
+
+
+def batch_workspace(njobs: int, device="cuda"):
+    import torch
+    return torch.empty(load().cdef_batch_workspace_bytes(max(1, njobs)), dtype=torch.uint8,
+                       device=device)
 
 
 # ---- preset selection (Section 5, Eq. 15) -------------------------------------

@@ -271,7 +271,7 @@ cdef_status cdef_job_validate(const cdef_job *job) {
 }
 
 size_t cdef_batch_workspace_bytes(int32_t njobs) {
-  return njobs < 1 ? 0 : (size_t)njobs * sizeof(cdef::JobDesc);
+  return njobs < 1 ? 0 : cdef::batch_queue_offset(njobs) + sizeof(cdef::BatchQueue);
 }
 
 cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_staging,
@@ -283,6 +283,8 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
   cdef::JobDesc *table = host_staging ? (cdef::JobDesc *)host_staging
                                       : (cdef::JobDesc *)malloc(need);
   if (!table) return CDEF_E_NOMEM;
+  // the persistent kernels' queue counters start at zero
+  memset((char *)table + cdef::batch_queue_offset(njobs), 0, sizeof(cdef::BatchQueue));
   int64_t items = 0;
   int32_t flags = 2;
   cdef_status st = CDEF_OK;
@@ -297,10 +299,12 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
     }
   }
   if (st == CDEF_OK) {
-    hipError_t e = host_staging
-                       ? hipMemcpyAsync(workspace, table, need, hipMemcpyHostToDevice,
-                                        (hipStream_t)stream)
-                       : hipMemcpy(workspace, table, need, hipMemcpyHostToDevice);
+    // ordered on `stream` after the work already there (an earlier launch
+    // may still read a table in this workspace); without staging the call
+    // waits for the copy, so the temporary table can be freed
+    hipError_t e =
+        hipMemcpyAsync(workspace, table, need, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e == hipSuccess && !host_staging) e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) st = CDEF_E_HIP;
   }
   if (!host_staging) free(table);
@@ -316,9 +320,44 @@ cdef_status cdef_batch_prepare(const cdef_job *jobs, int32_t njobs, void *host_s
 cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream) {
   if (!plan || !plan->table || plan->njobs < 1 || plan->nitems < 1) return CDEF_E_INVAL;
   if (plan->variant < 0 || plan->variant >= CDEF_BATCH_VARIANTS) return CDEF_E_INVAL;
+  cdef::BatchQueue *queue = reinterpret_cast<cdef::BatchQueue *>(
+      (char *)const_cast<void *>(plan->table) + cdef::batch_queue_offset(plan->njobs));
   return from_hip(cdef::launch_fused_batch((const cdef::JobDesc *)plan->table, plan->njobs,
                                            plan->nitems, plan->variant, (plan->flags & 1) != 0,
-                                           (plan->flags & 2) != 0, (hipStream_t)stream));
+                                           (plan->flags & 2) != 0, queue, (hipStream_t)stream));
+}
+
+cdef_status cdef_tuning_variant(const cdef_tuning *t, int32_t *variant) {
+  if (!t || !variant) return CDEF_E_INVAL;
+  if ((t->tile_w != 0 && t->tile_w != 64) || (t->tile_h != 0 && t->tile_h != 64))
+    return CDEF_E_UNSUPPORTED;
+  if (t->cand_group != 0 && t->cand_group != 64) return CDEF_E_UNSUPPORTED;
+  if (t->wg_per_cu != 0 && t->wg_per_cu != 2 && t->wg_per_cu != 3) return CDEF_E_UNSUPPORTED;
+  if (t->order != 0 && t->order != 1) return CDEF_E_INVAL;
+  if (t->persistent != 0 && t->persistent != 1) return CDEF_E_INVAL;
+  const int two = t->wg_per_cu == 2;
+  if (t->persistent) {
+    if (t->order != 0) return CDEF_E_UNSUPPORTED;  // the queues are XCD-contiguous
+    *variant = two ? 5 : 4;
+  } else {
+    *variant = (t->order ? 2 : 0) + two;
+  }
+  return CDEF_OK;
+}
+
+cdef_status cdef_search_batch(const cdef_job *jobs, int32_t n, const cdef_tuning *t,
+                              void *workspace, size_t workspace_bytes, void *stream) {
+  int32_t variant = 0;
+  if (t) {
+    const cdef_status st = cdef_tuning_variant(t, &variant);
+    if (st != CDEF_OK) return st;
+  }
+  cdef_batch_plan plan;
+  const cdef_status st =
+      cdef_batch_prepare(jobs, n, nullptr, workspace, workspace_bytes, &plan, stream);
+  if (st != CDEF_OK) return st;
+  plan.variant = variant;
+  return cdef_batch_launch(&plan, stream);
 }
 
 size_t cdef_select_presets_workspace_bytes(void) { return cdef::preset_workspace_bytes(); }

@@ -62,8 +62,25 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s);
 // nitems the total number of filter blocks.
 // extended: some job needs the extended kernels (4:4:4, weighted);
 // filter_only: every job is a filter job (the filter-only kernels run it).
+// Work-queue counters of the persistent batch kernels, in the caller's
+// workspace after the job table: next[x][0] counts the items claimed from
+// XCD x's range, done[0] the workgroups that have left; each on its own
+// 128-byte line.  Zero before a launch; the last workgroup to leave sets
+// them back to zero.
+struct BatchQueue {
+  uint32_t next[8][32];
+  uint32_t done[32];
+};
+// Byte offset of the queue in a batch workspace of njobs descriptors.
+inline size_t batch_queue_offset(int njobs) {
+  return ((size_t)njobs * sizeof(JobDesc) + 255) & ~(size_t)255;
+}
+
+// variant: 0..3 flat grids (see cdef.h), 4 / 5 persistent workgroups at 3 /
+// 2 waves per SIMD taking items from `queue`.
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              bool extended, bool filter_only, hipStream_t s);
+                              bool extended, bool filter_only, BatchQueue *queue,
+                              hipStream_t s);
 bool job_needs_extended(const JobDesc &j);
 
 // The kernels behind launch_fused_one / launch_fused_batch, built in sets of
@@ -80,6 +97,10 @@ hipError_t launch_batch_base2_xcd(const JobDesc *jobs, int njobs, int nitems, hi
 hipError_t launch_batch_base2_seq(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
 hipError_t launch_batch_ext_xcd(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
 hipError_t launch_batch_ext_seq(const JobDesc *jobs, int njobs, int nitems, hipStream_t s);
+hipError_t launch_batch_queue_base(int occ, const JobDesc *jobs, int njobs, int nitems,
+                                   BatchQueue *queue, hipStream_t s);
+hipError_t launch_batch_queue_ext(const JobDesc *jobs, int njobs, int nitems, BatchQueue *queue,
+                                  hipStream_t s);
 
 void fill_job_geometry(JobDesc &j);
 

@@ -53,13 +53,14 @@
 // and y - s below 2^12, strength sums below 2^13) but the source is no
 // longer folded into the rounding offset (16 (x - s) would not fit), and the
 // last two levels of the cross-lane sums run in 64 bits.
+#include <atomic>
 #include <type_traits>
 
 #include "cdef_device.hpp"
 #include "cdef_launch.hpp"
 
 // The kernels are built in sets, one translation unit of this source per
-// set (CDEF_KSET = 0..6) so that they compile in parallel; without
+// set (CDEF_KSET = 0..8) so that they compile in parallel; without
 // CDEF_KSET every set is built into one object.
 #ifndef CDEF_KSET
 #define CDEF_KSET -1
@@ -1541,6 +1542,105 @@ CDEF_BATCH_LAUNCHER(launch_batch_ext_seq, 2, false, true)
 #endif
 #undef CDEF_BATCH_LAUNCHER
 
+// Persistent batch: as many workgroups as fit on the device at once, each
+// taking filter blocks from a work queue until none is left.  The items are
+// split into 8 contiguous ranges, one per XCD (workgroups are dealt to the
+// XCDs round-robin, so workgroup w runs on XCD w mod 8 and its range's halo
+// rows stay in that XCD's L2); a workgroup whose range is used up goes on
+// to the next ranges in turn, so no XCD idles while another still has
+// items.  Claims are atomic increments of one counter per range; a range
+// that returned an index past its end is never asked again.  The last
+// workgroup to leave resets the counters, so launches of one batch must not
+// overlap.
+template <int OCC, bool X>
+__global__ __launch_bounds__(256, OCC) void k_fused_batch_queue(const JobDesc *__restrict__ jobs,
+                                                                int njobs, int nitems,
+                                                                BatchQueue *q) {
+  __shared__ __align__(16) SmemT<X> sm;
+  __shared__ int claimed;
+  const int per = nitems >> 3, rem = nitems & 7;
+  int r = blockIdx.x & 7;  // thread 0: the range it is drawing from
+  int ranges_left = 8;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int item = -1;
+      while (ranges_left > 0) {
+        const int len = per + (r < rem);
+        const uint32_t k = atomicAdd(&q->next[r][0], 1u);
+        if ((int)k < len) {
+          item = r * per + min(r, rem) + (int)k;
+          break;
+        }
+        r = (r + 1) & 7;
+        --ranges_left;
+      }
+      claimed = item;
+    }
+    __syncthreads();
+    const int item = claimed;
+    if (item < 0) break;
+    // a fresh, opaque thread index each time round: values derived from it
+    // are then recomputed per item instead of being hoisted out of the loop
+    // and held in registers across the whole item
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const JobDesc &J = jobs[job_of_item(jobs, njobs, item)];
+    run_item<X>(sm, J, item - J.item0, tid);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // every claim of this workgroup precedes its departure; the last one to
+    // leave knows that no claim is still to come
+    __threadfence();
+    if (atomicAdd(&q->done[0], 1u) == gridDim.x - 1) {
+      for (int x = 0; x < 8; ++x) atomicExch(&q->next[x][0], 0u);
+      atomicExch(&q->done[0], 0u);
+    }
+  }
+}
+
+// Resident workgroups of a kernel per device (queried once per device).
+template <class K>
+int resident_workgroups(K kernel) {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int c = cache[dev].load(std::memory_order_relaxed);
+  if (c == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        cus < 1 || per_cu < 1)
+      return 256;
+    c = cus * per_cu;
+    cache[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
+template <int OCC, bool X>
+hipError_t launch_queue_kernel(const JobDesc *jobs, int njobs, int nitems, BatchQueue *q,
+                               hipStream_t s) {
+  const int g = min(nitems, resident_workgroups(k_fused_batch_queue<OCC, X>));
+  hipLaunchKernelGGL((k_fused_batch_queue<OCC, X>), dim3(g), dim3(256), 0, s, jobs, njobs,
+                     nitems, q);
+  return hipGetLastError();
+}
+
+#if CDEF_IN_KSET(7)
+hipError_t launch_batch_queue_base(int occ, const JobDesc *jobs, int njobs, int nitems,
+                                   BatchQueue *q, hipStream_t s) {
+  return occ == 2 ? launch_queue_kernel<2, false>(jobs, njobs, nitems, q, s)
+                  : launch_queue_kernel<3, false>(jobs, njobs, nitems, q, s);
+}
+#endif
+#if CDEF_IN_KSET(8)
+hipError_t launch_batch_queue_ext(const JobDesc *jobs, int njobs, int nitems, BatchQueue *q,
+                                  hipStream_t s) {
+  return launch_queue_kernel<2, true>(jobs, njobs, nitems, q, s);
+}
+#endif
+
 #if CDEF_IN_KSET(5)
 // Filter-only kernels: the LDS holds just the tiles and per-block state
 // (31 KB without the 4:4:4 chroma tiles) and the code just the filter mode.
@@ -1613,12 +1713,21 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_batch_queue(int occ, bool extended, const JobDesc *jobs, int njobs, int nitems,
+                              BatchQueue *queue, hipStream_t s) {
+  return extended ? launch_batch_queue_ext(jobs, njobs, nitems, queue, s)
+                  : launch_batch_queue_base(occ, jobs, njobs, nitems, queue, s);
+}
+
 hipError_t launch_fused_batch(const JobDesc *jobs, int njobs, int nitems, int variant,
-                              bool extended, bool filter_only, hipStream_t s) {
+                              bool extended, bool filter_only, BatchQueue *queue,
+                              hipStream_t s) {
   // the variant picks the occupancy bound (3 or 2 waves per SIMD; the
-  // extended kernels always run at 2) and the filter-block order; it does
-  // not apply to filter-only batches
+  // extended kernels always run at 2), the filter-block order and a flat
+  // grid or persistent workgroups; it does not apply to filter-only batches
   if (filter_only) return launch_filter_batch(extended, jobs, njobs, nitems, s);
+  if (variant == 4 || variant == 5)
+    return launch_batch_queue(variant == 4 ? 3 : 2, extended, jobs, njobs, nitems, queue, s);
   const bool xcd = variant == 0 || variant == 1;
   if (extended)
     return xcd ? launch_batch_ext_xcd(jobs, njobs, nitems, s)

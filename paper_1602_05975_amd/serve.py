@@ -495,6 +495,62 @@ def _stats(reqs: List[Request], wall: float) -> dict:
                       for i in worst]}
 
 
+def capacity(pool, batching: bool, n_req: int, budget: int, seed: int = 2) -> float:
+    """Requests per second of one path with every request submitted at once."""
+    ex = GpuBatchExecutor() if batching else GpuPlainExecutor()
+    ex.set_epoch()
+    sch = Scheduler(ex, budget, batching=batching, release_outputs=True)
+    reqs = make_requests(pool, n_req, seed)
+    wall = run_trace(sch, reqs, np.zeros(len(reqs)))
+    return n_req / wall
+
+
+def rate_trace(pool, rate: float, n_req: int, warm: int, budget: int, seed: int) -> dict:
+    """Both paths on the same Poisson arrivals at `rate` requests/s: latency
+    percentiles and throughput of the n_req requests after `warm`."""
+    rng = np.random.default_rng(seed)
+    offs = np.cumsum(rng.exponential(1.0 / rate, n_req + warm))
+    res = {"rate_req_s": round(rate, 1)}
+    for name, mk, batching in (("plain", GpuPlainExecutor, False),
+                               ("batched", GpuBatchExecutor, True)):
+        ex = mk()
+        ex.set_epoch()
+        sch = Scheduler(ex, budget, batching=batching, release_outputs=True)
+        reqs = make_requests(pool, n_req + warm, 3)
+        run_trace(sch, reqs, offs)
+        kept = sorted(sch.finished, key=lambda r: r.rid)[warm:]
+        span = max(r.done for r in kept) - min(r.arrival for r in kept)
+        st = _stats(kept, span)
+        st["batches"] = sch.nbatches
+        res[name] = st
+        _log(f"rate {rate:.0f}/s {name}: p50 {st['p50_ms']} p99 {st['p99_ms']} ms")
+    res["p99_gain"] = round(res["plain"]["p99_ms"] / res["batched"]["p99_ms"], 3)
+    res["p50_gain"] = round(res["plain"]["p50_ms"] / res["batched"]["p50_ms"], 3)
+    return res
+
+
+WORKLOAD = ("Poisson arrivals of device-resident frames, resolutions uniform over "
+            "426x240..3840x2160, 8/10-bit, 4:2:0, 50% strength search / 50% "
+            "direction search + filter at random per-filter-block strengths")
+
+
+def latency_summary(n_req: int = 2000, warm: int = 200, frac: float = 0.7,
+                    pool_frames: int = 20) -> dict:
+    """The serving trace of the benchmark's headline line: the plain path's
+    capacity, then both paths at `frac` of it."""
+    import torch
+    _log("serving: building the request pool")
+    pool = make_request_pool(pool_frames)
+    budget = int(torch.cuda.mem_get_info()[0] * 0.9)
+    capacity(pool, False, min(warm, n_req), budget, seed=1)  # warm-up
+    plain_rate = capacity(pool, False, n_req, budget)
+    _log(f"serving: plain path capacity {plain_rate:.0f} requests/s")
+    res = rate_trace(pool, frac * plain_rate, n_req, warm, budget, int(frac * 100))
+    res.update({"workload": WORKLOAD, "rate_fraction_of_plain": frac,
+                "plain_capacity_req_s": round(plain_rate, 1)})
+    return res
+
+
 def bench_main(args) -> None:
     import torch
     n_req = 4000
@@ -502,52 +558,16 @@ def bench_main(args) -> None:
     _log("building the request pool")
     pool = make_request_pool()
     budget = int(torch.cuda.mem_get_info()[0] * 0.9)
-
-    # sustainable rate of the plain path: all requests back to back
-    reqs = make_requests(pool, warm, 1)
-    ex = GpuPlainExecutor()
-    ex.set_epoch()
-    sch = Scheduler(ex, budget, batching=False, release_outputs=True)
-    run_trace(sch, reqs, np.zeros(len(reqs)))
-    reqs = make_requests(pool, n_req, 2)
-    ex.set_epoch()
-    sch = Scheduler(ex, budget, batching=False, release_outputs=True)
-    wall = run_trace(sch, reqs, np.zeros(len(reqs)))
-    plain_rate = n_req / wall
+    capacity(pool, False, warm, budget, seed=1)  # warm-up
+    plain_rate = capacity(pool, False, n_req, budget)
     _log(f"plain path back-to-back: {plain_rate:.0f} requests/s")
-
-    # sustainable rate of the batched path
-    ex = GpuBatchExecutor()
-    ex.set_epoch()
-    sch = Scheduler(ex, budget, release_outputs=True)
-    reqs = make_requests(pool, n_req, 2)
-    wall = run_trace(sch, reqs, np.zeros(len(reqs)))
-    batched_rate = n_req / wall
+    batched_rate = capacity(pool, True, n_req, budget)
     _log(f"batched path back-to-back: {batched_rate:.0f} requests/s")
-
-    out = {"workload": "Poisson arrivals of device-resident frames, resolutions uniform over "
-                       "426x240..3840x2160, 8/10-bit, 4:2:0, 50% strength search / 50% "
-                       "direction search + filter at random per-filter-block strengths",
+    out = {"workload": WORKLOAD,
            "plain_capacity_req_s": round(plain_rate, 1),
            "batched_capacity_req_s": round(batched_rate, 1), "rates": []}
     for frac in (0.7, 0.3, 0.9, 1.2, 1.6):
-        lam = frac * plain_rate
-        rng = np.random.default_rng(int(frac * 100))
-        offs = np.cumsum(rng.exponential(1.0 / lam, n_req + warm))
-        res = {"rate_fraction_of_plain": frac, "rate_req_s": round(lam, 1)}
-        for name, mk, batching in (("plain", GpuPlainExecutor, False),
-                                   ("batched", GpuBatchExecutor, True)):
-            ex = mk()
-            ex.set_epoch()
-            sch = Scheduler(ex, budget, batching=batching, release_outputs=True)
-            reqs = make_requests(pool, n_req + warm, 3)
-            wall = run_trace(sch, reqs, offs)
-            kept = sorted(sch.finished, key=lambda r: r.rid)[warm:]
-            span = max(r.done for r in kept) - min(r.arrival for r in kept)
-            st = _stats(kept, span)
-            st["batches"] = sch.nbatches
-            res[name] = st
-            _log(f"rate {frac:.1f}x {name}: {st}")
-        res["p99_gain"] = round(res["plain"]["p99_ms"] / res["batched"]["p99_ms"], 3)
+        res = rate_trace(pool, frac * plain_rate, n_req, warm, budget, int(frac * 100))
+        res["rate_fraction_of_plain"] = frac
         out["rates"].append(res)
     print(json.dumps(out), flush=True)

@@ -2,7 +2,9 @@
 
 Every launch variant of cdef_batch_launch computes bit-identical results;
 they differ in the occupancy bound (waves per SIMD, hence the register
-budget) and in the order in which filter blocks are dealt to the XCDs.  The
+budget), in the order in which filter blocks are dealt to the XCDs, and in
+a flat grid (one workgroup per filter block) against persistent workgroups
+that take filter blocks from per-XCD work queues.  The
 tuner times each variant on the caller's prepared batch (HIP events on the
 launch stream) and remembers the fastest per batch signature -- the GPU
 architecture plus the multiset of (frame-size class, bit depth, layout,
@@ -19,13 +21,18 @@ from typing import Dict, Optional
 
 from . import cdef
 
-NUM_VARIANTS = 4
+NUM_VARIANTS = cdef.BATCH_VARIANTS
 VARIANT_NAMES = {
     0: "3 waves/SIMD, XCD-contiguous order",
     1: "2 waves/SIMD, XCD-contiguous order",
     2: "3 waves/SIMD, plain order",
     3: "2 waves/SIMD, plain order",
+    4: "3 waves/SIMD, persistent workgroups on per-XCD queues",
+    5: "2 waves/SIMD, persistent workgroups on per-XCD queues",
 }
+# the cdef_tuning of each variant (wg_per_cu, order, persistent)
+VARIANT_TUNING = {0: (3, 0, 0), 1: (2, 0, 0), 2: (3, 1, 0), 3: (2, 1, 0), 4: (3, 0, 1),
+                  5: (2, 0, 1)}
 _lock = threading.Lock()
 
 

@@ -125,7 +125,9 @@ def test_batch_argument_checks(lib):
     from paper_1602_05975_amd import cdef
     assert lib.cdef_batch_workspace_bytes(0) == 0
     per = lib.cdef_batch_workspace_bytes(1)
-    assert per > 0 and lib.cdef_batch_workspace_bytes(5) == 5 * per
+    # the job table (descriptors, padded to 256 bytes) and the work-queue counters
+    five = lib.cdef_batch_workspace_bytes(5)
+    assert per > 0 and five > per and (five - per) % 256 == 0 and five < 5 * per
     plan = cdef.CdefBatchPlan()
     j = cdef.CdefJob()
     j.recon = _frame()
@@ -231,3 +233,44 @@ def test_select_presets_noalloc_argument_checks(lib):
     assert call(mask=C.addressof(seven)) == -1
     assert lib.cdef_select_presets_workspace_bytes() <= 20480
 
+
+def test_tuning_to_variant(lib):
+    from paper_1602_05975_amd import cdef, tune
+    for v, (wg, order, pers) in tune.VARIANT_TUNING.items():
+        assert cdef.tuning_variant(cdef.tuning(wg, order, pers)) == v
+    assert cdef.tuning_variant(cdef.tuning()) == 0
+    t = cdef.tuning()
+    t.tile_w = t.tile_h = 64
+    t.cand_group = 64
+    assert cdef.tuning_variant(t) == 0
+    v = C.c_int32()
+    for field, value, status in (("tile_w", 32, -2), ("tile_h", 128, -2), ("cand_group", 16, -2),
+                                 ("wg_per_cu", 4, -2), ("order", 2, -1), ("persistent", 3, -1)):
+        t = cdef.tuning()
+        setattr(t, field, value)
+        assert lib.cdef_tuning_variant(C.byref(t), C.byref(v)) == status, field
+    assert lib.cdef_tuning_variant(C.byref(cdef.tuning(3, 1, 1)), C.byref(v)) == -2
+    assert lib.cdef_tuning_variant(None, C.byref(v)) == -1
+    assert set(tune.VARIANT_NAMES) == set(range(cdef.BATCH_VARIANTS))
+
+
+def test_search_batch_rejects_before_enqueue(lib):
+    # bad jobs, tunings and workspaces fail on the host (no GPU here)
+    from paper_1602_05975_amd import cdef
+    P = 0x20000
+    j = cdef.CdefJob()
+    j.recon = _frame()
+    j.src = _frame(ptr=0x900000)
+    j.sse = P
+    j.damping = 3
+    arr = (cdef.CdefJob * 1)(j)
+    n = lib.cdef_batch_workspace_bytes(1)
+    assert n >= C.sizeof(cdef.CdefJob)
+    assert lib.cdef_search_batch(arr, 1, C.byref(cdef.tuning(wg_per_cu=5)), C.c_void_p(P), n,
+                                 None) == -2
+    assert lib.cdef_search_batch(arr, 0, None, C.c_void_p(P), n, None) == -1
+    assert lib.cdef_search_batch(arr, 1, None, None, n, None) == -1
+    assert lib.cdef_search_batch(arr, 1, None, C.c_void_p(P), n - 1, None) == -4
+    j.damping = 9
+    arr = (cdef.CdefJob * 1)(j)
+    assert lib.cdef_search_batch(arr, 1, None, C.c_void_p(P), n, None) == -1

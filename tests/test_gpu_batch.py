@@ -277,3 +277,103 @@ def test_filter_only_batch_every_cut_block_size(oracle):
         ref = oracle.filter_frame(fr.recon, fr.width, fr.height, fr.bitdepth, od, ov, fr.skip,
                                   fr.damping, st, layout=fr.layout)
         assert (to_np_u16(outs[0]) == ref[0]).all(), (fr.width, fr.height)
+
+
+@pytest.mark.parametrize("variant", [4, 5])
+def test_persistent_variants_match_and_replay(oracle, variant):
+    # Persistent workgroups on the per-XCD queues: bit-identical to the flat
+    # grid over mixed jobs (searches, a 128-combination search, filters),
+    # launch after launch (the queue counters reset themselves at the end of
+    # each launch), under graph replay, and for a batch smaller than the
+    # device's resident workgroups as well as one much larger.
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    for nframes, big in ((3, False), (4, True)):
+        b = cdef.Batch()
+        outs, refs = [], []
+        for i in range(nframes):
+            w, h = ((1920, 1080) if big and i % 2 == 0 else (200 + 8 * i, 136 - 16 * i))
+            fr = s.make_frame(w, h, 10 if i % 2 else 8, s.LAYOUT_420, 26000 + 10 * variant + i,
+                              skip_prob=0.3, damping=3 + i % 4)
+            rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+            sk = torch.from_numpy(fr.skip).cuda()
+            full = i == 1
+            shape = (3, fr.fb_rows, fr.fb_cols) + ((2, 16, 4) if full else (16, 4))
+            t = torch.full(shape, -1, dtype=torch.int64, device="cuda")
+            b.add_search(rec, src, sk, fr.damping, t, full=full)
+            outs.append(t)
+            refs.append(cdef.search_strengths(rec, src, sk, fr.damping, full=full))
+            if i == 2:
+                st = torch.from_numpy(s.random_presets(fr, 26100 + i)).cuda()
+                o = [torch.full_like(p, -1) for p in rec.planes[:3]]
+                b.add_filter(rec, o, sk, fr.damping, st)
+                d, v = cdef.find_dir(rec)
+                outs.extend(o)
+                refs.extend(cdef.filter_frame(rec, d, v, sk, fr.damping, st))
+        b.prepare()
+        b.plan.variant = variant
+        torch.cuda.synchronize()
+        print(f"variant {variant}: {b.nitems} filter blocks", flush=True)
+        for rep in range(3):
+            for o in outs:
+                o.fill_(-1)
+            b.launch()
+            torch.cuda.synchronize()
+            for k, (o, r) in enumerate(zip(outs, refs)):
+                assert torch.equal(o, r), (rep, k)
+        stream = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(stream):
+            b.launch(stream)
+        stream.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            b.launch(stream)
+        for rep in range(3):
+            for o in outs:
+                o.fill_(rep)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for k, (o, r) in enumerate(zip(outs, refs)):
+                assert torch.equal(o, r), ("replay", rep, k)
+
+
+def test_search_batch_one_call_matches_prepare_launch(oracle):
+    # cdef_search_batch (validate + upload + launch in one call) in every
+    # tuning, against the oracle; an unsupported tuning enqueues nothing
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    frs = [s.make_frame(w, h, bd, s.LAYOUT_420, 27000 + w, skip_prob=0.3, damping=D)
+           for (w, h, bd, D) in ((200, 136, 10, 3), (131, 67, 8, 5), (64, 64, 10, 6))]
+    jobs, outs, keep = [], [], []
+    for fr in frs:
+        rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+        sk = torch.from_numpy(fr.skip).cuda()
+        t = torch.full((3, fr.fb_rows, fr.fb_cols, 16, 4), -1, dtype=torch.int64, device="cuda")
+        jobs.append(cdef.make_search_job(rec, src, sk, fr.damping, t))
+        outs.append(t)
+        keep.append((rec, src, sk))
+    ws = cdef.batch_workspace(len(jobs))
+    refs = []
+    for fr in frs:
+        ref, _, _, fbs = oracle_search(oracle, fr)
+        refs.append(ref.reshape((fr.fb_rows, fr.fb_cols) + ref.shape[1:]).transpose(2, 0, 1, 3, 4))
+    for variant in range(cdef.BATCH_VARIANTS):
+        from paper_1602_05975_amd import tune
+        t = cdef.tuning(*tune.VARIANT_TUNING[variant])
+        assert cdef.tuning_variant(t) == variant
+        for o in outs:
+            o.fill_(-1)
+        cdef.cdef_search_batch(jobs, t, ws)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert (o.cpu().numpy().view(np.uint64) == r).all(), variant
+    bad = cdef.tuning(wg_per_cu=4)
+    for o in outs:
+        o.fill_(-1)
+    with pytest.raises(cdef.CdefError):
+        cdef.cdef_search_batch(jobs, bad, ws)
+    torch.cuda.synchronize()
+    assert all((o == -1).all() for o in outs)

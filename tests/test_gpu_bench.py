@@ -23,7 +23,8 @@ def test_bench_workload_runs(workload, monkeypatch, capsys):
     print(f"bench.py --workload {workload} --frames 1 --steps 1 --warmup 0", file=sys.stderr,
           flush=True)
     monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", workload, "--frames", "1",
-                                      "--steps", "1", "--warmup", "0", "--no-cpu-baseline"])
+                                      "--steps", "1", "--warmup", "0", "--no-cpu-baseline",
+                                      "--batch-frames", "0", "--serve-requests", "0"])
     bench.main()
     lines = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")]
     assert len(lines) == 1
@@ -36,3 +37,26 @@ def test_bench_workload_runs(workload, monkeypatch, capsys):
     assert rec["unit"] and rec["metric"] and isinstance(rec["config"], dict)
     r = rec["roofline"]
     assert r["peak"] > 0 and 0 < r["frac"] < 1.5 and r["achieved"] > 0
+
+
+def test_bench_headline_line_carries_every_part(monkeypatch, capsys):
+    # the default line: the batched search, the serving trace's latency
+    # percentiles for both paths, the uneven batch, the CPU baseline (here on
+    # one filter-block row); sizes cut down to keep the test short
+    import bench
+    full = bench.cpu_baseline
+    monkeypatch.setattr(bench, "cpu_baseline",
+                        lambda fr: full(fr, fb_rows=1, single_rows=1, other_configs=False))
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--frames", "1", "--steps", "2", "--warmup",
+                                      "1", "--batch-frames", "6", "--serve-requests", "100"])
+    bench.main()
+    lines = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")]
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    lat = rec["frame_latency_ms"]
+    assert 0 < lat["p50"] <= lat["p99"] and 0 < lat["plain_p50"] <= lat["plain_p99"]
+    assert rec["serving"]["batched"]["requests"] == 100
+    assert rec["batching"]["bit_exact_vs_per_frame"]
+    cb = rec["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["single_thread"]["value"] > 0
+    assert cb["cpu_model"] and cb["nproc"] >= 1 and "gcc" in cb["oracle_build"]

@@ -130,7 +130,7 @@ def test_weighted_in_batch_equals_per_frame():
     b.prepare()
     assert b.plan.flags & 1
     print(f"batch of {len(jobs)} jobs with weighted searches", flush=True)
-    for variant in range(4):
+    for variant in range(cdef.BATCH_VARIANTS):
         b.plan.variant = variant
         for j in jobs:
             j[-1].fill_(-1)
