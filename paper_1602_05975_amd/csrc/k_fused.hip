@@ -54,6 +54,7 @@
 // longer folded into the rounding offset (16 (x - s) would not fit), and the
 // last two levels of the cross-lane sums run in 64 bits.
 #include <atomic>
+#include <cstddef>
 #include <type_traits>
 
 #include "cdef_device.hpp"
@@ -966,12 +967,38 @@ __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int 
 // Eq. (14) for one filtering unit from exact integer moments: n pixels,
 // sums of s, s^2, d, d^2 and the unit's SSE.  With V = n sum x^2 - (sum x)^2
 // = n^2 sigma^2, the weight is (Vs + Vd + C1 n^2) / (2 sqrt(Vs Vd + C2 n^4)).
-__device__ __forceinline__ double eq14(int n, uint32_t ss, uint32_t ss2, uint32_t sd, uint32_t sd2,
-                                       uint32_t sse, double C1, double C2) {
+// The unit's part (n, Vs and the constants times powers of n) is formed
+// once per unit; per pair, Vd is exact in double (its terms are integers
+// below 2^53) and 1 / sqrt comes from the hardware estimate refined by two
+// Newton steps (relative error a few units in the last place).
+struct Eq14Unit {
+  double n, vs, a, b;  // a = (Vs + C1 n^2) / 2, b = C2 n^4
+};
+
+__device__ __forceinline__ Eq14Unit eq14_unit(int n, uint32_t ss, uint32_t ss2, double C1,
+                                              double C2) {
   const double nn = (double)n * (double)n;
   const double vs = (double)((int64_t)n * ss2 - (int64_t)ss * ss);
-  const double vd = (double)((int64_t)n * sd2 - (int64_t)sd * sd);
-  return (vs + vd + C1 * nn) / (2.0 * sqrt(vs * vd + C2 * nn * nn)) * (double)sse;
+  return {(double)n, vs, 0.5 * (vs + C1 * nn), C2 * nn * nn};
+}
+
+__device__ __forceinline__ double eq14(const Eq14Unit &u, uint32_t sd, uint32_t sd2,
+                                       uint32_t sse) {
+  const double dd = (double)sd;
+  const double vd = fma(u.n, (double)sd2, -(dd * dd));
+  const double x = fma(u.vs, vd, u.b);
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return fma(0.5, vd, u.a) * y * (double)sse;
+}
+
+__device__ __forceinline__ double eq14(int n, uint32_t ss, uint32_t ss2, uint32_t sd, uint32_t sd2,
+                                       uint32_t sse, double C1, double C2) {
+  return eq14(eq14_unit(n, ss, ss2, C1, C2), sd, sd2, sse);
 }
 
 // Per-unit moments of the source and the unfiltered reconstruction, one
@@ -1118,6 +1145,207 @@ __device__ __forceinline__ void task_moments(s16x2 (&ev)[64], uint32_t sv, int l
   reduce_chunk<ROWS>(v, lane, m.d2hi);
 }
 
+// ---- Weighted-search moments through LDS (chroma not 4:4:4) ---------------
+// A task's e = y - s for its 64 pairs is transposed through a per-wave LDS
+// scratch, 16 pairs at a time, so that a lane holds samples of one pair and
+// one filtering unit: sum d, sum d^2 and sum e^2 then accumulate inside the
+// lane, two samples of the same unit per 32-bit word (v_dot2 squares and adds
+// both halves), instead of one transposing cross-lane reduction per moment and
+// unit.  Scratch layout: for each of 16 pairs, then for the source, four
+// blocks of 32 samples (16-bit), each block padded to 80 bytes so that the 64
+// lanes' 64-byte block reads fall on different LDS banks.  A luma task's
+// samples are unit A's 64 then unit B's, a 4:2:0 chroma task's its eight 4x4
+// units of 16 (unit 2k the low half of lane row k, unit 2k + 1 the high half).
+constexpr int kWsPairs = 16;
+constexpr int kWsBlock = 40;                   // entries per 32-sample block
+constexpr int kWsRow = 4 * kWsBlock;           // entries per pair (128 samples)
+constexpr int kWsE = kWsPairs * kWsRow;        // e entries
+constexpr int kWsEntries = kWsE + kWsRow;      // + the source samples
+
+// The tails of the extended layout's chroma tiles beyond their 4:2:0 extent
+// (36 rows of kCS recon samples, 32 x 32 source samples), unused unless
+// chroma is 4:4:4: one per wave, each 16-byte aligned.
+__device__ __forceinline__ uint16_t *moment_scratch(SmemCore<true> &sm, int wave) {
+  return wave == 0 ? sm.sc[1] + 32 * 32
+                   : wave == 1 ? sm.rc[0] + 36 * kCS
+                               : wave == 2 ? sm.rc[1] + 36 * kCS : sm.sc[0] + 32 * 32;
+}
+static_assert(SmemCore<true>::kCSrc - 32 * 32 >= kWsEntries, "scratch in the source tail");
+static_assert(SmemCore<true>::kCT - 36 * kCS >= kWsEntries, "scratch in the recon tail");
+static_assert(offsetof(SmemCore<true>, rc) % 16 == 0 && offsetof(SmemCore<true>, sc) % 16 == 0 &&
+                  (SmemCore<true>::kCT * 2) % 16 == 0 && (SmemCore<true>::kCSrc * 2) % 16 == 0 &&
+                  (36 * kCS * 2) % 16 == 0 && (32 * 32 * 2) % 16 == 0,
+              "16-byte aligned scratch");
+
+// Entries another lane of the wave wrote before this point are read after
+// it: the LDS serves one wave's accesses in order, and the fences keep the
+// compiler from moving them across.
+__device__ __forceinline__ void wave_lds_exchange() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  asm volatile("" ::: "memory");
+}
+
+// The 16 words of a 32-sample block of the scratch (at a multiple of 8 entries).
+__device__ __forceinline__ void ws_read16(const uint16_t *ws, int at, uint32_t (&v)[16]) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(ws + at);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint4 x = p[i];
+    v[4 * i] = x.x;
+    v[4 * i + 1] = x.y;
+    v[4 * i + 2] = x.z;
+    v[4 * i + 3] = x.w;
+  }
+}
+
+// sum d, sum d^2, sum e^2 over words [k0, k0 + K) of a lane's samples.
+template <int K>
+__device__ __forceinline__ void unit_moments(const uint32_t (&E)[16], const uint32_t (&S)[16],
+                                             int k0, uint32_t &sd, uint32_t &d2, uint32_t &e2) {
+  u16x2 s = {0, 0};
+  uint32_t a = 0;
+  int b = 0;
+#pragma unroll
+  for (int k = k0; k < k0 + K; ++k) {
+    const u16x2 d = as_u(E[k]) + as_u(S[k]);  // d = e + s, in [0, 2^b)
+    s += d;
+    a = __builtin_amdgcn_udot2(d, d, a, false);
+    b = __builtin_amdgcn_sdot2(as_s(E[k]), as_s(E[k]), b, false);
+  }
+  sd = (uint32_t)s.x + (uint32_t)s.y;
+  d2 = a;
+  e2 = (uint32_t)b;
+}
+
+// Luma tasks (plane 0) with the LDS moments.  Lane (q, h, g) = (lane >> 2,
+// (lane >> 1) & 1, lane & 1) reads unit h's samples 32 g .. 32 g + 31 of
+// pair 16 c + q for chunks c = 0..3; the two lanes g = 0, 1 then hold halves
+// of each sum, and lane g keeps chunks 2 g and 2 g + 1: pairs 32 g + q and
+// 32 g + 16 + q of unit h.
+template <bool B12>
+__device__ __forceinline__ void plane_tasks_wl(SmemT<true> &sm, const JobDesc &J, int n, int y0,
+                                               int x0, int wave, int lane, double C1,
+                                               double C2) {
+  uint16_t *ws = moment_scratch(sm, wave);
+  const int q = lane >> 2, h = (lane >> 1) & 1, g = lane & 1;
+  const int rd = kWsBlock * (lane & 3);                     // block 2 h + g
+  const int wa = kWsBlock * (lane >> 5) + (lane & 31);      // unit A's sample `lane`
+  const int wb = wa + 2 * kWsBlock;                         // unit B's
+  double acc[2] = {0.0, 0.0};
+  block_tasks<true, B12, 0>(
+      sm, J, 0, n, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t sv) {
+        s16x2 ev[64];
+        block_pairs<false, B12, 0>(sm, J, t, A, B, StoreErr{ev});
+        ws[kWsE + wa] = (uint16_t)sv;
+        ws[kWsE + wb] = (uint16_t)(sv >> 16);
+        uint32_t S[16], sd[4], d2[4], e2[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+          for (int i = 0; i < kWsPairs; ++i) {
+            const uint32_t v = __builtin_bit_cast(uint32_t, ev[16 * c + i]);
+            ws[kWsRow * i + wa] = (uint16_t)v;
+            ws[kWsRow * i + wb] = (uint16_t)(v >> 16);
+          }
+          wave_lds_exchange();
+          if (c == 0) ws_read16(ws, kWsE + rd, S);
+          uint32_t E[16];
+          ws_read16(ws, kWsRow * q + rd, E);
+          unit_moments<16>(E, S, 0, sd[c], d2[c], e2[c]);
+          wave_lds_exchange();  // read before the next chunk overwrites
+        }
+        // lane g: chunks 2 g + j (j = 0, 1), completed with the partner's half
+        uint32_t m[2][3];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const uint32_t keep[3] = {g ? sd[2 + j] : sd[j], g ? d2[2 + j] : d2[j],
+                                    g ? e2[2 + j] : e2[j]};
+          const uint32_t send[3] = {g ? sd[j] : sd[2 + j], g ? d2[j] : d2[2 + j],
+                                    g ? e2[j] : e2[2 + j]};
+#pragma unroll
+          for (int k = 0; k < 3; ++k)  // quad_perm [1, 0, 3, 2]: lane ^ 1
+            m[j][k] = keep[k] + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)send[k], 0xB1,
+                                                                       0xF, 0xF, false);
+        }
+        if (h == 0 || hasB) {
+          const int u = h ? B : A;
+          const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][0][u], sm.w.ustat[1][0][u],
+                                       sm.w.ustat[2][0][u], C1, C2);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[j] += eq14(e, m[j][0], m[j][1], m[j][2]);
+        }
+      });
+  // units A and B (h = 0, 1) hold the same pairs
+#pragma unroll
+  for (int j = 0; j < 2; ++j) acc[j] += __shfl_xor(acc[j], 2, 64);
+  if (h == 0) {
+    sm.w.wred[0][wave][32 * g + q] = acc[0];
+    sm.w.wred[0][wave][32 * g + 16 + q] = acc[1];
+  }
+}
+
+// 4:2:0 chroma tasks with the LDS moments: lane (q, w) = (lane >> 2,
+// lane & 3) reads units 2 w and 2 w + 1 (the low and high halves of task
+// row w) of pair 16 c + q whole, so it completes their moments alone; it
+// accumulates pairs 16 c + q, the four lanes w of a pair are summed at the
+// end.
+template <bool B12>
+__device__ __forceinline__ void chroma420_wl(SmemT<true> &sm, const JobDesc &J, int n, int y0,
+                                             int x0, int wave, int lane, double C1, double C2) {
+  const int c = J.bitdepth - 8, D = J.damping;
+  const int P = 1 + (wave >> 1);
+  uint16_t *ws = moment_scratch(sm, wave);
+  const int q = lane >> 2, w = lane & 3;
+  const int wr = kWsBlock * (lane >> 4) + (lane & 15);  // this lane's low-half sample
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  chroma420_tasks<true, B12>(
+      sm, J, 0, n, y0, x0, wave, lane,
+      [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t sv) {
+        s16x2 ev[64];
+        chroma_pairs<false, B12, false>(t, c, D, 0xFFFFu, 15u, false, StoreErr{ev});
+        // units of row w, from lane 16 w
+        const int src = w << 4;
+        const int uL = __shfl(L, src, 64), uH = __shfl(Hb, src, 64);
+        const int has = __shfl((hasL ? 1 : 0) | (hasH ? 2 : 0), src, 64);
+        const Eq14Unit eL = eq14_unit((int)sm.w.ustat[0][P][uL], sm.w.ustat[1][P][uL],
+                                      sm.w.ustat[2][P][uL], C1, C2);
+        const Eq14Unit eH = eq14_unit((int)sm.w.ustat[0][P][uH], sm.w.ustat[1][P][uH],
+                                      sm.w.ustat[2][P][uH], C1, C2);
+        ws[kWsE + wr] = (uint16_t)sv;
+        ws[kWsE + wr + 16] = (uint16_t)(sv >> 16);
+        uint32_t S[16];
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+#pragma unroll
+          for (int i = 0; i < kWsPairs; ++i) {
+            const uint32_t v = __builtin_bit_cast(uint32_t, ev[16 * ch + i]);
+            ws[kWsRow * i + wr] = (uint16_t)v;
+            ws[kWsRow * i + wr + 16] = (uint16_t)(v >> 16);
+          }
+          wave_lds_exchange();
+          if (ch == 0) ws_read16(ws, kWsE + kWsBlock * w, S);
+          uint32_t E[16];
+          ws_read16(ws, kWsRow * q + kWsBlock * w, E);
+          uint32_t sdL, d2L, e2L, sdH, d2H, e2H;
+          unit_moments<8>(E, S, 0, sdL, d2L, e2L);
+          unit_moments<8>(E, S, 8, sdH, d2H, e2H);
+          wave_lds_exchange();
+          if (has & 1) acc[ch] += eq14(eL, sdL, d2L, e2L);
+          if (has & 2) acc[ch] += eq14(eH, sdH, d2H, e2H);
+        }
+      });
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    acc[j] += __shfl_xor(acc[j], 1, 64);
+    acc[j] += __shfl_xor(acc[j], 2, 64);
+  }
+  if (w == 0)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sm.w.wred[P][wave & 1][16 * j + q] = acc[j];
+}
+
 // Weighted search over luma-shaped tasks of plane CH; lane k accumulates
 // pair k, and the wave's sums go to wred[CH][wave].
 template <bool B12, int CH>
@@ -1137,42 +1365,6 @@ __device__ __forceinline__ void plane_tasks_w(SmemT<true> &sm, const JobDesc &J,
                        m.sdhi[0], m.d2hi[0], m.e2hi[0], C1, C2);
       });
   sm.w.wred[CH][wave][lane] = accw;
-}
-
-// Weighted search over 4:2:0 chroma tasks: each row of 16 lanes holds one
-// 4x4 unit per half; lane l of a row accumulates pairs 4 (l mod 16) + j.
-template <bool B12>
-__device__ __forceinline__ void chroma420_w(SmemT<true> &sm, const JobDesc &J, int n, int y0,
-                                            int x0, int wave, int lane, double C1, double C2) {
-  const int c = J.bitdepth - 8, D = J.damping;
-  const int P = 1 + (wave >> 1);
-  double accw[4] = {0.0, 0.0, 0.0, 0.0};
-  chroma420_tasks<true, B12>(
-      sm, J, 0, n, y0, x0, wave, lane,
-      [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t sv) {
-        s16x2 ev[64];
-        chroma_pairs<false, B12, false>(t, c, D, 0xFFFFu, 15u, false, StoreErr{ev});
-        Moments<true, B12> m;
-        task_moments<true, B12>(ev, sv, lane, m);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (hasL)
-            accw[j] += eq14((int)sm.w.ustat[0][P][L], sm.w.ustat[1][P][L], sm.w.ustat[2][P][L],
-                            m.sdlo[j], m.d2lo[j], m.e2lo[j], C1, C2);
-          if (hasH)
-            accw[j] += eq14((int)sm.w.ustat[0][P][Hb], sm.w.ustat[1][P][Hb], sm.w.ustat[2][P][Hb],
-                            m.sdhi[j], m.d2hi[j], m.e2hi[j], C1, C2);
-        }
-      });
-  // the four rows hold the same pairs for different units
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    accw[j] += __shfl_xor(accw[j], 16, 64);
-    accw[j] += __shfl_xor(accw[j], 32, 64);
-  }
-  if (lane < 16)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) sm.w.wred[P][wave & 1][4 * lane + j] = accw[j];
 }
 
 template <bool B12>
@@ -1215,11 +1407,14 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
     if (lane == 0) sm.skipw[P] = w;
   }
 
-  plane_tasks_w<B12, 0>(sm, J, n, y0, x0, wave, lane, C1, C2);
-  if (c420) chroma420_w<B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
   if (c444) {
+    // the chroma tiles fill the extended layout: cross-lane reductions
+    plane_tasks_w<B12, 0>(sm, J, n, y0, x0, wave, lane, C1, C2);
     plane_tasks_w<B12, 1>(sm, J, n, y0, x0, wave, lane, C1, C2);
     plane_tasks_w<B12, 2>(sm, J, n, y0, x0, wave, lane, C1, C2);
+  } else {
+    plane_tasks_wl<B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
+    if (c420) chroma420_wl<B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
   }
   __syncthreads();
 
