@@ -499,6 +499,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-frames", type=int, default=64,
                     help="frames of the uneven batch measured in the headline line (0: skip)")
+    ap.add_argument("--serve-host-frames", type=int, default=300,
+                    help="frames of the host-memory serving trace in the headline line "
+                         "(each a search and a filter request; 0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="timed requests of the serving trace whose p50/p99 the headline "
                          "line reports (0: skip; report the batch launch time instead)")
@@ -718,6 +721,10 @@ def main():
         result["serving"] = tr
     else:
         result["frame_latency_ms"] = dict(result["batch_launch_ms"])
+    if headline and args.serve_host_frames > 0:
+        from paper_1602_05975_amd import serve
+        result["serving_host"] = serve.host_latency_summary(
+            n_frames=args.serve_host_frames, warm=max(10, args.serve_host_frames // 10))
     if headline and args.batch_frames > 0:
         result["batching"] = measure_batching(args.batch_frames, 10)
     if not args.no_cpu_baseline and args.workload == "search4k":

@@ -1,15 +1,20 @@
 """Continuous-batching CDEF server.
 
-Requests are frames that are already resident in device memory (as when
+Requests are frames either already resident in device memory (as when
 CDEF runs inside a GPU codec pipeline: the reconstruction is produced on the
-device and the source was uploaded once), each asking either for the
-encoder's strength search or for the direction search + filter at given
-per-filter-block strengths.  The scheduler
+device and the source was uploaded once) or arriving in pinned host memory,
+each asking either for the encoder's strength search or for the direction
+search + filter at given per-filter-block strengths.  The scheduler
 
 * validates each request on its own at submission (a bad request fails
   alone and never joins a batch),
-* admits requests first-in first-out while the device bytes of their
-  outputs fit a budget (by default 90 % of the free device memory),
+* admits requests first-in first-out while the device bytes they need fit a
+  budget (by default 90 % of the free device memory): their outputs, and for
+  a host frame not yet on the device its planes, which are uploaded on a
+  copy stream at admission and then stay resident (a later request on the
+  same frame -- the filter after the search, say -- finds them there) until
+  the budget needs room and no running request uses them (least recently
+  used first),
 * launches every admitted request not yet running as one batch
   (cdef_batch_prepare + cdef_batch_launch) on the next free stream of a
   small pool, without waiting for earlier batches, so requests that arrive
@@ -48,11 +53,16 @@ class Request:
     strengths: object = None            # filter: uint8 [fbr][fbc][4] device tensor
     skip: object = None
     damping: int = 3
+    host: Optional["HostFrame"] = None  # frame in pinned host memory (recon/src/skip set
+                                        # to its device copies at admission)
+    host_strengths: object = None       # filter, host frame: pinned uint8 [fbr][fbc][4]
     arrival: float = 0.0                # host clock, seconds
     # filled in by the server
     status: int = 0
     outputs: tuple = ()
     out_bytes: int = 0
+    in_bytes: int = 0                   # device bytes of frame planes this request uploaded
+    ready: object = None                # event after its uploads (None: nothing to wait for)
     admitted: float = -1.0
     done: float = -1.0
     job: object = None
@@ -60,7 +70,8 @@ class Request:
 
     @property
     def luma_px(self) -> int:
-        return self.recon.width * self.recon.height
+        f = self.host if self.host is not None else self.recon
+        return f.width * f.height
 
 
 def output_bytes(req: Request) -> int:
@@ -74,6 +85,126 @@ def output_bytes(req: Request) -> int:
     w, h = f.width, f.height
     px = w * h + (2 * ((w + 1) // 2) * ((h + 1) // 2) if f.nplanes == 3 else 0)
     return 2 * px + dv
+
+
+@dataclasses.dataclass
+class HostFrame:
+    """A frame in pinned host memory.  `key` names the frame: requests with the
+    same key share one device copy while it stays resident."""
+
+    key: object
+    recon: List            # pinned CPU tensors, 2-D, int16 storage
+    src: Optional[List]    # searches
+    skip: object           # pinned uint8 [ceil(h/8)][ceil(w/8)] or None
+    width: int
+    height: int
+    bitdepth: int
+    layout: int
+
+    def plane_bytes(self, planes) -> int:
+        return sum(t.numel() * t.element_size() for t in planes)
+
+
+class ResidentFrames:
+    """Device copies of host frames.  Uploads run on `stream`; an entry stays
+    after its requests finish and is evicted least recently used first when
+    room is needed and no request holds it."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.entries: "collections.OrderedDict" = collections.OrderedDict()
+
+    def bytes_needed(self, host: HostFrame, need_src: bool) -> int:
+        e = self.entries.get(host.key)
+        if e is None:
+            n = host.plane_bytes(host.recon)
+            if host.skip is not None:
+                n += host.skip.numel()
+            return n + (host.plane_bytes(host.src) if need_src else 0)
+        return host.plane_bytes(host.src) if need_src and e["src"] is None else 0
+
+    def _upload(self, planes):
+        import torch
+        out = []
+        with torch.cuda.stream(self.stream):
+            for t in planes:
+                d = torch.empty(t.shape, dtype=t.dtype, device="cuda")
+                d.copy_(t, non_blocking=True)
+                out.append(d)
+        return out
+
+    def _record(self):
+        """An event after the uploads enqueued so far."""
+        import torch
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    @staticmethod
+    def _done(ev) -> bool:
+        return ev.query()
+
+    def acquire(self, host: HostFrame, need_src: bool):
+        """The device entry of `host` (uploading what is missing), held until
+        release(); returns (entry, bytes newly resident, event or None)."""
+        e = self.entries.get(host.key)
+        added = self.bytes_needed(host, need_src)
+        fresh = False
+        if e is None:
+            rec = self._upload(host.recon)
+            skip = self._upload([host.skip])[0] if host.skip is not None else None
+            e = {"recon": cdef.Frame(rec, host.width, host.height, host.bitdepth, host.layout),
+                 "src": None, "skip": skip, "bytes": 0, "refs": 0, "event": None}
+            self.entries[host.key] = e
+            fresh = True
+        if need_src and e["src"] is None:
+            e["src"] = cdef.Frame(self._upload(host.src), host.width, host.height,
+                                  host.bitdepth, host.layout)
+            fresh = True
+        if fresh:
+            e["event"] = self._record()
+        e["bytes"] += added
+        e["refs"] += 1
+        self.entries.move_to_end(host.key)
+        ev = e["event"]
+        if ev is not None and self._done(ev):
+            e["event"] = ev = None
+        return e, added, ev
+
+    def release(self, key) -> None:
+        e = self.entries.get(key)
+        if e is not None:
+            e["refs"] -= 1
+
+    def evict(self, nbytes: int, keep=None) -> int:
+        """Drop idle entries other than `keep`, least recently used first,
+        until `nbytes` are freed or none is idle; returns the bytes freed."""
+        freed = 0
+        for key in list(self.entries):
+            if freed >= nbytes:
+                break
+            e = self.entries[key]
+            if e["refs"] == 0 and key != keep:
+                freed += e["bytes"]
+                del self.entries[key]
+        return freed
+
+    @property
+    def resident_bytes(self) -> int:
+        return sum(e["bytes"] for e in self.entries.values())
+
+
+def _attach_host(frames: ResidentFrames, req: Request) -> None:
+    """Point a host request at the device copies of its frame (uploading
+    what is missing) and upload its strengths."""
+    e, added, ev = frames.acquire(req.host, req.mode == SEARCH)
+    req.recon, req.skip = e["recon"], e["skip"]
+    req.src = e["src"] if req.mode == SEARCH else None
+    req.in_bytes = added
+    req.ready = ev
+    if req.mode == FILTER and req.host_strengths is not None:
+        req.strengths = frames._upload([req.host_strengths])[0]
+        req.ready = frames._record()
 
 
 class DeviceClock:
@@ -182,12 +313,26 @@ class GpuBatchExecutor:
         self.next = 0
         self.variant = variant
         self.clock = None
+        self.frames = ResidentFrames(torch.cuda.Stream())
 
     def set_epoch(self):
         self.clock = DeviceClock.shared()
 
+    def input_bytes(self, req: Request) -> int:
+        return 0 if req.host is None else self.frames.bytes_needed(req.host, req.mode == SEARCH)
+
+    def evict(self, nbytes: int, req: Optional[Request] = None) -> int:
+        keep = req.host.key if req is not None and req.host is not None else None
+        return self.frames.evict(nbytes, keep)
+
+    def release(self, req: Request) -> None:
+        if req.host is not None:
+            self.frames.release(req.host.key)
+
     def allocate(self, req: Request):
         torch = self.torch
+        if req.host is not None:
+            _attach_host(self.frames, req)
         f = req.recon
         br, bc = f.block_shape
         d = torch.empty((br, bc), dtype=torch.uint8, device="cuda")
@@ -224,6 +369,9 @@ class GpuBatchExecutor:
         for r in reqs:
             b.add_job(r.job, (r.recon, r.src, r.skip, r.strengths, r.outputs))
         s = self.streams[i]
+        for r in reqs:  # frames uploaded on the copy stream
+            if r.ready is not None:
+                s.wait_event(r.ready)
         b.prepare(s)
         if self.variant is not None:
             b.plan.variant = self.variant
@@ -268,10 +416,14 @@ class GpuPlainExecutor:
         self.pending: Dict[int, object] = {}
         self.next = 0
         self.clock = None
+        self.frames = ResidentFrames(self.stream)  # uploads in order on the one stream
 
     set_epoch = GpuBatchExecutor.set_epoch
     allocate = GpuBatchExecutor.allocate
     validate = GpuBatchExecutor.validate
+    input_bytes = GpuBatchExecutor.input_bytes
+    evict = GpuBatchExecutor.evict
+    release = GpuBatchExecutor.release
 
     def launch(self, reqs: List[Request]):
         assert len(reqs) == 1
@@ -304,9 +456,11 @@ class GpuPlainExecutor:
 
 
 class Scheduler:
-    """Admission by output bytes, continuous batching, completion polling.
+    """Admission by device bytes, continuous batching, completion polling.
     Executor-agnostic: it needs allocate / validate / launch / poll /
-    capacity."""
+    capacity, and for host frames input_bytes / evict / release (bytes a
+    request would upload, freeing idle resident frames, dropping a request's
+    hold on its frame)."""
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 256,
                  batching: bool = True, clock: Callable[[], float] = time.perf_counter,
@@ -341,29 +495,46 @@ class Scheduler:
                 return True
         return False
 
+    def _input_bytes(self, r: Request) -> int:
+        f = getattr(self.ex, "input_bytes", None)
+        return f(r) if f else 0
+
     def _admit(self, now: float) -> None:
         while self.queue:
             r = self.queue[0]
-            need = output_bytes(r)
+            out = output_bytes(r)
+            need = out + self._input_bytes(r)
             if need > self.budget:  # can never fit: reject rather than block the queue
                 self.queue.popleft()
                 r.status = cdef.CDEF_E_NOMEM
                 self.rejected.append(r)
                 continue
             if self.in_use + need > self.budget:
-                return
+                evict = getattr(self.ex, "evict", None)
+                if evict:  # idle resident frames, never the one `r` is about to use
+                    self.in_use -= evict(self.in_use + need - self.budget, r)
+                if self.in_use + need > self.budget:
+                    return
             self.queue.popleft()
             self.ex.allocate(r)
+            # frame planes it uploaded stay resident (and charged) until evicted
+            self.in_use += r.in_bytes
             st = self.ex.validate(r)
             if st != cdef.CDEF_OK:
                 r.status = st
                 r.outputs, r.job = (), None
+                self._release(r)
                 self.rejected.append(r)
                 continue
-            r.out_bytes = need
+            r.out_bytes = out
             r.admitted = now
-            self.in_use += need
+            self.in_use += out
             self.ready.append(r)
+
+    def _release(self, r: Request) -> None:
+        f = getattr(self.ex, "release", None)
+        if f:
+            f(r)
 
     def _retire(self) -> List[Request]:
         done = []
@@ -377,8 +548,11 @@ class Scheduler:
             for r in self.running.pop(h):
                 r.done = t
                 self.in_use -= r.out_bytes
+                self._release(r)
                 if self.release_outputs:
                     r.outputs, r.job = (), None
+                    if r.host is not None:  # the device frame belongs to the residency
+                        r.recon = r.src = r.skip = r.strengths = None
                 done.append(r)
         self.finished.extend(done)
         return done
@@ -467,6 +641,42 @@ def make_request_pool(n_frames: int = 20, seed: int = 4):
     return pool
 
 
+def make_host_pool(n_frames: int = 20, seed: int = 4):
+    """The request frames of make_request_pool in pinned host memory: per
+    frame (synth frame, recon planes, source planes, skip map, strengths)."""
+    import torch
+    from . import synth
+
+    def pin(a):
+        t = torch.from_numpy(a.view("int16") if a.dtype.name == "uint16" else a)
+        return t.pin_memory()
+
+    pool = []
+    for i, (w, h, bd, D) in enumerate(synth.mixed_frame_params(n_frames, 4)):
+        fr = synth.make_frame(w, h, bd, synth.LAYOUT_420, synth.workload_seed(synth.WL_SERVE, i),
+                              damping=D)
+        pool.append((fr, [pin(p) for p in fr.recon], [pin(p) for p in fr.src], None,
+                     pin(synth.random_strengths(fr, 70 + i))))
+    return pool
+
+
+def make_host_requests(pool, n_frames: int, seed: int, key0: int = 0):
+    """Frames arriving from host memory, each asking for the strength search
+    and then the filter (an encoder's two passes over one frame): 2 n_frames
+    requests; every frame is new (its own key), so each is uploaded once and
+    its filter request finds it resident."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n_frames):
+        fr, rec, src, skip, st = pool[int(rng.integers(0, len(pool)))]
+        host = HostFrame(key0 + k, rec, src, skip, fr.width, fr.height, fr.bitdepth, fr.layout)
+        stub = cdef.Frame([None] * 3, fr.width, fr.height, fr.bitdepth, fr.layout)
+        reqs.append(Request(rid=2 * k, mode=SEARCH, recon=stub, host=host, damping=fr.damping))
+        reqs.append(Request(rid=2 * k + 1, mode=FILTER, recon=stub, host=host,
+                            host_strengths=st, damping=fr.damping))
+    return reqs
+
+
 def make_requests(pool, n: int, seed: int) -> List[Request]:
     rng = np.random.default_rng(seed)
     reqs = []
@@ -529,6 +739,63 @@ def rate_trace(pool, rate: float, n_req: int, warm: int, budget: int, seed: int)
     return res
 
 
+def host_capacity(pool, batching: bool, n_frames: int, budget: int, seed: int = 2) -> float:
+    """Frames per second of one path with every host frame submitted at once."""
+    ex = GpuBatchExecutor() if batching else GpuPlainExecutor()
+    ex.set_epoch()
+    sch = Scheduler(ex, budget, batching=batching, release_outputs=True)
+    reqs = make_host_requests(pool, n_frames, seed, key0=10 ** 9 * (1 + seed))
+    wall = run_trace(sch, reqs, np.zeros(len(reqs)))
+    return n_frames / wall
+
+
+def host_rate_trace(pool, rate: float, n_frames: int, warm: int, budget: int, seed: int) -> dict:
+    """Both paths on the same Poisson arrivals of host frames (`rate` frames/s,
+    each a search request then a filter request): latency of each request
+    from the frame's arrival, over the frames after `warm`."""
+    rng = np.random.default_rng(seed)
+    offs = np.repeat(np.cumsum(rng.exponential(1.0 / rate, n_frames + warm)), 2)
+    res = {"rate_frames_s": round(rate, 1)}
+    for name, mk, batching in (("plain", GpuPlainExecutor, False),
+                               ("batched", GpuBatchExecutor, True)):
+        ex = mk()
+        ex.set_epoch()
+        sch = Scheduler(ex, budget, batching=batching, release_outputs=True)
+        reqs = make_host_requests(pool, n_frames + warm, 3, key0=10 ** 6 * (1 + seed))
+        run_trace(sch, reqs, offs)
+        kept = sorted(sch.finished, key=lambda r: r.rid)[2 * warm:]
+        span = max(r.done for r in kept) - min(r.arrival for r in kept)
+        st = _stats(kept, span)
+        st["batches"] = sch.nbatches
+        res[name] = st
+        _log(f"host frames {rate:.0f}/s {name}: p50 {st['p50_ms']} p99 {st['p99_ms']} ms")
+    res["p99_gain"] = round(res["plain"]["p99_ms"] / res["batched"]["p99_ms"], 3)
+    res["p50_gain"] = round(res["plain"]["p50_ms"] / res["batched"]["p50_ms"], 3)
+    return res
+
+
+HOST_WORKLOAD = ("Poisson arrivals of frames in pinned host memory (resolutions uniform over "
+                 "426x240..3840x2160, 8/10-bit, 4:2:0), each uploaded on admission and kept "
+                 "resident, asking for the strength search and then the filter at random "
+                 "per-filter-block strengths")
+
+
+def host_latency_summary(n_frames: int = 500, warm: int = 50, frac: float = 0.7,
+                         pool_frames: int = 20) -> dict:
+    """Host arrivals: the plain path's capacity, then both paths at `frac` of it."""
+    import torch
+    _log("serving from host memory: building the pinned pool")
+    pool = make_host_pool(pool_frames)
+    budget = int(torch.cuda.mem_get_info()[0] * 0.9)
+    host_capacity(pool, False, min(warm, n_frames), budget, seed=1)  # warm-up
+    plain = host_capacity(pool, False, n_frames, budget)
+    _log(f"serving from host memory: plain path capacity {plain:.0f} frames/s")
+    res = host_rate_trace(pool, frac * plain, n_frames, warm, budget, int(frac * 100))
+    res.update({"workload": HOST_WORKLOAD, "rate_fraction_of_plain": frac,
+                "plain_capacity_frames_s": round(plain, 1)})
+    return res
+
+
 WORKLOAD = ("Poisson arrivals of device-resident frames, resolutions uniform over "
             "426x240..3840x2160, 8/10-bit, 4:2:0, 50% strength search / 50% "
             "direction search + filter at random per-filter-block strengths")
@@ -570,4 +837,16 @@ def bench_main(args) -> None:
         res = rate_trace(pool, frac * plain_rate, n_req, warm, budget, int(frac * 100))
         res["rate_fraction_of_plain"] = frac
         out["rates"].append(res)
+    # frames arriving in host memory
+    hpool = make_host_pool()
+    n_fr = n_req // 4
+    host_capacity(hpool, False, warm, budget, seed=1)  # warm-up
+    hplain = host_capacity(hpool, False, n_fr, budget)
+    hbatch = host_capacity(hpool, True, n_fr, budget)
+    out["host"] = {"workload": HOST_WORKLOAD, "plain_capacity_frames_s": round(hplain, 1),
+                   "batched_capacity_frames_s": round(hbatch, 1), "rates": []}
+    for frac in (0.7, 1.2):
+        res = host_rate_trace(hpool, frac * hplain, n_fr, warm // 4, budget, int(frac * 100))
+        res["rate_fraction_of_plain"] = frac
+        out["host"]["rates"].append(res)
     print(json.dumps(out), flush=True)

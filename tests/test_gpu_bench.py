@@ -24,7 +24,8 @@ def test_bench_workload_runs(workload, monkeypatch, capsys):
           flush=True)
     monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", workload, "--frames", "1",
                                       "--steps", "1", "--warmup", "0", "--no-cpu-baseline",
-                                      "--batch-frames", "0", "--serve-requests", "0"])
+                                      "--batch-frames", "0", "--serve-requests", "0",
+                                      "--serve-host-frames", "0"])
     bench.main()
     lines = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")]
     assert len(lines) == 1
@@ -48,7 +49,8 @@ def test_bench_headline_line_carries_every_part(monkeypatch, capsys):
     monkeypatch.setattr(bench, "cpu_baseline",
                         lambda fr: full(fr, fb_rows=1, single_rows=1, other_configs=False))
     monkeypatch.setattr(sys, "argv", ["bench.py", "--frames", "1", "--steps", "2", "--warmup",
-                                      "1", "--batch-frames", "6", "--serve-requests", "100"])
+                                      "1", "--batch-frames", "6", "--serve-requests", "100",
+                                      "--serve-host-frames", "40"])
     bench.main()
     lines = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")]
     assert len(lines) == 1
@@ -56,6 +58,8 @@ def test_bench_headline_line_carries_every_part(monkeypatch, capsys):
     lat = rec["frame_latency_ms"]
     assert 0 < lat["p50"] <= lat["p99"] and 0 < lat["plain_p50"] <= lat["plain_p99"]
     assert rec["serving"]["batched"]["requests"] == 100
+    host = rec["serving_host"]
+    assert host["batched"]["requests"] == 2 * 40 and host["plain"]["p99_ms"] > 0
     assert rec["batching"]["bit_exact_vs_per_frame"]
     cb = rec["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["single_thread"]["value"] > 0

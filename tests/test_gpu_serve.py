@@ -110,3 +110,70 @@ def test_bad_request_fails_alone():
             assert torch.equal(got, ref)
         else:
             assert all(torch.equal(a, b) for a, b in zip(got, ref))
+
+
+def _host_pool():
+    import torch
+    from paper_1602_05975_amd import synth
+
+    def pin(a):
+        return torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a).pin_memory()
+
+    pool = []
+    for i, (w, h, bd, D) in enumerate([(426, 240, 8, 3), (200, 136, 10, 4), (131, 67, 10, 6),
+                                       (640, 360, 10, 3), (96, 70, 8, 5)]):
+        fr = synth.make_frame(w, h, bd, synth.LAYOUT_420, 78000 + i, skip_prob=0.2, damping=D)
+        st = synth.random_strengths(fr, 95 + i)
+        pool.append((fr, [pin(p) for p in fr.recon], [pin(p) for p in fr.src], pin(fr.skip),
+                     pin(st), st))
+    return pool
+
+
+@pytest.mark.parametrize("batching", [True, False])
+def test_host_arrivals_equal_alone(batching):
+    # Frames arrive in pinned host memory; each is uploaded on admission,
+    # kept resident for its later requests and evicted when idle and the
+    # budget (a few frames) needs room.  Every result equals the request
+    # computed alone on device copies made independently of the server.
+    import torch
+    from helpers import gpu_frame
+    from paper_1602_05975_amd import cdef, serve
+    pool = _host_pool()
+    rng = np.random.default_rng(12)
+    reqs, refs = [], []
+    keys = [int(k) for k in rng.integers(0, 9, size=40)]  # repeated keys: residency hits
+    for k, key in enumerate(keys):
+        fr, rec, src, skip, st, st_np = pool[key % len(pool)]
+        host = serve.HostFrame(key, rec, src, skip, fr.width, fr.height, fr.bitdepth, fr.layout)
+        stub = cdef.Frame([None] * 3, fr.width, fr.height, fr.bitdepth, fr.layout)
+        mode = serve.SEARCH if rng.random() < 0.5 else serve.FILTER
+        reqs.append(serve.Request(rid=k, mode=mode, recon=stub, host=host, damping=fr.damping,
+                                  host_strengths=st if mode == serve.FILTER else None))
+        refs.append((fr, st_np))
+    big = max(sum(p.nbytes for p in fr.recon + fr.src) + fr.skip.nbytes for fr, *_ in pool)
+    out = max(serve.output_bytes(r) for r in reqs)
+    budget = 3 * (big + out)
+    ex = serve.GpuBatchExecutor(n_streams=2) if batching else serve.GpuPlainExecutor()
+    ex.set_epoch()
+    sched = serve.Scheduler(ex, budget_bytes=budget, batching=batching)
+    offs = np.cumsum(np.random.default_rng(13).exponential(1.0 / 3000.0, len(reqs)))
+    print(f"serving {len(reqs)} host-memory requests, batching={batching}", flush=True)
+    serve.run_trace(sched, reqs, offs)
+    torch.cuda.synchronize()
+    assert len(sched.finished) == len(reqs) and not sched.rejected
+    assert sum(r.in_bytes > 0 for r in sched.finished) < len(reqs)  # some found their frame
+    assert sched.in_use == ex.frames.resident_bytes <= budget
+    for r in sched.finished:
+        fr, st_np = refs[r.rid]
+        rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+        sk = torch.from_numpy(fr.skip).cuda()
+        if r.mode == serve.SEARCH:
+            want = cdef.search_strengths(rec, src, sk, fr.damping)
+            torch.cuda.synchronize()
+            assert torch.equal(r.outputs[0], want), r.rid
+        else:
+            d, v = cdef.find_dir(rec)
+            want = cdef.filter_frame(rec, d, v, sk, fr.damping, torch.from_numpy(st_np).cuda())
+            torch.cuda.synchronize()
+            for a, b in zip(r.outputs[0], want):
+                assert torch.equal(a, b), r.rid

@@ -189,3 +189,97 @@ def test_batches_hold_one_mode_in_arrival_order():
     sched2 = serve.Scheduler(ex2, budget_bytes=1 << 30, clock=ex2.clock, split_modes=False)
     _run(sched2, ex2.clock, [_req(i, mode=m) for i, m in enumerate(modes)], [0.0] * 6, dt=5e-6)
     assert ex2.launches[0] == list(range(6))
+
+
+class FakeResident(serve.ResidentFrames):
+    """Residency without a device: uploads are recorded, events are done."""
+
+    def __init__(self):
+        super().__init__(stream=None)
+        self.uploads = []
+
+    def _upload(self, planes):
+        self.uploads.append(sum(t.numel() * t.element_size() for t in planes))
+        return [t for t in planes]
+
+    def _record(self):
+        return "event"
+
+    @staticmethod
+    def _done(ev):
+        return False
+
+
+class HostExecutor(FakeExecutor):
+    """FakeExecutor with host frames kept resident as the GPU executors do."""
+
+    def __init__(self, clock, cost_per_px=1e-9):
+        super().__init__(clock, cost_per_px)
+        self.frames = FakeResident()
+
+    def input_bytes(self, req):
+        return 0 if req.host is None else self.frames.bytes_needed(req.host, req.mode == serve.SEARCH)
+
+    def evict(self, nbytes, req=None):
+        keep = req.host.key if req is not None and req.host is not None else None
+        return self.frames.evict(nbytes, keep)
+
+    def release(self, req):
+        if req.host is not None:
+            self.frames.release(req.host.key)
+
+    def allocate(self, req):
+        if req.host is not None:
+            serve._attach_host(self.frames, req)
+        super().allocate(req)
+
+
+def _host(key, w=64, h=64):
+    import torch
+    rec = [torch.zeros((h, w), dtype=torch.int16), torch.zeros((h // 2, w // 2), dtype=torch.int16),
+           torch.zeros((h // 2, w // 2), dtype=torch.int16)]
+    src = [torch.zeros_like(t) for t in rec]
+    return serve.HostFrame(key, rec, src, None, w, h, 10, cdef.LAYOUT_420)
+
+
+def _hreq(rid, host, mode=serve.SEARCH):
+    return serve.Request(rid=rid, mode=mode, recon=cdef.Frame([None] * 3, host.width, host.height,
+                                                              10, cdef.LAYOUT_420),
+                         host=host, damping=3)
+
+
+def test_host_frames_are_charged_uploaded_once_and_evicted_when_idle():
+    clock = Clock()
+    ex = HostExecutor(clock)
+    a, b, c = _host("a"), _host("b"), _host("c")
+    planes = a.plane_bytes(a.recon)
+    out = serve.output_bytes(_hreq(0, a))
+    # room for two frames with sources and the outputs of two requests
+    budget = 2 * (2 * planes) + 2 * out
+    sched = serve.Scheduler(ex, budget_bytes=budget, clock=clock)
+    reqs = [_hreq(0, a), _hreq(1, a, serve.FILTER), _hreq(2, b), _hreq(3, c), _hreq(4, a)]
+    _run(sched, clock, reqs, [0.0, 1e-3, 2e-3, 3e-3, 4e-3], dt=1e-5)
+    assert sorted(r.rid for r in sched.finished) == [0, 1, 2, 3, 4] and not sched.rejected
+    # a: recon+src once for requests 0 and 1; b; c (evicting a, idle); a again
+    assert ex.frames.uploads.count(planes) == 2 * 4
+    assert [r.in_bytes for r in sorted(sched.finished, key=lambda r: r.rid)] == \
+        [2 * planes, 0, 2 * planes, 2 * planes, 2 * planes]
+    assert set(ex.frames.entries) <= {"a", "b", "c"} and len(ex.frames.entries) <= 2
+    assert sched.in_use == ex.frames.resident_bytes  # only resident frames stay charged
+    assert all(r.recon is not None and r.src is not None for r in sched.finished
+               if r.mode == serve.SEARCH)
+
+
+def test_a_frame_in_use_is_never_evicted():
+    clock = Clock()
+    ex = HostExecutor(clock, cost_per_px=1e-6)  # each request runs 4 ms
+    a, b = _host("a"), _host("b")
+    planes = a.plane_bytes(a.recon)
+    out = serve.output_bytes(_hreq(0, a))
+    sched = serve.Scheduler(ex, budget_bytes=2 * planes + 2 * out + 8, clock=clock)
+    # b cannot be admitted until a's request finishes and a can be evicted
+    reqs = [_hreq(0, a), _hreq(1, b)]
+    _run(sched, clock, reqs, [0.0, 1e-4], dt=1e-5)
+    r0, r1 = sorted(sched.finished, key=lambda r: r.rid)
+    assert r1.admitted >= r0.done
+    assert list(ex.frames.entries) == ["b"]
