@@ -225,6 +225,45 @@ def cpu_baseline(fr, fb_rows: int = 0, single_rows: int = 3, other_configs: bool
     return out
 
 
+def record_traffic(name, kernel, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir,
+                   copy_mib=512):
+    """profiles/<name>_4k_traffic.json from four rocprofv3 --pmc runs (csv
+    output): FETCH_SIZE and WRITE_SIZE of one launch of `kernel` (KiB per
+    dispatch, averaged over its dispatches), each scaled by what the same
+    counter reads for a device copy of copy_mib MiB (bench.py
+    --copy-calibration), together with the hash of the kernel sources."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter, match, largest=False):
+        vals = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row["Counter_Name"] == counter and match in row["Kernel_Name"]:
+                        vals.append(float(row["Counter_Value"]))
+        assert vals, (d, counter, match)
+        return max(vals) if largest else float(np.mean(vals))
+
+    fetch = per_dispatch(fetch_dir, "FETCH_SIZE", kernel)
+    write = per_dispatch(write_dir, "WRITE_SIZE", kernel)
+    cfetch = per_dispatch(copy_fetch_dir, "FETCH_SIZE", "copyBuffer", largest=True)
+    cwrite = per_dispatch(copy_write_dir, "WRITE_SIZE", "copyBuffer", largest=True)
+    nbytes = copy_mib << 20
+    fscale, wscale = nbytes / (cfetch * 1024), nbytes / (cwrite * 1024)
+    rec = {"kernel_hash": kernel_hash(), "kernel": kernel, "fetch_kib_raw": fetch,
+           "write_kib_raw": write, "copy_fetch_kib_raw": cfetch, "copy_write_kib_raw": cwrite,
+           "fetch_scale": fscale, "write_scale": wscale,
+           "hbm_bytes_per_launch": int(round(fetch * 1024 * fscale + write * 1024 * wscale)),
+           "hbm_read_bytes_per_launch": int(round(fetch * 1024 * fscale)),
+           "hbm_write_bytes_per_launch": int(round(write * 1024 * wscale))}
+    path = os.path.join(ROOT, "profiles", f"{name}_4k_traffic.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    return rec
+
+
 def load_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter runs, valid
     only while the kernel sources are unchanged since they were taken."""
@@ -533,7 +572,16 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for scaling HBM counters)")
+    ap.add_argument("--record-traffic", nargs=6, metavar=("NAME", "KERNEL", "FETCH_DIR",
+                                                        "WRITE_DIR", "COPY_FETCH_DIR",
+                                                        "COPY_WRITE_DIR"),
+                    help="only write profiles/NAME_4k_traffic.json from rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE runs of the workload and of "
+                         "--copy-calibration 512 (no GPU needed)")
     args = ap.parse_args()
+    if args.record_traffic:
+        print(json.dumps(record_traffic(*args.record_traffic)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(frames are independent: a batch shards across GPUs by frame with no exchange)",
