@@ -1,0 +1,118 @@
+"""Frames that live inside larger buffers, as codecs allocate them: row
+strides above the width, base addresses off the 16-byte grid, and different
+strides for the reconstruction, the source and the outputs.  The padding
+around each plane holds 0xFFFF (an out-of-range sample), so a kernel that
+read outside the frame would change a result; every result is compared
+with the oracle on contiguous copies, and the padding of the filter's
+output planes must come back untouched."""
+import numpy as np
+import pytest
+
+from helpers import ORACLE_THREADS, to_np_u16
+
+pytestmark = pytest.mark.gpu
+
+PAD = 0xFFFF
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_05975_amd import cdef
+    cdef.load()
+
+
+def _embed(planes, pad, fill=PAD):
+    """Device views of `planes` inside larger buffers, two rows down.  pad =
+    (extra, off): row stride width + extra + off, view starting `off` samples
+    into a row; pad = "aligned": every row stride a multiple of 8 samples and
+    16 bytes beyond the width, view 16-byte aligned (the kernels' 16-byte
+    staging path).  Returns (views, buffers)."""
+    import torch
+    views, bufs = [], []
+    for p in planes:
+        h, w = p.shape
+        if pad == "aligned":
+            off, stride = 0, (w + 7) // 8 * 8 + 8
+        else:
+            off, stride = pad[1], w + pad[0] + pad[1]
+        buf = torch.full((h + 4, stride), fill, dtype=torch.int32)
+        buf = buf.to(torch.int16).cuda()
+        v = buf[2:2 + h, off:off + w]
+        v.copy_(torch.from_numpy(p.view(np.int16)).cuda())
+        views.append(v)
+        bufs.append(buf)
+    return views, bufs
+
+
+# (width, height, bit depth, layout, recon / source / two output paddings, damping)
+CASES = [(200, 136, 10, 1, (24, 0), (29, 2), (27, 5), (33, 1), 3),
+         (200, 136, 10, 1, (13, 3), (18, 5), (16, 0), (22, 4), 4),
+         (136, 72, 12, 3, (40, 8), (45, 2), (43, 5), (49, 1), 5),
+         (131, 67, 8, 0, (7, 1), (12, 3), (10, 6), (16, 2), 6),
+         (264, 136, 10, 2, (16, 8), (21, 2), (19, 5), (25, 1), 3),
+         (328, 200, 8, 1, "aligned", "aligned", "aligned", (3, 1), 3),
+         (328, 200, 12, 3, "aligned", "aligned", (5, 3), "aligned", 4)]
+
+
+@pytest.mark.parametrize("w,h,bd,layout,rpad,spad,opad,bpad,D", CASES)
+def test_strided_planes_match_oracle(oracle, w, h, bd, layout, rpad, spad, opad, bpad, D):
+    import torch
+    from paper_1602_05975_amd import cdef, synth
+    fr = synth.make_frame(w, h, bd, layout, 81000 + w + bd + layout, skip_prob=0.3, damping=D)
+    rv, rbufs = _embed(fr.recon, rpad)
+    sv, sbufs = _embed(fr.src, spad)
+    rec = cdef.Frame(rv, w, h, bd, layout)
+    src = cdef.Frame(sv, w, h, bd, layout)
+    assert rv[0].stride(0) > w and not rv[0].is_contiguous()
+    if rpad == "aligned":
+        assert all(t.data_ptr() % 16 == 0 and t.stride(0) % 8 == 0 for t in rv + sv)
+    skip = torch.from_numpy(fr.skip).cuda()
+    st = synth.random_presets(fr, 81100 + h)
+    stg = torch.from_numpy(st).cuda()
+    print(f"strided {w}x{h} {bd}-bit layout {layout}: {rpad} {spad} {opad} {bpad}", flush=True)
+
+    sse, d, v = cdef.search_strengths(rec, src, skip, D, want_dir=True)
+    full = cdef.search_strengths(rec, src, skip, D, full=True)
+    wtd = cdef.search_strengths(rec, src, skip, D, weighted=True)
+    d2, v2 = cdef.find_dir(rec)
+    outs, obufs = _embed([np.zeros_like(p) for p in fr.recon], opad)
+    cdef.cdef_filter_frame(rec, outs, d, v, skip, D, stg)
+    # the same as batch jobs, filter outputs in other strided buffers
+    b = cdef.Batch()
+    bsse = torch.full_like(sse, -1)
+    b.add_search(rec, src, skip, D, bsse)
+    bouts, bobufs = _embed([np.zeros_like(p) for p in fr.recon], bpad)
+    b.add_filter(rec, bouts, skip, D, stg)
+    b.prepare()
+    b.launch()
+    torch.cuda.synchronize()
+
+    od, ov = oracle.find_dir(fr.recon[0], bd)
+    assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ov).all()
+    assert (d2.cpu().numpy() == od).all() and (v2.cpu().numpy() == ov).all()
+    ref, _, _ = oracle.search(fr.recon, fr.src, w, h, bd, fr.skip, D, threads=ORACLE_THREADS,
+                              layout=layout)
+    assert np.array_equal(sse.cpu().numpy().view(np.uint64), ref)
+    assert torch.equal(bsse, sse)
+    rfull, _, _ = oracle.search(fr.recon, fr.src, w, h, bd, fr.skip, D, threads=ORACLE_THREADS,
+                                full=True, layout=layout)
+    assert np.array_equal(full.cpu().numpy().view(np.uint64), rfull)
+    fbs = [(by, bx) for by in range(fr.fb_rows) for bx in range(fr.fb_cols)]
+    rw = oracle.search_fbs_weighted(fr.recon, fr.src, w, h, bd, od, ov, fr.skip, D, fbs,
+                                    threads=ORACLE_THREADS, layout=layout)
+    rw = np.moveaxis(rw.reshape((fr.fb_rows, fr.fb_cols) + rw.shape[1:]), 2, 0)
+    assert np.allclose(wtd.cpu().numpy(), rw, rtol=1e-10, atol=1e-9)
+    want = oracle.filter_frame(fr.recon, w, h, bd, od, ov, fr.skip, D, st, layout=layout)
+    for p in range(fr.nplanes):
+        for name, o, buf, in (("plain", outs[p], obufs[p]), ("batched", bouts[p], bobufs[p])):
+            assert np.array_equal(to_np_u16(o), want[p]), (name, p)
+            # nothing written around the frame
+            hb = buf.cpu().numpy().view(np.uint16).copy()
+            ph, pw = want[p].shape
+            oo = o.data_ptr() - buf.data_ptr()
+            r0, c0 = divmod(oo // 2, buf.stride(0))
+            hb[r0:r0 + ph, c0:c0 + pw] = PAD
+            assert (hb == PAD).all(), (name, p, "wrote outside the frame")
