@@ -549,9 +549,12 @@ def preset_workspace(device="cuda"):
 
 
 def select_presets(sse, lam: float, refine_passes: int = 0, stream=None, workspace=None,
-                   cand_mask=None) -> dict:
+                   cand_mask=None, retries: int = 1) -> dict:
     """Run the preset selection on a device SSE table and return the result
-    (this reads the result back, so it synchronizes the stream)."""
+    (this reads the result back, so it synchronizes the stream).  A selection
+    that could not complete (its workgroups were not all resident within the
+    kernels' bounded wait, behind other work on the device) is run again,
+    after every stream of the device has finished, up to `retries` times."""
     import numpy as np
     import torch
     dev = sse.device
@@ -560,8 +563,13 @@ def select_presets(sse, lam: float, refine_passes: int = 0, stream=None, workspa
     fl = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
     fc = torch.empty((fbr, fbc), dtype=torch.uint8, device=dev)
     ws = preset_workspace(dev) if workspace is None else workspace
-    cdef_select_presets(sse, lam, refine_passes, res, fl, fc, ws, stream, cand_mask)
-    r = CdefPresetResult.from_buffer_copy(res.cpu().numpy().tobytes())
+    for attempt in range(retries + 1):
+        cdef_select_presets(sse, lam, refine_passes, res, fl, fc, ws, stream, cand_mask)
+        r = CdefPresetResult.from_buffer_copy(res.cpu().numpy().tobytes())
+        if r.n != 0:
+            break
+        if attempt < retries:
+            torch.cuda.synchronize(dev)  # let the competing work drain first
     if r.n == 0:
         # the cooperative selection kernel gave up waiting for its workgroups
         # (all of them must be resident at once; see cdef_select_presets)

@@ -50,10 +50,16 @@ def test_select_presets_incomplete_result_raises(lib, monkeypatch):
     monkeypatch.setattr(cdef, "cdef_select_presets", lambda *a, **k: calls.append(a))
     monkeypatch.setattr(cdef, "preset_workspace", lambda device="cuda": torch.empty(16, dtype=torch.uint8))
     sse = torch.zeros((3, 2, 2, 16, 4), dtype=torch.int64)
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: calls.append("sync"))
     with pytest.raises(cdef.CdefError) as e:
         cdef.select_presets(sse, 1.0, 0)
     assert e.value.status == cdef.CDEF_E_TIMEOUT
     assert "did not complete" in str(e.value)
+    # one retry after the device has drained, then the error
+    assert len(calls) == 3 and calls[1] == "sync"
+    calls.clear()
+    with pytest.raises(cdef.CdefError):
+        cdef.select_presets(sse, 1.0, 0, retries=0)
     assert len(calls) == 1
 
 
