@@ -1474,15 +1474,26 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
                             ((uint32_t)(aB ? DB - floor_log2(aB) : 0) << 16);
         const uint32_t w1 = ((aA & 1) ? 3u : 4u) | (((aB & 1) ? 3u : 4u) << 16);
         const uint32_t w2 = ((aA & 1) ? 3u : 2u) | (((aB & 1) ? 3u : 2u) << 16);
-        u16x2 a[4];
+        // a tap group at strength 0 adds nothing (f = 0), and with one group
+        // the clamp cannot bind (its weights sum to 12/16 < 1); both
+        // decisions are wave-uniform (the task's two blocks, the block's
+        // preset)
+        const bool prim = (aA | aB) != 0, secd = py.sec != 0;
+        s16x2 P = splat(0), Q = splat(0);
+        if (prim) {
+          u16x2 a[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
-        const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
-        const int lq = py.sec ? floor_log2(py.sec) : 0;
-        const uint32_t qsh = (uint32_t)(py.sec ? DA - lq : 0) |
-                             ((uint32_t)(py.sec ? DB - lq : 0) << 16);
-        const s16x2 Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
-        const uint32_t y = __builtin_bit_cast(uint32_t, err_both<B12>(t, P, Q));
+          for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
+          P = group_sum(t, a, 0, sp, w1, w2);
+        }
+        if (secd) {
+          const int lq = floor_log2(py.sec);
+          const uint32_t qsh = (uint32_t)(DA - lq) | ((uint32_t)(DB - lq) << 16);
+          Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
+        }
+        const uint32_t y = __builtin_bit_cast(
+            uint32_t, prim && secd ? err_both<B12>(t, P, Q)
+                                   : prim || secd ? err_one<B12>(t, prim ? P : Q) : t.dxs);
         sm.sy[(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
         if (hasB) sm.sy[(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] = (uint16_t)(y >> 16);
       });
@@ -1495,12 +1506,20 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   const uint32_t css = splat32((uint32_t)pc.sec << c);
   const uint32_t cqsh = splat32((uint32_t)(pc.sec ? Dc - floor_log2(pc.sec) : 0));
   auto chroma_y = [&](const Taps &t) {
-    u16x2 a[4];
+    // as for luma: groups at strength 0 are skipped, and so is the clamp
+    // when one group is left
+    const bool prim = pc.pri != 0, secd = pc.sec != 0;
+    s16x2 P = splat(0), Q = splat(0);
+    if (prim) {
+      u16x2 a[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(csh);
-    const s16x2 P = group_sum(t, a, 0, csp, cw1, cw2);
-    const s16x2 Q = secondary(t, css, cqsh);
-    return __builtin_bit_cast(uint32_t, err_both<B12>(t, P, Q));
+      for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(csh);
+      P = group_sum(t, a, 0, csp, cw1, cw2);
+    }
+    if (secd) Q = secondary(t, css, cqsh);
+    return __builtin_bit_cast(uint32_t, prim && secd ? err_both<B12>(t, P, Q)
+                                        : prim || secd ? err_one<B12>(t, prim ? P : Q)
+                                                       : t.dxs);
   };
   if (c420) {
     const int p = wave >> 1, sub = lane >> 4, r4 = (lane >> 2) & 3, col4 = lane & 3;
