@@ -45,10 +45,62 @@ OPS_PER_SAMPLE_UNFILTERED = 3
 OPS_PER_FILTERED_SAMPLE_W = OPS_PER_FILTERED_SAMPLE + 64 * (13 - 8)
 OPS_PER_SAMPLE_MOMENTS = 6
 # The decoder path (direction search + the filter at one signaled preset
-# per filter block): per filtered sample 12 tap differences and magnitudes,
-# 8 clamp bounds, 4 primary and 8 secondary taps x 6, the sum, 3-op round,
-# add and clamp, about 126 element operations.
-OPS_PER_SAMPLE_FILTER = 126
+# per filter block).  Per sample of a filtered block, each tap of a group
+# whose strength is not 0 costs its difference and magnitude (2) and the
+# constrained term at that strength (6: shift, saturating subtract, min,
+# sign, weight, accumulate); a group at strength 0 adds nothing (f = 0).
+# With both groups the sum of the two, and the clamp to the range of the 12
+# taps (a max and a min per tap, then the clamp); with one group the clamp
+# cannot bind (weights sum to 12/16).  Round (3) and add x (1) in every
+# case.  Both groups: 127; primary only: 36; secondary only: 68; neither,
+# or a skipped block: 0 (the sample is copied).
+FILTER_OPS_PER_TAP = 2 + 6
+FILTER_OPS_CLAMP = 2 * 12 + 2
+FILTER_OPS_ROUND_ADD = 4
+
+
+def filter_ops_per_sample(pri_on, sec_on):
+    """Element operations per sample of a filtered block (arrays of bool)."""
+    pri_on, sec_on = np.asarray(pri_on, bool), np.asarray(sec_on, bool)
+    both = pri_on & sec_on
+    return np.where(pri_on | sec_on, FILTER_OPS_ROUND_ADD, 0) + \
+        FILTER_OPS_PER_TAP * (4 * pri_on + 8 * sec_on) + both * (FILTER_OPS_CLAMP + 1)
+
+
+def adjusted_luma_strength(pri, var):
+    """Eq. (13): the luma primary strength adjusted by the block variance v
+    (0 below v = 2^10; the log term 0 while v < 2^16)."""
+    pri, var = np.asarray(pri, np.int64), np.asarray(var, np.int64)
+    q = var >> 16
+    i = np.where(q > 0, np.minimum(np.floor(np.log2(np.maximum(q, 1))), 12), 0).astype(np.int64)
+    return np.where(var < 1024, 0, (pri * (4 + i) + 8) // 16)
+
+
+def filter_work(fr, strengths, var):
+    """(algorithmic ops, filtered luma samples, filtered chroma samples) of
+    the decoder path on one frame: strengths uint8 [fb_rows][fb_cols][4]
+    without the skip condition bit or the special preset, var the 8x8
+    blocks' variances from the direction search."""
+    assert not (strengths[..., 1] & 0x80).any() and not (strengths[..., 3] & 0x80).any()
+    assert (strengths[..., 0] < 16).all() and (strengths[..., 2] < 16).all()
+    br, bc = fr.blk_rows, fr.blk_cols
+    fb = strengths[np.arange(br)[:, None] // 8, np.arange(bc)[None, :] // 8].astype(np.int64)
+    live = ~fr.skip.astype(bool)
+    # samples of each 8x8 luma block and of its chroma blocks inside the frame
+    ys = np.minimum(8, fr.height - 8 * np.arange(br))[:, None]
+    xs = np.minimum(8, fr.width - 8 * np.arange(bc))[None, :]
+    n_y = ys * xs
+    ops = filter_ops_per_sample(adjusted_luma_strength(fb[..., 0], var) > 0,
+                                fb[..., 1] > 0) * n_y * live
+    n_c = 0
+    if fr.nplanes == 3:
+        sx, sy = synth_shift(fr.layout)
+        cy = -(-ys // (1 << sy)) if sy else ys
+        cx = -(-xs // (1 << sx)) if sx else xs
+        n_c = 2 * cy * cx
+        ops = ops + filter_ops_per_sample(fb[..., 2] > 0, fb[..., 3] > 0) * n_c * live
+    ops = int(ops.sum()) + OPS_PER_LUMA_PX_DIRSEARCH * fr.width * fr.height
+    return ops, int((n_y * live).sum()), int((n_c * live).sum())
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T int32 lane-ops/s;
 # packed 16-bit instructions do two element operations per lane.
 PEAK_PACKED_I16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -434,7 +486,8 @@ def run_filter(args):
     launch_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
     px = sum(f.width * f.height for f in frames)
     samples = sum(sum(int(np.prod(f.plane_dims(p))) for p in range(f.nplanes)) for f in frames)
-    ops = OPS_PER_SAMPLE_FILTER * samples + OPS_PER_LUMA_PX_DIRSEARCH * px
+    ops = sum(filter_work(fr, st.cpu().numpy(), v.cpu().numpy())[0]
+              for fr, _, _, st, _, v, _, _ in jobs)
     bytes_ = 2 * 2 * samples + sum(f.blk_rows * f.blk_cols for f in frames)
     achieved = ops / launch_s / 1e12
     print(json.dumps({
