@@ -236,7 +236,7 @@ typedef struct {
   int32_t nitems;     /* filter blocks over all jobs */
   int32_t variant;    /* launch variant 0..CDEF_BATCH_VARIANTS-1 (see below), 0 = default */
   int32_t flags;      /* set by cdef_batch_prepare (bit 0: a job needs the extended kernels
-                         -- weighted search or 4:4:4 -- which run at 2 waves per SIMD
+                         -- 4:4:4 -- which run at 2 waves per SIMD
                          whatever the variant; bit 1: every job is a filter job, run by
                          the filter-only kernels, to which the variant does not apply);
                          keep */
@@ -291,7 +291,7 @@ cdef_status cdef_batch_launch(const cdef_batch_plan *plan, void *stream);
  *                   CDEF_E_UNSUPPORTED).
  *   wg_per_cu:      workgroups (of 4 waves) resident per CU, i.e. waves per
  *                   SIMD: 3 (168 VGPRs) or 2 (256 VGPRs); 0 = 3.  The
- *                   extended kernels (weighted search, 4:4:4) always run 2.
+ *                   extended kernels (4:4:4) always run 2.
  *   cand_group:     strength pairs evaluated per pass over a filter block;
  *                   all 64 at once is the only grouping (0 = default).
  *   order:          0 = XCD-contiguous filter blocks, 1 = plain order.

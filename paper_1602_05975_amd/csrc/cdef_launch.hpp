@@ -60,7 +60,7 @@ hipError_t launch_fused_one(const JobDesc &job, hipStream_t s);
 
 // Many frames: `jobs` is a device array of njobs descriptors (item0 set),
 // nitems the total number of filter blocks.
-// extended: some job needs the extended kernels (4:4:4, weighted);
+// extended: some job needs the extended kernels (4:4:4);
 // filter_only: every job is a filter job (the filter-only kernels run it).
 // Work-queue counters of the persistent batch kernels, in the caller's
 // workspace after the job table: next[x][0] counts the items claimed from

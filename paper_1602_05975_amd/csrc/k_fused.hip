@@ -225,10 +225,9 @@ __device__ __forceinline__ s16x2 err_one(const Taps &t, s16x2 P) {
 // first, err_both for the others, with the four dependency chains advanced
 // step by step side by side, so that no packed result is read by the very
 // next instruction (which costs a wait state).  Used by the extended
-// kernels (weighted and 4:4:4 searches), whose two waves per SIMD hide few
-// wait states (weighted search +1 %); the base kernels' SSE searches, at
-// three waves per SIMD, measured 0.3 % slower with it and keep the
-// pair-by-pair order.
+// kernels, whose two waves per SIMD hide few wait states (4:4:4 search
+// +1 %); the base kernels, at three waves per SIMD, measured 0.3 % slower
+// with it and keep the pair-by-pair order.
 template <bool B12>
 __device__ __forceinline__ void err_row(const Taps &t, s16x2 P, const s16x2 (&Q)[4],
                                         s16x2 (&e)[4]) {
@@ -562,9 +561,15 @@ struct SmemCore {
   int n, nsk;
 };
 
+// Weighted search on the base layout: per-wave moment scratch in chunks of
+// 8 pairs (see plane_tasks_wb); waves 0-1 use `red`, waves 2-3 `wb`.
+constexpr int kWbPairs = 8;
+constexpr int kWbRow = 8 * 16 + 8;                   // 8 blocks of 16 samples + padding
+constexpr int kWbEntries = (kWbPairs + 1) * kWbRow;  // + the source samples
+
 template <bool X>
 struct SmemT : SmemCore<X> {
-  uint64_t red[3][4][64];  // [plane][wave][pair]: blocks with residual
+  alignas(16) uint64_t red[3][4][64];  // [plane][wave][pair]: blocks with residual
   union {
     uint64_t red2[3][4][64];  // the same over skipped blocks (full search)
     struct {
@@ -578,6 +583,7 @@ struct SmemT : SmemCore<X> {
   uint64_t skipsse[3];  // per plane: sum of (x - s)^2 over skipped blocks
   uint64_t allsse[3];   // the same over every in-frame pixel (full search)
   double skipw[3];      // Eq. (14) over skipped units, per plane
+  alignas(16) uint16_t wb[X ? 8 : 2 * kWbEntries];  // base layout: waves 2-3's moment scratch
 };
 
 // Stage the recon tiles (all modes) and, for the searches, the source
@@ -1064,12 +1070,13 @@ __device__ __forceinline__ double eq14(int n, uint32_t ss, uint32_t ss2, uint32_
 // unit row (8 or 4 pixels) per step; run by threads t0.. (nt of them) while
 // wave 0 runs the direction search.  Unit rows are dealt so that
 // neighbouring threads add into different units.
-__device__ __forceinline__ void unit_stats(SmemT<true> &sm, const JobDesc &J, int fby, int fbx,
-                                           int t, int nt) {
+template <bool X>
+__device__ __forceinline__ void unit_stats(SmemT<X> &sm, const JobDesc &J, int fby, int fbx, int t,
+                                           int nt) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
   const int planes = search_planes(J);
-  const bool c444 = J.layout == kLayout444;
+  const bool c444 = X && J.layout == kLayout444;
   // unit rows: 512 luma, then per chroma plane 256 (4x4 units) or 512 (8x8)
   const int crows = c444 ? 512 : 256;
   const int nrows = 512 + (planes - 1) * crows;
@@ -1206,34 +1213,44 @@ __device__ __forceinline__ void task_moments(s16x2 (&ev)[64], uint32_t sv, int l
 
 // ---- Weighted-search moments through LDS (chroma not 4:4:4) ---------------
 // A task's e = y - s for its 64 pairs is transposed through a per-wave LDS
-// scratch, 16 pairs at a time, so that a lane holds samples of one pair and
+// scratch, 8 pairs at a time, so that a lane holds samples of one pair and
 // one filtering unit: sum d, sum d^2 and sum e^2 then accumulate inside the
 // lane, two samples of the same unit per 32-bit word (v_dot2 squares and adds
 // both halves), instead of one transposing cross-lane reduction per moment and
-// unit.  Scratch layout: for each of 16 pairs, then for the source, four
-// blocks of 32 samples (16-bit), each block padded to 80 bytes so that the 64
-// lanes' 64-byte block reads fall on different LDS banks.  A luma task's
-// samples are unit A's 64 then unit B's, a 4:2:0 chroma task's its eight 4x4
-// units of 16 (unit 2k the low half of lane row k, unit 2k + 1 the high half).
-constexpr int kWsPairs = 16;
-constexpr int kWsBlock = 40;                   // entries per 32-sample block
-constexpr int kWsRow = 4 * kWsBlock;           // entries per pair (128 samples)
-constexpr int kWsE = kWsPairs * kWsRow;        // e entries
-constexpr int kWsEntries = kWsE + kWsRow;      // + the source samples
+// unit.  Scratch layout, per wave: a row per pair of 8 blocks of 16 samples
+// (16-bit) and 8 entries of padding, then a row of the source samples.  A
+// task's lane k writes its low-half sample at entry k and its high-half
+// sample at 64 + k of each row: a luma task's unit A (blocks 0-3, a quarter
+// of the unit each) then unit B (blocks 4-7); a 4:2:0 chroma task's units 0-3
+// (low halves of lane rows 0-3) then 4-7 (high halves).  The pairs are
+// written as the pair generator produces them, 8 at a time, so no lane holds
+// more than 8 errors, and the scratch fits beside the base layout at three
+// workgroups per CU.
 
-// The tails of the extended layout's chroma tiles beyond their 4:2:0 extent
-// (36 rows of kCS recon samples, 32 x 32 source samples), unused unless
-// chroma is 4:4:4: one per wave, each 16-byte aligned.
-__device__ __forceinline__ uint16_t *moment_scratch(SmemCore<true> &sm, int wave) {
+// The extended layout: the tails of its chroma tiles beyond their 4:2:0
+// extent (36 rows of kCS recon samples, 32 x 32 source samples), unused
+// unless chroma is 4:4:4: one per wave, each 16-byte aligned.
+__device__ __forceinline__ uint16_t *moment_scratch(SmemT<true> &sm, int wave) {
   return wave == 0 ? sm.sc[1] + 32 * 32
                    : wave == 1 ? sm.rc[0] + 36 * kCS
                                : wave == 2 ? sm.rc[1] + 36 * kCS : sm.sc[0] + 32 * 32;
 }
-static_assert(SmemCore<true>::kCSrc - 32 * 32 >= kWsEntries, "scratch in the source tail");
-static_assert(SmemCore<true>::kCT - 36 * kCS >= kWsEntries, "scratch in the recon tail");
+static_assert(SmemCore<true>::kCSrc - 32 * 32 >= kWbEntries, "scratch in the source tail");
+static_assert(SmemCore<true>::kCT - 36 * kCS >= kWbEntries, "scratch in the recon tail");
 static_assert(offsetof(SmemCore<true>, rc) % 16 == 0 && offsetof(SmemCore<true>, sc) % 16 == 0 &&
                   (SmemCore<true>::kCT * 2) % 16 == 0 && (SmemCore<true>::kCSrc * 2) % 16 == 0 &&
                   (36 * kCS * 2) % 16 == 0 && (32 * 32 * 2) % 16 == 0,
+              "16-byte aligned scratch");
+
+// The base layout: waves 0-1 in `red` (unused by the weighted search), waves
+// 2-3 in `wb`.
+__device__ __forceinline__ uint16_t *moment_scratch(SmemT<false> &sm, int wave) {
+  return wave < 2 ? reinterpret_cast<uint16_t *>(&sm.red[0][0][0]) + wave * kWbEntries
+                  : sm.wb + (wave - 2) * kWbEntries;
+}
+static_assert(2 * kWbEntries * 2 <= (int)sizeof(uint64_t) * 3 * 4 * 64, "scratch in red");
+static_assert((kWbEntries * 2) % 16 == 0 && (kWbRow * 2) % 16 == 0, "16-byte aligned rows");
+static_assert(offsetof(SmemT<false>, red) % 16 == 0 && offsetof(SmemT<false>, wb) % 16 == 0,
               "16-byte aligned scratch");
 
 // Entries another lane of the wave wrote before this point are read after
@@ -1246,11 +1263,11 @@ __device__ __forceinline__ void wave_lds_exchange() {
   asm volatile("" ::: "memory");
 }
 
-// The 16 words of a 32-sample block of the scratch (at a multiple of 8 entries).
-__device__ __forceinline__ void ws_read16(const uint16_t *ws, int at, uint32_t (&v)[16]) {
+// The 8 words of a 16-sample block of the scratch.
+__device__ __forceinline__ void wb_read8(const uint16_t *ws, int at, uint32_t (&v)[8]) {
   const uint4 *p = reinterpret_cast<const uint4 *>(ws + at);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 2; ++i) {
     const uint4 x = p[i];
     v[4 * i] = x.x;
     v[4 * i + 1] = x.y;
@@ -1259,150 +1276,161 @@ __device__ __forceinline__ void ws_read16(const uint16_t *ws, int at, uint32_t (
   }
 }
 
-// sum d, sum d^2, sum e^2 over words [k0, k0 + K) of a lane's samples.
-template <int K>
-__device__ __forceinline__ void unit_moments(const uint32_t (&E)[16], const uint32_t (&S)[16],
-                                             int k0, uint32_t &sd, uint32_t &d2, uint32_t &e2) {
+// sum d, sum d^2, sum e^2 over the 16 samples of 8 words (d = e + s).
+__device__ __forceinline__ void block_moments(const uint32_t (&E)[8], const uint32_t (&S)[8],
+                                              uint32_t (&m)[3]) {
   u16x2 s = {0, 0};
   uint32_t a = 0;
   int b = 0;
 #pragma unroll
-  for (int k = k0; k < k0 + K; ++k) {
-    const u16x2 d = as_u(E[k]) + as_u(S[k]);  // d = e + s, in [0, 2^b)
+  for (int k = 0; k < 8; ++k) {
+    const u16x2 d = as_u(E[k]) + as_u(S[k]);  // in [0, 2^b)
     s += d;
     a = __builtin_amdgcn_udot2(d, d, a, false);
     b = __builtin_amdgcn_sdot2(as_s(E[k]), as_s(E[k]), b, false);
   }
-  sd = (uint32_t)s.x + (uint32_t)s.y;
-  d2 = a;
-  e2 = (uint32_t)b;
+  m[0] = (uint32_t)s.x + (uint32_t)s.y;
+  m[1] = a;
+  m[2] = (uint32_t)b;
 }
 
-// Luma tasks (plane 0) with the LDS moments.  Lane (q, h, g) = (lane >> 2,
-// (lane >> 1) & 1, lane & 1) reads unit h's samples 32 g .. 32 g + 31 of
-// pair 16 c + q for chunks c = 0..3; the two lanes g = 0, 1 then hold halves
-// of each sum, and lane g keeps chunks 2 g and 2 g + 1: pairs 32 g + q and
-// 32 g + 16 + q of unit h.
-template <bool B12>
-__device__ __forceinline__ void plane_tasks_wl(SmemT<true> &sm, const JobDesc &J, int n, int y0,
+// Pair sink of the base-layout weighted search: keeps the errors of the
+// current chunk of 8 pairs; after a chunk's last pair it writes them to the
+// wave's scratch and the reading lane takes the moments of its block
+// (m[chunk]).  k is a compile-time constant at every call (the pair loops
+// are unrolled), so the chunk logic folds away.
+template <bool X>
+struct ChunkMoments {
+  static constexpr bool kRows = X;
+  uint16_t *ws;
+  int lane, rd, rq;         // this lane's entry in a row; the block and the row it reads
+  const uint32_t (&S)[8];   // the source words of the lane's block
+  uint32_t (&m)[8][3];
+  s16x2 ev[kWbPairs];
+  __device__ __forceinline__ void operator()(int k, s16x2 e) {
+    ev[k & 7] = e;
+    if ((k & 7) != 7) return;
+#pragma unroll
+    for (int i = 0; i < kWbPairs; ++i) {
+      const uint32_t v = __builtin_bit_cast(uint32_t, ev[i]);
+      ws[kWbRow * i + lane] = (uint16_t)v;
+      ws[kWbRow * i + 64 + lane] = (uint16_t)(v >> 16);
+    }
+    wave_lds_exchange();
+    uint32_t E[8];
+    wb_read8(ws, rq + rd, E);
+    block_moments(E, S, m[k >> 3]);
+    wave_lds_exchange();  // read before the next chunk overwrites
+  }
+};
+
+// The source row of a task, and each lane's source words.
+__device__ __forceinline__ void wb_source(uint16_t *ws, int lane, int rd, uint32_t sv,
+                                          uint32_t (&S)[8]) {
+  ws[kWbPairs * kWbRow + lane] = (uint16_t)sv;
+  ws[kWbPairs * kWbRow + 64 + lane] = (uint16_t)(sv >> 16);
+  wave_lds_exchange();
+  wb_read8(ws, kWbPairs * kWbRow + rd, S);
+}
+
+// One reduce-scatter level over the lanes of a quad: of the chunk sets
+// [c] and [c ^ BIT], each lane keeps the one whose bit matches its own
+// (`up`) and adds the partner lane's copy (DPP quad_perm CTRL).
+template <int BIT, int CTRL>
+__device__ __forceinline__ void quad_level(uint32_t (&m)[8][3], bool up) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (c & BIT) continue;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const uint32_t lo = m[c][j], hi = m[c | BIT][j];
+      const uint32_t keep = up ? hi : lo, send = up ? lo : hi;
+      m[c][j] = keep + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)send, CTRL, 0xF, 0xF, false);
+    }
+  }
+}
+
+// Luma tasks (plane 0).  Lane (q, h, r) = (lane >> 3, (lane >> 2) & 1,
+// lane & 3) reads quarter r of unit h of pair 8 c + q in chunk c; after the
+// task the quad's four lanes reduce-scatter their eight chunks' partial
+// moments so that lane r holds chunks r and r + 4 whole: pairs 8 r + q and
+// 32 + 8 r + q of unit h.
+template <bool X, bool B12>
+__device__ __forceinline__ void plane_tasks_wb(SmemT<X> &sm, const JobDesc &J, int n, int y0,
                                                int x0, int wave, int lane, double C1,
                                                double C2) {
   uint16_t *ws = moment_scratch(sm, wave);
-  const int q = lane >> 2, h = (lane >> 1) & 1, g = lane & 1;
-  const int rd = kWsBlock * (lane & 3);                     // block 2 h + g
-  const int wa = kWsBlock * (lane >> 5) + (lane & 31);      // unit A's sample `lane`
-  const int wb = wa + 2 * kWsBlock;                         // unit B's
+  const int q = lane >> 3, h = (lane >> 2) & 1, r = lane & 3;
+  const int rd = 16 * (lane & 7), rq = kWbRow * q;  // block 4 h + r of pair row q
   double acc[2] = {0.0, 0.0};
-  block_tasks<true, B12, 0>(
+  block_tasks<X, B12, 0>(
       sm, J, 0, n, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t sv) {
-        s16x2 ev[64];
-        block_pairs<false, B12, 0>(sm, J, t, A, B, StoreErr{ev});
-        ws[kWsE + wa] = (uint16_t)sv;
-        ws[kWsE + wb] = (uint16_t)(sv >> 16);
-        uint32_t S[16], sd[4], d2[4], e2[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-#pragma unroll
-          for (int i = 0; i < kWsPairs; ++i) {
-            const uint32_t v = __builtin_bit_cast(uint32_t, ev[16 * c + i]);
-            ws[kWsRow * i + wa] = (uint16_t)v;
-            ws[kWsRow * i + wb] = (uint16_t)(v >> 16);
-          }
-          wave_lds_exchange();
-          if (c == 0) ws_read16(ws, kWsE + rd, S);
-          uint32_t E[16];
-          ws_read16(ws, kWsRow * q + rd, E);
-          unit_moments<16>(E, S, 0, sd[c], d2[c], e2[c]);
-          wave_lds_exchange();  // read before the next chunk overwrites
-        }
-        // lane g: chunks 2 g + j (j = 0, 1), completed with the partner's half
-        uint32_t m[2][3];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const uint32_t keep[3] = {g ? sd[2 + j] : sd[j], g ? d2[2 + j] : d2[j],
-                                    g ? e2[2 + j] : e2[j]};
-          const uint32_t send[3] = {g ? sd[j] : sd[2 + j], g ? d2[j] : d2[2 + j],
-                                    g ? e2[j] : e2[2 + j]};
-#pragma unroll
-          for (int k = 0; k < 3; ++k)  // quad_perm [1, 0, 3, 2]: lane ^ 1
-            m[j][k] = keep[k] + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)send[k], 0xB1,
-                                                                       0xF, 0xF, false);
-        }
+        uint32_t S[8], m[8][3];
+        wb_source(ws, lane, rd, sv, S);
+        ChunkMoments<X> sink{ws, lane, rd, rq, S, m, {}};
+        block_pairs<false, B12, 0>(sm, J, t, A, B, sink);
+        quad_level<2, 0x4E>(m, (r & 2) != 0);  // quad_perm [2, 3, 0, 1]: lane ^ 2
+        quad_level<1, 0xB1>(m, (r & 1) != 0);  // quad_perm [1, 0, 3, 2]: lane ^ 1
         if (h == 0 || hasB) {
           const int u = h ? B : A;
           const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][0][u], sm.w.ustat[1][0][u],
                                        sm.w.ustat[2][0][u], C1, C2);
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[j] += eq14(e, m[j][0], m[j][1], m[j][2]);
+          acc[0] += eq14(e, m[0][0], m[0][1], m[0][2]);  // chunk r
+          acc[1] += eq14(e, m[4][0], m[4][1], m[4][2]);  // chunk r + 4
         }
       });
   // units A and B (h = 0, 1) hold the same pairs
 #pragma unroll
-  for (int j = 0; j < 2; ++j) acc[j] += __shfl_xor(acc[j], 2, 64);
+  for (int j = 0; j < 2; ++j) acc[j] += __shfl_xor(acc[j], 4, 64);
   if (h == 0) {
-    sm.w.wred[0][wave][32 * g + q] = acc[0];
-    sm.w.wred[0][wave][32 * g + 16 + q] = acc[1];
+    sm.w.wred[0][wave][8 * r + q] = acc[0];
+    sm.w.wred[0][wave][32 + 8 * r + q] = acc[1];
   }
 }
 
-// 4:2:0 chroma tasks with the LDS moments: lane (q, w) = (lane >> 2,
-// lane & 3) reads units 2 w and 2 w + 1 (the low and high halves of task
-// row w) of pair 16 c + q whole, so it completes their moments alone; it
-// accumulates pairs 16 c + q, the four lanes w of a pair are summed at the
-// end.
-template <bool B12>
-__device__ __forceinline__ void chroma420_wl(SmemT<true> &sm, const JobDesc &J, int n, int y0,
+// 4:2:0 chroma tasks: lane (q, u) = (lane >> 3, lane & 7) reads unit u of
+// pair 8 c + q whole (16 samples), so it completes the moments alone and
+// adds the unit's Eq. (14) term to pair 8 c + q; the eight lanes u of a pair
+// are summed at the end.
+template <bool X, bool B12>
+__device__ __forceinline__ void chroma420_wb(SmemT<X> &sm, const JobDesc &J, int n, int y0,
                                              int x0, int wave, int lane, double C1, double C2) {
   const int c = J.bitdepth - 8, D = J.damping;
   const int P = 1 + (wave >> 1);
   uint16_t *ws = moment_scratch(sm, wave);
-  const int q = lane >> 2, w = lane & 3;
-  const int wr = kWsBlock * (lane >> 4) + (lane & 15);  // this lane's low-half sample
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  chroma420_tasks<true, B12>(
+  const int q = lane >> 3, u = lane & 7;
+  const int rd = 16 * u, rq = kWbRow * q;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  chroma420_tasks<X, B12>(
       sm, J, 0, n, y0, x0, wave, lane,
       [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t sv) {
-        s16x2 ev[64];
-        chroma_pairs<false, B12, false>(t, c, D, 0xFFFFu, 15u, false, StoreErr{ev});
-        // units of row w, from lane 16 w
-        const int src = w << 4;
+        // unit u: the low half (u < 4) or the high half of lane row u & 3
+        const int src = (u & 3) << 4;
         const int uL = __shfl(L, src, 64), uH = __shfl(Hb, src, 64);
         const int has = __shfl((hasL ? 1 : 0) | (hasH ? 2 : 0), src, 64);
-        const Eq14Unit eL = eq14_unit((int)sm.w.ustat[0][P][uL], sm.w.ustat[1][P][uL],
-                                      sm.w.ustat[2][P][uL], C1, C2);
-        const Eq14Unit eH = eq14_unit((int)sm.w.ustat[0][P][uH], sm.w.ustat[1][P][uH],
-                                      sm.w.ustat[2][P][uH], C1, C2);
-        ws[kWsE + wr] = (uint16_t)sv;
-        ws[kWsE + wr + 16] = (uint16_t)(sv >> 16);
-        uint32_t S[16];
+        const bool mine = (has >> (u >> 2)) & 1;
+        const int unit = u < 4 ? uL : uH;
+        const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][P][unit], sm.w.ustat[1][P][unit],
+                                     sm.w.ustat[2][P][unit], C1, C2);
+        uint32_t S[8], m[8][3];
+        wb_source(ws, lane, rd, sv, S);
+        ChunkMoments<X> sink{ws, lane, rd, rq, S, m, {}};
+        chroma_pairs<false, B12, false>(t, c, D, 0xFFFFu, 15u, false, sink);
+        if (mine) {
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-#pragma unroll
-          for (int i = 0; i < kWsPairs; ++i) {
-            const uint32_t v = __builtin_bit_cast(uint32_t, ev[16 * ch + i]);
-            ws[kWsRow * i + wr] = (uint16_t)v;
-            ws[kWsRow * i + wr + 16] = (uint16_t)(v >> 16);
-          }
-          wave_lds_exchange();
-          if (ch == 0) ws_read16(ws, kWsE + kWsBlock * w, S);
-          uint32_t E[16];
-          ws_read16(ws, kWsRow * q + kWsBlock * w, E);
-          uint32_t sdL, d2L, e2L, sdH, d2H, e2H;
-          unit_moments<8>(E, S, 0, sdL, d2L, e2L);
-          unit_moments<8>(E, S, 8, sdH, d2H, e2H);
-          wave_lds_exchange();
-          if (has & 1) acc[ch] += eq14(eL, sdL, d2L, e2L);
-          if (has & 2) acc[ch] += eq14(eH, sdH, d2H, e2H);
+          for (int k = 0; k < 8; ++k) acc[k] += eq14(e, m[k][0], m[k][1], m[k][2]);
         }
       });
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    acc[j] += __shfl_xor(acc[j], 1, 64);
-    acc[j] += __shfl_xor(acc[j], 2, 64);
+  for (int k = 0; k < 8; ++k) {
+    acc[k] += __shfl_xor(acc[k], 1, 64);
+    acc[k] += __shfl_xor(acc[k], 2, 64);
+    acc[k] += __shfl_xor(acc[k], 4, 64);
   }
-  if (w == 0)
+  if (u == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) sm.w.wred[P][wave & 1][16 * j + q] = acc[j];
+    for (int k = 0; k < 8; ++k) sm.w.wred[P][wave & 1][8 * k + q] = acc[k];
+  }
 }
 
 // Weighted search over luma-shaped tasks of plane CH; lane k accumulates
@@ -1426,8 +1454,8 @@ __device__ __forceinline__ void plane_tasks_w(SmemT<true> &sm, const JobDesc &J,
   sm.w.wred[CH][wave][lane] = accw;
 }
 
-template <bool B12>
-__device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobDesc &J, int fby,
+template <bool X, bool B12>
+__device__ __forceinline__ void search_item_weighted(SmemT<X> &sm, const JobDesc &J, int fby,
                                                      int fbx, int tid) {
   const int lane = tid & 63, wave = tid >> 6;
   const int y0 = fby * 64, x0 = fbx * 64;
@@ -1439,7 +1467,7 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
   const double C1 = 6.25 * (double)(1 << (2 * c)), C2 = 312.5 * (double)(1 << (4 * c));
 
   __builtin_amdgcn_s_setprio(2);  // as in the SSE search
-  stage_item<true>(sm, J, fby, fbx, tid, true);
+  stage_item<X>(sm, J, fby, fbx, tid, true);
   for (int i = tid; i < 6 * 3 * 64; i += 256) (&sm.w.ustat[0][0][0])[i] = 0;
   __syncthreads();
   if (wave == 0)
@@ -1466,14 +1494,18 @@ __device__ __forceinline__ void search_item_weighted(SmemT<true> &sm, const JobD
     if (lane == 0) sm.skipw[P] = w;
   }
 
-  if (c444) {
+  if (X && c444) {
     // the chroma tiles fill the extended layout: cross-lane reductions
-    plane_tasks_w<B12, 0>(sm, J, n, y0, x0, wave, lane, C1, C2);
-    plane_tasks_w<B12, 1>(sm, J, n, y0, x0, wave, lane, C1, C2);
-    plane_tasks_w<B12, 2>(sm, J, n, y0, x0, wave, lane, C1, C2);
+    if constexpr (X) {
+      plane_tasks_w<B12, 0>(sm, J, n, y0, x0, wave, lane, C1, C2);
+      plane_tasks_w<B12, 1>(sm, J, n, y0, x0, wave, lane, C1, C2);
+      plane_tasks_w<B12, 2>(sm, J, n, y0, x0, wave, lane, C1, C2);
+    }
   } else {
-    plane_tasks_wl<B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
-    if (c420) chroma420_wl<B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
+    // the same code on both layouts, so that a job's table does not depend
+    // on the kernel its batch runs on
+    plane_tasks_wb<X, B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
+    if (c420) chroma420_wb<X, B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
   }
   __syncthreads();
 
@@ -1702,14 +1734,12 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
 template <bool X, bool FILTER = true>
 __device__ __forceinline__ void run_item(SmemT<X> &sm, const JobDesc &J, int item, int tid) {
   const int fby = item / J.fbc, fbx = item - fby * J.fbc;
-  if constexpr (X) {
-    if (J.mode == kModeSearchWeighted) {
-      if (J.bitdepth == 12)
-        search_item_weighted<true>(sm, J, fby, fbx, tid);
-      else
-        search_item_weighted<false>(sm, J, fby, fbx, tid);
-      return;
-    }
+  if (J.mode == kModeSearchWeighted) {
+    if (J.bitdepth == 12)
+      search_item_weighted<X, true>(sm, J, fby, fbx, tid);
+    else
+      search_item_weighted<X, false>(sm, J, fby, fbx, tid);
+    return;
   }
   if (J.bitdepth == 12) {
     if (J.mode == kModeSearch)
@@ -1976,7 +2006,7 @@ void fill_job_geometry(JobDesc &j) {
 }
 
 bool job_needs_extended(const JobDesc &j) {
-  return j.mode == kModeSearchWeighted || (j.nplanes == 3 && j.layout == kLayout444);
+  return j.nplanes == 3 && j.layout == kLayout444;
 }
 
 hipError_t launch_fused_one(const JobDesc &job, hipStream_t s) {

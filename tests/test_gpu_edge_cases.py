@@ -184,8 +184,8 @@ def test_edge_case_all_modes(oracle, kind, bd, layout):
     for p in range(fr.nplanes):
         _assert_table(f"filter plane {p}", to_np_u16(outs[p]), w_filt[p])
 
-    # the same four as batch jobs: the base kernels (search, search128,
-    # filter) and the extended one (weighted)
+    # the same four as batch jobs: one batch of the search, search128 and
+    # filter jobs, and one of the weighted search
     res = {}
     base = cdef.Batch()
     for name, kw in (("search", {}), ("search128", {"full": True})):

@@ -128,7 +128,8 @@ def test_weighted_in_batch_equals_per_frame():
         b.add_search(rec, src, skip, D, out, full=full, weighted=weighted)
         jobs.append((rec, src, skip, D, full, weighted, out))
     b.prepare()
-    assert b.plan.flags & 1
+    # 4:2:0 weighted searches run on the base kernels (three waves per SIMD)
+    assert not (b.plan.flags & 1)
     print(f"batch of {len(jobs)} jobs with weighted searches", flush=True)
     for variant in range(cdef.BATCH_VARIANTS):
         b.plan.variant = variant
@@ -140,3 +141,40 @@ def test_weighted_in_batch_equals_per_frame():
             want = cdef.search_strengths(rec, src, skip, D, full=full, weighted=weighted)
             torch.cuda.synchronize()
             assert torch.equal(out, want), (variant, full, weighted)
+
+
+def test_weighted_420_in_extended_batch_equals_per_frame():
+    # a 4:4:4 job puts the whole batch on the extended kernels; the 4:2:0
+    # and 4:0:0 weighted jobs in it run the same moment code there, so their
+    # tables equal the per-frame (base kernel) ones bit for bit
+    import torch
+    from paper_1602_05975_amd import cdef
+    s = _synth()
+    b = cdef.Batch()
+    jobs = []
+    for i, (w, h, bd, layout, mode) in enumerate([(200, 136, 10, s.LAYOUT_420, "weighted"),
+                                                  (136, 72, 10, s.LAYOUT_444, "search"),
+                                                  (131, 67, 12, s.LAYOUT_420, "weighted"),
+                                                  (72, 40, 8, s.LAYOUT_400, "weighted")]):
+        fr = s.make_frame(w, h, bd, layout, 65500 + i, skip_prob=0.3, damping=3 + i)
+        rec, src = gpu_frame(fr.recon, fr), gpu_frame(fr.src, fr)
+        skip = torch.from_numpy(fr.skip).cuda()
+        weighted = mode == "weighted"
+        shape = (fr.search_planes, fr.fb_rows, fr.fb_cols, 16, 4)
+        out = torch.full(shape, -1, dtype=torch.float64 if weighted else torch.int64,
+                         device="cuda")
+        b.add_search(rec, src, skip, fr.damping, out, weighted=weighted)
+        jobs.append((rec, src, skip, fr.damping, weighted, out))
+    b.prepare()
+    assert b.plan.flags & 1
+    print(f"extended batch of {len(jobs)} jobs", flush=True)
+    for variant in range(cdef.BATCH_VARIANTS):
+        b.plan.variant = variant
+        for j in jobs:
+            j[-1].fill_(-1)
+        b.launch()
+        torch.cuda.synchronize()
+        for rec, src, skip, D, weighted, out in jobs:
+            want = cdef.search_strengths(rec, src, skip, D, weighted=weighted)
+            torch.cuda.synchronize()
+            assert torch.equal(out, want), (variant, weighted)

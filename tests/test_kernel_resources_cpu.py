@@ -15,7 +15,7 @@ RES = os.path.join(ROOT, "paper_1602_05975_amd", "_build", "kernel_resources.jso
 BUDGET = {
     "k_fused_batchILi3ELb1ELb0E": (3, 8),   # the headline kernel
     "k_fused_batchILi3ELb0ELb0E": (3, 8),
-    "k_fused_batchILi2ELb1ELb1E": (2, 8),   # weighted search, 4:4:4
+    "k_fused_batchILi2ELb1ELb1E": (2, 8),   # 4:4:4
     "k_fused_batchILi2ELb0ELb1E": (2, 8),
     "k_fused_oneE": (3, 12),                # 11 spilled on cold paths; per-frame A/B unchanged
     "k_fused_one_xE": (2, 8),
