@@ -426,13 +426,6 @@ struct SquareSum {
   }
 };
 
-// Keeps every pair's y - s of a task.
-struct StoreErr {
-  static constexpr bool kRows = true;
-  s16x2 (&e)[64];
-  __device__ __forceinline__ void operator()(int k, s16x2 v) const { e[k] = v; }
-};
-
 // One butterfly level at lane distance 8, 4, 2 or 1: the partner lane (DPP
 // `ctrl`) lies in the other half of the group; of the values v[0, 2 HALF)
 // each lane keeps one half (the upper if `up`) and adds the partner's copy.
@@ -503,18 +496,6 @@ __device__ __forceinline__ uint64_t reduce_transpose(const int (&acc)[64], int l
   return reduce_transpose_u<B12>(v, lane);
 }
 
-// Sums within each row of 16 lanes: 64 values per lane in, and lane l of a
-// row returns the row's totals of values 4 (l mod 16) .. 4 (l mod 16) + 3.
-__device__ __forceinline__ void reduce_rows_transpose(uint32_t (&v)[64], int lane,
-                                                      uint32_t (&out)[4]) {
-  dpp_level<32, 0x140>(v, (lane & 8) != 0);
-  dpp_level<16, 0x141>(v, (lane & 4) != 0);
-  dpp_level<8, 0x4E>(v, (lane & 2) != 0);
-  dpp_level<4, 0xB1>(v, (lane & 1) != 0);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) out[j] = v[j];
-}
-
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -561,8 +542,8 @@ struct SmemCore {
   int n, nsk;
 };
 
-// Weighted search on the base layout: per-wave moment scratch in chunks of
-// 8 pairs (see plane_tasks_wb); waves 0-1 use `red`, waves 2-3 `wb`.
+// Weighted search: per-wave moment scratch in chunks of 8 pairs (see
+// ChunkMoments); waves 0-1 use `red`, idle in that mode, waves 2-3 `wb`.
 constexpr int kWbPairs = 8;
 constexpr int kWbRow = 8 * 16 + 8;                   // 8 blocks of 16 samples + padding
 constexpr int kWbEntries = (kWbPairs + 1) * kWbRow;  // + the source samples
@@ -583,7 +564,7 @@ struct SmemT : SmemCore<X> {
   uint64_t skipsse[3];  // per plane: sum of (x - s)^2 over skipped blocks
   uint64_t allsse[3];   // the same over every in-frame pixel (full search)
   double skipw[3];      // Eq. (14) over skipped units, per plane
-  alignas(16) uint16_t wb[X ? 8 : 2 * kWbEntries];  // base layout: waves 2-3's moment scratch
+  alignas(16) uint16_t wb[2 * kWbEntries];  // weighted search: waves 2-3's moment scratch
 };
 
 // Stage the recon tiles (all modes) and, for the searches, the source
@@ -1136,82 +1117,7 @@ __device__ __forceinline__ void unit_stats(SmemT<X> &sm, const JobDesc &J, int f
   }
 }
 
-// The per-pair moments of a task, summed over the lanes of each unit (all
-// 64 lanes for 8x8 units, each row of 16 for 4x4 chroma units): sum d,
-// sum d^2 and sum (d - s)^2 for either half.  Sum d is packed two units per
-// register while a unit's sum stays below 2^16 (8x8 units up to 10 bits,
-// 4x4 units up to 12); otherwise each half is summed on its own.
-template <bool ROWS, bool B12>
-struct Moments {
-  static constexpr int K = ROWS ? 4 : 1;
-  uint32_t sdlo[K], sdhi[K], d2lo[K], d2hi[K], e2lo[K], e2hi[K];
-};
-
-template <bool ROWS>
-__device__ __forceinline__ void reduce_chunk(uint32_t (&v)[64], int lane,
-                                             uint32_t (&o)[ROWS ? 4 : 1]) {
-  if constexpr (ROWS)
-    reduce_rows_transpose(v, lane, o);
-  else
-    o[0] = (uint32_t)reduce_transpose_u<false>(v, lane);  // unit sums stay below 2^32
-}
-
-template <bool ROWS, bool B12>
-__device__ __forceinline__ void task_moments(s16x2 (&ev)[64], uint32_t sv, int lane,
-                                             Moments<ROWS, B12> &m) {
-  constexpr int K = Moments<ROWS, B12>::K;
-  uint32_t v[64];
-  // squares of the 16-bit halves as single 24-bit multiplies of the
-  // selected halves (|e| and d stay below 2^12, so every square is exact)
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    const int e = (int)(int16_t)(__builtin_bit_cast(uint32_t, ev[i]) & 0xFFFFu);
-    v[i] = (uint32_t)__mul24(e, e);
-  }
-  reduce_chunk<ROWS>(v, lane, m.e2lo);
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    const int e = (int)__builtin_bit_cast(uint32_t, ev[i]) >> 16;
-    v[i] = (uint32_t)__mul24(e, e);
-  }
-  reduce_chunk<ROWS>(v, lane, m.e2hi);
-  // d = e + s, in place
-  const s16x2 s = as_s(sv);
-#pragma unroll
-  for (int i = 0; i < 64; ++i) ev[i] = ev[i] + s;
-  if constexpr (ROWS || !B12) {
-#pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i]);
-    uint32_t sd[K];
-    reduce_chunk<ROWS>(v, lane, sd);
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      m.sdlo[j] = sd[j] & 0xFFFF;
-      m.sdhi[j] = sd[j] >> 16;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i]) & 0xFFFF;
-    reduce_chunk<ROWS>(v, lane, m.sdlo);
-#pragma unroll
-    for (int i = 0; i < 64; ++i) v[i] = __builtin_bit_cast(uint32_t, ev[i]) >> 16;
-    reduce_chunk<ROWS>(v, lane, m.sdhi);
-  }
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    const uint32_t d = __builtin_bit_cast(uint32_t, ev[i]) & 0xFFFFu;
-    v[i] = __umul24(d, d);
-  }
-  reduce_chunk<ROWS>(v, lane, m.d2lo);
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    const uint32_t d = __builtin_bit_cast(uint32_t, ev[i]) >> 16;
-    v[i] = __umul24(d, d);
-  }
-  reduce_chunk<ROWS>(v, lane, m.d2hi);
-}
-
-// ---- Weighted-search moments through LDS (chroma not 4:4:4) ---------------
+// ---- Weighted-search moments through LDS ----------------------------------
 // A task's e = y - s for its 64 pairs is transposed through a per-wave LDS
 // scratch, 8 pairs at a time, so that a lane holds samples of one pair and
 // one filtering unit: sum d, sum d^2 and sum e^2 then accumulate inside the
@@ -1225,32 +1131,17 @@ __device__ __forceinline__ void task_moments(s16x2 (&ev)[64], uint32_t sv, int l
 // (low halves of lane rows 0-3) then 4-7 (high halves).  The pairs are
 // written as the pair generator produces them, 8 at a time, so no lane holds
 // more than 8 errors, and the scratch fits beside the base layout at three
-// workgroups per CU.
+// workgroups per CU.  4:4:4 chroma planes are shaped like luma.
 
-// The extended layout: the tails of its chroma tiles beyond their 4:2:0
-// extent (36 rows of kCS recon samples, 32 x 32 source samples), unused
-// unless chroma is 4:4:4: one per wave, each 16-byte aligned.
-__device__ __forceinline__ uint16_t *moment_scratch(SmemT<true> &sm, int wave) {
-  return wave == 0 ? sm.sc[1] + 32 * 32
-                   : wave == 1 ? sm.rc[0] + 36 * kCS
-                               : wave == 2 ? sm.rc[1] + 36 * kCS : sm.sc[0] + 32 * 32;
-}
-static_assert(SmemCore<true>::kCSrc - 32 * 32 >= kWbEntries, "scratch in the source tail");
-static_assert(SmemCore<true>::kCT - 36 * kCS >= kWbEntries, "scratch in the recon tail");
-static_assert(offsetof(SmemCore<true>, rc) % 16 == 0 && offsetof(SmemCore<true>, sc) % 16 == 0 &&
-                  (SmemCore<true>::kCT * 2) % 16 == 0 && (SmemCore<true>::kCSrc * 2) % 16 == 0 &&
-                  (36 * kCS * 2) % 16 == 0 && (32 * 32 * 2) % 16 == 0,
-              "16-byte aligned scratch");
-
-// The base layout: waves 0-1 in `red` (unused by the weighted search), waves
-// 2-3 in `wb`.
-__device__ __forceinline__ uint16_t *moment_scratch(SmemT<false> &sm, int wave) {
+template <bool X>
+__device__ __forceinline__ uint16_t *moment_scratch(SmemT<X> &sm, int wave) {
   return wave < 2 ? reinterpret_cast<uint16_t *>(&sm.red[0][0][0]) + wave * kWbEntries
                   : sm.wb + (wave - 2) * kWbEntries;
 }
 static_assert(2 * kWbEntries * 2 <= (int)sizeof(uint64_t) * 3 * 4 * 64, "scratch in red");
 static_assert((kWbEntries * 2) % 16 == 0 && (kWbRow * 2) % 16 == 0, "16-byte aligned rows");
-static_assert(offsetof(SmemT<false>, red) % 16 == 0 && offsetof(SmemT<false>, wb) % 16 == 0,
+static_assert(offsetof(SmemT<false>, red) % 16 == 0 && offsetof(SmemT<false>, wb) % 16 == 0 &&
+                  offsetof(SmemT<true>, red) % 16 == 0 && offsetof(SmemT<true>, wb) % 16 == 0,
               "16-byte aligned scratch");
 
 // Entries another lane of the wave wrote before this point are read after
@@ -1350,12 +1241,12 @@ __device__ __forceinline__ void quad_level(uint32_t (&m)[8][3], bool up) {
   }
 }
 
-// Luma tasks (plane 0).  Lane (q, h, r) = (lane >> 3, (lane >> 2) & 1,
-// lane & 3) reads quarter r of unit h of pair 8 c + q in chunk c; after the
-// task the quad's four lanes reduce-scatter their eight chunks' partial
-// moments so that lane r holds chunks r and r + 4 whole: pairs 8 r + q and
-// 32 + 8 r + q of unit h.
-template <bool X, bool B12>
+// Luma-shaped tasks of plane CH (luma, 4:4:4 chroma).  Lane (q, h, r) =
+// (lane >> 3, (lane >> 2) & 1, lane & 3) reads quarter r of unit h of pair
+// 8 c + q in chunk c; after the task the quad's four lanes reduce-scatter
+// their eight chunks' partial moments so that lane r holds chunks r and
+// r + 4 whole: pairs 8 r + q and 32 + 8 r + q of unit h.
+template <bool X, bool B12, int CH>
 __device__ __forceinline__ void plane_tasks_wb(SmemT<X> &sm, const JobDesc &J, int n, int y0,
                                                int x0, int wave, int lane, double C1,
                                                double C2) {
@@ -1363,18 +1254,18 @@ __device__ __forceinline__ void plane_tasks_wb(SmemT<X> &sm, const JobDesc &J, i
   const int q = lane >> 3, h = (lane >> 2) & 1, r = lane & 3;
   const int rd = 16 * (lane & 7), rq = kWbRow * q;  // block 4 h + r of pair row q
   double acc[2] = {0.0, 0.0};
-  block_tasks<X, B12, 0>(
+  block_tasks<X, B12, CH>(
       sm, J, 0, n, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t sv) {
         uint32_t S[8], m[8][3];
         wb_source(ws, lane, rd, sv, S);
         ChunkMoments<X> sink{ws, lane, rd, rq, S, m, {}};
-        block_pairs<false, B12, 0>(sm, J, t, A, B, sink);
+        block_pairs<false, B12, CH>(sm, J, t, A, B, sink);
         quad_level<2, 0x4E>(m, (r & 2) != 0);  // quad_perm [2, 3, 0, 1]: lane ^ 2
         quad_level<1, 0xB1>(m, (r & 1) != 0);  // quad_perm [1, 0, 3, 2]: lane ^ 1
         if (h == 0 || hasB) {
           const int u = h ? B : A;
-          const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][0][u], sm.w.ustat[1][0][u],
-                                       sm.w.ustat[2][0][u], C1, C2);
+          const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][CH][u], sm.w.ustat[1][CH][u],
+                                       sm.w.ustat[2][CH][u], C1, C2);
           acc[0] += eq14(e, m[0][0], m[0][1], m[0][2]);  // chunk r
           acc[1] += eq14(e, m[4][0], m[4][1], m[4][2]);  // chunk r + 4
         }
@@ -1383,8 +1274,8 @@ __device__ __forceinline__ void plane_tasks_wb(SmemT<X> &sm, const JobDesc &J, i
 #pragma unroll
   for (int j = 0; j < 2; ++j) acc[j] += __shfl_xor(acc[j], 4, 64);
   if (h == 0) {
-    sm.w.wred[0][wave][8 * r + q] = acc[0];
-    sm.w.wred[0][wave][32 + 8 * r + q] = acc[1];
+    sm.w.wred[CH][wave][8 * r + q] = acc[0];
+    sm.w.wred[CH][wave][32 + 8 * r + q] = acc[1];
   }
 }
 
@@ -1433,27 +1324,6 @@ __device__ __forceinline__ void chroma420_wb(SmemT<X> &sm, const JobDesc &J, int
   }
 }
 
-// Weighted search over luma-shaped tasks of plane CH; lane k accumulates
-// pair k, and the wave's sums go to wred[CH][wave].
-template <bool B12, int CH>
-__device__ __forceinline__ void plane_tasks_w(SmemT<true> &sm, const JobDesc &J, int n, int y0,
-                                              int x0, int wave, int lane, double C1, double C2) {
-  double accw = 0.0;
-  block_tasks<true, B12, CH>(
-      sm, J, 0, n, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t sv) {
-        s16x2 ev[64];
-        block_pairs<false, B12, CH>(sm, J, t, A, B, StoreErr{ev});
-        Moments<false, B12> m;
-        task_moments<false, B12>(ev, sv, lane, m);
-        accw += eq14((int)sm.w.ustat[0][CH][A], sm.w.ustat[1][CH][A], sm.w.ustat[2][CH][A],
-                     m.sdlo[0], m.d2lo[0], m.e2lo[0], C1, C2);
-        if (hasB)
-          accw += eq14((int)sm.w.ustat[0][CH][B], sm.w.ustat[1][CH][B], sm.w.ustat[2][CH][B],
-                       m.sdhi[0], m.d2hi[0], m.e2hi[0], C1, C2);
-      });
-  sm.w.wred[CH][wave][lane] = accw;
-}
-
 template <bool X, bool B12>
 __device__ __forceinline__ void search_item_weighted(SmemT<X> &sm, const JobDesc &J, int fby,
                                                      int fbx, int tid) {
@@ -1494,18 +1364,15 @@ __device__ __forceinline__ void search_item_weighted(SmemT<X> &sm, const JobDesc
     if (lane == 0) sm.skipw[P] = w;
   }
 
-  if (X && c444) {
-    // the chroma tiles fill the extended layout: cross-lane reductions
-    if constexpr (X) {
-      plane_tasks_w<B12, 0>(sm, J, n, y0, x0, wave, lane, C1, C2);
-      plane_tasks_w<B12, 1>(sm, J, n, y0, x0, wave, lane, C1, C2);
-      plane_tasks_w<B12, 2>(sm, J, n, y0, x0, wave, lane, C1, C2);
+  // the same code on both layouts, so that a job's table does not depend on
+  // the kernel its batch runs on
+  plane_tasks_wb<X, B12, 0>(sm, J, n, y0, x0, wave, lane, C1, C2);
+  if (c420) chroma420_wb<X, B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
+  if constexpr (X) {
+    if (c444) {
+      plane_tasks_wb<X, B12, 1>(sm, J, n, y0, x0, wave, lane, C1, C2);
+      plane_tasks_wb<X, B12, 2>(sm, J, n, y0, x0, wave, lane, C1, C2);
     }
-  } else {
-    // the same code on both layouts, so that a job's table does not depend
-    // on the kernel its batch runs on
-    plane_tasks_wb<X, B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
-    if (c420) chroma420_wb<X, B12>(sm, J, n, y0, x0, wave, lane, C1, C2);
   }
   __syncthreads();
 
