@@ -827,7 +827,13 @@ __device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, i
     tap_samples(dA, rt, bA, ta);
     tap_samples(dB, rt, bB, tb);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) tp[k] = (ta[k] | (tb[k] << 16)) & vm;
+    for (int k = 0; k < 12; ++k) tp[k] = ta[k] | (tb[k] << 16);
+    // the mask only where a lane is outside the frame or has no block B
+    // (wave-uniform): most tasks skip it
+    if (SRC && __builtin_amdgcn_read_exec() != __ballot(vA && vB)) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) tp[k] &= vm;
+    }
     Taps t;
     prepare<B12>(t, xv, sv, tp);
     body(t, A, B, hasB, sv);
@@ -898,8 +904,14 @@ __device__ __forceinline__ void chroma420_tasks(SmemCore<X> &sm, const JobDesc &
     for (int k = 0; k < 6; ++k) {
       const int oL = sm.coff[dL][k], oH = sm.coff[dH][k];
       const int slot = (k >> 1) * 4 + (k & 1) * 2;
-      tp[slot] = ((uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16)) & vm;
-      tp[slot + 1] = ((uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16)) & vm;
+      tp[slot] = (uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16);
+      tp[slot + 1] = (uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16);
+    }
+    // as for luma tasks: the mask only where a lane is outside the frame or
+    // past the list's end (wave-uniform)
+    if (SRC && __builtin_amdgcn_read_exec() != __ballot(vL && vH)) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) tp[k] &= vm;
     }
     Taps t;
     prepare<B12>(t, xv, sv, tp);
