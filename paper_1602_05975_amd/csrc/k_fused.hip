@@ -323,8 +323,6 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
 #pragma unroll
   for (int si = 1; si < 4; ++si)
     if (!SUB || ((pm & 1) && ((qm >> si) & 1))) sink(si, err_one<B12>(t, Q[si]));
-  uint32_t prev_sh = 0xFFFFFFFFu;
-  u16x2 a[4];
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
     if (SUB && !((pm >> S) & 1)) continue;
@@ -335,14 +333,13 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
     const uint32_t sh = sha | (shb << 16);
     const uint32_t w1 = ((sa & 1) ? 3u : 4u) | (((sb & 1) ? 3u : 4u) << 16);
     const uint32_t w2 = ((sa & 1) ? 3u : 2u) | (((sb & 1) ? 3u : 2u) << 16);
-    // the shift pair changes only a few times over S = 1..15; a subset
-    // re-shifts at every strength it visits (cheaper than the per-lane
-    // selects the compiler makes of the test there)
-    if (SUB || sh != prev_sh) {
-      prev_sh = sh;
+    // the shift pair changes only a few times over S = 1..15, but skipping
+    // the re-shift where it does not makes the magnitudes a value carried
+    // across a branch at every strength, which the compiler copies (4
+    // moves per strength, more than the 4 shifts)
+    u16x2 a[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
-    }
+    for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
     const s16x2 P = group_sum(t, a, 0, sp, w1, w2);
     if constexpr (!SUB && std::decay_t<Sink>::kRows) {
       s16x2 e[4];
