@@ -358,9 +358,13 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
 // Chroma task: strengths are not adjusted (uniform over the plane); the
 // chroma damping is max(D - 1, floor(log2 S^(p))) for both tap groups, which
 // differs from D - 1 only for D = 3 and S^(p) >= 8.
-template <bool FULL, bool B12, bool SUB, class Sink>
-__device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, uint32_t pm, uint32_t qm,
-                                             bool sp19, Sink &&sink) {
+// D3: D = 3, where the chroma damping of the secondary taps changes at
+// S^(p) = 8.  Callers pick the variant outside their task loops (with_d3),
+// so that no branch splits a loop's unrolled strength sequence.
+template <bool FULL, bool B12, bool SUB, bool D3, class Sink>
+__device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int Drt, uint32_t pm,
+                                             uint32_t qm, bool sp19, Sink &&sink) {
+  const int D = D3 ? 3 : Drt;
   if (FULL) {
     if (!SUB || sp19) sink(0, chroma_special<B12>(t, c, D));
   } else if (!SUB || (pm & qm & 1)) {
@@ -375,7 +379,7 @@ __device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, uint32
 #pragma unroll
   for (int S = 1; S < 16; ++S) {
     const int lg = S >= 8 ? 3 : S >= 4 ? 2 : S >= 2 ? 1 : 0;
-    if (S == 8 && D == 3) secondaries(t, c, 3, Q);  // chroma damping becomes 3
+    if (S == 8 && D3) secondaries(t, c, 3, Q);  // chroma damping becomes 3
     const int Dc = max(D - 1, lg);
     // the shift changes only where floor(log2 S) does (compile-time), so the
     // magnitudes are re-shifted there, also when a subset skips that S
@@ -398,6 +402,15 @@ __device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int D, uint32
         if (!SUB || ((qm >> si) & 1)) sink(4 * S + si, err_both<B12>(t, P, Q[si]));
     }
   }
+}
+
+// Runs f(std::true_type) when D = 3, f(std::false_type) otherwise.
+template <class F>
+__device__ __forceinline__ void with_d3(int D, F &&f) {
+  if (D == 3)
+    f(std::true_type{});
+  else
+    f(std::false_type{});
 }
 
 // The subset of a job: S^(p) mask, S^(s) index mask, skip-bit mask (all
@@ -837,8 +850,9 @@ __device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, i
   }
 }
 
-// The pair generator of a luma-shaped task of plane CH.
-template <bool FULL, bool B12, int CH, bool SUB = false, bool X, class Sink>
+// The pair generator of a luma-shaped task of plane CH (D3: see
+// chroma_pairs; luma ignores it).
+template <bool FULL, bool B12, int CH, bool SUB = false, bool D3 = false, bool X, class Sink>
 __device__ __forceinline__ void block_pairs(SmemT<X> &sm, const JobDesc &J, const Taps &t, int A,
                                             int B, Sink &&sink) {
   const int c = J.bitdepth - 8, D = J.damping;
@@ -849,7 +863,7 @@ __device__ __forceinline__ void block_pairs(SmemT<X> &sm, const JobDesc &J, cons
     const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
     luma_pairs<FULL, B12, SUB>(t, adjA, adjB, a19A, a19B, c, D, sub.pm, sub.qm, sp19, sink);
   } else {
-    chroma_pairs<FULL, B12, SUB>(t, c, D, sub.pm, sub.qm, sp19, sink);
+    chroma_pairs<FULL, B12, SUB, D3>(t, c, D, sub.pm, sub.qm, sp19, sink);
   }
 }
 
@@ -860,10 +874,17 @@ __device__ __forceinline__ void plane_tasks(SmemT<X> &sm, const JobDesc &J, int 
   int acc[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) acc[i] = 0;
-  block_tasks<X, B12, CH>(sm, J, first, count, y0, x0, wave, lane,
-                          [&](const Taps &t, int A, int B, bool, uint32_t) {
-                            block_pairs<FULL, B12, CH, SUB>(sm, J, t, A, B, SquareSum<X>{acc});
-                          });
+  auto run = [&](auto d3) {
+    block_tasks<X, B12, CH>(sm, J, first, count, y0, x0, wave, lane,
+                            [&](const Taps &t, int A, int B, bool, uint32_t) {
+                              block_pairs<FULL, B12, CH, SUB, decltype(d3)::value>(
+                                  sm, J, t, A, B, SquareSum<X>{acc});
+                            });
+  };
+  if constexpr (CH == 0)
+    run(std::false_type{});
+  else
+    with_d3(J.damping, run);
   red[wave * 64 + lane] = reduce_transpose<B12>(acc, lane);
 }
 
@@ -928,11 +949,13 @@ __device__ __forceinline__ void chroma420_sse(SmemT<X> &sm, const JobDesc &J, in
   int acc[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) acc[i] = 0;
-  chroma420_tasks<X, B12>(sm, J, first, count, y0, x0, wave, lane,
-                          [&](const Taps &t, int, int, bool, bool, uint32_t) {
-                            chroma_pairs<FULL, B12, SUB>(t, c, D, sub.pm, sub.qm, sp19,
-                                                         SquareSum<X>{acc});
-                          });
+  with_d3(D, [&](auto d3) {
+    chroma420_tasks<X, B12>(sm, J, first, count, y0, x0, wave, lane,
+                            [&](const Taps &t, int, int, bool, bool, uint32_t) {
+                              chroma_pairs<FULL, B12, SUB, decltype(d3)::value>(
+                                  t, c, D, sub.pm, sub.qm, sp19, SquareSum<X>{acc});
+                            });
+  });
   red[1 + (wave >> 1)][wave & 1][lane] = reduce_transpose<B12>(acc, lane);
 }
 
@@ -1263,22 +1286,29 @@ __device__ __forceinline__ void plane_tasks_wb(SmemT<X> &sm, const JobDesc &J, i
   const int q = lane >> 3, h = (lane >> 2) & 1, r = lane & 3;
   const int rd = 16 * (lane & 7), rq = kWbRow * q;  // block 4 h + r of pair row q
   double acc[2] = {0.0, 0.0};
-  block_tasks<X, B12, CH>(
-      sm, J, 0, n, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t sv) {
-        uint32_t S[8], m[8][3];
-        wb_source(ws, lane, rd, sv, S);
-        ChunkMoments<X> sink{ws, lane, rd, rq, S, m, {}};
-        block_pairs<false, B12, CH>(sm, J, t, A, B, sink);
-        quad_level<2, 0x4E>(m, (r & 2) != 0);  // quad_perm [2, 3, 0, 1]: lane ^ 2
-        quad_level<1, 0xB1>(m, (r & 1) != 0);  // quad_perm [1, 0, 3, 2]: lane ^ 1
-        if (h == 0 || hasB) {
-          const int u = h ? B : A;
-          const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][CH][u], sm.w.ustat[1][CH][u],
-                                       sm.w.ustat[2][CH][u], C1, C2);
-          acc[0] += eq14(e, m[0][0], m[0][1], m[0][2]);  // chunk r
-          acc[1] += eq14(e, m[4][0], m[4][1], m[4][2]);  // chunk r + 4
-        }
-      });
+  auto run = [&](auto d3) {
+    block_tasks<X, B12, CH>(
+        sm, J, 0, n, y0, x0, wave, lane,
+        [&](const Taps &t, int A, int B, bool hasB, uint32_t sv) {
+          uint32_t S[8], m[8][3];
+          wb_source(ws, lane, rd, sv, S);
+          ChunkMoments<X> sink{ws, lane, rd, rq, S, m, {}};
+          block_pairs<false, B12, CH, false, decltype(d3)::value>(sm, J, t, A, B, sink);
+          quad_level<2, 0x4E>(m, (r & 2) != 0);  // quad_perm [2, 3, 0, 1]: lane ^ 2
+          quad_level<1, 0xB1>(m, (r & 1) != 0);  // quad_perm [1, 0, 3, 2]: lane ^ 1
+          if (h == 0 || hasB) {
+            const int u = h ? B : A;
+            const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][CH][u], sm.w.ustat[1][CH][u],
+                                         sm.w.ustat[2][CH][u], C1, C2);
+            acc[0] += eq14(e, m[0][0], m[0][1], m[0][2]);  // chunk r
+            acc[1] += eq14(e, m[4][0], m[4][1], m[4][2]);  // chunk r + 4
+          }
+        });
+  };
+  if constexpr (CH == 0)
+    run(std::false_type{});
+  else
+    with_d3(J.damping, run);
   // units A and B (h = 0, 1) hold the same pairs
 #pragma unroll
   for (int j = 0; j < 2; ++j) acc[j] += __shfl_xor(acc[j], 4, 64);
@@ -1301,26 +1331,29 @@ __device__ __forceinline__ void chroma420_wb(SmemT<X> &sm, const JobDesc &J, int
   const int q = lane >> 3, u = lane & 7;
   const int rd = 16 * u, rq = kWbRow * q;
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  chroma420_tasks<X, B12>(
-      sm, J, 0, n, y0, x0, wave, lane,
-      [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t sv) {
-        // unit u: the low half (u < 4) or the high half of lane row u & 3
-        const int src = (u & 3) << 4;
-        const int uL = __shfl(L, src, 64), uH = __shfl(Hb, src, 64);
-        const int has = __shfl((hasL ? 1 : 0) | (hasH ? 2 : 0), src, 64);
-        const bool mine = (has >> (u >> 2)) & 1;
-        const int unit = u < 4 ? uL : uH;
-        const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][P][unit], sm.w.ustat[1][P][unit],
-                                     sm.w.ustat[2][P][unit], C1, C2);
-        uint32_t S[8], m[8][3];
-        wb_source(ws, lane, rd, sv, S);
-        ChunkMoments<X> sink{ws, lane, rd, rq, S, m, {}};
-        chroma_pairs<false, B12, false>(t, c, D, 0xFFFFu, 15u, false, sink);
-        if (mine) {
+  with_d3(D, [&](auto d3) {
+    chroma420_tasks<X, B12>(
+        sm, J, 0, n, y0, x0, wave, lane,
+        [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t sv) {
+          // unit u: the low half (u < 4) or the high half of lane row u & 3
+          const int src = (u & 3) << 4;
+          const int uL = __shfl(L, src, 64), uH = __shfl(Hb, src, 64);
+          const int has = __shfl((hasL ? 1 : 0) | (hasH ? 2 : 0), src, 64);
+          const bool mine = (has >> (u >> 2)) & 1;
+          const int unit = u < 4 ? uL : uH;
+          const Eq14Unit e = eq14_unit((int)sm.w.ustat[0][P][unit], sm.w.ustat[1][P][unit],
+                                       sm.w.ustat[2][P][unit], C1, C2);
+          uint32_t S[8], m[8][3];
+          wb_source(ws, lane, rd, sv, S);
+          ChunkMoments<X> sink{ws, lane, rd, rq, S, m, {}};
+          chroma_pairs<false, B12, false, decltype(d3)::value>(t, c, D, 0xFFFFu, 15u, false,
+                                                               sink);
+          if (mine) {
 #pragma unroll
-          for (int k = 0; k < 8; ++k) acc[k] += eq14(e, m[k][0], m[k][1], m[k][2]);
-        }
-      });
+            for (int k = 0; k < 8; ++k) acc[k] += eq14(e, m[k][0], m[k][1], m[k][2]);
+          }
+        });
+  });
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     acc[k] += __shfl_xor(acc[k], 1, 64);
