@@ -307,10 +307,13 @@ __device__ __forceinline__ s16x2 chroma_special(const Taps &t, int c, int D) {
 //
 // SUB: only the strengths of a subset (pm: S^(p) mask, qm: S^(s) index mask,
 // sp19: the special preset) are evaluated; the sink sees no other pair.
+// Per block of the task (A: low halves, B: high halves): adj the adjusted
+// strengths, lsh and par their shifts and parities (SmemCore::lsh, lpar).
 template <bool FULL, bool B12, bool SUB, class Sink>
-__device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_t adjB, int a19A,
-                                           int a19B, int c, int D, uint32_t pm, uint32_t qm,
-                                           bool sp19, Sink &&sink) {
+__device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_t adjB,
+                                           uint64_t lshA, uint64_t lshB, uint32_t parA,
+                                           uint32_t parB, int a19A, int a19B, int c, int D,
+                                           uint32_t pm, uint32_t qm, bool sp19, Sink &&sink) {
   // pair (0, 0) filters nothing; in the full search its slot carries the
   // special preset instead (the unfiltered distortion is summed elsewhere)
   if (FULL) {
@@ -327,12 +330,12 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
   for (int S = 1; S < 16; ++S) {
     if (SUB && !((pm >> S) & 1)) continue;
     const uint32_t sa = (uint32_t)(adjA >> (4 * S)) & 15u, sb = (uint32_t)(adjB >> (4 * S)) & 15u;
-    const uint32_t sp = (sa << c) | (sb << (16 + c));
-    const uint32_t sha = sa ? (uint32_t)(D - floor_log2((int)sa)) : 0u;
-    const uint32_t shb = sb ? (uint32_t)(D - floor_log2((int)sb)) : 0u;
-    const uint32_t sh = sha | (shb << 16);
-    const uint32_t w1 = ((sa & 1) ? 3u : 4u) | (((sb & 1) ? 3u : 4u) << 16);
-    const uint32_t w2 = ((sa & 1) ? 3u : 2u) | (((sb & 1) ? 3u : 2u) << 16);
+    const uint32_t sp = (sa | (sb << 16)) << c;
+    const uint32_t sh =
+        ((uint32_t)(lshA >> (4 * S)) & 15u) | (((uint32_t)(lshB >> (4 * S)) & 15u) << 16);
+    // weights 4, 2 at even strengths, 3, 3 at odd ones
+    const uint32_t odd = ((parA >> S) & 1u) | (((parB >> S) & 1u) << 16);
+    const uint32_t w1 = 0x00040004u - odd, w2 = 0x00020002u + odd;
     // the shift pair changes only a few times over S = 1..15, but skipping
     // the re-shift where it does not makes the magnitudes a value carried
     // across a branch at every strength, which the compiler copies (4
@@ -543,6 +546,11 @@ struct SmemCore {
   uint16_t rc[2][kCT];
   uint16_t sc[2][kCSrc];  // searches: source; filter: filtered chroma
   uint64_t adj[64];
+  // searches, per block and primary strength S = 1..15 of the adjusted
+  // strength a_S: 4 bits of D - floor(log2 a_S) (0 where a_S = 0), and bit S
+  // of its parity
+  uint64_t lsh[64];
+  uint16_t lpar[64];
   int32_t var[64];
   int16_t coff[8][6];
   uint8_t dir[64];
@@ -726,7 +734,21 @@ __device__ __forceinline__ void direction_search(SmemCore<X> &sm, const JobDesc 
   }
   sm.dir[b] = (uint8_t)d;
   sm.var[b] = v;
-  sm.adj[b] = adjusted_strengths(v);
+  const uint64_t adj = adjusted_strengths(v);
+  sm.adj[b] = adj;
+  if constexpr (!PACKED) {
+    const int D = J.damping;
+    uint64_t shw = 0;
+    uint32_t par = 0;
+#pragma unroll
+    for (int S = 1; S < 16; ++S) {
+      const int a = (int)(adj >> (4 * S)) & 15;
+      if (a) shw |= (uint64_t)(D - floor_log2(a)) << (4 * S);
+      par |= (uint32_t)(a & 1) << S;
+    }
+    sm.lsh[b] = shw;
+    sm.lpar[b] = (uint16_t)par;
+  }
   const bool active = in && !sk;
   const uint64_t below = (1ull << lane) - 1ull;
   const uint64_t m = __ballot(active);
@@ -860,8 +882,11 @@ __device__ __forceinline__ void block_pairs(SmemT<X> &sm, const JobDesc &J, cons
   const bool sp19 = sub.has(1, 0);
   if (CH == 0) {
     const uint64_t adjA = uniform64(sm.adj[A]), adjB = uniform64(sm.adj[B]);
+    const uint64_t lshA = uniform64(sm.lsh[A]), lshB = uniform64(sm.lsh[B]);
+    const uint32_t parA = uniform(sm.lpar[A]), parB = uniform(sm.lpar[B]);
     const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
-    luma_pairs<FULL, B12, SUB>(t, adjA, adjB, a19A, a19B, c, D, sub.pm, sub.qm, sp19, sink);
+    luma_pairs<FULL, B12, SUB>(t, adjA, adjB, lshA, lshB, parA, parB, a19A, a19B, c, D, sub.pm,
+                               sub.qm, sp19, sink);
   } else {
     chroma_pairs<FULL, B12, SUB, D3>(t, c, D, sub.pm, sub.qm, sp19, sink);
   }
