@@ -765,54 +765,80 @@ __device__ __forceinline__ void direction_search(SmemCore<X> &sm, const JobDesc 
 
 // Sum of (x - s)^2 over pixels of skipped blocks, for each searched plane,
 // and in the full search also over every in-frame pixel; run by threads
-// t0.. of the workgroup (nt of them).  Per-lane partial sums stay below
-// 2^32 (at most 22 pixels of 12 bits); the wave sums are 64-bit.
+// t0.. of the workgroup (nt of them).  The work unit is a block row (8
+// samples of a luma-shaped plane, 4 of a 4:2:0 chroma plane), read as one
+// 16- or 8-byte word from each tile; its squares go through v_dot2, two
+// samples per instruction.  A row that the frame edge cuts takes the
+// samples one by one.  Per-lane partial sums stay below 2^32 (at most 24
+// samples of 12 bits); the wave sums are 64-bit.
 template <bool FULL, bool X>
 __device__ __forceinline__ void skipped_sse(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
                                             int t, int nt, int lane) {
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   uint32_t e[3] = {0, 0, 0}, a[3] = {0, 0, 0};
   const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
-  for (int i = t; i < 64 * 64; i += nt) {
-    const int r = i >> 6, col = i & 63;
-    if (y0 + r < H && x0 + col < W) {
-      const bool sk = sm.flag[(r >> 3) * 8 + (col >> 3)] & 2;
-      const int k = (r + 2) * kLS + kLC0 + col;
-      const int dd = (int)sm.ry[k] - (int)sm.sy[i];
-      const uint32_t q = (uint32_t)(dd * dd);
-      if (sk) e[0] += q;
-      a[0] += q;
-      if constexpr (X) {
-        if (c444) {
-          const int d1 = (int)sm.rc[0][k] - (int)sm.sc[0][i];
-          const int d2 = (int)sm.rc[1][k] - (int)sm.sc[1][i];
-          const uint32_t q1 = (uint32_t)(d1 * d1), q2 = (uint32_t)(d2 * d2);
-          if (sk) {
-            e[1] += q1;
-            e[2] += q2;
-          }
-          a[1] += q1;
-          a[2] += q2;
+  // squares of the differences of N 16-bit words pairs (2 samples each)
+  auto sq = [](const uint32_t *xw, const uint32_t *sw, int n) {
+    uint32_t q = 0;
+    for (int w = 0; w < n; ++w) {
+      const s16x2 d = as_s(xw[w]) - as_s(sw[w]);
+      q = __builtin_amdgcn_sdot2(d, d, q, false);
+    }
+    return q;
+  };
+  // luma-shaped planes: 512 rows of 8 samples (row r, block column bc)
+  auto plane8 = [&](const uint16_t *rt, const uint16_t *st, int P) {
+    for (int i = t; i < 512; i += nt) {
+      const int r = i >> 3, bc = i & 7, col = 8 * bc;
+      const int fl = sm.flag[(r >> 3) * 8 + bc];
+      if (!(fl & 1) || (!FULL && !(fl & 2)) || y0 + r >= H) continue;
+      uint32_t q;
+      if (x0 + col + 8 <= W) {
+        const uint4 xv = *reinterpret_cast<const uint4 *>(rt + (r + 2) * kLS + kLC0 + col);
+        const uint4 sv = *reinterpret_cast<const uint4 *>(st + r * 64 + col);
+        const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w}, sw[4] = {sv.x, sv.y, sv.z, sv.w};
+        q = sq(xw, sw, 4);
+      } else {
+        q = 0;
+        for (int j = 0; j < 8 && x0 + col + j < W; ++j) {
+          const int dd = (int)rt[(r + 2) * kLS + kLC0 + col + j] - (int)st[r * 64 + col + j];
+          q += (uint32_t)(dd * dd);
         }
       }
+      if (fl & 2) e[P] += q;
+      a[P] += q;
+    }
+  };
+  plane8(sm.ry, sm.sy, 0);
+  if constexpr (X) {
+    if (c444) {
+      plane8(sm.rc[0], sm.sc[0], 1);
+      plane8(sm.rc[1], sm.sc[1], 2);
     }
   }
   if (J.nplanes == 3 && J.layout == kLayout420) {
+    // 4:2:0 chroma: per plane 256 rows of 4 samples (4x4 blocks)
     const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
-    for (int i = t; i < 32 * 32; i += nt) {
-      const int r = i >> 5, col = i & 31;
-      if (cy0 + r < ch && cx0 + col < cw) {
-        const int k = (r + 2) * kCS + kCC0 + col;
-        const int d1 = (int)sm.rc[0][k] - (int)sm.sc[0][i];
-        const int d2 = (int)sm.rc[1][k] - (int)sm.sc[1][i];
-        const uint32_t q1 = (uint32_t)(d1 * d1), q2 = (uint32_t)(d2 * d2);
-        if (sm.flag[(r >> 2) * 8 + (col >> 2)] & 2) {
-          e[1] += q1;
-          e[2] += q2;
+    for (int i = t; i < 512; i += nt) {
+      const int p = i >> 8, r = (i >> 3) & 31, bc = i & 7, col = 4 * bc;
+      const int fl = sm.flag[(r >> 2) * 8 + bc];
+      if (!(fl & 1) || (!FULL && !(fl & 2)) || cy0 + r >= ch) continue;
+      uint32_t q;
+      if (cx0 + col + 4 <= cw) {
+        const uint2 xv = *reinterpret_cast<const uint2 *>(sm.rc[p] + (r + 2) * kCS + kCC0 + col);
+        const uint2 sv = *reinterpret_cast<const uint2 *>(sm.sc[p] + r * 32 + col);
+        const uint32_t xw[2] = {xv.x, xv.y}, sw[2] = {sv.x, sv.y};
+        q = sq(xw, sw, 2);
+      } else {
+        q = 0;
+        for (int j = 0; j < 4 && cx0 + col + j < cw; ++j) {
+          const int dd =
+              (int)sm.rc[p][(r + 2) * kCS + kCC0 + col + j] - (int)sm.sc[p][r * 32 + col + j];
+          q += (uint32_t)(dd * dd);
         }
-        a[1] += q1;
-        a[2] += q2;
       }
+      if (fl & 2) e[1 + p] += q;
+      a[1 + p] += q;
     }
   }
 #pragma unroll
