@@ -307,13 +307,16 @@ __device__ __forceinline__ s16x2 chroma_special(const Taps &t, int c, int D) {
 //
 // SUB: only the strengths of a subset (pm: S^(p) mask, qm: S^(s) index mask,
 // sp19: the special preset) are evaluated; the sink sees no other pair.
-// Per block of the task (A: low halves, B: high halves): adj the adjusted
-// strengths, lsh and par their shifts and parities (SmemCore::lsh, lpar).
-template <bool FULL, bool B12, bool SUB, class Sink>
+// QALL: the subset has every S^(s) (qm = 15), so no pair needs its own
+// test.  Per block of the task (A: low halves, B: high halves): adj the
+// adjusted strengths, lsh and par their shifts and parities
+// (SmemCore::lsh, lpar).
+template <bool FULL, bool B12, bool SUB, bool QALL = false, class Sink>
 __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_t adjB,
                                            uint64_t lshA, uint64_t lshB, uint32_t parA,
                                            uint32_t parB, int a19A, int a19B, int c, int D,
                                            uint32_t pm, uint32_t qm, bool sp19, Sink &&sink) {
+  if constexpr (QALL) qm = 15u;
   // pair (0, 0) filters nothing; in the full search its slot carries the
   // special preset instead (the unfiltered distortion is summed elsewhere)
   if (FULL) {
@@ -364,10 +367,11 @@ __device__ __forceinline__ void luma_pairs(const Taps &t, uint64_t adjA, uint64_
 // D3: D = 3, where the chroma damping of the secondary taps changes at
 // S^(p) = 8.  Callers pick the variant outside their task loops (with_d3),
 // so that no branch splits a loop's unrolled strength sequence.
-template <bool FULL, bool B12, bool SUB, bool D3, class Sink>
+template <bool FULL, bool B12, bool SUB, bool D3, bool QALL = false, class Sink>
 __device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int Drt, uint32_t pm,
                                              uint32_t qm, bool sp19, Sink &&sink) {
   const int D = D3 ? 3 : Drt;
+  if constexpr (QALL) qm = 15u;  // as in luma_pairs
   if (FULL) {
     if (!SUB || sp19) sink(0, chroma_special<B12>(t, c, D));
   } else if (!SUB || (pm & qm & 1)) {
@@ -407,13 +411,19 @@ __device__ __forceinline__ void chroma_pairs(const Taps &t, int c, int Drt, uint
   }
 }
 
-// Runs f(std::true_type) when D = 3, f(std::false_type) otherwise.
+// Runs f(std::true_type) when b holds, f(std::false_type) otherwise: a
+// runtime choice made once, outside a task loop, between two instantiations.
 template <class F>
-__device__ __forceinline__ void with_d3(int D, F &&f) {
-  if (D == 3)
+__device__ __forceinline__ void with_flag(bool b, F &&f) {
+  if (b)
     f(std::true_type{});
   else
     f(std::false_type{});
+}
+
+template <class F>
+__device__ __forceinline__ void with_d3(int D, F &&f) {
+  with_flag(D == 3, f);
 }
 
 // The subset of a job: S^(p) mask, S^(s) index mask, skip-bit mask (all
@@ -900,7 +910,8 @@ __device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, i
 
 // The pair generator of a luma-shaped task of plane CH (D3: see
 // chroma_pairs; luma ignores it).
-template <bool FULL, bool B12, int CH, bool SUB = false, bool D3 = false, bool X, class Sink>
+template <bool FULL, bool B12, int CH, bool SUB = false, bool D3 = false, bool QALL = false,
+          bool X, class Sink>
 __device__ __forceinline__ void block_pairs(SmemT<X> &sm, const JobDesc &J, const Taps &t, int A,
                                             int B, Sink &&sink) {
   const int c = J.bitdepth - 8, D = J.damping;
@@ -911,10 +922,10 @@ __device__ __forceinline__ void block_pairs(SmemT<X> &sm, const JobDesc &J, cons
     const uint64_t lshA = uniform64(sm.lsh[A]), lshB = uniform64(sm.lsh[B]);
     const uint32_t parA = uniform(sm.lpar[A]), parB = uniform(sm.lpar[B]);
     const int a19A = FULL ? uniform(sm.adj19[A]) : 0, a19B = FULL ? uniform(sm.adj19[B]) : 0;
-    luma_pairs<FULL, B12, SUB>(t, adjA, adjB, lshA, lshB, parA, parB, a19A, a19B, c, D, sub.pm,
-                               sub.qm, sp19, sink);
+    luma_pairs<FULL, B12, SUB, QALL>(t, adjA, adjB, lshA, lshB, parA, parB, a19A, a19B, c, D,
+                                     sub.pm, sub.qm, sp19, sink);
   } else {
-    chroma_pairs<FULL, B12, SUB, D3>(t, c, D, sub.pm, sub.qm, sp19, sink);
+    chroma_pairs<FULL, B12, SUB, D3, QALL>(t, c, D, sub.pm, sub.qm, sp19, sink);
   }
 }
 
@@ -925,17 +936,25 @@ __device__ __forceinline__ void plane_tasks(SmemT<X> &sm, const JobDesc &J, int 
   int acc[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) acc[i] = 0;
-  auto run = [&](auto d3) {
+  auto run = [&](auto d3, auto qall) {
     block_tasks<X, B12, CH>(sm, J, first, count, y0, x0, wave, lane,
                             [&](const Taps &t, int A, int B, bool, uint32_t) {
-                              block_pairs<FULL, B12, CH, SUB, decltype(d3)::value>(
-                                  sm, J, t, A, B, SquareSum<X>{acc});
+                              block_pairs<FULL, B12, CH, SUB, decltype(d3)::value,
+                                          decltype(qall)::value>(sm, J, t, A, B,
+                                                                 SquareSum<X>{acc});
                             });
   };
+  // a subset with every S^(s) takes loops without per-pair tests
+  auto run_q = [&](auto d3) {
+    if constexpr (SUB)
+      with_flag(Subset(J.cand).qm == 15u, [&](auto qall) { run(d3, qall); });
+    else
+      run(d3, std::false_type{});
+  };
   if constexpr (CH == 0)
-    run(std::false_type{});
+    run_q(std::false_type{});
   else
-    with_d3(J.damping, run);
+    with_d3(J.damping, run_q);
   red[wave * 64 + lane] = reduce_transpose<B12>(acc, lane);
 }
 
@@ -1000,12 +1019,19 @@ __device__ __forceinline__ void chroma420_sse(SmemT<X> &sm, const JobDesc &J, in
   int acc[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) acc[i] = 0;
-  with_d3(D, [&](auto d3) {
+  auto run = [&](auto d3, auto qall) {
     chroma420_tasks<X, B12>(sm, J, first, count, y0, x0, wave, lane,
                             [&](const Taps &t, int, int, bool, bool, uint32_t) {
-                              chroma_pairs<FULL, B12, SUB, decltype(d3)::value>(
-                                  t, c, D, sub.pm, sub.qm, sp19, SquareSum<X>{acc});
+                              chroma_pairs<FULL, B12, SUB, decltype(d3)::value,
+                                           decltype(qall)::value>(t, c, D, sub.pm, sub.qm, sp19,
+                                                                  SquareSum<X>{acc});
                             });
+  };
+  with_d3(D, [&](auto d3) {
+    if constexpr (SUB)
+      with_flag(sub.qm == 15u, [&](auto qall) { run(d3, qall); });
+    else
+      run(d3, std::false_type{});
   });
   red[1 + (wave >> 1)][wave & 1][lane] = reduce_transpose<B12>(acc, lane);
 }
