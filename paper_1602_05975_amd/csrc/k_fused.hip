@@ -1528,8 +1528,15 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   __syncthreads();
   __builtin_amdgcn_s_setprio(0);
   const uint8_t *st = J.strengths + 4 * ((int64_t)fby * J.fbc + fbx);
-  const Preset py = decode_preset(st[0], st[1]);
-  const Preset pc = decode_preset(st[2], st[3]);
+  // the filter block's four strength bytes are wave-uniform: read once and
+  // decoded in scalar registers, so that every per-task quantity derived
+  // from them (adjusted strengths, dampings, shifts, weights, the tap groups
+  // in use) stays scalar too
+  const uint32_t sw = (uint32_t)uniform(
+      (int)((uint32_t)st[0] | ((uint32_t)st[1] << 8) | ((uint32_t)st[2] << 16) |
+            ((uint32_t)st[3] << 24)));
+  const Preset py = decode_preset(sw & 255, (sw >> 8) & 255);
+  const Preset pc = decode_preset((sw >> 16) & 255, sw >> 24);
   const int n = sm.n, nsk = sm.nsk;
   const int ny = n == 0 ? 0 : n + (py.skipcond ? nsk : 0);
   const int nc = n == 0 ? 0 : n + (pc.skipcond ? nsk : 0);
