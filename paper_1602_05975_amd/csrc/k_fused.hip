@@ -1545,42 +1545,45 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   const int r8 = lane >> 3, col8 = lane & 7;
 
   // luma: per-block adjusted primary strength (Eq. 13), its parity weights
-  // and damping (raised for 16..19), per 16-bit half
-  block_tasks<X, B12, 0, false>(
-      sm, J, 0, ny, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
-        const int aA = py.pri == 19 ? uniform(sm.adj19[A])
-                                    : (int)(uniform64(sm.adj[A]) >> (4 * py.pri)) & 15;
-        const int aB = py.pri == 19 ? uniform(sm.adj19[B])
-                                    : (int)(uniform64(sm.adj[B]) >> (4 * py.pri)) & 15;
-        const int DA = luma_damping(D, aA), DB = luma_damping(D, aB);
-        const uint32_t sp = ((uint32_t)aA << c) | ((uint32_t)aB << (16 + c));
-        const uint32_t sh = (uint32_t)(aA ? DA - floor_log2(aA) : 0) |
-                            ((uint32_t)(aB ? DB - floor_log2(aB) : 0) << 16);
-        const uint32_t w1 = ((aA & 1) ? 3u : 4u) | (((aB & 1) ? 3u : 4u) << 16);
-        const uint32_t w2 = ((aA & 1) ? 3u : 2u) | (((aB & 1) ? 3u : 2u) << 16);
-        // a tap group at strength 0 adds nothing (f = 0), and with one group
-        // the clamp cannot bind (its weights sum to 12/16 < 1); both
-        // decisions are wave-uniform (the task's two blocks, the block's
-        // preset)
-        const bool prim = (aA | aB) != 0, secd = py.sec != 0;
-        s16x2 P = splat(0), Q = splat(0);
-        if (prim) {
-          u16x2 a[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
-          P = group_sum(t, a, 0, sp, w1, w2);
-        }
-        if (secd) {
-          const int lq = floor_log2(py.sec);
-          const uint32_t qsh = (uint32_t)(DA - lq) | ((uint32_t)(DB - lq) << 16);
-          Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
-        }
-        const uint32_t y = __builtin_bit_cast(
-            uint32_t, prim && secd ? err_both<B12>(t, P, Q)
-                                   : prim || secd ? err_one<B12>(t, prim ? P : Q) : t.dxs);
-        sm.sy[(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
-        if (hasB) sm.sy[(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] = (uint16_t)(y >> 16);
-      });
+  // and damping (raised for 16..19), per 16-bit half.  A tap group at
+  // strength 0 adds nothing (f = 0), and with one group the clamp cannot
+  // bind (its weights sum to 12/16 < 1): whether the secondary group is in
+  // use is the filter block's (a loop instantiation each), whether the
+  // primary one is the task's (its two blocks' adjusted strengths).
+  with_flag(py.sec != 0, [&](auto sec_used) {
+    constexpr bool secd = decltype(sec_used)::value;
+    block_tasks<X, B12, 0, false>(
+        sm, J, 0, ny, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
+          const int aA = py.pri == 19 ? uniform(sm.adj19[A])
+                                      : (int)(uniform64(sm.adj[A]) >> (4 * py.pri)) & 15;
+          const int aB = py.pri == 19 ? uniform(sm.adj19[B])
+                                      : (int)(uniform64(sm.adj[B]) >> (4 * py.pri)) & 15;
+          const int DA = luma_damping(D, aA), DB = luma_damping(D, aB);
+          const uint32_t sp = ((uint32_t)aA << c) | ((uint32_t)aB << (16 + c));
+          const uint32_t sh = (uint32_t)(aA ? DA - floor_log2(aA) : 0) |
+                              ((uint32_t)(aB ? DB - floor_log2(aB) : 0) << 16);
+          const uint32_t w1 = ((aA & 1) ? 3u : 4u) | (((aB & 1) ? 3u : 4u) << 16);
+          const uint32_t w2 = ((aA & 1) ? 3u : 2u) | (((aB & 1) ? 3u : 2u) << 16);
+          const bool prim = (aA | aB) != 0;
+          s16x2 P = splat(0), Q = splat(0);
+          if (prim) {
+            u16x2 a[4];
+  #pragma unroll
+            for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
+            P = group_sum(t, a, 0, sp, w1, w2);
+          }
+          if constexpr (secd) {
+            const int lq = floor_log2(py.sec);
+            const uint32_t qsh = (uint32_t)(DA - lq) | ((uint32_t)(DB - lq) << 16);
+            Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
+          }
+          const uint32_t y = __builtin_bit_cast(
+              uint32_t, prim && secd ? err_both<B12>(t, P, Q)
+                                     : prim || secd ? err_one<B12>(t, prim ? P : Q) : t.dxs);
+          sm.sy[(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
+          if (hasB) sm.sy[(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] = (uint16_t)(y >> 16);
+        });
+  });
 
   // chroma: one preset for both planes; damping max(D - 1, floor(log2 S^(p)))
   const int Dc = pc.pri ? max(D - 1, floor_log2(pc.pri)) : D - 1;
@@ -1589,52 +1592,56 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   const uint32_t cw1 = splat32((pc.pri & 1) ? 3u : 4u), cw2 = splat32((pc.pri & 1) ? 3u : 2u);
   const uint32_t css = splat32((uint32_t)pc.sec << c);
   const uint32_t cqsh = splat32((uint32_t)(pc.sec ? Dc - floor_log2(pc.sec) : 0));
-  auto chroma_y = [&](const Taps &t) {
-    // as for luma: groups at strength 0 are skipped, and so is the clamp
-    // when one group is left
-    const bool prim = pc.pri != 0, secd = pc.sec != 0;
+  // as for luma, but both groups' use is the filter block's: one loop
+  // instantiation per combination
+  auto chroma_y = [&](const Taps &t, auto pri_used, auto sec_used) {
+    constexpr bool prim = decltype(pri_used)::value, secd = decltype(sec_used)::value;
     s16x2 P = splat(0), Q = splat(0);
-    if (prim) {
+    if constexpr (prim) {
       u16x2 a[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(csh);
       P = group_sum(t, a, 0, csp, cw1, cw2);
     }
-    if (secd) Q = secondary(t, css, cqsh);
+    if constexpr (secd) Q = secondary(t, css, cqsh);
     return __builtin_bit_cast(uint32_t, prim && secd ? err_both<B12>(t, P, Q)
                                         : prim || secd ? err_one<B12>(t, prim ? P : Q)
                                                        : t.dxs);
   };
-  if (c420) {
-    const int p = wave >> 1, sub = lane >> 4, r4 = (lane >> 2) & 3, col4 = lane & 3;
-    (void)sub;
-    chroma420_tasks<X, B12, false>(
-        sm, J, 0, nc, y0, x0, wave, lane,
-        [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t) {
-          const uint32_t y = chroma_y(t);
-          if (hasL) sm.sc[p][(4 * (L >> 3) + r4) * 32 + 4 * (L & 7) + col4] = (uint16_t)y;
-          if (hasH)
-            sm.sc[p][(4 * (Hb >> 3) + r4) * 32 + 4 * (Hb & 7) + col4] = (uint16_t)(y >> 16);
-        });
-  }
-  if constexpr (X) {
-    if (c444) {
-      auto plane444 = [&](auto ch) {
-        constexpr int CH = decltype(ch)::value;
-        block_tasks<X, B12, CH, false>(
+  with_flag(pc.pri != 0, [&](auto pri_used) {
+    with_flag(pc.sec != 0, [&](auto sec_used) {
+      if (c420) {
+        const int p = wave >> 1, sub = lane >> 4, r4 = (lane >> 2) & 3, col4 = lane & 3;
+        (void)sub;
+        chroma420_tasks<X, B12, false>(
             sm, J, 0, nc, y0, x0, wave, lane,
-            [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
-              const uint32_t y = chroma_y(t);
-              sm.sc[CH - 1][(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
-              if (hasB)
-                sm.sc[CH - 1][(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] =
-                    (uint16_t)(y >> 16);
+            [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t) {
+              const uint32_t y = chroma_y(t, pri_used, sec_used);
+              if (hasL) sm.sc[p][(4 * (L >> 3) + r4) * 32 + 4 * (L & 7) + col4] = (uint16_t)y;
+              if (hasH)
+                sm.sc[p][(4 * (Hb >> 3) + r4) * 32 + 4 * (Hb & 7) + col4] = (uint16_t)(y >> 16);
             });
-      };
-      plane444(std::integral_constant<int, 1>{});
-      plane444(std::integral_constant<int, 2>{});
-    }
-  }
+      }
+      if constexpr (X) {
+        if (c444) {
+          auto plane444 = [&](auto ch) {
+            constexpr int CH = decltype(ch)::value;
+            block_tasks<X, B12, CH, false>(
+                sm, J, 0, nc, y0, x0, wave, lane,
+                [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
+                  const uint32_t y = chroma_y(t, pri_used, sec_used);
+                  sm.sc[CH - 1][(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
+                  if (hasB)
+                    sm.sc[CH - 1][(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] =
+                        (uint16_t)(y >> 16);
+                });
+          };
+          plane444(std::integral_constant<int, 1>{});
+          plane444(std::integral_constant<int, 2>{});
+        }
+      }
+    });
+  });
   __syncthreads();
 
   // copy-out: filtered pixels from the result tiles, the rest unchanged.
