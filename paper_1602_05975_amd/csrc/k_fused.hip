@@ -1547,42 +1547,46 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   // luma: per-block adjusted primary strength (Eq. 13), its parity weights
   // and damping (raised for 16..19), per 16-bit half.  A tap group at
   // strength 0 adds nothing (f = 0), and with one group the clamp cannot
-  // bind (its weights sum to 12/16 < 1): whether the secondary group is in
-  // use is the filter block's (a loop instantiation each), whether the
-  // primary one is the task's (its two blocks' adjusted strengths).
-  with_flag(py.sec != 0, [&](auto sec_used) {
-    constexpr bool secd = decltype(sec_used)::value;
-    block_tasks<X, B12, 0, false>(
-        sm, J, 0, ny, y0, x0, wave, lane, [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
-          const int aA = py.pri == 19 ? uniform(sm.adj19[A])
-                                      : (int)(uniform64(sm.adj[A]) >> (4 * py.pri)) & 15;
-          const int aB = py.pri == 19 ? uniform(sm.adj19[B])
-                                      : (int)(uniform64(sm.adj[B]) >> (4 * py.pri)) & 15;
-          const int DA = luma_damping(D, aA), DB = luma_damping(D, aB);
-          const uint32_t sp = ((uint32_t)aA << c) | ((uint32_t)aB << (16 + c));
-          const uint32_t sh = (uint32_t)(aA ? DA - floor_log2(aA) : 0) |
-                              ((uint32_t)(aB ? DB - floor_log2(aB) : 0) << 16);
-          const uint32_t w1 = ((aA & 1) ? 3u : 4u) | (((aB & 1) ? 3u : 4u) << 16);
-          const uint32_t w2 = ((aA & 1) ? 3u : 2u) | (((aB & 1) ? 3u : 2u) << 16);
-          const bool prim = (aA | aB) != 0;
-          s16x2 P = splat(0), Q = splat(0);
-          if (prim) {
-            u16x2 a[4];
-  #pragma unroll
-            for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
-            P = group_sum(t, a, 0, sp, w1, w2);
-          }
-          if constexpr (secd) {
-            const int lq = floor_log2(py.sec);
-            const uint32_t qsh = (uint32_t)(DA - lq) | ((uint32_t)(DB - lq) << 16);
-            Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
-          }
-          const uint32_t y = __builtin_bit_cast(
-              uint32_t, prim && secd ? err_both<B12>(t, P, Q)
-                                     : prim || secd ? err_one<B12>(t, prim ? P : Q) : t.dxs);
-          sm.sy[(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
-          if (hasB) sm.sy[(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] = (uint16_t)(y >> 16);
-        });
+  // bind (its weights sum to 12/16 < 1), so the groups in use are decided
+  // per filter block (a task-loop instantiation each).  A block whose
+  // adjusted primary strength is 0 under a preset with S^(p) > 0 still runs
+  // the primary group, at strength 0: it adds 0, and the clamp it brings
+  // cannot bind either.
+  with_flag(py.pri != 0, [&](auto pri_used) {
+    with_flag(py.sec != 0, [&](auto sec_used) {
+      constexpr bool prim = decltype(pri_used)::value, secd = decltype(sec_used)::value;
+      block_tasks<X, B12, 0, false>(
+          sm, J, 0, ny, y0, x0, wave, lane,
+          [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
+            const int aA = py.pri == 19 ? uniform(sm.adj19[A])
+                                        : (int)(uniform64(sm.adj[A]) >> (4 * py.pri)) & 15;
+            const int aB = py.pri == 19 ? uniform(sm.adj19[B])
+                                        : (int)(uniform64(sm.adj[B]) >> (4 * py.pri)) & 15;
+            const int DA = luma_damping(D, aA), DB = luma_damping(D, aB);
+            const uint32_t sp = ((uint32_t)aA << c) | ((uint32_t)aB << (16 + c));
+            const uint32_t sh = (uint32_t)(aA ? DA - floor_log2(aA) : 0) |
+                                ((uint32_t)(aB ? DB - floor_log2(aB) : 0) << 16);
+            const uint32_t w1 = ((aA & 1) ? 3u : 4u) | (((aB & 1) ? 3u : 4u) << 16);
+            const uint32_t w2 = ((aA & 1) ? 3u : 2u) | (((aB & 1) ? 3u : 2u) << 16);
+            s16x2 P = splat(0), Q = splat(0);
+            if constexpr (prim) {
+              u16x2 a[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) a[k] = t.ad[k] >> as_u(sh);
+              P = group_sum(t, a, 0, sp, w1, w2);
+            }
+            if constexpr (secd) {
+              const int lq = floor_log2(py.sec);
+              const uint32_t qsh = (uint32_t)(DA - lq) | ((uint32_t)(DB - lq) << 16);
+              Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
+            }
+            const uint32_t y = __builtin_bit_cast(
+                uint32_t, prim && secd ? err_both<B12>(t, P, Q)
+                                       : prim || secd ? err_one<B12>(t, prim ? P : Q) : t.dxs);
+            sm.sy[(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
+            if (hasB) sm.sy[(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] = (uint16_t)(y >> 16);
+          });
+    });
   });
 
   // chroma: one preset for both planes; damping max(D - 1, floor(log2 S^(p)))
