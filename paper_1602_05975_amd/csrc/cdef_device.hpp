@@ -231,7 +231,7 @@ static __constant__ CutLineCounts kCutLineCounts = make_cut_line_counts();
 // (v, v) = B + B with its halves swapped.  Full-rate 16-bit work only; no
 // 32-bit multiply.
 template <int D>
-__device__ __forceinline__ int line_square(const uint32_t (&A)[15], int l) {
+__device__ __forceinline__ int line_square(const uint32_t (&A)[15], int l, int acc = 0) {
   constexpr PackedLines T = make_packed_lines(D);
   const int p = T.lo[l], q = T.hi[l];
   uint32_t w;
@@ -242,7 +242,7 @@ __device__ __forceinline__ int line_square(const uint32_t (&A)[15], int l) {
   else
     w = A[q] & 0xFFFF0000u;
   const s16x2 b = __builtin_bit_cast(s16x2, w);
-  return __builtin_amdgcn_sdot2(b, b + b.yx, 0, false);
+  return __builtin_amdgcn_sdot2(b, b + b.yx, acc, false);
 }
 
 // The 840-scaled s_D of Eq. (5) for one direction.  x: the 32 packed words of
@@ -274,15 +274,26 @@ __device__ __forceinline__ int dir_cost_packed(const uint32_t (&x)[32], int bw, 
     return __mul24(sq, 105);
   } else {
     // v^2 <= 1024^2 and 840 / N <= 840: both factors fit 24 bits
-    const uint64_t cnt = PARTIAL ? kCutLineCounts.w[D][bh - 1][bw - 1] : 0;
     int c = 0;
+    if constexpr (PARTIAL) {
+      const uint64_t cnt = kCutLineCounts.w[D][bh - 1][bw - 1];
 #pragma unroll
-    for (int l = 0; l < T.nl; ++l) {
-      const int sq = line_square<D>(A, l);
-      if (PARTIAL)
-        c += __mul24(sq, inv840((int)(cnt >> (4 * l)) & 15));
-      else
-        c += __mul24(sq, 840 / T.n[l]);
+      for (int l = 0; l < T.nl; ++l)
+        c += __mul24(line_square<D>(A, l), inv840((int)(cnt >> (4 * l)) & 15));
+    } else {
+      // the squares of the lines of one length accumulate in v_dot2 and are
+      // scaled by 840 / N once (at most 8 lines of 2^20: unsigned 24 bits)
+      int sq[9];
+#pragma unroll
+      for (int n = 0; n < 9; ++n) sq[n] = 0;
+#pragma unroll
+      for (int l = 0; l < T.nl; ++l) sq[T.n[l]] = line_square<D>(A, l, sq[T.n[l]]);
+#pragma unroll
+      for (int n = 1; n < 9; ++n) {
+        bool used = false;
+        for (int l = 0; l < T.nl; ++l) used = used || T.n[l] == n;
+        if (used) c = (int)__umul24((unsigned)sq[n], 840u / n) + c;
+      }
     }
     return c;
   }

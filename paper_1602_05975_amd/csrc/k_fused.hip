@@ -562,7 +562,7 @@ struct SmemCore {
   uint64_t lsh[64];
   uint16_t lpar[64];
   int32_t var[64];
-  int16_t coff[8][6];
+  int16_t coff[8][6];  // 4:2:0 chroma tap offsets in bytes, per direction and tap position
   uint8_t dir[64];
   uint8_t list[64];   // blocks with residual, then (full search, filter) skipped blocks
   uint8_t adj19[64];  // Eq. (13) applied to 19 (full search, filter)
@@ -663,7 +663,7 @@ __device__ __forceinline__ void stage_item(SmemCore<X> &sm, const JobDesc &J, in
   if (tid < 48) {
     const int d = tid / 6, k = tid - 6 * (tid / 6);
     const int dd = k < 2 ? d : k < 4 ? (d + 2) & 7 : (d + 6) & 7;
-    sm.coff[d][k] = (int16_t)(tap_dr(dd, k & 1) * kCS + tap_dc(dd, k & 1));
+    sm.coff[d][k] = (int16_t)(2 * (tap_dr(dd, k & 1) * kCS + tap_dc(dd, k & 1)));
   }
   if (tid < 64) {
     const int by = fby * 8 + (tid >> 3), bx = fbx * 8 + (tid & 7);
@@ -987,13 +987,20 @@ __device__ __forceinline__ void chroma420_tasks(SmemCore<X> &sm, const JobDesc &
     const uint32_t xv = ((uint32_t)rt[bL] | ((uint32_t)rt[bH] << 16)) & vm;
     const uint32_t sv =
         SRC ? ((uint32_t)st[rL * 32 + cL] | ((uint32_t)st[rH * 32 + cH] << 16)) & vm : 0u;
+    // the directions differ between lanes, so the tap addresses are formed
+    // per lane: a byte offset from the table added to or subtracted from the
+    // sample's byte address (one add per tap, the offset's sign extension
+    // folded into it)
+    const char *pL = reinterpret_cast<const char *>(rt + bL);
+    const char *pH = reinterpret_cast<const char *>(rt + bH);
+    auto at = [](const char *q) { return (uint32_t)*reinterpret_cast<const uint16_t *>(q); };
     uint32_t tp[12];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int oL = sm.coff[dL][k], oH = sm.coff[dH][k];
       const int slot = (k >> 1) * 4 + (k & 1) * 2;
-      tp[slot] = (uint32_t)rt[bL + oL] | ((uint32_t)rt[bH + oH] << 16);
-      tp[slot + 1] = (uint32_t)rt[bL - oL] | ((uint32_t)rt[bH - oH] << 16);
+      tp[slot] = at(pL + oL) | (at(pH + oH) << 16);
+      tp[slot + 1] = at(pL - oL) | (at(pH - oH) << 16);
     }
     // as for luma tasks: the mask only where a lane is outside the frame or
     // past the list's end (wave-uniform)
