@@ -874,6 +874,9 @@ __device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, i
   const uint16_t *st = CH == 0 ? sm.sy : sm.sc[CH - 1];
   const int ntask = (count + 1) >> 1;
   const int r = lane >> 3, col = lane & 7;
+  // a sample's tile index is the lane's place in a block plus the block's
+  // origin, which is wave-uniform: one add per block
+  const int lr = (r + 2) * kLS + kLC0 + col, ls = r * 64 + col;
   for (int tk = wave; tk < ntask; tk += 4) {
     const int A = uniform(sm.list[first + 2 * tk]);
     const bool hasB = 2 * tk + 1 < count;
@@ -886,11 +889,15 @@ __device__ __forceinline__ void block_tasks(SmemCore<X> &sm, const JobDesc &J, i
     // searches: lanes outside the frame see zeros and add nothing to a sum;
     // filter mode discards them (only in-frame pixels are copied out)
     const uint32_t vm = !SRC ? ~0u : (vA ? 0x0000FFFFu : 0u) | (vB ? 0xFFFF0000u : 0u);
-    const int bA = (rA + 2) * kLS + kLC0 + cA, bB = (rB + 2) * kLS + kLC0 + cB;
+    const int bA = lr + uniform(8 * (A >> 3) * kLS + 8 * (A & 7));
+    const int bB = lr + uniform(8 * (B >> 3) * kLS + 8 * (B & 7));
     const uint32_t xv = ((uint32_t)rt[bA] | ((uint32_t)rt[bB] << 16)) & vm;
     // without a source (filter mode) y - s is y itself
     const uint32_t sv =
-        SRC ? ((uint32_t)st[rA * 64 + cA] | ((uint32_t)st[rB * 64 + cB] << 16)) & vm : 0u;
+        SRC ? ((uint32_t)st[ls + uniform(512 * (A >> 3) + 8 * (A & 7))] |
+               ((uint32_t)st[ls + uniform(512 * (B >> 3) + 8 * (B & 7))] << 16)) &
+                  vm
+            : 0u;
     uint32_t ta[12], tb[12], tp[12];
     tap_samples(dA, rt, bA, ta);
     tap_samples(dB, rt, bB, tb);
@@ -1014,6 +1021,64 @@ __device__ __forceinline__ void chroma420_tasks(SmemCore<X> &sm, const JobDesc &
   }
 }
 
+// The same tasks with a lane's two samples side by side in one block row:
+// lane (b, r, j) = (lane >> 3, (lane >> 1) & 3, lane & 1) holds columns 2j
+// and 2j + 1 of row r of list entry first + 8 tk + b.  Both samples share
+// the block's direction and their taps sit side by side too, so each tap of
+// the pair is one 32-bit LDS read (at 2-byte alignment for odd offsets) and
+// no halves are merged.  The searches, with 64 pairs of arithmetic per
+// read, gain from it; the filter mode, with little arithmetic per read,
+// measured 7 % slower with the unaligned reads and keeps the layout above.
+// For each task, body(taps, block, has block, packed source) consumes the
+// pairs.
+template <bool X, bool B12, bool SRC = true, class Body>
+__device__ __forceinline__ void chroma420_row_tasks(SmemCore<X> &sm, const JobDesc &J, int first,
+                                                    int count, int y0, int x0, int wave,
+                                                    int lane, Body &&body) {
+  const int W = J.width, H = J.height;
+  const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
+  const int p = wave >> 1;
+  const uint16_t *rt = sm.rc[p];
+  const uint16_t *st = sm.sc[p];
+  const int ntask = (count + 7) >> 3;
+  const int sub = lane >> 3, r = (lane >> 1) & 3, col = 2 * (lane & 1);
+  auto pair_at = [](const char *q) {
+    uint32_t v;
+    __builtin_memcpy(&v, __builtin_assume_aligned(q, 2), 4);
+    return v;
+  };
+  for (int tk = wave & 1; tk < ntask; tk += 2) {
+    const int i = 8 * tk + sub;
+    const bool has = i < count;
+    const int L = has ? sm.list[first + i] : 0;
+    const int rL = 4 * (L >> 3) + r, cL = 4 * (L & 7) + col;
+    const bool rin = has && cy0 + rL < ch;
+    const bool v0 = rin && cx0 + cL < cw, v1 = rin && cx0 + cL + 1 < cw;
+    const uint32_t vm = !SRC ? ~0u : (v0 ? 0x0000FFFFu : 0u) | (v1 ? 0xFFFF0000u : 0u);
+    // an even sample index: the pair is one aligned word
+    const int b = (rL + 2) * kCS + kCC0 + cL;
+    const int d = sm.dir[L];
+    const uint32_t xv = *reinterpret_cast<const uint32_t *>(rt + b) & vm;
+    const uint32_t sv = SRC ? *reinterpret_cast<const uint32_t *>(st + rL * 32 + cL) & vm : 0u;
+    const char *pb = reinterpret_cast<const char *>(rt + b);
+    uint32_t tp[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int o = sm.coff[d][k];
+      const int slot = (k >> 1) * 4 + (k & 1) * 2;
+      tp[slot] = pair_at(pb + o);
+      tp[slot + 1] = pair_at(pb - o);
+    }
+    if (SRC && __builtin_amdgcn_read_exec() != __ballot(v0 && v1)) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) tp[k] &= vm;
+    }
+    Taps t;
+    prepare<B12>(t, xv, sv, tp);
+    body(t, L, has, sv);
+  }
+}
+
 // SSE search over 4:2:0 chroma tasks; plane 1 + p's totals go to
 // red[1 + p][wave & 1].
 template <bool FULL, bool B12, bool SUB, bool X>
@@ -1027,12 +1092,12 @@ __device__ __forceinline__ void chroma420_sse(SmemT<X> &sm, const JobDesc &J, in
 #pragma unroll
   for (int i = 0; i < 64; ++i) acc[i] = 0;
   auto run = [&](auto d3, auto qall) {
-    chroma420_tasks<X, B12>(sm, J, first, count, y0, x0, wave, lane,
-                            [&](const Taps &t, int, int, bool, bool, uint32_t) {
-                              chroma_pairs<FULL, B12, SUB, decltype(d3)::value,
-                                           decltype(qall)::value>(t, c, D, sub.pm, sub.qm, sp19,
-                                                                  SquareSum<X>{acc});
-                            });
+    chroma420_row_tasks<X, B12>(sm, J, first, count, y0, x0, wave, lane,
+                                [&](const Taps &t, int, bool, uint32_t) {
+                                  chroma_pairs<FULL, B12, SUB, decltype(d3)::value,
+                                               decltype(qall)::value>(
+                                      t, c, D, sub.pm, sub.qm, sp19, SquareSum<X>{acc});
+                                });
   };
   with_d3(D, [&](auto d3) {
     if constexpr (SUB)
@@ -1051,7 +1116,7 @@ __device__ __forceinline__ int plane_waves(const JobDesc &J, int P) {
 template <bool FULL, bool B12, bool SUB, bool X>
 __device__ __forceinline__ void search_item(SmemT<X> &sm, const JobDesc &J, int fby, int fbx,
                                             int tid) {
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = uniform(tid >> 6);  // scalar task loops
   const int y0 = fby * 64, x0 = fbx * 64;
   const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
   const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
@@ -1453,7 +1518,7 @@ __device__ __forceinline__ void chroma420_wb(SmemT<X> &sm, const JobDesc &J, int
 template <bool X, bool B12>
 __device__ __forceinline__ void search_item_weighted(SmemT<X> &sm, const JobDesc &J, int fby,
                                                      int fbx, int tid) {
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = uniform(tid >> 6);  // scalar task loops
   const int y0 = fby * 64, x0 = fbx * 64;
   const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
   const bool c444 = J.nplanes == 3 && J.layout == kLayout444;
@@ -1525,7 +1590,7 @@ __device__ __forceinline__ void search_item_weighted(SmemT<X> &sm, const JobDesc
 template <bool X, bool B12, bool PACKED>
 __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, int fby, int fbx,
                                             int tid) {
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = uniform(tid >> 6), lane = tid & 63;  // scalar task loops
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int c = J.bitdepth - 8, D = J.damping;
   __builtin_amdgcn_s_setprio(2);  // as in the searches
@@ -1549,7 +1614,7 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   const int nc = n == 0 ? 0 : n + (pc.skipcond ? nsk : 0);
   const bool c420 = J.nplanes == 3 && J.layout == kLayout420;
   const bool c444 = X && J.nplanes == 3 && J.layout == kLayout444;
-  const int r8 = lane >> 3, col8 = lane & 7;
+  const int ly = (lane >> 3) * 64 + (lane & 7);  // a lane's place in a block of a 64-wide tile
 
   // luma: per-block adjusted primary strength (Eq. 13), its parity weights
   // and damping (raised for 16..19), per 16-bit half.  A tap group at
@@ -1590,8 +1655,8 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
             const uint32_t y = __builtin_bit_cast(
                 uint32_t, prim && secd ? err_both<B12>(t, P, Q)
                                        : prim || secd ? err_one<B12>(t, prim ? P : Q) : t.dxs);
-            sm.sy[(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
-            if (hasB) sm.sy[(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] = (uint16_t)(y >> 16);
+            sm.sy[ly + uniform(512 * (A >> 3) + 8 * (A & 7))] = (uint16_t)y;
+            if (hasB) sm.sy[ly + uniform(512 * (B >> 3) + 8 * (B & 7))] = (uint16_t)(y >> 16);
           });
     });
   });
@@ -1622,8 +1687,7 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   with_flag(pc.pri != 0, [&](auto pri_used) {
     with_flag(pc.sec != 0, [&](auto sec_used) {
       if (c420) {
-        const int p = wave >> 1, sub = lane >> 4, r4 = (lane >> 2) & 3, col4 = lane & 3;
-        (void)sub;
+        const int p = wave >> 1, r4 = (lane >> 2) & 3, col4 = lane & 3;
         chroma420_tasks<X, B12, false>(
             sm, J, 0, nc, y0, x0, wave, lane,
             [&](const Taps &t, int L, int Hb, bool hasL, bool hasH, uint32_t) {
@@ -1641,9 +1705,9 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
                 sm, J, 0, nc, y0, x0, wave, lane,
                 [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
                   const uint32_t y = chroma_y(t, pri_used, sec_used);
-                  sm.sc[CH - 1][(8 * (A >> 3) + r8) * 64 + 8 * (A & 7) + col8] = (uint16_t)y;
+                  sm.sc[CH - 1][ly + uniform(512 * (A >> 3) + 8 * (A & 7))] = (uint16_t)y;
                   if (hasB)
-                    sm.sc[CH - 1][(8 * (B >> 3) + r8) * 64 + 8 * (B & 7) + col8] =
+                    sm.sc[CH - 1][ly + uniform(512 * (B >> 3) + 8 * (B & 7))] =
                         (uint16_t)(y >> 16);
                 });
           };
