@@ -556,11 +556,20 @@ struct SmemCore {
   uint16_t rc[2][kCT];
   uint16_t sc[2][kCSrc];  // searches: source; filter: filtered chroma
   uint64_t adj[64];
-  // searches, per block and primary strength S = 1..15 of the adjusted
-  // strength a_S: 4 bits of D - floor(log2 a_S) (0 where a_S = 0), and bit S
-  // of its parity
-  uint64_t lsh[64];
-  uint16_t lpar[64];
+  union {
+    // searches, per block and primary strength S = 1..15 of the adjusted
+    // strength a_S: 4 bits of D - floor(log2 a_S) (0 where a_S = 0), and
+    // bit S of its parity
+    struct {
+      uint64_t lsh[64];
+      uint16_t lpar[64];
+    };
+    // filter mode, per block under the filter block's luma preset: word 0
+    // holds the adjusted primary strength scaled to the bit depth (low half)
+    // and its magnitude shift (high half), word 1 its parity (low half) and
+    // the secondary taps' shift (high half)
+    uint32_t fpar[64][2];
+  };
   int32_t var[64];
   int16_t coff[8][6];  // 4:2:0 chroma tap offsets in bytes, per direction and tap position
   uint8_t dir[64];
@@ -678,9 +687,9 @@ __device__ __forceinline__ void stage_item(SmemCore<X> &sm, const JobDesc &J, in
 // (the full search lists the skipped in-frame blocks after them).
 // PACKED: Algorithm 1 on packed 16-bit halves (half the registers; the
 // filter kernels), else in 32-bit lanes (fewer issue cycles; the searches).
-template <bool FULL, bool X, bool PACKED = false>
+template <bool FULL, bool X, bool PACKED = false, bool FILT = false>
 __device__ __forceinline__ void direction_search(SmemCore<X> &sm, const JobDesc &J, int fby, int fbx,
-                                                 int lane) {
+                                                 int lane, const Preset &py = Preset{}) {
   const int b = lane;
   const int by = fby * 8 + (b >> 3), bx = fbx * 8 + (b & 7);
   const int c = J.bitdepth - 8;
@@ -746,7 +755,17 @@ __device__ __forceinline__ void direction_search(SmemCore<X> &sm, const JobDesc 
   sm.var[b] = v;
   const uint64_t adj = adjusted_strengths(v);
   sm.adj[b] = adj;
-  if constexpr (!PACKED) {
+  if constexpr (FILT) {
+    // the filter block's luma preset: per block the Eq. (13) strength (the
+    // special preset's 19 adjusted the same way), its damping, shifts and
+    // parity, once here instead of in every task
+    const int a = py.pri == 19 ? adjust_strength(19, v) : (int)(adj >> (4 * py.pri)) & 15;
+    const int Da = luma_damping(J.damping, a);
+    const uint32_t sh = a ? (uint32_t)(Da - floor_log2(a)) : 0u;
+    const uint32_t qsh = py.sec ? (uint32_t)(Da - floor_log2(py.sec)) : 0u;
+    sm.fpar[b][0] = ((uint32_t)a << c) | (sh << 16);
+    sm.fpar[b][1] = (uint32_t)(a & 1) | (qsh << 16);
+  } else if constexpr (!PACKED) {
     const int D = J.damping;
     uint64_t shw = 0;
     uint32_t par = 0;
@@ -1594,21 +1613,21 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   const int W = J.width, H = J.height, y0 = fby * 64, x0 = fbx * 64;
   const int c = J.bitdepth - 8, D = J.damping;
   __builtin_amdgcn_s_setprio(2);  // as in the searches
-  stage_item<X>(sm, J, fby, fbx, tid, false);
-  __syncthreads();
-  if (wave == 0) direction_search<true, X, PACKED>(sm, J, fby, fbx, lane);
-  __syncthreads();
-  __builtin_amdgcn_s_setprio(0);
   const uint8_t *st = J.strengths + 4 * ((int64_t)fby * J.fbc + fbx);
   // the filter block's four strength bytes are wave-uniform: read once and
   // decoded in scalar registers, so that every per-task quantity derived
-  // from them (adjusted strengths, dampings, shifts, weights, the tap groups
-  // in use) stays scalar too
+  // from them (dampings, shifts, weights, the tap groups in use) stays
+  // scalar too
   const uint32_t sw = (uint32_t)uniform(
       (int)((uint32_t)st[0] | ((uint32_t)st[1] << 8) | ((uint32_t)st[2] << 16) |
             ((uint32_t)st[3] << 24)));
   const Preset py = decode_preset(sw & 255, (sw >> 8) & 255);
   const Preset pc = decode_preset((sw >> 16) & 255, sw >> 24);
+  stage_item<X>(sm, J, fby, fbx, tid, false);
+  __syncthreads();
+  if (wave == 0) direction_search<true, X, PACKED, true>(sm, J, fby, fbx, lane, py);
+  __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
   const int n = sm.n, nsk = sm.nsk;
   const int ny = n == 0 ? 0 : n + (py.skipcond ? nsk : 0);
   const int nc = n == 0 ? 0 : n + (pc.skipcond ? nsk : 0);
@@ -1630,16 +1649,16 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
       block_tasks<X, B12, 0, false>(
           sm, J, 0, ny, y0, x0, wave, lane,
           [&](const Taps &t, int A, int B, bool hasB, uint32_t) {
-            const int aA = py.pri == 19 ? uniform(sm.adj19[A])
-                                        : (int)(uniform64(sm.adj[A]) >> (4 * py.pri)) & 15;
-            const int aB = py.pri == 19 ? uniform(sm.adj19[B])
-                                        : (int)(uniform64(sm.adj[B]) >> (4 * py.pri)) & 15;
-            const int DA = luma_damping(D, aA), DB = luma_damping(D, aB);
-            const uint32_t sp = ((uint32_t)aA << c) | ((uint32_t)aB << (16 + c));
-            const uint32_t sh = (uint32_t)(aA ? DA - floor_log2(aA) : 0) |
-                                ((uint32_t)(aB ? DB - floor_log2(aB) : 0) << 16);
-            const uint32_t w1 = ((aA & 1) ? 3u : 4u) | (((aB & 1) ? 3u : 4u) << 16);
-            const uint32_t w2 = ((aA & 1) ? 3u : 2u) | (((aB & 1) ? 3u : 2u) << 16);
+            // per-block words from the direction search, halves paired
+            const uint32_t fA0 = (uint32_t)uniform((int)sm.fpar[A][0]);
+            const uint32_t fB0 = (uint32_t)uniform((int)sm.fpar[B][0]);
+            const uint32_t fA1 = (uint32_t)uniform((int)sm.fpar[A][1]);
+            const uint32_t fB1 = (uint32_t)uniform((int)sm.fpar[B][1]);
+            const uint32_t sp = (fA0 & 0xFFFFu) | (fB0 << 16);
+            const uint32_t sh = (fA0 >> 16) | (fB0 & 0xFFFF0000u);
+            const uint32_t odd = (fA1 & 0xFFFFu) | (fB1 << 16);
+            // weights 4, 2 at even strengths, 3, 3 at odd ones
+            const uint32_t w1 = 0x00040004u - odd, w2 = 0x00020002u + odd;
             s16x2 P = splat(0), Q = splat(0);
             if constexpr (prim) {
               u16x2 a[4];
@@ -1648,8 +1667,7 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
               P = group_sum(t, a, 0, sp, w1, w2);
             }
             if constexpr (secd) {
-              const int lq = floor_log2(py.sec);
-              const uint32_t qsh = (uint32_t)(DA - lq) | ((uint32_t)(DB - lq) << 16);
+              const uint32_t qsh = (fA1 >> 16) | (fB1 & 0xFFFF0000u);
               Q = secondary(t, splat32((uint32_t)py.sec << c), qsh);
             }
             const uint32_t y = __builtin_bit_cast(
