@@ -151,17 +151,20 @@ cdef_status make_job(const cdef_job *j, cdef::JobDesc *o) {
   o->cand = j->candidates;
   cdef::fill_job_geometry(*o);
   // 16-byte staging is possible when every plane read starts 16-byte aligned
-  // and every row pitch keeps it so
+  // and every row pitch keeps it so (and is small enough for the 32-bit row
+  // offsets of that path)
+  auto fits16 = [](const void *base, int32_t pitch) {
+    return ((uintptr_t)base & 15) == 0 && (pitch & 7) == 0 && pitch < cdef::kPitch16Max;
+  };
   bool al = true;
   for (int p = 0; p < r.nplanes; ++p) {
-    al = al && ((uintptr_t)o->rec[p] & 15) == 0 && (o->rstride[p] & 7) == 0;
-    if (search) al = al && ((uintptr_t)o->src[p] & 15) == 0 && (o->sstride[p] & 7) == 0;
+    al = al && fits16(o->rec[p], o->rstride[p]);
+    if (search) al = al && fits16(o->src[p], o->sstride[p]);
   }
   o->flags = al ? cdef::kAligned16 : 0;
   if (j->mode == CDEF_MODE_FILTER) {
     bool ao = true;
-    for (int p = 0; p < r.nplanes; ++p)
-      ao = ao && ((uintptr_t)o->out[p] & 15) == 0 && (o->ostride[p] & 7) == 0;
+    for (int p = 0; p < r.nplanes; ++p) ao = ao && fits16(o->out[p], o->ostride[p]);
     if (ao) o->flags |= cdef::kOut16;
   }
   return CDEF_OK;

@@ -444,24 +444,58 @@ __device__ __forceinline__ void stage_interior(uint16_t *lds, const uint16_t *pl
 // and row pitch are 16-byte aligned, into LDS rows of LSTRIDE samples: row r,
 // chunk q reads plane[(y0 + r) * stride + xs + 8 q .. + 7], xs a multiple of 8.
 // The caller guarantees that the whole rectangle lies inside the plane.
+// Frame planes live in device (global) memory: byte pointers into them in
+// the global address space, so that loads and stores through them are
+// global instructions with a scalar base, not flat ones.
+using GlobalBytes = const __attribute__((address_space(1))) char *;
+using GlobalBytesOut = __attribute__((address_space(1))) char *;
+__device__ __forceinline__ GlobalBytes to_global(const uint16_t *p) {
+  return (GlobalBytes)(reinterpret_cast<const char *>(p));
+}
+__device__ __forceinline__ GlobalBytesOut to_global_out(uint16_t *p) {
+  return (GlobalBytesOut)(reinterpret_cast<char *>(p));
+}
+// 16- and 8-byte moves through such pointers (plain vector types: the HIP
+// vector classes have no assignment in that address space)
+using U32x4 = uint32_t __attribute__((ext_vector_type(4)));
+using U32x2 = uint32_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint4 load16(GlobalBytes p) {
+  return __builtin_bit_cast(uint4, *reinterpret_cast<const __attribute__((address_space(1))) U32x4 *>(p));
+}
+__device__ __forceinline__ void store16(GlobalBytesOut p, uint4 v) {
+  *reinterpret_cast<__attribute__((address_space(1))) U32x4 *>(p) = __builtin_bit_cast(U32x4, v);
+}
+__device__ __forceinline__ void store8(GlobalBytesOut p, uint2 v) {
+  *reinterpret_cast<__attribute__((address_space(1))) U32x2 *>(p) = __builtin_bit_cast(U32x2, v);
+}
+
 template <int ROWS, int Q, int LSTRIDE, int NT>
 __device__ __forceinline__ void stage_rows16(uint16_t *lds, const uint16_t *plane, int64_t stride,
                                              int y0, int xs, int tid) {
   constexpr int N = ROWS * Q, ITER = (N + NT - 1) / NT;
+  // global loads from a wave-uniform base at 32-bit byte offsets: the
+  // callers take this path only for pitches below 2^23 samples, so a row
+  // offset is a 24-bit product
+  // offset, with e = r Q + q: r pitch + 16 q = r (pitch - 16 Q) + 16 e (the
+  // callers' bounds keep the staged row inside the plane's row, so a pitch
+  // holds at least its 16 Q bytes)
+  const GlobalBytes base = to_global(plane + (int64_t)y0 * stride + xs);
+  const uint32_t rstep = 2u * (uint32_t)stride - 16u * Q;
   uint4 v[ITER];
 #pragma unroll
   for (int k = 0; k < ITER; ++k) {
     const int e = tid + k * NT;
-    const int r = e / Q, q = e - r * Q;
+    const int r = e / Q;
     v[k] = make_uint4(0, 0, 0, 0);
     if (e < N)
-      v[k] = *reinterpret_cast<const uint4 *>(plane + (int64_t)(y0 + r) * stride + xs + 8 * q);
+      v[k] = load16(base + (__umul24((uint32_t)r, rstep) + 16u * (uint32_t)e));
   }
+  static_assert(LSTRIDE >= 8 * Q, "an LDS tile row holds the staged row");
 #pragma unroll
   for (int k = 0; k < ITER; ++k) {
     const int e = tid + k * NT;
-    const int r = e / Q, q = e - r * Q;
-    if (e < N) *reinterpret_cast<uint4 *>(lds + r * LSTRIDE + 8 * q) = v[k];
+    const int r = e / Q;
+    if (e < N) *reinterpret_cast<uint4 *>(lds + r * (LSTRIDE - 8 * Q) + 8 * e) = v[k];
   }
 }
 

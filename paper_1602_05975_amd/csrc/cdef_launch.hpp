@@ -27,9 +27,13 @@ enum JobMode : int32_t {
 };
 // kDirIn: filter mode takes dir / var as inputs (cdef_filter_frame) instead
 // of running the direction search and optionally writing them.
-// kOut16: filter mode's output planes have 16-byte aligned bases and row
-// pitches.
+// kAligned16: every plane the job reads has a 16-byte aligned base and row
+// pitch, and a pitch below kPitch16Max samples.
+// kOut16: the same for filter mode's output planes.
 enum JobFlags : int32_t { kAligned16 = 1, kDirIn = 2, kOut16 = 4 };
+// Pitch limit of the 16-byte paths: 68 rows of a tile then span less than
+// 2^31 bytes and a row offset is a 24-bit product (samples, 2 bytes each).
+constexpr int32_t kPitch16Max = 1 << 23;
 
 // One frame of work as the fused kernel reads it (kernel argument for a
 // single frame, or an element of a device-resident table for a batch).

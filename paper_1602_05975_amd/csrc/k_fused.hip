@@ -1741,14 +1741,21 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   // Aligned outputs move a block row at a time (16 bytes; 8 for 4:2:0
   // chroma): every sample of it shares the block's decision.
   const bool out16 = J.flags & kOut16;
+  // aligned outputs: a wave-uniform base per plane and 32-bit byte offsets
+  // (their pitches are below 2^23 samples)
+  auto out_row = [&](int p, int y, int x) {
+    return to_global_out(J.out[p] + (int64_t)y * J.ostride[p] + x);
+  };
   if (out16 && x0 + 64 <= W) {
+    GlobalBytesOut ob = out_row(0, y0, x0);
+    const uint32_t pitch = 2u * (uint32_t)J.ostride[0];
     for (int e = tid; e < 64 * 8; e += 256) {
       const int r = e >> 3, q = e & 7;
       if (y0 + r >= H) continue;
       const bool filt = n > 0 && (!(sm.flag[(r >> 3) * 8 + q] & 2) || py.skipcond);
       const uint4 v = filt ? *reinterpret_cast<const uint4 *>(&sm.sy[r * 64 + 8 * q])
                            : *reinterpret_cast<const uint4 *>(&sm.ry[(r + 2) * kLS + kLC0 + 8 * q]);
-      *reinterpret_cast<uint4 *>(&J.out[0][(int64_t)(y0 + r) * J.ostride[0] + x0 + 8 * q]) = v;
+      store16(ob + (__umul24((uint32_t)r, pitch) + 16u * q), v);
     }
   } else {
     for (int e = tid; e < 64 * 64; e += 256) {
@@ -1775,15 +1782,19 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   if constexpr (X) {
     if (c444) {
       if (out16 && x0 + 64 <= W) {
-        for (int e = tid; e < 2 * 64 * 8; e += 256) {
-          const int p = e >> 9, r = (e >> 3) & 63, q = e & 7;
-          if (y0 + r >= H) continue;
-          const bool filt = n > 0 && (!(sm.flag[(r >> 3) * 8 + q] & 2) || pc.skipcond);
-          const uint4 v =
-              filt ? *reinterpret_cast<const uint4 *>(&sm.sc[p][r * 64 + 8 * q])
-                   : *reinterpret_cast<const uint4 *>(&sm.rc[p][(r + 2) * kLS + kLC0 + 8 * q]);
-          *reinterpret_cast<uint4 *>(
-              &J.out[1 + p][(int64_t)(y0 + r) * J.ostride[1 + p] + x0 + 8 * q]) = v;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          GlobalBytesOut ob = out_row(1 + p, y0, x0);
+          const uint32_t pitch = 2u * (uint32_t)J.ostride[1 + p];
+          for (int e = tid; e < 64 * 8; e += 256) {
+            const int r = e >> 3, q = e & 7;
+            if (y0 + r >= H) continue;
+            const bool filt = n > 0 && (!(sm.flag[(r >> 3) * 8 + q] & 2) || pc.skipcond);
+            const uint4 v =
+                filt ? *reinterpret_cast<const uint4 *>(&sm.sc[p][r * 64 + 8 * q])
+                     : *reinterpret_cast<const uint4 *>(&sm.rc[p][(r + 2) * kLS + kLC0 + 8 * q]);
+            store16(ob + (__umul24((uint32_t)r, pitch) + 16u * q), v);
+          }
         }
         return;
       }
@@ -1800,14 +1811,19 @@ __device__ __forceinline__ void filter_item(SmemCore<X> &sm, const JobDesc &J, i
   }
   const int cw = (W + 1) >> 1, ch = (H + 1) >> 1, cy0 = y0 >> 1, cx0 = x0 >> 1;
   if (out16 && cx0 + 32 <= cw) {
-    for (int e = tid; e < 2 * 32 * 8; e += 256) {
-      const int p = e >> 8, r = (e >> 3) & 31, q = e & 7;
-      if (cy0 + r >= ch) continue;
-      const bool filt = n > 0 && (!(sm.flag[(r >> 2) * 8 + q] & 2) || pc.skipcond);
-      const uint2 v = filt ? *reinterpret_cast<const uint2 *>(&sm.sc[p][r * 32 + 4 * q])
-                           : *reinterpret_cast<const uint2 *>(&sm.rc[p][(r + 2) * kCS + kCC0 + 4 * q]);
-      *reinterpret_cast<uint2 *>(
-          &J.out[1 + p][(int64_t)(cy0 + r) * J.ostride[1 + p] + cx0 + 4 * q]) = v;
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+      GlobalBytesOut ob = out_row(1 + pl, cy0, cx0);
+      const uint32_t pitch = 2u * (uint32_t)J.ostride[1 + pl];
+      for (int e = tid; e < 32 * 8; e += 256) {
+        const int r = e >> 3, q = e & 7;
+        if (cy0 + r >= ch) continue;
+        const bool filt = n > 0 && (!(sm.flag[(r >> 2) * 8 + q] & 2) || pc.skipcond);
+        const uint2 v =
+            filt ? *reinterpret_cast<const uint2 *>(&sm.sc[pl][r * 32 + 4 * q])
+                 : *reinterpret_cast<const uint2 *>(&sm.rc[pl][(r + 2) * kCS + kCC0 + 4 * q]);
+        store8(ob + (__umul24((uint32_t)r, pitch) + 8u * q), v);
+      }
     }
     return;
   }

@@ -116,3 +116,46 @@ def test_strided_planes_match_oracle(oracle, w, h, bd, layout, rpad, spad, opad,
             r0, c0 = divmod(oo // 2, buf.stride(0))
             hb[r0:r0 + ph, c0:c0 + pw] = PAD
             assert (hb == PAD).all(), (name, p, "wrote outside the frame")
+
+
+@pytest.mark.parametrize("stride", [(1 << 23) - 8, 1 << 23])
+def test_pitch_limit_of_16_byte_paths(oracle, stride):
+    """Row pitches at the limit of the 16-byte staging and copy-out paths:
+    below 2^23 samples they take 32-bit row offsets, at 2^23 the kernels go
+    sample by sample.  Both match the oracle (the frame has interior filter
+    blocks, which take the 16-byte path when the pitch allows)."""
+    import torch
+    from paper_1602_05975_amd import cdef, synth
+    w, h, bd, D = 200, 136, 10, 3
+    fr = synth.make_frame(w, h, bd, synth.LAYOUT_400, 81500 + (stride & 15), skip_prob=0.3,
+                          damping=D)
+
+    def big(p):
+        # built on the device: a host copy of a 2 GiB buffer is not needed
+        buf = torch.full((h + 4, stride), -1, dtype=torch.int16, device="cuda")
+        v = buf[2:2 + h, 0:w]
+        v.copy_(torch.from_numpy(p.view(np.int16)).cuda())
+        assert v.data_ptr() % 16 == 0 and v.stride(0) == stride
+        return v, buf
+
+    rv, rbuf = big(fr.recon[0])
+    sv, sbuf = big(fr.src[0])
+    ov, obuf = big(np.zeros_like(fr.recon[0]))
+    rec = cdef.Frame([rv], w, h, bd, synth.LAYOUT_400)
+    src = cdef.Frame([sv], w, h, bd, synth.LAYOUT_400)
+    skip = torch.from_numpy(fr.skip).cuda()
+    st = torch.from_numpy(synth.random_presets(fr, 81600)).cuda()
+    print(f"pitch {stride}: {w}x{h} 10-bit 4:0:0", flush=True)
+    sse, d, v = cdef.search_strengths(rec, src, skip, D, want_dir=True)
+    cdef.cdef_filter_frame(rec, [ov], d, v, skip, D, st)
+    torch.cuda.synchronize()
+    od, ovar = oracle.find_dir(fr.recon[0], bd)
+    assert (d.cpu().numpy() == od).all() and (v.cpu().numpy() == ovar).all()
+    ref, _, _ = oracle.search(fr.recon, fr.src, w, h, bd, fr.skip, D, threads=ORACLE_THREADS,
+                              layout=synth.LAYOUT_400)
+    assert np.array_equal(sse.cpu().numpy().view(np.uint64), ref)
+    want = oracle.filter_frame(fr.recon, w, h, bd, od, ovar, fr.skip, D, st.cpu().numpy(),
+                               layout=synth.LAYOUT_400)
+    assert np.array_equal(to_np_u16(ov), want[0])
+    # the rows below and above the frame are untouched
+    assert (obuf[:2, :w] == -1).all() and (obuf[2 + h:, :w] == -1).all()
